@@ -1,0 +1,240 @@
+"""Seeded synthetic workloads for the GL-ECSIM particle pass.
+
+The generator itself is C (``gen.c``, Philox4x32-10 + Box-Muller); this module
+builds it, describes the workloads, and returns numpy arrays.  It holds none
+of the PIC method's arithmetic: it only draws particles and evaluates analytic
+initial conditions.  The CPU oracle and the GPU path both take their inputs
+from here.
+
+Units are normalised: c = 1, e = 1, m_e = 1 and n0 = 1/(4 pi), so that the
+electron plasma frequency and inertial length are 1.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import math
+import os
+import subprocess
+from typing import Dict, Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "gen.c")
+_LIB = os.path.join(_HERE, "libsynth.so")
+N0 = 1.0 / (4.0 * math.pi)
+
+PROF_UNIFORM, PROF_SHOCK_TUBE, PROF_HARRIS2 = 0, 1, 2
+
+
+class _Cfg(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int), ("n", ctypes.c_int * 3), ("dx", ctypes.c_double * 3),
+        ("ppc", ctypes.c_int), ("nsp", ctypes.c_int),
+        ("q", ctypes.c_double * 4), ("m", ctypes.c_double * 4), ("vth", ctypes.c_double * 4),
+        ("paired", ctypes.c_int), ("seed", ctypes.c_uint32), ("profile", ctypes.c_int),
+        ("n0", ctypes.c_double), ("u0", ctypes.c_double * 3), ("ushock", ctypes.c_double),
+        ("B0", ctypes.c_double * 3), ("lambda_", ctypes.c_double), ("nb", ctypes.c_double),
+        ("Bh", ctypes.c_double), ("psi", ctypes.c_double), ("dsheet", ctypes.c_double * 4),
+    ]
+
+
+def build(force: bool = True) -> str:
+    """Compile gen.c into libsynth.so with gcc (OpenMP over cells)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        L = ctypes.CDLL(_LIB)
+        L.synth_philox4x32_10.argtypes = [ctypes.POINTER(ctypes.c_uint32)] * 3
+        L.synth_particles.restype = ctypes.c_int64
+        L.synth_particles.argtypes = [ctypes.POINTER(_Cfg), ctypes.c_int, ctypes.c_int64, ctypes.c_int64,
+                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                      ctypes.c_int]
+        L.synth_fields.argtypes = [ctypes.POINTER(_Cfg), ctypes.c_void_p, ctypes.c_void_p]
+        L.synth_cfg_size.restype = ctypes.c_int
+        assert L.synth_cfg_size() == ctypes.sizeof(_Cfg), "synth_cfg layout mismatch"
+        _lib = L
+    return _lib
+
+
+def philox4x32_10(ctr, key):
+    c = (ctypes.c_uint32 * 4)(*[int(x) & 0xFFFFFFFF for x in ctr])
+    k = (ctypes.c_uint32 * 2)(*[int(x) & 0xFFFFFFFF for x in key])
+    o = (ctypes.c_uint32 * 4)()
+    lib().synth_philox4x32_10(c, k, o)
+    return [int(x) for x in o]
+
+
+@dataclasses.dataclass
+class Workload:
+    """Initial state + run parameters of one synthetic workload."""
+    name: str
+    dim: int
+    n: tuple
+    dx: tuple
+    ppc: int
+    q: tuple
+    m: tuple
+    vth: tuple
+    paired: bool = False
+    seed: int = 1
+    profile: int = PROF_UNIFORM
+    n0: float = N0
+    u0: tuple = (0.0, 0.0, 0.0)
+    ushock: float = 0.0
+    B0: tuple = (0.0, 0.0, 0.0)
+    lam: float = 1.0
+    nb: float = 0.0
+    Bh: float = 0.0
+    psi: float = 0.0
+    dsheet: tuple = (0.0, 0.0)
+    # run parameters
+    dt: float = 0.5
+    theta: float = 0.5
+    steps: int = 1
+    lf_E: bool = True
+    lf_B: bool = True
+    beta_lim: float = 1.0
+    a_mode: int = 1          # 0: a = c (light speed), 1: a = |u| (bulk speed)
+    comoving: bool = True
+    n_smooth_u: int = 5
+    fp32: bool = False
+    note: str = ""
+
+    @property
+    def nsp(self) -> int:
+        return len(self.q)
+
+    @property
+    def ncells(self) -> int:
+        return int(np.prod(self.n[: self.dim]))
+
+    def nparticles(self) -> int:
+        return self.ncells * self.ppc * self.nsp
+
+    def cfg(self) -> _Cfg:
+        c = _Cfg()
+        c.dim = self.dim
+        for d in range(3):
+            c.n[d] = int(self.n[d]) if d < self.dim else 1
+            c.dx[d] = float(self.dx[d]) if d < self.dim else 1.0
+        c.ppc, c.nsp = self.ppc, self.nsp
+        for s in range(self.nsp):
+            c.q[s], c.m[s], c.vth[s] = self.q[s], self.m[s], self.vth[s]
+            c.dsheet[s] = self.dsheet[s] if s < len(self.dsheet) else 0.0
+        c.paired, c.seed, c.profile = int(self.paired), self.seed, self.profile
+        c.n0 = self.n0
+        for d in range(3):
+            c.u0[d], c.B0[d] = self.u0[d], self.B0[d]
+        c.ushock, c.lambda_, c.nb, c.Bh, c.psi = self.ushock, self.lam, self.nb, self.Bh, self.psi
+        return c
+
+    def replace(self, **kw) -> "Workload":
+        return dataclasses.replace(self, **kw)
+
+
+def particles(wl: Workload, s: int, cell_begin: int = 0, cell_end: Optional[int] = None,
+              f32: bool = False) -> Dict[str, np.ndarray]:
+    """Particles of species s in cells [cell_begin, cell_end), cell-major.
+
+    Returns dict with 'cell' (int32 [n]), 'off' ([3, n], offset in cell),
+    'v' ([3, n]) and 'w' ([n]) in float64 (or float32 if f32)."""
+    if cell_end is None:
+        cell_end = wl.ncells
+    n = (cell_end - cell_begin) * wl.ppc
+    dt = np.float32 if f32 else np.float64
+    cell = np.empty(n, np.int32)
+    off = np.empty((3, n), dt)
+    v = np.empty((3, n), dt)
+    w = np.empty(n, dt)
+    c = wl.cfg()
+    got = lib().synth_particles(ctypes.byref(c), s, cell_begin, cell_end, cell.ctypes.data,
+                                off.ctypes.data, v.ctypes.data, w.ctypes.data, int(f32))
+    assert got == n
+    return {"cell": cell, "off": off, "v": v, "w": w}
+
+
+def fields(wl: Workload):
+    """Initial E (nodes) and B (cell centres), float64 arrays [3, N]."""
+    N = wl.ncells
+    E = np.empty((3, N), np.float64)
+    B = np.empty((3, N), np.float64)
+    c = wl.cfg()
+    lib().synth_fields(ctypes.byref(c), E.ctypes.data, B.ctypes.data)
+    return E, B
+
+
+def _harris(name, dim, n, mi, ppc, guide, steps, fp32):
+    # v_A = B0 / sqrt(4 pi n0 m_i) = B0 / sqrt(m_i); pressure balance
+    # n0 (Te + Ti) = B0^2 / (8 pi)  =>  Te + Ti = B0^2 / 2, with Ti/Te = 5.
+    B0 = 0.5
+    Tsum = B0 * B0 / 2.0
+    Te, Ti = Tsum / 6.0, 5.0 * Tsum / 6.0
+    di = math.sqrt(mi)
+    lam = 0.5 * di
+    ui_minus_ue = B0 / lam  # curl B = 4 pi J with 4 pi n0 = 1
+    ui, ue = ui_minus_ue * Ti / (Te + Ti), -ui_minus_ue * Te / (Te + Ti)
+    return Workload(
+        name=name, dim=dim, n=n, dx=(0.5, 0.5, 0.5), ppc=ppc, q=(-1.0, 1.0), m=(1.0, mi),
+        vth=(math.sqrt(Te), math.sqrt(Ti / mi)), paired=False, seed=3 if dim == 2 else 5,
+        profile=PROF_HARRIS2, u0=(guide, 0.0, 0.0), lam=lam, nb=0.1, Bh=B0,
+        psi=0.05 * B0 * di, dsheet=(ue, ui), dt=0.5, theta=0.5, steps=steps,
+        lf_E=True, lf_B=True, beta_lim=1.0, a_mode=1, comoving=True, fp32=fp32)
+
+
+def workloads() -> Dict[str, Workload]:
+    """The five workloads (C1..C5) plus small parity cases."""
+    W = {}
+    # C1: 1D3V shock tube, FP64, plain method.
+    W["c1"] = Workload(
+        name="c1_shock_tube_1d", dim=1, n=(64, 1, 1), dx=(0.5, 1, 1), ppc=100,
+        q=(-1.0, 1.0), m=(1.0, 25.0), vth=(0.05, 0.01), paired=True, seed=1,
+        profile=PROF_SHOCK_TUBE, ushock=0.1, B0=(0.0, 0.0, 0.1), dt=0.5, theta=0.5, steps=20,
+        lf_E=False, lf_B=False, beta_lim=1.0, a_mode=1, comoving=False, fp32=False)
+    # C2: 2D3V fast flow noise test.
+    W["c2"] = Workload(
+        name="c2_fast_flow_2d", dim=2, n=(256, 128, 1), dx=(0.8, 0.8, 1), ppc=64,
+        q=(-1.0, 1.0), m=(1.0, 100.0), vth=(0.02, 0.02 * math.sqrt(0.5 / 100.0)), paired=False,
+        seed=2, profile=PROF_UNIFORM, u0=(0.2, 0.0, 0.0), B0=(0.0, 0.0, 0.217), dt=0.5,
+        theta=0.5, steps=200, lf_E=True, lf_B=True, beta_lim=1.0, a_mode=1, comoving=True,
+        fp32=False)
+    # C3: 2D3V Harris sheet reconnection (double sheet, periodic).
+    W["c3"] = _harris("c3_harris_2d", 2, (512, 256, 1), 25.0, 100, 0.0, 500, True)
+    # C4: 3D3V collisionless shock (periodic, mirror-symmetric colliding flows).
+    th = math.radians(30.0)
+    W["c4"] = Workload(
+        name="c4_shock_3d", dim=3, n=(128, 64, 64), dx=(0.5, 0.5, 0.5), ppc=27,
+        q=(-1.0, 1.0), m=(1.0, 25.0), vth=(0.05, 0.01), paired=False, seed=4,
+        profile=PROF_SHOCK_TUBE, ushock=0.15, B0=(0.15 * math.cos(th), 0.15 * math.sin(th), 0.0),
+        dt=0.5, theta=0.5, steps=200, lf_E=True, lf_B=True, beta_lim=1.0, a_mode=1,
+        comoving=True, fp32=True)
+    # C5: 3D3V reconnection at HBM scale with a guide flow.
+    W["c5"] = _harris("c5_harris_3d", 3, (256, 128, 128), 100.0, 64, 0.2, 50, True)
+    return W
+
+
+def small(name: str, dim: int = 3, n=(6, 5, 4), ppc: int = 7, fp32: bool = False,
+          base: str = "c5", **kw) -> Workload:
+    """A small parity case with the same structure as a full workload."""
+    wl = workloads()[base]
+    nn = tuple(n[:dim]) + (1,) * (3 - dim)
+    dx = tuple(wl.dx[:dim]) + (1.0,) * (3 - dim) if wl.dim >= dim else (0.5,) * dim + (1.0,) * (3 - dim)
+    out = wl.replace(name=name, dim=dim, n=nn, dx=dx, ppc=ppc, fp32=fp32)
+    if out.profile == PROF_HARRIS2 and dim < 2:
+        out = out.replace(profile=PROF_UNIFORM)
+    if out.profile == PROF_HARRIS2:
+        out = out.replace(lam=max(1.0, nn[1] * dx[1] / 8.0))
+    return out.replace(**kw)
