@@ -1,0 +1,225 @@
+/*
+ * glecsim.h -- C ABI of the MI355X (gfx950) GL-ECSIM particle pass.
+ *
+ * Method: Chen, Zhou & Toth, "Suppressing spurious oscillations and particle
+ * noise in particle-in-cell simulations" (arXiv 2506.11320), built on the
+ * energy-conserving semi-implicit PIC scheme (ECSIM).  The library runs one
+ * PIC step on one GPU:
+ *
+ *   deposit   particles -> comoving current J_eff and mass matrices
+ *             (Sec. 3.1: predicted current, alpha, mass matrix M_{s,gg'},
+ *             comoving decomposition, modified E system)
+ *   solve     implicit E^{n+theta} (Sec. 2.1 eq. ECSIM-E with the mass term
+ *             of Sec. 3.1 and the limited Lax-Friedrichs diffusion of
+ *             Sec. 2.2) by restarted GMRES in FP64
+ *   update    B^{n+1} with the limited LF flux (Sec. 2.2 eqs. 1d-b-diss,
+ *             flux-b), E^{n+1} from the theta-method (Sec. 2.1)
+ *   push      implicit mover (Sec. 3.1), then the particles are re-binned
+ *             by cell with a stable integer sort
+ *
+ * Mesh: E at nodes, B at cell centres (Sec. 2.1); node (i,j,k) at
+ * (i dx, j dy, k dz), cell (i,j,k) centred at ((i+1/2) dx, ...).  Every
+ * active axis is periodic and needs at least 3 cells.  Grid arrays are
+ * component-major [ncomp][N], linear index i + nx*(j + ny*k), N = cells =
+ * nodes.  Units are the normalised Gaussian units of the paper (c, 4 pi).
+ *
+ * Conventions for every function:
+ *  - Return value: GE_OK (0), a negative error code, or a positive warning.
+ *    ge_last_error() returns the message of the last failure of a context.
+ *  - Pointers documented as "device" are GPU memory owned by the caller and
+ *    only read or written during the call (or its stream work); the library
+ *    never frees them.  The library owns its own buffers (particles,
+ *    mass matrices, Krylov basis) and frees them in ge_destroy().
+ *  - All GPU work is enqueued on the stream given to ge_create().  Calls that
+ *    return host data (ge_solve_fields, ge_diagnostics, ge_sync, ge_step)
+ *    synchronise that stream; the others are asynchronous.
+ *  - A context is not thread-safe; use one per host thread.
+ */
+#ifndef GLECSIM_H
+#define GLECSIM_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  GE_OK = 0,
+  GE_ERR_ARG = -1,        /* invalid argument or unsupported configuration */
+  GE_ERR_OOM = -2,        /* device allocation failed */
+  GE_ERR_HIP = -3,        /* a HIP runtime call failed */
+  GE_ERR_CFL = -4,        /* a particle moved one cell or more in a step
+                             (it was clamped to the neighbouring cell) */
+  GE_ERR_NONFINITE = -5,  /* NaN or Inf met in the solve */
+  GE_ERR_STATE = -6,      /* call out of order (e.g. push before a solve) */
+  GE_WARN_NOT_CONVERGED = 1 /* GMRES hit maxit; best iterate kept */
+};
+
+enum { GE_FP64 = 0, GE_FP32 = 1 };           /* particle and mass-matrix precision */
+enum { GE_A_LIGHT = 0, GE_A_BULK = 1 };      /* diffusion speed a: c, or |u| */
+enum { GE_PC_NONE = 0, GE_PC_JACOBI = 1 };   /* GMRES preconditioner */
+
+typedef struct ge_ctx ge_ctx;
+
+typedef struct {
+  int dim;        /* 1, 2 or 3 active axes (x, then y, then z) */
+  int n[3];       /* cells per axis; n[d] >= 3 for active d, 1 otherwise */
+  double dx[3];   /* spacing per active axis */
+} ge_grid;
+
+typedef struct {
+  double theta;       /* time-centring, 0.5 <= theta <= 1 (Sec. 2.1) */
+  double c;           /* speed of light */
+  double dt;          /* time step */
+  int lf_E, lf_B;     /* limited LF diffusion in the E solve / B update (Sec. 2.2) */
+  double beta_lim;    /* MC limiter beta (Sec. 2.2); 0 = unlimited first order */
+  int a_mode;         /* GE_A_LIGHT (a = a_const) or GE_A_BULK (a = |u|) */
+  double a_const;     /* diffusion speed for GE_A_LIGHT */
+  int comoving;       /* 1: comoving-frame current (Sec. 3.1), 0: lab frame */
+  int n_smooth_u;     /* filter passes for u (Sec. 3.1 uses 5) */
+  double phi_u;       /* filter weight (0.5) */
+  int precision;      /* GE_FP64 or GE_FP32 (particles, deposit, mass matrices) */
+} ge_params;
+
+typedef struct { double q, m; } ge_species;   /* charge and mass per physical particle */
+
+typedef struct {
+  int iterations;      /* matvecs spent */
+  int restarts;
+  int converged;       /* 1 if ||b - A x|| <= tol ||b|| on the true residual */
+  double relres;       /* final true relative residual */
+  double bnorm;
+  double seconds;      /* host wall time of the solve */
+} ge_solve_report;
+
+typedef struct {
+  double W_E, W_B;     /* field energies sum |E|^2 dV/8pi (nodes), sum |B|^2 dV/8pi (cells) */
+  double K[4];         /* kinetic energy per species, sum 1/2 m w |v|^2 */
+  double P[4][3];      /* momentum per species, sum m w v */
+  double gauss;        /* ||div_NC E - 4 pi rho_c|| / ||4 pi rho_c||, rho_c = cell mean of node charge */
+  int nsp;
+} ge_diag;
+
+/* ------------------------------------------------------------------ setup */
+
+/* Create a context.  grid, params: host structs, copied.  hip_stream: a
+ * hipStream_t (NULL = the null stream).  *out receives the context.
+ * Errors: GE_ERR_ARG for an invalid grid/params, GE_ERR_OOM/HIP. */
+int ge_create(const ge_grid* grid, const ge_params* params, void* hip_stream, ge_ctx** out);
+
+/* Free every library-owned buffer.  Accepts NULL. */
+void ge_destroy(ge_ctx* ctx);
+
+/* Message of the last failed call on ctx (never NULL). */
+const char* ge_last_error(const ge_ctx* ctx);
+
+/* Add a species of n macro-particles (Sec. 3.1: macro-particles with charge
+ * q_s w_p and mass m_s w_p).  All arrays are device memory, read only:
+ *   cell[n]      int32 linear cell index, non-decreasing (sorted by cell)
+ *   off[3*n]     position inside the cell in units of dx, in [0,1), layout
+ *                [3][n]; components of inactive axes are ignored
+ *   v[3*n]       velocity, layout [3][n]
+ *   w[n]         weight (physical particles per macro-particle)
+ * off, v, w are double for GE_FP64 and float for GE_FP32.  Positions are
+ * taken as x^{n+1/2} and velocities as v^n.  The data are copied into
+ * library-owned buffers.  At most 4 species; call before the first deposit.
+ * Errors: GE_ERR_ARG if unsorted, out of range or too many species. */
+int ge_add_species(ge_ctx* ctx, const ge_species* sp, int64_t n, const int32_t* cell, const void* off,
+                   const void* v, const void* w);
+
+/* Copy initial fields: E at nodes, B at cell centres; device double [3][N]. */
+int ge_set_fields(ge_ctx* ctx, const double* E_nodes, const double* B_cells);
+
+/* --------------------------------------------------------- step components */
+
+/* Particle-to-grid pass at the current positions (Sec. 3.1): node-averaged
+ * B, alpha per particle, lab current, mass matrices
+ * Mtilde = sum_s beta_s M_s and M0 = sum_s M_s (half stencil), charge
+ * and mass moments; then the smoothed bulk velocity u (n_smooth_u passes of
+ * the digital filter of Sec. 2.4), E_M = -u x B, the effective current
+ * J_eff = J_lab - (1/dV)(M0 u + Mtilde E_M) (comoving) or J_lab, the LF
+ * coefficients (Sec. 2.2, limiter lagged to E^n) and the right-hand side
+ * b = E^n + c theta dt curl B^n - 4 pi theta dt J_eff.  Asynchronous. */
+int ge_deposit(ge_ctx* ctx);
+
+/* Solve A E^{n+theta} = b (Sec. 2.1/2.2/3.1) by restarted GMRES(restart) in
+ * FP64, starting from E^n, until ||b - A x|| <= tol ||b||.  precond:
+ * GE_PC_NONE or GE_PC_JACOBI (node 3x3 block diagonal, right-preconditioned).
+ * report: host struct, may be NULL.  Synchronises.  Returns GE_OK,
+ * GE_WARN_NOT_CONVERGED, or an error (GE_ERR_STATE before ge_deposit). */
+int ge_solve_fields(ge_ctx* ctx, double tol, int maxit, int restart, int precond, ge_solve_report* report);
+
+/* Implicit mover (Sec. 3.1) with E^{n+theta} from the last solve and the
+ * node-averaged B^n of the last deposit, then the stable re-binning of every
+ * species by cell.  Asynchronous; a CFL violation is reported by the next
+ * synchronising call (GE_ERR_CFL). */
+int ge_push(ge_ctx* ctx);
+
+/* B^{n+1} = B^n - c dt curl E^{n+theta} + dt D_B(B^n) and
+ * E^{n+1} = (E^{n+theta} - (1 - theta) E^n)/theta.  Asynchronous. */
+int ge_update_fields(ge_ctx* ctx);
+
+/* One full step: deposit, solve, push, update.  Synchronises. */
+int ge_step(ge_ctx* ctx, double tol, int maxit, int restart, int precond, ge_solve_report* report);
+
+/* Wait for the stream; returns GE_ERR_CFL if a push clamped a particle since
+ * the last check, else GE_OK. */
+int ge_sync(ge_ctx* ctx);
+
+/* ------------------------------------------------------- inputs and outputs */
+
+enum {
+  GE_F_E = 0,        /* E^n at nodes            [3][N] */
+  GE_F_B = 1,        /* B^n at cells            [3][N] */
+  GE_F_ETH = 2,      /* E^{n+theta}             [3][N] */
+  GE_F_BN = 3,       /* B averaged to nodes     [3][N] */
+  GE_F_J_LAB = 4,    /* lab current             [3][N] */
+  GE_F_J_EFF = 5,    /* effective current       [3][N] */
+  GE_F_RHO = 6,      /* charge density per species [nsp][N] */
+  GE_F_MM = 7,       /* sum_s m_s sum_p w v W   [3][N] */
+  GE_F_MASS = 8,     /* sum_s m_s sum_p w W     [N] */
+  GE_F_U = 9,        /* smoothed bulk velocity  [3][N] */
+  GE_F_EM = 10,      /* motional field -u x B   [3][N] */
+  GE_F_MTILDE = 11,  /* sum_s beta_s M_s, half stencil [nh][9][N] */
+  GE_F_M0 = 12,      /* sum_s M_s, half stencil [nh][9][N] */
+  GE_F_KAPPA_E = 13, /* E diffusion coefficients [3 axes][3 comps][N] */
+  GE_F_KAPPA_B = 14, /* B diffusion coefficients [3 axes][3 comps][N] */
+  GE_F_RHS = 15      /* right-hand side b       [3][N] */
+};
+/* Half stencil: nh = 14 (3D), 5 (2D), 2 (1D) offsets o with M_{g,g+o}
+ * stored at node g: o = 0 first, then every o != 0 whose last nonzero
+ * component (z, then y, then x) is +1, enumerated z-major then y then x.
+ * M_{g+o,g} equals M_{g,g+o} (the same 3x3, not transposed), entry e = 3i+j. */
+
+/* Copy an internal field to dst (device double, the layout above).
+ * GE_F_MTILDE/M0 are widened to double for GE_FP32. */
+int ge_gather(ge_ctx* ctx, int what, double* dst);
+
+/* Overwrite an internal field from src (device double, same layout).  Only
+ * GE_F_E, GE_F_B, GE_F_ETH, GE_F_BN and GE_F_RHS may be set; it lets a caller
+ * drive one component from known inputs (e.g. a push with a given E^{n+theta}). */
+int ge_set(ge_ctx* ctx, int what, const double* src);
+
+/* Number of half-stencil offsets (14, 5 or 2). */
+int ge_half_stencil(const ge_ctx* ctx);
+
+/* Particles of species s in sorted order (by cell, stable), into device
+ * arrays: cell[n] int32, off[3][n], v[3][n], w[n] (double for GE_FP64,
+ * float for GE_FP32).  n must equal the species' count. */
+int ge_get_particles(ge_ctx* ctx, int s, int64_t n, int32_t* cell, void* off, void* v, void* w);
+
+/* y = A x for the current operator (device double [3][N]); the matvec of the
+ * solve.  Asynchronous. */
+int ge_apply_operator(ge_ctx* ctx, const double* x, double* y);
+
+/* FP64 energies, momenta and Gauss residual (host struct).  Synchronises. */
+int ge_diagnostics(ge_ctx* ctx, ge_diag* out);
+
+/* Seconds spent in each phase since the last call (device events), host
+ * array of 8: sort-and-push, deposit, grid pass, solve, update, diag, 0, 0. */
+int ge_timings(ge_ctx* ctx, double* out8);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

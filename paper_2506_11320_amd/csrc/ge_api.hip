@@ -1,0 +1,386 @@
+// C ABI of the gfx950 GL-ECSIM library: context, buffers and step sequencing.
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "ge_internal.h"
+
+int ge_fail(ge_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+namespace {
+
+template <typename P>
+int dalloc(ge_ctx* c, P** p, size_t bytes) {
+  *p = nullptr;
+  if (bytes == 0) bytes = 8;
+  hipError_t e = hipMalloc((void**)p, bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    return ge_fail(c, GE_ERR_OOM, "hipMalloc of " + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e));
+  }
+  return GE_OK;
+}
+template <typename P>
+void dfree(P*& p) {
+  if (p) (void)hipFree((void*)p);
+  p = nullptr;
+}
+
+int check_flags(ge_ctx* c) {
+  int h[4] = {0, 0, 0, 0};
+  GE_HIP(c, hipMemcpyAsync(h, c->flags, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+  GE_HIP(c, hipStreamSynchronize(c->stream));
+  if (h[0] || h[1] || h[2]) GE_HIP(c, hipMemsetAsync(c->flags, 0, sizeof(int) * 4, c->stream));
+  if (h[1]) return ge_fail(c, GE_ERR_STATE, "internal: particle run bookkeeping mismatch in the push");
+  if (h[2]) return ge_fail(c, GE_ERR_ARG, "particles not sorted by cell or cell index out of range");
+  if (h[0]) return ge_fail(c, GE_ERR_CFL, "a particle moved one cell or more in one step (clamped)");
+  return GE_OK;
+}
+
+void ev_begin(ge_ctx* c, int k) { (void)hipEventRecord(c->ev[2 * (k % 4)], c->stream); }
+
+}  // namespace
+
+extern "C" {
+
+const char* ge_last_error(const ge_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int ge_half_stencil(const ge_ctx* ctx) { return ctx ? ctx->nh : 0; }
+
+int ge_create(const ge_grid* grid, const ge_params* params, void* hip_stream, ge_ctx** out) {
+  if (!grid || !params || !out) return GE_ERR_ARG;
+  *out = nullptr;
+  ge_ctx* c = new ge_ctx();
+  std::memset((void*)&c->G, 0, sizeof(c->G));
+  c->grid = *grid;
+  c->P = *params;
+  c->stream = (hipStream_t)hip_stream;
+  const int dim = grid->dim;
+  auto bad = [&](const std::string& m) {
+    // the caller gets no context on failure; report through stderr-free code
+    delete c;
+    (void)m;
+    return GE_ERR_ARG;
+  };
+  if (dim < 1 || dim > 3) return bad("dim");
+  int64_t N = 1;
+  for (int d = 0; d < 3; ++d) {
+    if (d < dim) {
+      if (grid->n[d] < 3 || !(grid->dx[d] > 0)) return bad("n/dx");
+      N *= grid->n[d];
+    } else if (grid->n[d] != 1) {
+      return bad("inactive axes need n = 1");
+    }
+  }
+  if (N > (int64_t)1 << 31) return bad("grid too large");
+  if (!(params->theta >= 0.5 && params->theta <= 1.0) || !(params->dt > 0) || !(params->c > 0)) return bad("theta/dt/c");
+  if (params->precision != GE_FP64 && params->precision != GE_FP32) return bad("precision");
+  if (params->n_smooth_u < 0 || params->beta_lim < 0) return bad("n_smooth_u/beta_lim");
+  DGrid& G = c->G;
+  G.dim = dim;
+  G.N = N;
+  G.dV = 1.0;
+  for (int d = 0; d < 3; ++d) {
+    G.n[d] = d < dim ? grid->n[d] : 1;
+    G.dx[d] = d < dim ? grid->dx[d] : 1.0;
+    G.idx[d] = 1.0 / G.dx[d];
+    if (d < dim) G.dV *= G.dx[d];
+  }
+  c->nsp = 0;
+  c->nh = half_count(dim);
+  c->ND = dim == 3 ? 27 : (dim == 2 ? 9 : 3);
+  c->NC = 1 << dim;
+  c->NR = c->ND;
+  c->Q = 18 * c->NR + c->NC * (7 + GE_MAX_SPECIES);
+  c->kr_m = 64;
+  const size_t es = params->precision == GE_FP32 ? 4 : 8;
+  int rc = GE_OK;
+  double** f3[] = {&c->E, &c->B, &c->Eth, &c->Bn, &c->Jlab, &c->Jeff, &c->mm, &c->u, &c->utmp, &c->EM, &c->rhs, &c->Bnew,
+                   &c->ccell, &c->kw, &c->kr, &c->kx, &c->Zp};
+  for (auto p : f3)
+    if (!rc) rc = dalloc(c, p, sizeof(double) * 3 * N);
+  if (!rc) rc = dalloc(c, &c->rho, sizeof(double) * GE_MAX_SPECIES * N);
+  if (!rc) rc = dalloc(c, &c->mass, sizeof(double) * N);
+  if (!rc) rc = dalloc(c, &c->anode, sizeof(double) * N);
+  if (!rc) rc = dalloc(c, &c->kE, sizeof(double) * 9 * N);
+  if (!rc) rc = dalloc(c, &c->kB, sizeof(double) * 9 * N);
+  if (!rc) rc = dalloc(c, &c->jac, sizeof(double) * 9 * N);
+  if (!rc && params->precision == GE_FP32) {
+    rc = dalloc(c, &c->Eth32, sizeof(float) * 3 * N);
+    if (!rc) rc = dalloc(c, &c->Bn32, sizeof(float) * 3 * N);
+  }
+  if (!rc) rc = dalloc(c, &c->Mt, es * c->nh * 9 * N);
+  if (!rc) rc = dalloc(c, &c->M0, es * c->nh * 9 * N);
+  if (!rc) rc = dalloc(c, &c->cellQ, es * (size_t)c->Q * N);
+  if (!rc) rc = dalloc(c, &c->seg_next, sizeof(int32_t) * N);
+  c->scan_nblocks = (N + 1023) / 1024;
+  if (!rc) rc = dalloc(c, &c->scan_blocks, sizeof(int32_t) * (c->scan_nblocks + 1));
+  if (!rc) rc = dalloc(c, &c->V, sizeof(double) * 3 * N * (c->kr_m + 1));
+  if (!rc) rc = dalloc(c, &c->hdev, sizeof(double) * 256);
+  if (!rc) rc = dalloc(c, &c->partials, sizeof(double) * 8 * 512);
+  if (!rc) rc = dalloc(c, &c->flags, sizeof(int) * 4);
+  if (rc) {
+    ge_destroy(c);
+    return rc;
+  }
+  hipStream_t s = c->stream;
+  (void)hipMemsetAsync(c->E, 0, sizeof(double) * 3 * N, s);
+  (void)hipMemsetAsync(c->B, 0, sizeof(double) * 3 * N, s);
+  (void)hipMemsetAsync(c->kE, 0, sizeof(double) * 9 * N, s);
+  (void)hipMemsetAsync(c->kB, 0, sizeof(double) * 9 * N, s);
+  (void)hipMemsetAsync(c->rho, 0, sizeof(double) * GE_MAX_SPECIES * N, s);
+  (void)hipMemsetAsync(c->flags, 0, sizeof(int) * 4, s);
+  for (int k = 0; k < 8; ++k) {
+    (void)hipEventCreate(&c->ev[k]);
+    c->tsum[k] = 0;
+  }
+  if (hipGetLastError() != hipSuccess) {
+    ge_destroy(c);
+    return GE_ERR_HIP;
+  }
+  *out = c;
+  return GE_OK;
+}
+
+void ge_destroy(ge_ctx* c) {
+  if (!c) return;
+  if (c->stream || true) (void)hipStreamSynchronize(c->stream);
+  double** f[] = {&c->E, &c->B, &c->Eth, &c->Bn, &c->Jlab, &c->Jeff, &c->rho, &c->mm, &c->mass, &c->u, &c->utmp,
+                  &c->EM, &c->anode, &c->kE, &c->kB, &c->rhs, &c->Bnew, &c->ccell, &c->jac, &c->V, &c->Zp,
+                  &c->kw, &c->kr, &c->kx, &c->hdev, &c->partials, &c->scal};
+  for (auto p : f) dfree(*p);
+  dfree(c->Eth32);
+  dfree(c->Bn32);
+  dfree(c->Mt);
+  dfree(c->M0);
+  dfree(c->cellQ);
+  dfree(c->seg_next);
+  dfree(c->scan_blocks);
+  dfree(c->flags);
+  for (int s = 0; s < c->nsp; ++s)
+    for (int b = 0; b < 2; ++b) {
+      dfree(c->sp[s].off[b]);
+      dfree(c->sp[s].v[b]);
+      dfree(c->sp[s].w[b]);
+      dfree(c->sp[s].sub_start[b]);
+      dfree(c->sp[s].sub_cnt[b]);
+    }
+  for (int k = 0; k < 8; ++k)
+    if (c->ev[k]) (void)hipEventDestroy(c->ev[k]);
+  delete c;
+}
+
+int ge_add_species(ge_ctx* c, const ge_species* sp, int64_t n, const int32_t* cell, const void* off, const void* v,
+                   const void* w) {
+  if (!c || !sp) return GE_ERR_ARG;
+  if (c->nsp >= GE_MAX_SPECIES) return ge_fail(c, GE_ERR_ARG, "at most 4 species");
+  if (c->have_deposit) return ge_fail(c, GE_ERR_STATE, "species must be added before the first deposit");
+  if (n < 0 || n >= ((int64_t)1 << 31)) return ge_fail(c, GE_ERR_ARG, "particle count out of range (< 2^31)");
+  if (n > 0 && (!cell || !off || !v || !w)) return ge_fail(c, GE_ERR_ARG, "null particle array");
+  if (!(sp->m > 0)) return ge_fail(c, GE_ERR_ARG, "species mass must be positive");
+  const int s = c->nsp;
+  SpeciesBuf& S = c->sp[s];
+  std::memset((void*)&S, 0, sizeof(S));
+  S.q = sp->q;
+  S.m = sp->m;
+  S.beta = sp->q * c->P.dt / (2.0 * sp->m);
+  S.n = n;
+  const size_t es = c->P.precision == GE_FP32 ? 4 : 8;
+  int rc = GE_OK;
+  for (int b = 0; b < 2 && !rc; ++b) {
+    rc = dalloc(c, &S.off[b], es * 3 * n);
+    if (!rc) rc = dalloc(c, &S.v[b], es * 3 * n);
+    if (!rc) rc = dalloc(c, &S.w[b], es * n);
+    if (!rc) rc = dalloc(c, &S.sub_start[b], sizeof(int32_t) * c->ND * c->G.N);
+    if (!rc) rc = dalloc(c, &S.sub_cnt[b], sizeof(int32_t) * c->ND * c->G.N);
+  }
+  c->nsp = s + 1;  // so that ge_destroy frees partial allocations
+  if (rc) {
+    for (int b = 0; b < 2; ++b) {
+      dfree(S.off[b]); dfree(S.v[b]); dfree(S.w[b]); dfree(S.sub_start[b]); dfree(S.sub_cnt[b]);
+    }
+    c->nsp = s;
+    return rc;
+  }
+  rc = ge_launch_load_species(c, s, cell, off, v, w);
+  if (rc) return rc;
+  rc = check_flags(c);
+  if (rc) {
+    for (int b = 0; b < 2; ++b) {
+      dfree(S.off[b]); dfree(S.v[b]); dfree(S.w[b]); dfree(S.sub_start[b]); dfree(S.sub_cnt[b]);
+    }
+    c->nsp = s;
+    return rc;
+  }
+  return GE_OK;
+}
+
+int ge_set_fields(ge_ctx* c, const double* E, const double* B) {
+  if (!c || !E || !B) return GE_ERR_ARG;
+  const size_t bytes = sizeof(double) * 3 * c->G.N;
+  GE_HIP(c, hipMemcpyAsync(c->E, E, bytes, hipMemcpyDeviceToDevice, c->stream));
+  GE_HIP(c, hipMemcpyAsync(c->B, B, bytes, hipMemcpyDeviceToDevice, c->stream));
+  return GE_OK;
+}
+
+int ge_deposit(ge_ctx* c) {
+  if (!c) return GE_ERR_ARG;
+  if (c->nsp == 0) return ge_fail(c, GE_ERR_STATE, "no species");
+  int rc;
+  (void)hipEventRecord(c->ev[2], c->stream);
+  if ((rc = ge_launch_node_avg(c))) return rc;
+  if ((rc = ge_launch_deposit(c))) return rc;
+  (void)hipEventRecord(c->ev[3], c->stream);
+  c->have_deposit = 1;
+  if ((rc = ge_launch_grid_pass(c))) return rc;
+  (void)hipEventRecord(c->ev[4], c->stream);
+  c->have_solve = 0;
+  return GE_OK;
+}
+
+int ge_solve_fields(ge_ctx* c, double tol, int maxit, int restart, int precond, ge_solve_report* rep) {
+  if (!c) return GE_ERR_ARG;
+  if (!c->have_deposit) return ge_fail(c, GE_ERR_STATE, "ge_solve_fields before ge_deposit");
+  if (!(tol > 0) || maxit < 1) return ge_fail(c, GE_ERR_ARG, "tol/maxit");
+  GE_HIP(c, hipMemcpyAsync(c->Eth, c->E, sizeof(double) * 3 * c->G.N, hipMemcpyDeviceToDevice, c->stream));
+  int rc = ge_gmres(c, tol, maxit, restart, precond, rep);
+  if (rc < 0) return rc;
+  c->have_solve = 1;
+  int fr = check_flags(c);
+  return fr ? fr : rc;
+}
+
+int ge_push(ge_ctx* c) {
+  if (!c) return GE_ERR_ARG;
+  if (!c->have_solve) return ge_fail(c, GE_ERR_STATE, "ge_push needs E^{n+theta} (solve or ge_set GE_F_ETH)");
+  int rc;
+  (void)hipEventRecord(c->ev[0], c->stream);
+  if (c->P.precision == GE_FP32)
+    if ((rc = ge_launch_to_f32(c, c->Eth, c->Eth32, 3 * c->G.N))) return rc;
+  for (int s = 0; s < c->nsp; ++s)
+    if ((rc = ge_launch_push(c, s))) return rc;
+  (void)hipEventRecord(c->ev[1], c->stream);
+  return GE_OK;
+}
+
+int ge_update_fields(ge_ctx* c) {
+  if (!c) return GE_ERR_ARG;
+  if (!c->have_solve) return ge_fail(c, GE_ERR_STATE, "ge_update_fields needs a solve");
+  int rc = ge_launch_update(c);
+  if (rc) return rc;
+  c->have_solve = 0;
+  c->have_deposit = 0;
+  return GE_OK;
+}
+
+int ge_step(ge_ctx* c, double tol, int maxit, int restart, int precond, ge_solve_report* rep) {
+  int rc = ge_deposit(c);
+  if (rc) return rc;
+  int sr = ge_solve_fields(c, tol, maxit, restart, precond, rep);
+  if (sr < 0) return sr;
+  if ((rc = ge_push(c))) return rc;
+  if ((rc = ge_update_fields(c))) return rc;
+  rc = check_flags(c);
+  return rc ? rc : sr;
+}
+
+int ge_sync(ge_ctx* c) {
+  if (!c) return GE_ERR_ARG;
+  return check_flags(c);
+}
+
+int ge_gather(ge_ctx* c, int what, double* dst) {
+  if (!c || !dst) return GE_ERR_ARG;
+  const int64_t N = c->G.N;
+  const double* src = nullptr;
+  int64_t cnt = 3 * N;
+  switch (what) {
+    case GE_F_E: src = c->E; break;
+    case GE_F_B: src = c->B; break;
+    case GE_F_ETH: src = c->Eth; break;
+    case GE_F_BN: src = c->Bn; break;
+    case GE_F_J_LAB: src = c->Jlab; break;
+    case GE_F_J_EFF: src = c->Jeff; break;
+    case GE_F_RHO: src = c->rho; cnt = (int64_t)c->nsp * N; break;
+    case GE_F_MM: src = c->mm; break;
+    case GE_F_MASS: src = c->mass; cnt = N; break;
+    case GE_F_U: src = c->u; break;
+    case GE_F_EM: src = c->EM; break;
+    case GE_F_MTILDE: return ge_launch_widen_M(c, c->Mt, dst);
+    case GE_F_M0: return ge_launch_widen_M(c, c->M0, dst);
+    case GE_F_KAPPA_E: src = c->kE; cnt = 9 * N; break;
+    case GE_F_KAPPA_B: src = c->kB; cnt = 9 * N; break;
+    case GE_F_RHS: src = c->rhs; break;
+    default: return ge_fail(c, GE_ERR_ARG, "unknown field id");
+  }
+  GE_HIP(c, hipMemcpyAsync(dst, src, sizeof(double) * cnt, hipMemcpyDeviceToDevice, c->stream));
+  return GE_OK;
+}
+
+int ge_set(ge_ctx* c, int what, const double* src) {
+  if (!c || !src) return GE_ERR_ARG;
+  const int64_t N = c->G.N;
+  double* dst = nullptr;
+  switch (what) {
+    case GE_F_E: dst = c->E; break;
+    case GE_F_B: dst = c->B; break;
+    case GE_F_ETH: dst = c->Eth; break;
+    case GE_F_BN: dst = c->Bn; break;
+    case GE_F_RHS: dst = c->rhs; break;
+    default: return ge_fail(c, GE_ERR_ARG, "field id cannot be set");
+  }
+  GE_HIP(c, hipMemcpyAsync(dst, src, sizeof(double) * 3 * N, hipMemcpyDeviceToDevice, c->stream));
+  if (what == GE_F_ETH) c->have_solve = 1;
+  if (what == GE_F_BN && c->P.precision == GE_FP32) return ge_launch_to_f32(c, c->Bn, c->Bn32, 3 * N);
+  return GE_OK;
+}
+
+int ge_get_particles(ge_ctx* c, int s, int64_t n, int32_t* cell, void* off, void* v, void* w) {
+  if (!c || s < 0 || s >= c->nsp) return GE_ERR_ARG;
+  if (n != c->sp[s].n) return ge_fail(c, GE_ERR_ARG, "particle count mismatch");
+  if (!cell || !off || !v || !w) return ge_fail(c, GE_ERR_ARG, "null output");
+  return ge_launch_get_particles(c, s, cell, off, v, w);
+}
+
+int ge_apply_operator(ge_ctx* c, const double* x, double* y) {
+  if (!c || !x || !y) return GE_ERR_ARG;
+  return ge_launch_apply_A(c, x, y);
+}
+
+int ge_diagnostics(ge_ctx* c, ge_diag* out) {
+  if (!c || !out) return GE_ERR_ARG;
+  std::memset(out, 0, sizeof(*out));
+  out->nsp = c->nsp;
+  double f[4];
+  int rc = ge_launch_field_diag(c, f);
+  if (rc) return rc;
+  const double k8 = c->G.dV / (8.0 * M_PI);
+  out->W_E = f[0] * k8;
+  out->W_B = f[1] * k8;
+  out->gauss = f[3] > 0 ? std::sqrt(f[2] / f[3]) : std::sqrt(f[2]);
+  for (int s = 0; s < c->nsp; ++s) {
+    double m4[4];
+    if ((rc = ge_launch_particle_moments(c, s, m4))) return rc;
+    out->K[s] = 0.5 * c->sp[s].m * m4[0];
+    for (int d = 0; d < 3; ++d) out->P[s][d] = c->sp[s].m * m4[1 + d];
+  }
+  return check_flags(c);
+}
+
+int ge_timings(ge_ctx* c, double* out8) {
+  if (!c || !out8) return GE_ERR_ARG;
+  GE_HIP(c, hipStreamSynchronize(c->stream));
+  float ms = 0;
+  for (int k = 0; k < 8; ++k) out8[k] = 0;
+  if (hipEventElapsedTime(&ms, c->ev[0], c->ev[1]) == hipSuccess) out8[0] = ms * 1e-3;
+  if (hipEventElapsedTime(&ms, c->ev[2], c->ev[3]) == hipSuccess) out8[1] = ms * 1e-3;
+  if (hipEventElapsedTime(&ms, c->ev[3], c->ev[4]) == hipSuccess) out8[2] = ms * 1e-3;
+  (void)hipGetLastError();
+  return GE_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,589 @@
+// Grid-side kernels of the GL-ECSIM step on gfx950: node assembly of the
+// deposited sums, bulk velocity and its digital filter, motional field,
+// comoving current, limited Lax-Friedrichs coefficients, right-hand side, the
+// implicit E operator and the field updates.  Fields are FP64, [comp][N].
+#include <cmath>
+
+#include "ge_internal.h"
+
+namespace {
+
+constexpr double FOUR_PI = 12.566370614359172953850573533118;
+
+template <int DIM>
+struct Gd {
+  static constexpr int NC = 1 << DIM;
+  static constexpr int NR = DIM == 3 ? 27 : (DIM == 2 ? 9 : 3);
+};
+
+__device__ inline int ax_bit(int a, int d) { return (a >> d) & 1; }
+
+// ----------------------------------------------------------------- node average of B
+template <int DIM>
+__global__ void k_node_avg(DGrid G, const double* __restrict__ B, double* __restrict__ Bn, float* __restrict__ Bn32) {
+  int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (g >= G.N) return;
+  for (int q = 0; q < 3; ++q) {
+    double s = 0;
+    for (int a = 0; a < Gd<DIM>::NC; ++a)
+      s += B[q * G.N + nbr3(G, g, -ax_bit(a, 0), DIM >= 2 ? -ax_bit(a, 1) : 0, DIM >= 3 ? -ax_bit(a, 2) : 0)];
+    s /= Gd<DIM>::NC;
+    Bn[q * G.N + g] = s;
+    if (Bn32) Bn32[q * G.N + g] = (float)s;
+  }
+}
+
+// ----------------------------------------------------------------- assembly
+// Sum the per-cell quadratic-row sums into the node-pair half stencil and the
+// per-cell corner sums into nodes, in a fixed order (deterministic).
+template <typename T, int DIM>
+__global__ __launch_bounds__(256) void k_assemble(DGrid G, const T* __restrict__ Q, int nsp, int nh, T* __restrict__ Mt,
+                                                  T* __restrict__ M0, double* __restrict__ Jlab, double* __restrict__ mm,
+                                                  double* __restrict__ mass, double* __restrict__ rho) {
+  constexpr int NC = Gd<DIM>::NC, NR = Gd<DIM>::NR;
+  int64_t g = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  if (g >= G.N) return;
+  const int64_t N = G.N;
+  int64_t cells[8];
+  for (int a = 0; a < NC; ++a)
+    cells[a] = nbr3(G, g, -ax_bit(a, 0), DIM >= 2 ? -ax_bit(a, 1) : 0, DIM >= 3 ? -ax_bit(a, 2) : 0);
+  for (int h = 0; h < nh; ++h) {
+    int o[3];
+    half_offset(DIM, h, o);
+    int rows[8], use[8];
+    for (int a = 0; a < NC; ++a) {
+      int ok = 1, r = 0, mul = 1;
+      for (int d = 0; d < DIM; ++d) {
+        int b = ax_bit(a, d) + o[d];
+        if (b < 0 || b > 1) ok = 0;
+        r += (2 * ax_bit(a, d) + o[d]) * mul;
+        mul *= 3;
+      }
+      use[a] = ok;
+      rows[a] = r;
+    }
+    for (int e = 0; e < 9; ++e) {
+      double smt = 0, sm0 = 0;
+      for (int a = 0; a < NC; ++a) {
+        if (!use[a]) continue;
+        smt += (double)Q[(int64_t)(rows[a] * 9 + e) * N + cells[a]];
+        sm0 += (double)Q[(int64_t)(9 * NR + rows[a] * 9 + e) * N + cells[a]];
+      }
+      Mt[(int64_t)(h * 9 + e) * N + g] = (T)smt;
+      M0[(int64_t)(h * 9 + e) * N + g] = (T)sm0;
+    }
+  }
+  const double idV = 1.0 / G.dV;
+  const int NK = 7 + nsp;
+  for (int k = 0; k < NK; ++k) {
+    double s = 0;
+    for (int a = 0; a < NC; ++a) s += (double)Q[(int64_t)(18 * NR + k * NC + a) * N + cells[a]];
+    if (k < 3) Jlab[k * N + g] = s * idV;
+    else if (k < 6) mm[(k - 3) * N + g] = s;
+    else if (k == 6) mass[g] = s;
+    else rho[(k - 7) * N + g] = s * idV;
+  }
+}
+
+// ----------------------------------------------------------------- bulk velocity, filter, E_M
+__global__ void k_bulk_u(int64_t N, const double* __restrict__ mm, const double* __restrict__ mass, double* __restrict__ u) {
+  int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (g >= N) return;
+  double m = mass[g];
+  for (int q = 0; q < 3; ++q) u[q * N + g] = m > 0 ? mm[q * N + g] / m : 0.0;
+}
+
+// One pass of the digital filter (Sec. 2.4) along 'axis' with stride d:
+// v* = phi v + (1 - phi)/2 (v_{-d} + v_{+d}).
+__global__ void k_filter(DGrid G, const double* __restrict__ src, double* __restrict__ dst, int axis, int d, double phi) {
+  int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (g >= G.N) return;
+  int o[3] = {0, 0, 0};
+  o[axis] = d;
+  int64_t gp = nbr3(G, g, o[0], o[1], o[2]);
+  int64_t gm = nbr3(G, g, -o[0], -o[1], -o[2]);
+  const double half = 0.5 * (1.0 - phi);
+  for (int q = 0; q < 3; ++q) dst[q * G.N + g] = phi * src[q * G.N + g] + half * (src[q * G.N + gm] + src[q * G.N + gp]);
+}
+
+// E_M = -u x B (Sec. 3.1) and the diffusion speed at nodes (Sec. 2.2).
+__global__ void k_motional(int64_t N, const double* __restrict__ u, const double* __restrict__ Bn, double* __restrict__ EM,
+                           double* __restrict__ anode, int a_mode, double a_const) {
+  int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (g >= N) return;
+  double ux = u[g], uy = u[N + g], uz = u[2 * N + g];
+  double bx = Bn[g], by = Bn[N + g], bz = Bn[2 * N + g];
+  EM[g] = -(uy * bz - uz * by);
+  EM[N + g] = -(uz * bx - ux * bz);
+  EM[2 * N + g] = -(ux * by - uy * bx);
+  anode[g] = a_mode == GE_A_LIGHT ? a_const : sqrt(ux * ux + uy * uy + uz * uz);
+}
+
+// y_g = sum over the 3^DIM neighbours g' of M_{g,g'} x_{g'}, half stencil.
+template <typename T, int DIM>
+__device__ inline void apply_half(const DGrid& G, const T* __restrict__ M, const double* __restrict__ x, int64_t g,
+                                  int nh, double y[3]) {
+  const int64_t N = G.N;
+  y[0] = y[1] = y[2] = 0;
+  int gx, gy, gz;
+  unflat3(G, g, gx, gy, gz);
+  for (int h = 0; h < nh; ++h) {
+    int o[3];
+    half_offset(DIM, h, o);
+    const int64_t gp = flat3(G, gx + o[0], gy + o[1], gz + o[2]);
+    double xp[3] = {x[gp], x[N + gp], x[2 * N + gp]};
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) y[i] += (double)M[(int64_t)(h * 9 + 3 * i + j) * N + g] * xp[j];
+    if (h == 0) continue;
+    const int64_t gm = flat3(G, gx - o[0], gy - o[1], gz - o[2]);
+    double xm[3] = {x[gm], x[N + gm], x[2 * N + gm]};
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) y[i] += (double)M[(int64_t)(h * 9 + 3 * i + j) * N + gm] * xm[j];
+  }
+}
+
+// J_eff = J_lab - (1/dV)(M0 u + Mtilde E_M)  (Sec. 3.1, comoving frame)
+template <typename T, int DIM>
+__global__ __launch_bounds__(256) void k_comoving(DGrid G, int nh, const T* __restrict__ Mt, const T* __restrict__ M0,
+                                                  const double* __restrict__ u, const double* __restrict__ EM,
+                                                  const double* __restrict__ Jlab, double* __restrict__ Jeff) {
+  int64_t g = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  if (g >= G.N) return;
+  double a[3], b[3];
+  apply_half<T, DIM>(G, M0, u, g, nh, a);
+  apply_half<T, DIM>(G, Mt, EM, g, nh, b);
+  const double idV = 1.0 / G.dV;
+  for (int q = 0; q < 3; ++q) Jeff[q * G.N + g] = Jlab[q * G.N + g] - idV * (a[q] + b[q]);
+}
+
+// ----------------------------------------------------------------- limited LF coefficients
+// Generalised MC limiter (Sec. 2.2) of r = num/den: max(0, min(beta r,
+// (1+r)/2, beta)); den = 0 reads r = 1 (num = 0), +inf (num > 0) or -inf.
+__device__ inline double mc_limiter(double num, double den, double beta) {
+  double r;
+  if (den == 0.0) {
+    if (num == 0.0) r = 1.0;
+    else return num > 0.0 ? beta : 0.0;
+  } else {
+    r = num / den;
+  }
+  double m = fmin(fmin(beta * r, 0.5 * (1.0 + r)), beta);
+  return m > 0.0 ? m : 0.0;
+}
+
+// E: flux between node g and g + e_d (stored at g); ratio lagged to E^n.
+template <int DIM>
+__global__ void k_kappa_E(DGrid G, const double* __restrict__ E, const double* __restrict__ anode, double beta,
+                          double* __restrict__ kE) {
+  int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (g >= G.N) return;
+  const int64_t N = G.N;
+  for (int d = 0; d < 3; ++d) {
+    if (d >= DIM) {
+      for (int m = 0; m < 3; ++m) kE[(d * 3 + m) * N + g] = 0.0;
+      continue;
+    }
+    int o[3] = {0, 0, 0};
+    o[d] = 1;
+    int64_t gp = nbr3(G, g, o[0], o[1], o[2]), gm = nbr3(G, g, -o[0], -o[1], -o[2]);
+    double a = 0.5 * (anode[g] + anode[gp]);
+    for (int m = 0; m < 3; ++m) {
+      double phi = mc_limiter(E[m * N + g] - E[m * N + gm], E[m * N + gp] - E[m * N + g], beta);
+      kE[(d * 3 + m) * N + g] = 0.5 * (1.0 - phi) * a;
+    }
+  }
+}
+
+// B: face between cell c and c + e_d (stored at c); a = mean over the face's nodes.
+template <int DIM>
+__global__ void k_kappa_B(DGrid G, const double* __restrict__ B, const double* __restrict__ anode, double beta,
+                          double* __restrict__ kB) {
+  int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (c >= G.N) return;
+  const int64_t N = G.N;
+  for (int d = 0; d < 3; ++d) {
+    if (d >= DIM) {
+      for (int m = 0; m < 3; ++m) kB[(d * 3 + m) * N + c] = 0.0;
+      continue;
+    }
+    double asum = 0;
+    int nf = 0;
+    for (int t = 0; t < (1 << DIM); ++t) {
+      if (ax_bit(t, d)) continue;
+      int o[3] = {0, 0, 0};
+      for (int e = 0; e < DIM; ++e) o[e] = ax_bit(t, e);
+      o[d] = 1;
+      asum += anode[nbr3(G, c, o[0], o[1], o[2])];
+      ++nf;
+    }
+    double a = asum / nf;
+    int o[3] = {0, 0, 0};
+    o[d] = 1;
+    int64_t cp = nbr3(G, c, o[0], o[1], o[2]), cm = nbr3(G, c, -o[0], -o[1], -o[2]);
+    for (int m = 0; m < 3; ++m) {
+      double phi = mc_limiter(B[m * N + c] - B[m * N + cm], B[m * N + cp] - B[m * N + c], beta);
+      kB[(d * 3 + m) * N + c] = 0.5 * (1.0 - phi) * a;
+    }
+  }
+}
+
+// ----------------------------------------------------------------- curls
+// Node -> cell derivative along d: difference of the means over the cell's
+// upper and lower faces.  Cell -> node: difference of the means over the
+// cells on the node's upper and lower side.
+template <int DIM>
+__global__ void k_curl_nc(DGrid G, const double* __restrict__ E, double* __restrict__ C) {
+  int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (c >= G.N) return;
+  const int64_t N = G.N;
+  constexpr int NC = Gd<DIM>::NC;
+  double up[3][3] = {{0}}, lo[3][3] = {{0}};  // [axis][comp]
+  for (int a = 0; a < NC; ++a) {
+    int64_t g = nbr3(G, c, ax_bit(a, 0), DIM >= 2 ? ax_bit(a, 1) : 0, DIM >= 3 ? ax_bit(a, 2) : 0);
+    double e0 = E[g], e1 = E[N + g], e2 = E[2 * N + g];
+    for (int d = 0; d < DIM; ++d) {
+      if (ax_bit(a, d)) { up[d][0] += e0; up[d][1] += e1; up[d][2] += e2; }
+      else { lo[d][0] += e0; lo[d][1] += e1; lo[d][2] += e2; }
+    }
+  }
+  double D[3][3] = {{0}};  // D[d][comp] = d comp / d x_d
+  const double inv = 2.0 / NC;
+  for (int d = 0; d < DIM; ++d)
+    for (int q = 0; q < 3; ++q) D[d][q] = (up[d][q] - lo[d][q]) * inv * G.idx[d];
+  C[c] = D[1][2] - D[2][1];
+  C[N + c] = D[2][0] - D[0][2];
+  C[2 * N + c] = D[0][1] - D[1][0];
+}
+
+template <int DIM>
+__device__ inline void curl_cn_at(const DGrid& G, const double* __restrict__ B, int64_t g, double out[3]) {
+  const int64_t N = G.N;
+  constexpr int NC = Gd<DIM>::NC;
+  double up[3][3] = {{0}}, lo[3][3] = {{0}};
+  for (int a = 0; a < NC; ++a) {
+    int64_t cc = nbr3(G, g, -ax_bit(a, 0), DIM >= 2 ? -ax_bit(a, 1) : 0, DIM >= 3 ? -ax_bit(a, 2) : 0);
+    double b0 = B[cc], b1 = B[N + cc], b2 = B[2 * N + cc];
+    for (int d = 0; d < DIM; ++d) {
+      if (ax_bit(a, d)) { lo[d][0] += b0; lo[d][1] += b1; lo[d][2] += b2; }
+      else { up[d][0] += b0; up[d][1] += b1; up[d][2] += b2; }
+    }
+  }
+  double D[3][3] = {{0}};
+  const double inv = 2.0 / NC;
+  for (int d = 0; d < DIM; ++d)
+    for (int q = 0; q < 3; ++q) D[d][q] = (up[d][q] - lo[d][q]) * inv * G.idx[d];
+  out[0] = D[1][2] - D[2][1];
+  out[1] = D[2][0] - D[0][2];
+  out[2] = D[0][1] - D[1][0];
+}
+
+// Diffusion term (D F)_g for component m: sum_d [k_g (F_{g+e}-F_g) - k_{g-e} (F_g - F_{g-e})] / dx_d
+template <int DIM>
+__device__ inline double diffusion_at(const DGrid& G, const double* __restrict__ kap, const double* __restrict__ F,
+                                      int64_t g, int m) {
+  const int64_t N = G.N;
+  double s = 0;
+  for (int d = 0; d < DIM; ++d) {
+    int o[3] = {0, 0, 0};
+    o[d] = 1;
+    int64_t gp = nbr3(G, g, o[0], o[1], o[2]), gm = nbr3(G, g, -o[0], -o[1], -o[2]);
+    double f0 = F[m * N + g];
+    s += (kap[(d * 3 + m) * N + g] * (F[m * N + gp] - f0) - kap[(d * 3 + m) * N + gm] * (f0 - F[m * N + gm])) * G.idx[d];
+  }
+  return s;
+}
+
+// b = E^n + c theta dt curl_CN B^n - 4 pi theta dt J_eff
+template <int DIM>
+__global__ void k_rhs(DGrid G, const double* __restrict__ E, const double* __restrict__ B, const double* __restrict__ J,
+                      double ctd, double ftd, double* __restrict__ b) {
+  int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (g >= G.N) return;
+  double cb[3];
+  curl_cn_at<DIM>(G, B, g, cb);
+  for (int q = 0; q < 3; ++q) b[q * G.N + g] = E[q * G.N + g] + ctd * cb[q] - ftd * J[q * G.N + g];
+}
+
+// A x = x + (c theta dt)^2 curl_CN C + (4 pi theta dt / dV) Mtilde x - theta dt D_E x, C = curl_NC x
+template <typename T, int DIM>
+__global__ __launch_bounds__(256) void k_apply_A(DGrid G, int nh, const double* __restrict__ x, const double* __restrict__ C,
+                                                 const T* __restrict__ Mt, const double* __restrict__ kE, double k2,
+                                                 double mcoef, double tdt, double* __restrict__ y) {
+  int64_t g = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  if (g >= G.N) return;
+  double cc[3];
+  curl_cn_at<DIM>(G, C, g, cc);
+  double mx[3] = {0, 0, 0};
+  if (Mt) apply_half<T, DIM>(G, Mt, x, g, nh, mx);
+  for (int q = 0; q < 3; ++q) {
+    double v = x[q * G.N + g] + k2 * cc[q] + mcoef * mx[q];
+    if (kE) v -= tdt * diffusion_at<DIM>(G, kE, x, g, q);
+    y[q * G.N + g] = v;
+  }
+}
+
+// B^{n+1} = B^n - c dt curl_NC E^{n+theta} + dt D_B B^n  (C holds curl_NC E^{n+theta})
+template <int DIM>
+__global__ void k_update_B(DGrid G, const double* __restrict__ B, const double* __restrict__ C,
+                           const double* __restrict__ kB, double cdt, double dt, double* __restrict__ Bnew) {
+  int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (c >= G.N) return;
+  for (int q = 0; q < 3; ++q) {
+    double v = B[q * G.N + c] - cdt * C[q * G.N + c];
+    if (kB) v += dt * diffusion_at<DIM>(G, kB, B, c, q);
+    Bnew[q * G.N + c] = v;
+  }
+}
+
+__global__ void k_update_E(int64_t n3, double theta, const double* __restrict__ Eth, double* __restrict__ E) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n3) return;
+  E[i] = (Eth[i] - (1.0 - theta) * E[i]) / theta;
+}
+
+// ----------------------------------------------------------------- Jacobi (node 3x3 diagonal block)
+template <typename T, int DIM>
+__global__ void k_jacobi_setup(DGrid G, const T* __restrict__ Mt, const double* __restrict__ kE, double k2, double mcoef,
+                               double tdt, double* __restrict__ jac) {
+  int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (g >= G.N) return;
+  const int64_t N = G.N;
+  double A[9];
+  for (int e = 0; e < 9; ++e) A[e] = Mt ? mcoef * (double)Mt[(int64_t)e * N + g] : 0.0;
+  const double avg = 1.0 / (double)(1 << (DIM - 1));
+  for (int m = 0; m < 3; ++m) {
+    double cc = 0;
+    for (int d = 0; d < DIM; ++d)
+      if (d != m) cc += 2.0 * G.idx[d] * G.idx[d] * avg;
+    double dd = 0;
+    if (kE)
+      for (int d = 0; d < DIM; ++d) {
+        int o[3] = {0, 0, 0};
+        o[d] = 1;
+        int64_t gm = nbr3(G, g, -o[0], -o[1], -o[2]);
+        dd += (kE[(d * 3 + m) * N + g] + kE[(d * 3 + m) * N + gm]) * G.idx[d];
+      }
+    A[4 * m] += 1.0 + k2 * cc + tdt * dd;
+  }
+  double det = A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6]) + A[2] * (A[3] * A[7] - A[4] * A[6]);
+  double id = det != 0.0 ? 1.0 / det : 0.0;
+  double I[9];
+  I[0] = (A[4] * A[8] - A[5] * A[7]) * id;
+  I[1] = (A[2] * A[7] - A[1] * A[8]) * id;
+  I[2] = (A[1] * A[5] - A[2] * A[4]) * id;
+  I[3] = (A[5] * A[6] - A[3] * A[8]) * id;
+  I[4] = (A[0] * A[8] - A[2] * A[6]) * id;
+  I[5] = (A[2] * A[3] - A[0] * A[5]) * id;
+  I[6] = (A[3] * A[7] - A[4] * A[6]) * id;
+  I[7] = (A[1] * A[6] - A[0] * A[7]) * id;
+  I[8] = (A[0] * A[4] - A[1] * A[3]) * id;
+  for (int e = 0; e < 9; ++e) jac[(int64_t)e * N + g] = I[e];
+}
+
+__global__ void k_jacobi_apply(int64_t N, const double* __restrict__ jac, const double* __restrict__ x, double* __restrict__ y) {
+  int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (g >= N) return;
+  double a = x[g], b = x[N + g], c = x[2 * N + g];
+  for (int i = 0; i < 3; ++i)
+    y[i * N + g] = jac[(3 * i) * N + g] * a + jac[(3 * i + 1) * N + g] * b + jac[(3 * i + 2) * N + g] * c;
+}
+
+// ----------------------------------------------------------------- conversions and diagnostics
+template <typename S, typename D>
+__global__ void k_convert(const S* __restrict__ src, D* __restrict__ dst, int64_t n) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = (D)src[i];
+}
+
+// block partials of |E|^2 (nodes), |B|^2 (cells), |div E - 4 pi rho_c|^2 and |4 pi rho_c|^2
+template <int DIM>
+__global__ __launch_bounds__(256) void k_field_diag(DGrid G, const double* __restrict__ E, const double* __restrict__ B,
+                                                    const double* __restrict__ rho, int nsp, double* __restrict__ part) {
+  __shared__ double sh[4][256];
+  constexpr int NC = Gd<DIM>::NC;
+  const int64_t N = G.N;
+  double a[4] = {0, 0, 0, 0};
+  for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < N; c += (int64_t)gridDim.x * blockDim.x) {
+    for (int q = 0; q < 3; ++q) {
+      a[0] += E[q * N + c] * E[q * N + c];
+      a[1] += B[q * N + c] * B[q * N + c];
+    }
+    double up[3] = {0, 0, 0}, lo[3] = {0, 0, 0}, rc = 0;
+    for (int k = 0; k < NC; ++k) {
+      int64_t g = nbr3(G, c, ax_bit(k, 0), DIM >= 2 ? ax_bit(k, 1) : 0, DIM >= 3 ? ax_bit(k, 2) : 0);
+      for (int d = 0; d < DIM; ++d) {
+        if (ax_bit(k, d)) up[d] += E[d * N + g];
+        else lo[d] += E[d * N + g];
+      }
+      for (int s = 0; s < nsp; ++s) rc += rho[s * N + g];
+    }
+    double div = 0;
+    for (int d = 0; d < DIM; ++d) div += (up[d] - lo[d]) * (2.0 / NC) * G.idx[d];
+    double r4 = FOUR_PI * rc / NC;
+    a[2] += (div - r4) * (div - r4);
+    a[3] += r4 * r4;
+  }
+  for (int k = 0; k < 4; ++k) sh[k][threadIdx.x] = a[k];
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s)
+      for (int k = 0; k < 4; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x < 4) part[threadIdx.x * gridDim.x + blockIdx.x] = sh[threadIdx.x][0];
+}
+
+inline dim3 grid1(int64_t n) { return dim3((unsigned)((n + 255) / 256)); }
+
+}  // namespace
+
+// ===================================================================== host
+#define DISPATCH_DIM(c, KERNEL, ...)                                                                     \
+  switch ((c)->G.dim) {                                                                                  \
+    case 1: hipLaunchKernelGGL(KERNEL<1>, __VA_ARGS__); break;                                           \
+    case 2: hipLaunchKernelGGL(KERNEL<2>, __VA_ARGS__); break;                                           \
+    default: hipLaunchKernelGGL(KERNEL<3>, __VA_ARGS__); break;                                          \
+  }
+
+int ge_launch_node_avg(ge_ctx* c) {
+  float* b32 = c->P.precision == GE_FP32 ? c->Bn32 : nullptr;
+  DISPATCH_DIM(c, k_node_avg, grid1(c->G.N), dim3(256), 0, c->stream, c->G, c->B, c->Bn, b32);
+  GE_HIP(c, hipGetLastError());
+  return GE_OK;
+}
+
+template <typename T, int DIM>
+static void assemble_t(ge_ctx* c) {
+  hipLaunchKernelGGL((k_assemble<T, DIM>), grid1(c->G.N), dim3(256), 0, c->stream, c->G, (const T*)c->cellQ, c->nsp,
+                     c->nh, (T*)c->Mt, (T*)c->M0, c->Jlab, c->mm, c->mass, c->rho);
+}
+template <typename T, int DIM>
+static void comoving_t(ge_ctx* c) {
+  hipLaunchKernelGGL((k_comoving<T, DIM>), grid1(c->G.N), dim3(256), 0, c->stream, c->G, c->nh, (const T*)c->Mt,
+                     (const T*)c->M0, c->u, c->EM, c->Jlab, c->Jeff);
+}
+#define DISPATCH_TD(c, FN)                                          \
+  switch ((c)->G.dim * 2 + ((c)->P.precision == GE_FP32 ? 1 : 0)) { \
+    case 2: FN<double, 1>(c); break;                                \
+    case 3: FN<float, 1>(c); break;                                 \
+    case 4: FN<double, 2>(c); break;                                \
+    case 5: FN<float, 2>(c); break;                                 \
+    case 6: FN<double, 3>(c); break;                                \
+    default: FN<float, 3>(c); break;                                \
+  }
+
+// Everything between the particle deposit and the linear solve.
+int ge_launch_grid_pass(ge_ctx* c) {
+  const DGrid& G = c->G;
+  const int64_t N = G.N;
+  DISPATCH_TD(c, assemble_t);
+  GE_HIP(c, hipGetLastError());
+  hipLaunchKernelGGL(k_bulk_u, grid1(N), dim3(256), 0, c->stream, N, c->mm, c->mass, c->u);
+  // filter passes: strides 1, 2, 1, 2, ...; each pass sweeps x, then y, then z
+  for (int k = 0; k < c->P.n_smooth_u; ++k)
+    for (int ax = 0; ax < G.dim; ++ax) {
+      hipLaunchKernelGGL(k_filter, grid1(N), dim3(256), 0, c->stream, G, c->u, c->utmp, ax, (k % 2 == 0) ? 1 : 2,
+                         c->P.phi_u);
+      std::swap(c->u, c->utmp);
+    }
+  hipLaunchKernelGGL(k_motional, grid1(N), dim3(256), 0, c->stream, N, c->u, c->Bn, c->EM, c->anode, c->P.a_mode,
+                     c->P.a_const);
+  if (c->P.comoving) {
+    DISPATCH_TD(c, comoving_t);
+  } else {
+    GE_HIP(c, hipMemcpyAsync(c->Jeff, c->Jlab, sizeof(double) * 3 * N, hipMemcpyDeviceToDevice, c->stream));
+  }
+  if (c->P.lf_E) DISPATCH_DIM(c, k_kappa_E, grid1(N), dim3(256), 0, c->stream, G, c->E, c->anode, c->P.beta_lim, c->kE);
+  if (c->P.lf_B) DISPATCH_DIM(c, k_kappa_B, grid1(N), dim3(256), 0, c->stream, G, c->B, c->anode, c->P.beta_lim, c->kB);
+  const double ctd = c->P.c * c->P.theta * c->P.dt, ftd = 4.0 * M_PI * c->P.theta * c->P.dt;
+  DISPATCH_DIM(c, k_rhs, grid1(N), dim3(256), 0, c->stream, G, c->E, c->B, c->Jeff, ctd, ftd, c->rhs);
+  GE_HIP(c, hipGetLastError());
+  return GE_OK;
+}
+
+template <typename T, int DIM>
+static void apply_t(ge_ctx* c, const double* x, double* y) {
+  const double ctd = c->P.c * c->P.theta * c->P.dt;
+  const double mcoef = 4.0 * M_PI * c->P.theta * c->P.dt / c->G.dV;
+  hipLaunchKernelGGL(k_curl_nc<DIM>, grid1(c->G.N), dim3(256), 0, c->stream, c->G, x, c->ccell);
+  hipLaunchKernelGGL((k_apply_A<T, DIM>), grid1(c->G.N), dim3(256), 0, c->stream, c->G, c->nh, x, c->ccell,
+                     c->have_deposit ? (const T*)c->Mt : nullptr, c->P.lf_E ? c->kE : nullptr, ctd * ctd, mcoef,
+                     c->P.theta * c->P.dt, y);
+}
+int ge_launch_apply_A(ge_ctx* c, const double* x, double* y) {
+  switch (c->G.dim * 2 + (c->P.precision == GE_FP32 ? 1 : 0)) {
+    case 2: apply_t<double, 1>(c, x, y); break;
+    case 3: apply_t<float, 1>(c, x, y); break;
+    case 4: apply_t<double, 2>(c, x, y); break;
+    case 5: apply_t<float, 2>(c, x, y); break;
+    case 6: apply_t<double, 3>(c, x, y); break;
+    default: apply_t<float, 3>(c, x, y); break;
+  }
+  GE_HIP(c, hipGetLastError());
+  return GE_OK;
+}
+
+int ge_launch_update(ge_ctx* c) {
+  const int64_t N = c->G.N;
+  DISPATCH_DIM(c, k_curl_nc, grid1(N), dim3(256), 0, c->stream, c->G, c->Eth, c->ccell);
+  DISPATCH_DIM(c, k_update_B, grid1(N), dim3(256), 0, c->stream, c->G, c->B, c->ccell, c->P.lf_B ? c->kB : nullptr,
+               c->P.c * c->P.dt, c->P.dt, c->Bnew);
+  std::swap(c->B, c->Bnew);
+  hipLaunchKernelGGL(k_update_E, grid1(3 * N), dim3(256), 0, c->stream, 3 * N, c->P.theta, c->Eth, c->E);
+  GE_HIP(c, hipGetLastError());
+  return GE_OK;
+}
+
+int ge_launch_widen_M(ge_ctx* c, const void* M, double* dst) {
+  const int64_t n = (int64_t)c->nh * 9 * c->G.N;
+  if (c->P.precision == GE_FP32)
+    hipLaunchKernelGGL((k_convert<float, double>), grid1(n), dim3(256), 0, c->stream, (const float*)M, dst, n);
+  else
+    GE_HIP(c, hipMemcpyAsync(dst, M, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
+  GE_HIP(c, hipGetLastError());
+  return GE_OK;
+}
+
+int ge_launch_to_f32(ge_ctx* c, const double* src, float* dst, int64_t n) {
+  hipLaunchKernelGGL((k_convert<double, float>), grid1(n), dim3(256), 0, c->stream, src, dst, n);
+  GE_HIP(c, hipGetLastError());
+  return GE_OK;
+}
+
+template <typename T, int DIM>
+static void jac_t(ge_ctx* c) {
+  const double ctd = c->P.c * c->P.theta * c->P.dt;
+  const double mcoef = 4.0 * M_PI * c->P.theta * c->P.dt / c->G.dV;
+  hipLaunchKernelGGL((k_jacobi_setup<T, DIM>), grid1(c->G.N), dim3(256), 0, c->stream, c->G,
+                     c->have_deposit ? (const T*)c->Mt : nullptr, c->P.lf_E ? c->kE : nullptr, ctd * ctd, mcoef,
+                     c->P.theta * c->P.dt, c->jac);
+}
+int ge_launch_jacobi_setup(ge_ctx* c) {
+  DISPATCH_TD(c, jac_t);
+  GE_HIP(c, hipGetLastError());
+  return GE_OK;
+}
+int ge_launch_jacobi_apply(ge_ctx* c, const double* x, double* y) {
+  hipLaunchKernelGGL(k_jacobi_apply, grid1(c->G.N), dim3(256), 0, c->stream, c->G.N, c->jac, x, y);
+  GE_HIP(c, hipGetLastError());
+  return GE_OK;
+}
+
+int ge_launch_field_diag(ge_ctx* c, double* out) {
+  const int nbk = 256;
+  DISPATCH_DIM(c, k_field_diag, dim3(nbk), dim3(256), 0, c->stream, c->G, c->E, c->B, c->rho, c->nsp, c->partials);
+  GE_HIP(c, hipGetLastError());
+  double h[4 * 256];
+  GE_HIP(c, hipMemcpyAsync(h, c->partials, sizeof(double) * 4 * nbk, hipMemcpyDeviceToHost, c->stream));
+  GE_HIP(c, hipStreamSynchronize(c->stream));
+  for (int k = 0; k < 4; ++k) {
+    double a = 0;
+    for (int b = 0; b < nbk; ++b) a += h[k * nbk + b];
+    out[k] = a;
+  }
+  return GE_OK;
+}

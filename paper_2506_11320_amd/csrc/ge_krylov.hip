@@ -1,0 +1,227 @@
+// Restarted GMRES in FP64 for the implicit E system.  The Arnoldi basis is
+// orthogonalised by classical Gram-Schmidt applied twice (CGS2): each pass is
+// one fused multi-dot (block partial sums, reduced in a fixed order, so every
+// run gives the same bits) and one fused multi-axpy.  The Hessenberg column
+// travels to the host once per iteration for the Givens update.
+#include <chrono>
+#include <cmath>
+#include <vector>
+
+#include "ge_internal.h"
+
+namespace {
+
+constexpr int KB = 256;       // threads per block
+constexpr int KRED = 512;     // blocks of a multi-dot
+constexpr int HSTRIDE = 64;   // layout of the small device buffer hdev
+
+// part[i * KRED + b] = block b's share of V_i . w, i < NV
+template <int NV>
+__global__ __launch_bounds__(KB) void k_multidot(const double* __restrict__ V, int64_t ld, const double* __restrict__ w,
+                                                 int64_t n, double* __restrict__ part) {
+  __shared__ double sh[NV][KB];
+  double a[NV];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) a[i] = 0;
+  for (int64_t k = blockIdx.x * (int64_t)KB + threadIdx.x; k < n; k += (int64_t)gridDim.x * KB) {
+    const double wk = w[k];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) a[i] += V[i * ld + k] * wk;
+  }
+#pragma unroll
+  for (int i = 0; i < NV; ++i) sh[i][threadIdx.x] = a[i];
+  __syncthreads();
+  for (int s = KB / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s)
+#pragma unroll
+      for (int i = 0; i < NV; ++i) sh[i][threadIdx.x] += sh[i][threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x < NV) part[threadIdx.x * KRED + blockIdx.x] = sh[threadIdx.x][0];
+}
+
+// out[i] = sum_b part[i * KRED + b] in a fixed tree order (one block per i)
+__global__ __launch_bounds__(KB) void k_reduce(const double* __restrict__ part, double* __restrict__ out) {
+  __shared__ double sh[KB];
+  const int i = blockIdx.x;
+  double a = 0;
+  for (int b = threadIdx.x; b < KRED; b += KB) a += part[i * KRED + b];
+  sh[threadIdx.x] = a;
+  __syncthreads();
+  for (int s = KB / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[i] = sh[0];
+}
+
+// w[k] += sign * sum_{i<nv} h[i] V_i[k]
+__global__ __launch_bounds__(KB) void k_multiaxpy(double* __restrict__ w, const double* __restrict__ V, int64_t ld, int nv,
+                                                  const double* __restrict__ h, double sign, int64_t n) {
+  __shared__ double hs[HSTRIDE];
+  if (threadIdx.x < nv) hs[threadIdx.x] = h[threadIdx.x];
+  __syncthreads();
+  for (int64_t k = blockIdx.x * (int64_t)KB + threadIdx.x; k < n; k += (int64_t)gridDim.x * KB) {
+    double s = 0;
+    for (int i = 0; i < nv; ++i) s += hs[i] * V[i * ld + k];
+    w[k] += sign * s;
+  }
+}
+
+// v = w / sqrt(*nrm2)
+__global__ void k_normalize(double* __restrict__ v, const double* __restrict__ w, const double* __restrict__ nrm2, int64_t n) {
+  const double inv = 1.0 / sqrt(*nrm2);
+  for (int64_t k = blockIdx.x * (int64_t)KB + threadIdx.x; k < n; k += (int64_t)gridDim.x * KB) v[k] = w[k] * inv;
+}
+// r = b - r
+__global__ void k_residual(double* __restrict__ r, const double* __restrict__ b, int64_t n) {
+  for (int64_t k = blockIdx.x * (int64_t)KB + threadIdx.x; k < n; k += (int64_t)gridDim.x * KB) r[k] = b[k] - r[k];
+}
+__global__ void k_add(double* __restrict__ x, const double* __restrict__ z, int64_t n) {
+  for (int64_t k = blockIdx.x * (int64_t)KB + threadIdx.x; k < n; k += (int64_t)gridDim.x * KB) x[k] += z[k];
+}
+__global__ void k_sum2(double* __restrict__ a, const double* __restrict__ b, int nv) {
+  int i = threadIdx.x;
+  if (i < nv) a[i] += b[i];
+}
+
+inline dim3 vgrid(int64_t n) {
+  int64_t b = (n + KB - 1) / KB;
+  return dim3((unsigned)(b < 8192 ? b : 8192));
+}
+
+}  // namespace
+
+// dots[i] = V_i . w for i < nv (device output)
+static int multidot(ge_ctx* c, const double* V, int64_t ld, int nv, const double* w, int64_t n, double* dots) {
+  for (int i0 = 0; i0 < nv; i0 += 8) {
+    const int k = nv - i0 < 8 ? nv - i0 : 8;
+    const double* Vi = V + (int64_t)i0 * ld;
+    double* part = c->partials;
+    switch (k) {
+#define MD(K) case K: hipLaunchKernelGGL(k_multidot<K>, dim3(KRED), dim3(KB), 0, c->stream, Vi, ld, w, n, part); break;
+      MD(1) MD(2) MD(3) MD(4) MD(5) MD(6) MD(7) MD(8)
+#undef MD
+    }
+    hipLaunchKernelGGL(k_reduce, dim3(k), dim3(KB), 0, c->stream, part, dots + i0);
+  }
+  GE_HIP(c, hipGetLastError());
+  return GE_OK;
+}
+
+static int precond_apply(ge_ctx* c, int precond, const double* x, double* y, int64_t n) {
+  if (precond == GE_PC_JACOBI) return ge_launch_jacobi_apply(c, x, y);
+  GE_HIP(c, hipMemcpyAsync(y, x, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
+  return GE_OK;
+}
+
+int ge_gmres(ge_ctx* c, double tol, int maxit, int m, int precond, ge_solve_report* rep) {
+  auto t0 = std::chrono::steady_clock::now();
+  const int64_t n = 3 * c->G.N;
+  if (m < 1 || m > c->kr_m) return ge_fail(c, GE_ERR_ARG, "restart out of range (1.." + std::to_string(c->kr_m) + ")");
+  if (precond != GE_PC_NONE && precond != GE_PC_JACOBI) return ge_fail(c, GE_ERR_ARG, "unknown preconditioner");
+  int rc;
+  double* x = c->Eth;
+  double* V = c->V;
+  double* w = c->kw;
+  double* z = c->Zp;
+  double* hd = c->hdev;  // [0,64): h1, [64,128): h2, [128]: |w|^2, [192,256): y
+  if (precond == GE_PC_JACOBI && (rc = ge_launch_jacobi_setup(c))) return rc;
+  // ||b||
+  if ((rc = multidot(c, c->rhs, n, 1, c->rhs, n, hd + 128))) return rc;
+  double bn2;
+  GE_HIP(c, hipMemcpyAsync(&bn2, hd + 128, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  GE_HIP(c, hipStreamSynchronize(c->stream));
+  double bnorm = std::sqrt(bn2);
+  if (!(bnorm >= 0) || std::isinf(bnorm)) return ge_fail(c, GE_ERR_NONFINITE, "non-finite right-hand side");
+  const double bref = bnorm > 0 ? bnorm : 1.0;
+  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), s(m + 1), y(m), hh(2 * HSTRIDE + 1);
+  int it = 0, restarts = 0, conv = 0;
+  double rel = 0;
+  while (true) {
+    // r = b - A x, beta = ||r||
+    if ((rc = ge_launch_apply_A(c, x, V))) return rc;
+    hipLaunchKernelGGL(k_residual, vgrid(n), dim3(KB), 0, c->stream, V, c->rhs, n);
+    if ((rc = multidot(c, V, n, 1, V, n, hd + 128))) return rc;
+    double b2;
+    GE_HIP(c, hipMemcpyAsync(&b2, hd + 128, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    GE_HIP(c, hipStreamSynchronize(c->stream));
+    const double beta = std::sqrt(b2);
+    if (!std::isfinite(beta)) return ge_fail(c, GE_ERR_NONFINITE, "non-finite residual in GMRES");
+    rel = beta / bref;
+    if (rel <= tol) { conv = 1; break; }
+    if (it >= maxit) break;
+    hipLaunchKernelGGL(k_normalize, vgrid(n), dim3(KB), 0, c->stream, V, V, hd + 128, n);
+    std::fill(s.begin(), s.end(), 0.0);
+    s[0] = beta;
+    int k = 0;
+    for (int j = 0; j < m && it < maxit; ++j) {
+      double* vj = V + (int64_t)j * n;
+      double* vn = V + (int64_t)(j + 1) * n;
+      const double* av_in = vj;
+      if (precond != GE_PC_NONE) {
+        if ((rc = precond_apply(c, precond, vj, z, n))) return rc;
+        av_in = z;
+      }
+      if ((rc = ge_launch_apply_A(c, av_in, w))) return rc;
+      // CGS2
+      if ((rc = multidot(c, V, n, j + 1, w, n, hd))) return rc;
+      hipLaunchKernelGGL(k_multiaxpy, vgrid(n), dim3(KB), 0, c->stream, w, V, n, j + 1, hd, -1.0, n);
+      if ((rc = multidot(c, V, n, j + 1, w, n, hd + HSTRIDE))) return rc;
+      hipLaunchKernelGGL(k_multiaxpy, vgrid(n), dim3(KB), 0, c->stream, w, V, n, j + 1, hd + HSTRIDE, -1.0, n);
+      hipLaunchKernelGGL(k_sum2, dim3(1), dim3(HSTRIDE), 0, c->stream, hd, hd + HSTRIDE, j + 1);
+      if ((rc = multidot(c, w, n, 1, w, n, hd + 128))) return rc;
+      hipLaunchKernelGGL(k_normalize, vgrid(n), dim3(KB), 0, c->stream, vn, w, hd + 128, n);
+      GE_HIP(c, hipGetLastError());
+      GE_HIP(c, hipMemcpyAsync(hh.data(), hd, sizeof(double) * (2 * HSTRIDE + 1), hipMemcpyDeviceToHost, c->stream));
+      GE_HIP(c, hipStreamSynchronize(c->stream));
+      ++it;
+      for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hh[i];
+      const double hn = std::sqrt(hh[128]);
+      if (!std::isfinite(hn)) return ge_fail(c, GE_ERR_NONFINITE, "non-finite Arnoldi vector");
+      H[(size_t)(j + 1) * m + j] = hn;
+      for (int i = 0; i < j; ++i) {
+        const double a0 = cs[i] * H[(size_t)i * m + j] + sn[i] * H[(size_t)(i + 1) * m + j];
+        const double a1 = -sn[i] * H[(size_t)i * m + j] + cs[i] * H[(size_t)(i + 1) * m + j];
+        H[(size_t)i * m + j] = a0;
+        H[(size_t)(i + 1) * m + j] = a1;
+      }
+      const double a = H[(size_t)j * m + j], bb = H[(size_t)(j + 1) * m + j];
+      const double den = std::sqrt(a * a + bb * bb);
+      cs[j] = den > 0 ? a / den : 1.0;
+      sn[j] = den > 0 ? bb / den : 0.0;
+      H[(size_t)j * m + j] = den;
+      H[(size_t)(j + 1) * m + j] = 0.0;
+      s[j + 1] = -sn[j] * s[j];
+      s[j] = cs[j] * s[j];
+      k = j + 1;
+      if (std::fabs(s[j + 1]) <= tol * bref || hn == 0.0) break;
+    }
+    // y = H^{-1} s; x += M^{-1} (V y)
+    for (int i = k - 1; i >= 0; --i) {
+      double t = s[i];
+      for (int l = i + 1; l < k; ++l) t -= H[(size_t)i * m + l] * y[l];
+      y[i] = t / H[(size_t)i * m + i];
+    }
+    GE_HIP(c, hipMemcpyAsync(hd + 192, y.data(), sizeof(double) * k, hipMemcpyHostToDevice, c->stream));
+    if (precond == GE_PC_NONE) {
+      hipLaunchKernelGGL(k_multiaxpy, vgrid(n), dim3(KB), 0, c->stream, x, V, n, k, hd + 192, 1.0, n);
+    } else {
+      GE_HIP(c, hipMemsetAsync(w, 0, sizeof(double) * n, c->stream));
+      hipLaunchKernelGGL(k_multiaxpy, vgrid(n), dim3(KB), 0, c->stream, w, V, n, k, hd + 192, 1.0, n);
+      if ((rc = precond_apply(c, precond, w, z, n))) return rc;
+      hipLaunchKernelGGL(k_add, vgrid(n), dim3(KB), 0, c->stream, x, z, n);
+    }
+    GE_HIP(c, hipGetLastError());
+    ++restarts;
+  }
+  if (rep) {
+    rep->iterations = it;
+    rep->restarts = restarts;
+    rep->converged = conv;
+    rep->relres = rel;
+    rep->bnorm = bnorm;
+    rep->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  return conv ? GE_OK : GE_WARN_NOT_CONVERGED;
+}

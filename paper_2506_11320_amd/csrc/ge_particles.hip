@@ -1,0 +1,793 @@
+// Particle-side kernels of the GL-ECSIM pass on gfx950: loading, the
+// implicit mover with stable re-binning, and the mass-matrix/current deposit.
+//
+// Particle storage.  Each species keeps two buffers (ping-pong) of
+// structure-of-arrays data (offset in the cell [3][n], velocity [3][n],
+// weight [n]).  A buffer is ordered by "home" cell h (the cell a particle
+// occupied before the last push) and, inside a home segment, partitioned by
+// the direction d in {-1,0,1}^dim to the particle's present cell h + d.  The
+// run of (h, d) starts at sub_start[d][h] and holds sub_cnt[d][h] particles.
+// The particles now in cell c are the runs (c - d, d) taken in ascending
+// linear order of the home cell: that concatenation is exactly the order a
+// stable sort by present cell gives, so the re-binning is an integer,
+// deterministic, bit-exact stable sort that moves each particle once, inside
+// the push.
+#include "ge_internal.h"
+
+namespace {
+
+template <int DIM>
+struct Dm {
+  static constexpr int ND = DIM == 3 ? 27 : (DIM == 2 ? 9 : 3);  // directions = quad rows
+  static constexpr int NC = 1 << DIM;                             // corners
+  static constexpr int NRB = DIM == 3 ? 2 : 1;                    // 16-row MFMA blocks
+};
+
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+__device__ inline int rl_i(int x, int l) { return __builtin_amdgcn_readlane(x, l); }
+__device__ inline float rl(float x, int l) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l)); }
+__device__ inline double rl(double x, int l) {
+  int64_t b = __double_as_longlong(x);
+  int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), l);
+  int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((int64_t)hi << 32) | (uint32_t)lo);
+}
+__device__ inline uint64_t lanemask_lt(int lane) { return lane == 0 ? 0ull : ((~0ull) >> (64 - lane)); }
+
+// Offset e (neighbour h = c + e along one axis) of rank j in ascending order
+// of the neighbour's coordinate, on a periodic axis of n >= 3 cells.
+__device__ inline int axis_order(int ci, int n, int j) {
+  if (ci == 0) return j == 0 ? 0 : (j == 1 ? 1 : -1);
+  if (ci == n - 1) return j == 0 ? 1 : (j == 1 ? -1 : 0);
+  return j - 1;
+}
+
+// Collect the runs of particles present in cell c, ascending by home cell.
+// Lane j < ND loads run j; the non-empty runs are compacted into s_start /
+// s_pre (exclusive prefix of counts).  Returns the total; nseg the run count.
+template <int DIM>
+__device__ int runs_setup(const DGrid& G, int64_t c, const int32_t* __restrict__ sub_start,
+                          const int32_t* __restrict__ sub_cnt, int* s_start, int* s_pre, int lane, int& nseg) {
+  int cx, cy, cz;
+  unflat3(G, c, cx, cy, cz);
+  int cnt = 0, st = 0;
+  if (lane < Dm<DIM>::ND) {
+    int jx = lane % 3, jy = (lane / 3) % 3, jz = lane / 9;
+    int ex = axis_order(cx, G.n[0], jx);
+    int ey = DIM >= 2 ? axis_order(cy, G.n[1], jy) : 0;
+    int ez = DIM >= 3 ? axis_order(cz, G.n[2], jz) : 0;
+    int64_t h = flat3(G, cx + ex, cy + ey, cz + ez);
+    int dir = (1 - ex) + (DIM >= 2 ? 3 * (1 - ey) : 0) + (DIM >= 3 ? 9 * (1 - ez) : 0);
+    cnt = sub_cnt[(int64_t)dir * G.N + h];
+    st = sub_start[(int64_t)dir * G.N + h];
+  }
+  int incl = cnt;
+#pragma unroll
+  for (int d = 1; d < 32; d <<= 1) {
+    int t = __shfl_up(incl, d, 64);
+    if (lane >= d) incl += t;
+  }
+  int total = rl_i(incl, 31);
+  uint64_t m = __ballot(cnt > 0);
+  if (cnt > 0) {
+    int pos = __popcll(m & lanemask_lt(lane));
+    s_start[pos] = st;
+    s_pre[pos] = incl - cnt;
+  }
+  nseg = __popcll(m);
+  wave_sync();
+  return total;
+}
+
+__device__ inline int run_index(int t, const int* s_start, const int* s_pre, int nseg) {
+  int k = 0;
+  for (int i = 1; i < nseg; ++i)
+    if (s_pre[i] <= t) k = i;
+  return s_start[k] + (t - s_pre[k]);
+}
+
+// Field values at the 2^DIM corner nodes of cell c, broadcast to every lane.
+template <typename T, int DIM>
+__device__ void corner_fields(const DGrid& G, int64_t c, const T* __restrict__ F, int lane, T out[3][8]) {
+  constexpr int NC = Dm<DIM>::NC;
+  T val = 0;
+  if (lane < 3 * NC) {
+    int q = lane / NC, a = lane % NC;
+    int64_t g = nbr3(G, c, a & 1, DIM >= 2 ? (a >> 1) & 1 : 0, DIM >= 3 ? (a >> 2) & 1 : 0);
+    val = F[q * G.N + g];
+  }
+#pragma unroll
+  for (int q = 0; q < 3; ++q)
+#pragma unroll
+    for (int a = 0; a < NC; ++a) out[q][a] = rl(val, q * NC + a);
+}
+
+template <typename T, int DIM>
+__device__ inline void lin_weights(const T f[3], T W[8]) {
+  constexpr int NC = Dm<DIM>::NC;
+#pragma unroll
+  for (int a = 0; a < NC; ++a) {
+    T w = (a & 1) ? f[0] : (T)1 - f[0];
+    if (DIM >= 2) w *= ((a >> 1) & 1) ? f[1] : (T)1 - f[1];
+    if (DIM >= 3) w *= ((a >> 2) & 1) ? f[2] : (T)1 - f[2];
+    W[a] = w;
+  }
+}
+
+template <typename T, int DIM>
+__device__ inline void gather3(const T W[8], const T F[3][8], T out[3]) {
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    T s = 0;
+#pragma unroll
+    for (int a = 0; a < Dm<DIM>::NC; ++a) s += W[a] * F[q][a];
+    out[q] = s;
+  }
+}
+
+// The implicit mover (Sec. 3.1): vbar = alpha (v + beta E_p),
+// v^{n+1} = 2 vbar - v^n, x^{n+3/2} = x^{n+1/2} + dt v^{n+1}.  alpha applied
+// as (t + beta t x B + beta^2 (t.B) B) / (1 + beta^2 |B|^2).  Returns the
+// direction code of the cell move; clamps a move of one cell or more.
+template <typename T, int DIM>
+__device__ inline int push_one(T f[3], T v[3], const T Ec[3][8], const T Bc[3][8], T beta, const T dtx[3],
+                               int& clamped) {
+  T W[8];
+  lin_weights<T, DIM>(f, W);
+  T Ep[3], Bp[3];
+  gather3<T, DIM>(W, Ec, Ep);
+  gather3<T, DIM>(W, Bc, Bp);
+  T t0 = v[0] + beta * Ep[0], t1 = v[1] + beta * Ep[1], t2 = v[2] + beta * Ep[2];
+  T b2 = Bp[0] * Bp[0] + Bp[1] * Bp[1] + Bp[2] * Bp[2];
+  T den = (T)1 / ((T)1 + beta * beta * b2);
+  T tb = beta * beta * (t0 * Bp[0] + t1 * Bp[1] + t2 * Bp[2]);
+  T vb0 = (t0 + beta * (t1 * Bp[2] - t2 * Bp[1]) + tb * Bp[0]) * den;
+  T vb1 = (t1 + beta * (t2 * Bp[0] - t0 * Bp[2]) + tb * Bp[1]) * den;
+  T vb2 = (t2 + beta * (t0 * Bp[1] - t1 * Bp[0]) + tb * Bp[2]) * den;
+  v[0] = (T)2 * vb0 - v[0];
+  v[1] = (T)2 * vb1 - v[1];
+  v[2] = (T)2 * vb2 - v[2];
+  int dir = 0, mul = 1;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    T s = f[d] + v[d] * dtx[d];
+    if (!(s >= (T)-1 && s < (T)2)) {  // also catches NaN
+      clamped = 1;
+      s = (s != s) ? (T)0.5 : (s < (T)-1 ? (T)-1 : (T)1.5);
+    }
+    T e = floor(s);
+    T fn = s - e;
+    if (fn >= (T)1) { fn = 0; e += (T)1; }
+    f[d] = fn;
+    dir += ((int)e + 1) * mul;
+    mul *= 3;
+  }
+  return dir;
+}
+
+// ------------------------------------------------------------------ push
+template <typename T>
+struct PushArgs {
+  const T *off, *v, *w;
+  T *off_o, *v_o, *w_o;
+  const int32_t *sub_start, *sub_cnt, *seg_next;
+  int32_t *sub_start_o, *sub_cnt_o;
+  const T *E, *B;  // E^{n+theta} and node-averaged B^n, [3][N]
+  T beta;
+  T dtx[3];
+  int64_t n;
+  int* flags;
+};
+
+template <typename T, int DIM>
+__global__ __launch_bounds__(256) void k_push(DGrid G, PushArgs<T> A) {
+  constexpr int ND = Dm<DIM>::ND;
+  __shared__ int s_start[4][32], s_pre[4][32];
+  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t c = xcd_block(blockIdx.x, gridDim.x) * 4 + wid;
+  if (c >= G.N) return;
+  int nseg;
+  const int total = runs_setup<DIM>(G, c, A.sub_start, A.sub_cnt, s_start[wid], s_pre[wid], lane, nseg);
+  T Ec[3][8], Bc[3][8];
+  corner_fields<T, DIM>(G, c, A.E, lane, Ec);
+  corner_fields<T, DIM>(G, c, A.B, lane, Bc);
+  const int64_t base = A.seg_next[c];
+  const int64_t N = A.n;
+  int mycnt = 0, dir_off = 0, running = 0, clamped = 0, bad = 0;
+  // pass 0 counts the particles per direction, pass 1 writes them
+#pragma clang loop unroll(disable)
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int t0 = 0; t0 < total; t0 += 64) {
+      const int t = t0 + lane;
+      const bool act = t < total;
+      T f[3] = {0, 0, 0}, v[3] = {0, 0, 0}, w = 0;
+      int dir = -1;
+      if (act) {
+        const int i = run_index(t, s_start[wid], s_pre[wid], nseg);
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) f[d] = A.off[d * N + i];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) v[d] = A.v[d * N + i];
+        w = A.w[i];
+        dir = push_one<T, DIM>(f, v, Ec, Bc, A.beta, A.dtx, clamped);
+      }
+      uint64_t rem = __ballot(act);
+      int pos = -1;
+      while (rem) {
+        const int l0 = __ffsll((unsigned long long)rem) - 1;
+        const int d0 = rl_i(dir, l0);
+        const uint64_t m = __ballot(act && dir == d0);
+        if (pass == 0) {
+          if (lane == d0) mycnt += __popcll(m);
+        } else {
+          const int b0 = rl_i(dir_off, d0) + rl_i(running, d0);
+          if (act && dir == d0) pos = b0 + __popcll(m & lanemask_lt(lane));
+          if (lane == d0) running += __popcll(m);
+        }
+        rem &= ~m;
+      }
+      if (pass == 1 && act) {
+        if (pos >= 0 && pos < total) {
+          const int64_t o = base + pos;
+#pragma unroll
+          for (int d = 0; d < 3; ++d) A.off_o[d * N + o] = f[d];
+#pragma unroll
+          for (int d = 0; d < 3; ++d) A.v_o[d * N + o] = v[d];
+          A.w_o[o] = w;
+        } else {
+          bad = 1;
+        }
+      }
+    }
+    if (pass == 0) {
+      int incl = mycnt;
+#pragma unroll
+      for (int d = 1; d < 32; d <<= 1) {
+        int tt = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += tt;
+      }
+      dir_off = incl - mycnt;
+    }
+  }
+  if (lane < ND) {
+    A.sub_start_o[(int64_t)lane * G.N + c] = (int32_t)(base + dir_off);
+    A.sub_cnt_o[(int64_t)lane * G.N + c] = mycnt;
+    if (running != mycnt) bad = 1;
+  }
+  if (clamped) atomicOr(&A.flags[0], 1);
+  if (bad) atomicOr(&A.flags[1], 1);
+}
+
+// ------------------------------------------------------------------ scan
+// cnt[c] = particles now in cell c; seg[c] = exclusive prefix over cells.
+template <int DIM>
+__global__ __launch_bounds__(256) void k_count(DGrid G, const int32_t* __restrict__ sub_cnt, int32_t* __restrict__ cnt) {
+  int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (c >= G.N) return;
+  int cx, cy, cz;
+  unflat3(G, c, cx, cy, cz);
+  int s = 0;
+  for (int j = 0; j < Dm<DIM>::ND; ++j) {
+    int ex = j % 3 - 1, ey = DIM >= 2 ? (j / 3) % 3 - 1 : 0, ez = DIM >= 3 ? j / 9 - 1 : 0;
+    int64_t h = flat3(G, cx + ex, cy + ey, cz + ez);
+    int dir = (1 - ex) + (DIM >= 2 ? 3 * (1 - ey) : 0) + (DIM >= 3 ? 9 * (1 - ez) : 0);
+    s += sub_cnt[(int64_t)dir * G.N + h];
+  }
+  cnt[c] = s;
+}
+
+constexpr int SCAN_ITEMS = 4;
+constexpr int SCAN_BLOCK = 256;
+
+__device__ int block_excl_scan(int x, int* sh, int& total) {
+  // 256 threads, 4 waves
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  int incl = x;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    int t = __shfl_up(incl, d, 64);
+    if (lane >= d) incl += t;
+  }
+  if (lane == 63) sh[wid] = incl;
+  __syncthreads();
+  int off = 0;
+  for (int k = 0; k < wid; ++k) off += sh[k];
+  total = sh[0] + sh[1] + sh[2] + sh[3];
+  __syncthreads();
+  return off + incl - x;
+}
+
+__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_reduce(const int32_t* __restrict__ a, int64_t n, int32_t* __restrict__ bsum) {
+  __shared__ int sh[4];
+  int64_t b0 = (int64_t)blockIdx.x * SCAN_BLOCK * SCAN_ITEMS;
+  int s = 0;
+  for (int k = 0; k < SCAN_ITEMS; ++k) {
+    int64_t i = b0 + (int64_t)threadIdx.x * SCAN_ITEMS + k;
+    if (i < n) s += a[i];
+  }
+  int total;
+  block_excl_scan(s, sh, total);
+  if (threadIdx.x == 0) bsum[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_blocks(int32_t* __restrict__ bsum, int64_t nb) {
+  __shared__ int sh[4];
+  int carry = 0;
+  for (int64_t b0 = 0; b0 < nb; b0 += SCAN_BLOCK) {
+    int64_t i = b0 + threadIdx.x;
+    int x = i < nb ? bsum[i] : 0;
+    int total;
+    int e = block_excl_scan(x, sh, total);
+    if (i < nb) bsum[i] = carry + e;
+    carry += total;
+  }
+}
+
+__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_final(const int32_t* __restrict__ a, int64_t n,
+                                                           const int32_t* __restrict__ boff, int32_t* __restrict__ out) {
+  __shared__ int sh[4];
+  int64_t b0 = (int64_t)blockIdx.x * SCAN_BLOCK * SCAN_ITEMS;
+  int vals[SCAN_ITEMS];
+  int s = 0;
+  for (int k = 0; k < SCAN_ITEMS; ++k) {
+    int64_t i = b0 + (int64_t)threadIdx.x * SCAN_ITEMS + k;
+    vals[k] = i < n ? a[i] : 0;
+    s += vals[k];
+  }
+  int total;
+  int e = block_excl_scan(s, sh, total) + boff[blockIdx.x];
+  for (int k = 0; k < SCAN_ITEMS; ++k) {
+    int64_t i = b0 + (int64_t)threadIdx.x * SCAN_ITEMS + k;
+    if (i < n) out[i] = e;
+    e += vals[k];
+  }
+}
+
+// ------------------------------------------------------------------ deposit
+// For every cell, one wavefront reduces over the cell's particles, species by
+// species, with FP32 (or FP64) MFMA 16x16x4: A[row][p] = quadratic weight
+// product of row r = (ix, iy, iz) (per axis (1-f)^2, f(1-f), f^2), B[p][col]
+// = (w alpha (9), w alpha v (3), w v (3), w).  Every node-pair product
+// W_a W_b of the cell is one of these rows, and every linear weight W_a is a
+// sum of them, so S = A B holds the whole cell's contribution to the mass
+// matrices, current and moments.
+template <typename T>
+struct DepSpecies {
+  const T *off, *v, *w;
+  const int32_t *sub_start, *sub_cnt;
+  T q, m, beta;
+  int64_t n;
+};
+template <typename T>
+struct DepArgs {
+  DepSpecies<T> sp[GE_MAX_SPECIES];
+  int nsp;
+  const T* Bn;  // [3][N]
+  T* cellQ;     // [Q][N]
+};
+
+template <typename T>
+struct Mfma;
+template <>
+struct Mfma<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  __device__ static v4 op(float a, float b, v4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  __device__ static int row(int lane, int i) { return 4 * (lane >> 4) + i; }
+};
+template <>
+struct Mfma<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  __device__ static v4 op(double a, double b, v4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+  __device__ static int row(int lane, int i) { return (lane >> 4) + 4 * i; }
+};
+
+template <typename T, int DIM>
+struct DepCfg {
+  static constexpr int WPB = sizeof(T) == 4 ? 4 : 2;          // waves per block
+  static constexpr int AW = 16 * Dm<DIM>::NRB;                 // A row width
+  static constexpr int STRIDE = AW + 16;                       // staged floats per particle
+};
+
+template <typename T, int DIM>
+__global__ __launch_bounds__(256) void k_deposit(DGrid G, DepArgs<T> A) {
+  using M = Mfma<T>;
+  typedef typename M::v4 v4;
+  constexpr int ND = Dm<DIM>::ND, NC = Dm<DIM>::NC, NRB = Dm<DIM>::NRB;
+  constexpr int WPB = DepCfg<T, DIM>::WPB, AW = DepCfg<T, DIM>::AW, ST = DepCfg<T, DIM>::STRIDE;
+  constexpr int NR = ND;
+  __shared__ int s_start[WPB][32], s_pre[WPB][32];
+  __shared__ T s_stage[WPB][64 * ST];
+  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (wid >= WPB) return;
+  const int64_t c = xcd_block(blockIdx.x, gridDim.x) * WPB + wid;
+  if (c >= G.N) return;
+  T* stage = s_stage[wid];
+  T Bc[3][8];
+  corner_fields<T, DIM>(G, c, A.Bn, lane, Bc);
+  const int col = lane & 15;
+  T Rmt[NRB][4], Rm0[NRB][4], Rlin[NRB][4], Rrho[GE_MAX_SPECIES][NRB][4];
+#pragma unroll
+  for (int rb = 0; rb < NRB; ++rb)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      Rmt[rb][i] = Rm0[rb][i] = Rlin[rb][i] = 0;
+#pragma unroll
+      for (int s = 0; s < GE_MAX_SPECIES; ++s) Rrho[s][rb][i] = 0;
+    }
+  for (int s = 0; s < A.nsp; ++s) {
+    const DepSpecies<T>& S = A.sp[s];
+    int nseg;
+    const int total = runs_setup<DIM>(G, c, S.sub_start, S.sub_cnt, s_start[wid], s_pre[wid], lane, nseg);
+    v4 acc[NRB];
+#pragma unroll
+    for (int rb = 0; rb < NRB; ++rb) acc[rb] = v4{0, 0, 0, 0};
+    const int64_t N = S.n;
+    for (int t0 = 0; t0 < total; t0 += 64) {
+      const int t = t0 + lane;
+      T arow[AW], bcol[16];
+#pragma unroll
+      for (int k = 0; k < AW; ++k) arow[k] = 0;
+#pragma unroll
+      for (int k = 0; k < 16; ++k) bcol[k] = 0;
+      if (t < total) {
+        const int i = run_index(t, s_start[wid], s_pre[wid], nseg);
+        T f[3] = {0, 0, 0}, v[3];
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) f[d] = S.off[d * N + i];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) v[d] = S.v[d * N + i];
+        const T w = S.w[i];
+        T W[8];
+        lin_weights<T, DIM>(f, W);
+        T Bp[3];
+        gather3<T, DIM>(W, Bc, Bp);
+        // alpha (Sec. 3.1), row-major
+        const T be = S.beta;
+        const T den = (T)1 / ((T)1 + be * be * (Bp[0] * Bp[0] + Bp[1] * Bp[1] + Bp[2] * Bp[2]));
+        const T bb = be * be;
+        T al[9];
+        al[0] = (1 + bb * Bp[0] * Bp[0]) * den;
+        al[1] = (be * Bp[2] + bb * Bp[0] * Bp[1]) * den;
+        al[2] = (-be * Bp[1] + bb * Bp[0] * Bp[2]) * den;
+        al[3] = (-be * Bp[2] + bb * Bp[1] * Bp[0]) * den;
+        al[4] = (1 + bb * Bp[1] * Bp[1]) * den;
+        al[5] = (be * Bp[0] + bb * Bp[1] * Bp[2]) * den;
+        al[6] = (be * Bp[1] + bb * Bp[2] * Bp[0]) * den;
+        al[7] = (-be * Bp[0] + bb * Bp[2] * Bp[1]) * den;
+        al[8] = (1 + bb * Bp[2] * Bp[2]) * den;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) bcol[k] = w * al[k];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) bcol[9 + r] = w * (al[3 * r] * v[0] + al[3 * r + 1] * v[1] + al[3 * r + 2] * v[2]);
+#pragma unroll
+        for (int r = 0; r < 3; ++r) bcol[12 + r] = w * v[r];
+        bcol[15] = w;
+        // quadratic weight products per axis
+        T X[3][3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          if (d < DIM) {
+            const T g0 = (T)1 - f[d];
+            X[d][0] = g0 * g0;
+            X[d][1] = f[d] * g0;
+            X[d][2] = f[d] * f[d];
+          } else {
+            X[d][0] = 1; X[d][1] = 0; X[d][2] = 0;
+          }
+        }
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          const int ix = r % 3, iy = (r / 3) % 3, iz = r / 9;
+          arow[r] = X[0][ix] * X[1][iy] * X[2][iz];
+        }
+      }
+      T* my = stage + lane * ST;
+#pragma unroll
+      for (int k = 0; k < AW; ++k) my[k] = arow[k];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) my[AW + k] = bcol[k];
+      wave_sync();
+      const int cnt = min(64, total - t0);
+      const int nsteps = (cnt + 3) >> 2;
+      for (int stp = 0; stp < nsteps; ++stp) {
+        const T* pr = stage + (4 * stp + (lane >> 4)) * ST;
+        const T b = pr[AW + col];
+#pragma unroll
+        for (int rb = 0; rb < NRB; ++rb) acc[rb] = M::op(pr[16 * rb + col], b, acc[rb]);
+      }
+      wave_sync();
+    }
+    // scale this species' sums into the cell totals
+    const T qs = S.q, ms = S.m, bq = S.beta * S.q;
+#pragma unroll
+    for (int rb = 0; rb < NRB; ++rb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const T val = acc[rb][i];
+        if (col < 9) {
+          Rmt[rb][i] += bq * val;
+          Rm0[rb][i] += qs * val;
+        } else {
+          Rlin[rb][i] += (col < 12 ? qs : ms) * val;
+        }
+        if (col == 15) Rrho[s][rb][i] += qs * val;
+      }
+  }
+  // write the cell's quadratic-row sums of Mtilde and M0
+  const int64_t NN = G.N;
+  T* Q = A.cellQ;
+#pragma unroll
+  for (int rb = 0; rb < NRB; ++rb)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int r = 16 * rb + M::row(lane, i);
+      if (col < 9 && r < NR) {
+        Q[(int64_t)(r * 9 + col) * NN + c] = Rmt[rb][i];
+        Q[(int64_t)(9 * NR + r * 9 + col) * NN + c] = Rm0[rb][i];
+      }
+    }
+  // corner sums of the linear quantities: W_a = prod_d (X_{a_d} + X_{a_d+1})
+  const int NK = 7 + A.nsp;
+  T* lin = stage;  // reuse: [NR][NK]
+#pragma unroll
+  for (int rb = 0; rb < NRB; ++rb)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int r = 16 * rb + M::row(lane, i);
+      if (r < NR) {
+        if (col >= 9) lin[r * NK + (col - 9)] = Rlin[rb][i];
+        if (col == 15)
+          for (int s = 0; s < A.nsp; ++s) lin[r * NK + 7 + s] = Rrho[s][rb][i];
+      }
+    }
+  wave_sync();
+  for (int t = lane; t < NC * NK; t += 64) {
+    const int a = t % NC, k = t / NC;
+    T s = 0;
+#pragma unroll
+    for (int b = 0; b < NC; ++b) {
+      int r = ((a & 1) + (b & 1));
+      if (DIM >= 2) r += 3 * (((a >> 1) & 1) + ((b >> 1) & 1));
+      if (DIM >= 3) r += 9 * (((a >> 2) & 1) + ((b >> 2) & 1));
+      s += lin[r * NK + k];
+    }
+    Q[(int64_t)(18 * NR + k * NC + a) * NN + c] = s;
+  }
+}
+
+// ------------------------------------------------------------------ load / read back
+template <int DIM>
+__global__ void k_load_bounds(DGrid G, const int32_t* __restrict__ cell, int64_t n, int32_t* __restrict__ st,
+                              int32_t* __restrict__ en, int* flags) {
+  int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  int32_t c = cell[p];
+  if (c < 0 || c >= G.N) { atomicOr(&flags[2], 1); return; }
+  if (p > 0 && cell[p - 1] > c) atomicOr(&flags[2], 1);
+  if (p == 0 || cell[p - 1] != c) st[c] = (int32_t)p;
+  if (p == n - 1 || cell[p + 1] != c) en[c] = (int32_t)(p + 1);
+}
+__global__ void k_load_fix(int64_t N, const int32_t* __restrict__ st, int32_t* __restrict__ en) {
+  int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (c >= N) return;
+  int32_t e = en[c];
+  en[c] = e > 0 ? e - st[c] : 0;
+}
+
+template <typename T, int DIM>
+__global__ __launch_bounds__(256) void k_get_particles(DGrid G, const T* __restrict__ off, const T* __restrict__ v,
+                                                       const T* __restrict__ w, const int32_t* __restrict__ sub_start,
+                                                       const int32_t* __restrict__ sub_cnt, const int32_t* __restrict__ seg,
+                                                       int64_t n, int32_t* __restrict__ cell_o, T* __restrict__ off_o,
+                                                       T* __restrict__ v_o, T* __restrict__ w_o) {
+  __shared__ int s_start[4][32], s_pre[4][32];
+  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t c = blockIdx.x * 4 + wid;
+  if (c >= G.N) return;
+  int nseg;
+  const int total = runs_setup<DIM>(G, c, sub_start, sub_cnt, s_start[wid], s_pre[wid], lane, nseg);
+  const int64_t base = seg[c];
+  for (int t = lane; t < total; t += 64) {
+    const int i = run_index(t, s_start[wid], s_pre[wid], nseg);
+    const int64_t o = base + t;
+    cell_o[o] = (int32_t)c;
+    for (int d = 0; d < 3; ++d) off_o[d * n + o] = off[d * n + i];
+    for (int d = 0; d < 3; ++d) v_o[d * n + o] = v[d * n + i];
+    w_o[o] = w[i];
+  }
+}
+
+// Kinetic energy and momentum of one species, deterministic block partials.
+template <typename T>
+__global__ __launch_bounds__(256) void k_particle_moments(const T* __restrict__ v, const T* __restrict__ w, int64_t n,
+                                                          double* __restrict__ part) {
+  __shared__ double sh[4][256];
+  double a[4] = {0, 0, 0, 0};
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
+    double vx = v[p], vy = v[n + p], vz = v[2 * n + p], ww = w[p];
+    a[0] += ww * (vx * vx + vy * vy + vz * vz);
+    a[1] += ww * vx; a[2] += ww * vy; a[3] += ww * vz;
+  }
+  for (int k = 0; k < 4; ++k) sh[k][threadIdx.x] = a[k];
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s)
+      for (int k = 0; k < 4; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x < 4) part[threadIdx.x * gridDim.x + blockIdx.x] = sh[threadIdx.x][0];
+}
+
+}  // namespace
+
+// ===================================================================== host
+static int scan_into(ge_ctx* c, const int32_t* in, int32_t* out) {
+  const int64_t N = c->G.N;
+  const int64_t per = SCAN_BLOCK * SCAN_ITEMS;
+  const int64_t nb = (N + per - 1) / per;
+  hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(SCAN_BLOCK), 0, c->stream, in, N, c->scan_blocks);
+  hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(SCAN_BLOCK), 0, c->stream, c->scan_blocks, nb);
+  hipLaunchKernelGGL(k_scan_final, dim3(nb), dim3(SCAN_BLOCK), 0, c->stream, in, N, c->scan_blocks, out);
+  GE_HIP(c, hipGetLastError());
+  return GE_OK;
+}
+
+// seg_next <- exclusive scan of the per-cell counts of species s
+int ge_launch_scan_counts(ge_ctx* c, int s) {
+  SpeciesBuf& S = c->sp[s];
+  const int64_t N = c->G.N;
+  dim3 gb((N + 255) / 256);
+  int32_t* cnt = c->seg_next;  // counts first, scanned in place via a temp
+  switch (c->G.dim) {
+    case 1: hipLaunchKernelGGL(k_count<1>, gb, dim3(256), 0, c->stream, c->G, S.sub_cnt[S.cur], cnt); break;
+    case 2: hipLaunchKernelGGL(k_count<2>, gb, dim3(256), 0, c->stream, c->G, S.sub_cnt[S.cur], cnt); break;
+    default: hipLaunchKernelGGL(k_count<3>, gb, dim3(256), 0, c->stream, c->G, S.sub_cnt[S.cur], cnt); break;
+  }
+  GE_HIP(c, hipGetLastError());
+  return scan_into(c, cnt, cnt);
+}
+
+template <typename T, int DIM>
+static void launch_push_t(ge_ctx* c, int s) {
+  SpeciesBuf& S = c->sp[s];
+  PushArgs<T> A;
+  const int cur = S.cur, nxt = 1 - S.cur;
+  A.off = (const T*)S.off[cur]; A.v = (const T*)S.v[cur]; A.w = (const T*)S.w[cur];
+  A.off_o = (T*)S.off[nxt]; A.v_o = (T*)S.v[nxt]; A.w_o = (T*)S.w[nxt];
+  A.sub_start = S.sub_start[cur]; A.sub_cnt = S.sub_cnt[cur]; A.seg_next = c->seg_next;
+  A.sub_start_o = S.sub_start[nxt]; A.sub_cnt_o = S.sub_cnt[nxt];
+  if (sizeof(T) == 4) { A.E = (const T*)c->Eth32; A.B = (const T*)c->Bn32; }
+  else { A.E = (const T*)c->Eth; A.B = (const T*)c->Bn; }
+  A.beta = (T)S.beta;
+  for (int d = 0; d < 3; ++d) A.dtx[d] = (T)(c->P.dt * c->G.idx[d]);
+  A.n = S.n;
+  A.flags = c->flags;
+  const int64_t nb = (c->G.N + 3) / 4;
+  hipLaunchKernelGGL((k_push<T, DIM>), dim3(nb), dim3(256), 0, c->stream, c->G, A);
+}
+
+int ge_launch_push(ge_ctx* c, int s) {
+  int rc = ge_launch_scan_counts(c, s);
+  if (rc) return rc;
+  const bool f32 = c->P.precision == GE_FP32;
+  switch (c->G.dim * 2 + (f32 ? 1 : 0)) {
+    case 2: launch_push_t<double, 1>(c, s); break;
+    case 3: launch_push_t<float, 1>(c, s); break;
+    case 4: launch_push_t<double, 2>(c, s); break;
+    case 5: launch_push_t<float, 2>(c, s); break;
+    case 6: launch_push_t<double, 3>(c, s); break;
+    default: launch_push_t<float, 3>(c, s); break;
+  }
+  GE_HIP(c, hipGetLastError());
+  c->sp[s].cur = 1 - c->sp[s].cur;
+  return GE_OK;
+}
+
+template <typename T, int DIM>
+static void launch_deposit_t(ge_ctx* c) {
+  DepArgs<T> A;
+  A.nsp = c->nsp;
+  for (int s = 0; s < c->nsp; ++s) {
+    SpeciesBuf& S = c->sp[s];
+    A.sp[s].off = (const T*)S.off[S.cur]; A.sp[s].v = (const T*)S.v[S.cur]; A.sp[s].w = (const T*)S.w[S.cur];
+    A.sp[s].sub_start = S.sub_start[S.cur]; A.sp[s].sub_cnt = S.sub_cnt[S.cur];
+    A.sp[s].q = (T)S.q; A.sp[s].m = (T)S.m; A.sp[s].beta = (T)S.beta; A.sp[s].n = S.n;
+  }
+  A.Bn = sizeof(T) == 4 ? (const T*)c->Bn32 : (const T*)c->Bn;
+  A.cellQ = (T*)c->cellQ;
+  constexpr int WPB = DepCfg<T, DIM>::WPB;
+  const int64_t nb = (c->G.N + WPB - 1) / WPB;
+  hipLaunchKernelGGL((k_deposit<T, DIM>), dim3(nb), dim3(64 * WPB), 0, c->stream, c->G, A);
+}
+
+int ge_launch_deposit(ge_ctx* c) {
+  const bool f32 = c->P.precision == GE_FP32;
+  switch (c->G.dim * 2 + (f32 ? 1 : 0)) {
+    case 2: launch_deposit_t<double, 1>(c); break;
+    case 3: launch_deposit_t<float, 1>(c); break;
+    case 4: launch_deposit_t<double, 2>(c); break;
+    case 5: launch_deposit_t<float, 2>(c); break;
+    case 6: launch_deposit_t<double, 3>(c); break;
+    default: launch_deposit_t<float, 3>(c); break;
+  }
+  GE_HIP(c, hipGetLastError());
+  return GE_OK;
+}
+
+int ge_launch_load_species(ge_ctx* c, int s, const int32_t* cell, const void* off, const void* v, const void* w) {
+  SpeciesBuf& S = c->sp[s];
+  const int64_t N = c->G.N, n = S.n;
+  const size_t es = c->P.precision == GE_FP32 ? 4 : 8;
+  GE_HIP(c, hipMemcpyAsync(S.off[0], off, 3 * n * es, hipMemcpyDeviceToDevice, c->stream));
+  GE_HIP(c, hipMemcpyAsync(S.v[0], v, 3 * n * es, hipMemcpyDeviceToDevice, c->stream));
+  GE_HIP(c, hipMemcpyAsync(S.w[0], w, n * es, hipMemcpyDeviceToDevice, c->stream));
+  for (int b = 0; b < 2; ++b) {
+    GE_HIP(c, hipMemsetAsync(S.sub_start[b], 0, sizeof(int32_t) * c->ND * N, c->stream));
+    GE_HIP(c, hipMemsetAsync(S.sub_cnt[b], 0, sizeof(int32_t) * c->ND * N, c->stream));
+  }
+  S.cur = 0;
+  const int center = (c->ND - 1) / 2;
+  int32_t* st = S.sub_start[0] + (int64_t)center * N;
+  int32_t* en = S.sub_cnt[0] + (int64_t)center * N;
+  if (n > 0) {
+    dim3 gp((n + 255) / 256);
+    switch (c->G.dim) {
+      case 1: hipLaunchKernelGGL(k_load_bounds<1>, gp, dim3(256), 0, c->stream, c->G, cell, n, st, en, c->flags); break;
+      case 2: hipLaunchKernelGGL(k_load_bounds<2>, gp, dim3(256), 0, c->stream, c->G, cell, n, st, en, c->flags); break;
+      default: hipLaunchKernelGGL(k_load_bounds<3>, gp, dim3(256), 0, c->stream, c->G, cell, n, st, en, c->flags); break;
+    }
+  }
+  hipLaunchKernelGGL(k_load_fix, dim3((N + 255) / 256), dim3(256), 0, c->stream, N, st, en);
+  GE_HIP(c, hipGetLastError());
+  return GE_OK;
+}
+
+template <typename T, int DIM>
+static void launch_get_t(ge_ctx* c, int s, int32_t* cell, void* off, void* v, void* w) {
+  SpeciesBuf& S = c->sp[s];
+  hipLaunchKernelGGL((k_get_particles<T, DIM>), dim3((c->G.N + 3) / 4), dim3(256), 0, c->stream, c->G,
+                     (const T*)S.off[S.cur], (const T*)S.v[S.cur], (const T*)S.w[S.cur], S.sub_start[S.cur],
+                     S.sub_cnt[S.cur], c->seg_next, S.n, cell, (T*)off, (T*)v, (T*)w);
+}
+
+int ge_launch_get_particles(ge_ctx* c, int s, int32_t* cell, void* off, void* v, void* w) {
+  int rc = ge_launch_scan_counts(c, s);
+  if (rc) return rc;
+  const bool f32 = c->P.precision == GE_FP32;
+  switch (c->G.dim * 2 + (f32 ? 1 : 0)) {
+    case 2: launch_get_t<double, 1>(c, s, cell, off, v, w); break;
+    case 3: launch_get_t<float, 1>(c, s, cell, off, v, w); break;
+    case 4: launch_get_t<double, 2>(c, s, cell, off, v, w); break;
+    case 5: launch_get_t<float, 2>(c, s, cell, off, v, w); break;
+    case 6: launch_get_t<double, 3>(c, s, cell, off, v, w); break;
+    default: launch_get_t<float, 3>(c, s, cell, off, v, w); break;
+  }
+  GE_HIP(c, hipGetLastError());
+  return GE_OK;
+}
+
+int ge_launch_particle_moments(ge_ctx* c, int s, double* out4) {
+  SpeciesBuf& S = c->sp[s];
+  const int nbk = 256;
+  double* part = c->partials;  // needs 4 * nbk
+  if (c->P.precision == GE_FP32)
+    hipLaunchKernelGGL(k_particle_moments<float>, dim3(nbk), dim3(256), 0, c->stream, (const float*)S.v[S.cur],
+                       (const float*)S.w[S.cur], S.n, part);
+  else
+    hipLaunchKernelGGL(k_particle_moments<double>, dim3(nbk), dim3(256), 0, c->stream, (const double*)S.v[S.cur],
+                       (const double*)S.w[S.cur], S.n, part);
+  GE_HIP(c, hipGetLastError());
+  double h[4 * 256];
+  GE_HIP(c, hipMemcpyAsync(h, part, sizeof(double) * 4 * nbk, hipMemcpyDeviceToHost, c->stream));
+  GE_HIP(c, hipStreamSynchronize(c->stream));
+  for (int k = 0; k < 4; ++k) {
+    double a = 0;
+    for (int b = 0; b < nbk; ++b) a += h[k * nbk + b];
+    out4[k] = a;
+  }
+  return GE_OK;
+}

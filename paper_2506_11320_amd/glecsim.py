@@ -1,0 +1,250 @@
+"""Python binding of libglecsim.so (the gfx950 GL-ECSIM library).
+
+Argument marshalling only: every step of the method runs in the library's
+HIP kernels.  PyTorch provides device memory and the stream.  There is no
+CPU fallback: if the library or a GPU is missing, construction raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Dict, Optional
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libglecsim.so")
+
+GE_OK = 0
+GE_ERR_ARG, GE_ERR_OOM, GE_ERR_HIP, GE_ERR_CFL, GE_ERR_NONFINITE, GE_ERR_STATE = -1, -2, -3, -4, -5, -6
+GE_WARN_NOT_CONVERGED = 1
+GE_FP64, GE_FP32 = 0, 1
+GE_A_LIGHT, GE_A_BULK = 0, 1
+GE_PC_NONE, GE_PC_JACOBI = 0, 1
+FIELDS = {
+    "E": 0, "B": 1, "Eth": 2, "Bn": 3, "J_lab": 4, "J_eff": 5, "rho": 6, "mm": 7, "mass": 8, "u": 9,
+    "EM": 10, "Mt": 11, "M0": 12, "kappa_E": 13, "kappa_B": 14, "rhs": 15,
+}
+EXPORTS = [
+    "ge_create", "ge_destroy", "ge_last_error", "ge_add_species", "ge_set_fields", "ge_deposit", "ge_solve_fields",
+    "ge_push", "ge_update_fields", "ge_step", "ge_sync", "ge_gather", "ge_set", "ge_half_stencil",
+    "ge_get_particles", "ge_apply_operator", "ge_diagnostics", "ge_timings",
+]
+
+
+class GEGrid(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("n", ctypes.c_int * 3), ("dx", ctypes.c_double * 3)]
+
+
+class GEParams(ctypes.Structure):
+    _fields_ = [("theta", ctypes.c_double), ("c", ctypes.c_double), ("dt", ctypes.c_double),
+                ("lf_E", ctypes.c_int), ("lf_B", ctypes.c_int), ("beta_lim", ctypes.c_double),
+                ("a_mode", ctypes.c_int), ("a_const", ctypes.c_double), ("comoving", ctypes.c_int),
+                ("n_smooth_u", ctypes.c_int), ("phi_u", ctypes.c_double), ("precision", ctypes.c_int)]
+
+
+class GESpecies(ctypes.Structure):
+    _fields_ = [("q", ctypes.c_double), ("m", ctypes.c_double)]
+
+
+class GESolveReport(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("restarts", ctypes.c_int), ("converged", ctypes.c_int),
+                ("relres", ctypes.c_double), ("bnorm", ctypes.c_double), ("seconds", ctypes.c_double)]
+
+
+class GEDiag(ctypes.Structure):
+    _fields_ = [("W_E", ctypes.c_double), ("W_B", ctypes.c_double), ("K", ctypes.c_double * 4),
+                ("P", (ctypes.c_double * 3) * 4), ("gauss", ctypes.c_double), ("nsp", ctypes.c_int)]
+
+
+class GlecsimError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"glecsim error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libglecsim.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with paper_2506_11320_amd/build.py (no CPU fallback)")
+    L = ctypes.CDLL(path)
+    vp, i64, d = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double
+    L.ge_create.argtypes = [ctypes.POINTER(GEGrid), ctypes.POINTER(GEParams), vp, ctypes.POINTER(vp)]
+    L.ge_destroy.argtypes = [vp]
+    L.ge_destroy.restype = None
+    L.ge_last_error.argtypes = [vp]
+    L.ge_last_error.restype = ctypes.c_char_p
+    L.ge_add_species.argtypes = [vp, ctypes.POINTER(GESpecies), i64, vp, vp, vp, vp]
+    L.ge_set_fields.argtypes = [vp, vp, vp]
+    for name in ["ge_deposit", "ge_push", "ge_update_fields", "ge_sync"]:
+        getattr(L, name).argtypes = [vp]
+    L.ge_solve_fields.argtypes = [vp, d, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(GESolveReport)]
+    L.ge_step.argtypes = [vp, d, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(GESolveReport)]
+    L.ge_gather.argtypes = [vp, ctypes.c_int, vp]
+    L.ge_set.argtypes = [vp, ctypes.c_int, vp]
+    L.ge_half_stencil.argtypes = [vp]
+    L.ge_get_particles.argtypes = [vp, ctypes.c_int, i64, vp, vp, vp, vp]
+    L.ge_apply_operator.argtypes = [vp, vp, vp]
+    L.ge_diagnostics.argtypes = [vp, ctypes.POINTER(GEDiag)]
+    L.ge_timings.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+    _lib = L
+    return L
+
+
+def _ptr(t: torch.Tensor) -> int:
+    assert t.is_cuda and t.is_contiguous(), "device tensors must be contiguous CUDA/HIP tensors"
+    return t.data_ptr()
+
+
+class Simulation:
+    """One GL-ECSIM context on one GPU (see include/glecsim.h)."""
+
+    def __init__(self, dim: int, n, dx, *, theta: float, dt: float, c: float = 1.0, lf_E: bool = True,
+                 lf_B: bool = True, beta_lim: float = 1.0, a_mode: int = GE_A_BULK, a_const: float = 1.0,
+                 comoving: bool = True, n_smooth_u: int = 5, phi_u: float = 0.5, fp32: bool = False,
+                 device: str = "cuda:0", stream: Optional[torch.cuda.Stream] = None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("glecsim needs a GPU (no CPU fallback)")
+        self.L = load_library()
+        self.device = torch.device(device)
+        self.dim = dim
+        self.n = tuple(int(n[d]) if d < dim else 1 for d in range(3))
+        self.N = 1
+        for d in range(dim):
+            self.N *= self.n[d]
+        self.fp32 = fp32
+        self.fdtype = torch.float32 if fp32 else torch.float64
+        g = GEGrid()
+        g.dim = dim
+        for d in range(3):
+            g.n[d] = self.n[d]
+            g.dx[d] = float(dx[d]) if d < dim else 1.0
+        p = GEParams(theta, c, dt, int(lf_E), int(lf_B), beta_lim, a_mode, a_const, int(comoving), n_smooth_u,
+                     phi_u, GE_FP32 if fp32 else GE_FP64)
+        self.params = p
+        with torch.cuda.device(self.device):
+            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        rc = self.L.ge_create(ctypes.byref(g), ctypes.byref(p), ctypes.c_void_p(self.stream.cuda_stream),
+                              ctypes.byref(h))
+        if rc != GE_OK:
+            raise GlecsimError(rc, "ge_create failed (invalid grid/params or out of memory)")
+        self.h = h
+        self.nsp = 0
+        self.counts = []
+
+    # -------------------------------------------------------------- plumbing
+    def _check(self, rc: int, allow_warn: bool = False) -> int:
+        if rc < 0 or (rc > 0 and not allow_warn):
+            raise GlecsimError(rc, self.L.ge_last_error(self.h).decode())
+        return rc
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.ge_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -------------------------------------------------------------- setup
+    def add_species(self, q: float, m: float, cell: torch.Tensor, off: torch.Tensor, v: torch.Tensor,
+                    w: torch.Tensor):
+        n = int(cell.numel())
+        assert cell.dtype == torch.int32 and off.dtype == self.fdtype and v.dtype == self.fdtype
+        assert off.shape == (3, n) and v.shape == (3, n) and w.shape == (n,)
+        sp = GESpecies(q, m)
+        self._check(self.L.ge_add_species(self.h, ctypes.byref(sp), n, _ptr(cell), _ptr(off), _ptr(v), _ptr(w)))
+        self.nsp += 1
+        self.counts.append(n)
+
+    def set_fields(self, E: torch.Tensor, B: torch.Tensor):
+        assert E.dtype == torch.float64 and E.shape == (3, self.N) and B.shape == (3, self.N)
+        self._check(self.L.ge_set_fields(self.h, _ptr(E), _ptr(B)))
+
+    # -------------------------------------------------------------- step
+    def deposit(self):
+        self._check(self.L.ge_deposit(self.h))
+
+    def solve(self, tol: float = 1e-8, maxit: int = 1000, restart: int = 30, precond: int = GE_PC_NONE) -> Dict:
+        r = GESolveReport()
+        rc = self._check(self.L.ge_solve_fields(self.h, tol, maxit, restart, precond, ctypes.byref(r)), True)
+        return {"iterations": r.iterations, "restarts": r.restarts, "converged": bool(r.converged),
+                "relres": r.relres, "bnorm": r.bnorm, "seconds": r.seconds, "rc": rc}
+
+    def push(self):
+        self._check(self.L.ge_push(self.h))
+
+    def update_fields(self):
+        self._check(self.L.ge_update_fields(self.h))
+
+    def step(self, tol: float = 1e-8, maxit: int = 1000, restart: int = 30, precond: int = GE_PC_NONE) -> Dict:
+        r = GESolveReport()
+        rc = self._check(self.L.ge_step(self.h, tol, maxit, restart, precond, ctypes.byref(r)), True)
+        return {"iterations": r.iterations, "converged": bool(r.converged), "relres": r.relres, "rc": rc,
+                "seconds": r.seconds}
+
+    def sync(self):
+        self._check(self.L.ge_sync(self.h))
+
+    # -------------------------------------------------------------- data
+    def half_stencil(self) -> int:
+        return int(self.L.ge_half_stencil(self.h))
+
+    def field_shape(self, what: str):
+        N = self.N
+        if what in ("rho",):
+            return (self.nsp, N)
+        if what == "mass":
+            return (N,)
+        if what in ("Mt", "M0"):
+            return (self.half_stencil(), 9, N)
+        if what in ("kappa_E", "kappa_B"):
+            return (3, 3, N)
+        return (3, N)
+
+    def gather(self, what: str) -> torch.Tensor:
+        out = torch.empty(self.field_shape(what), dtype=torch.float64, device=self.device)
+        self._check(self.L.ge_gather(self.h, FIELDS[what], _ptr(out)))
+        return out
+
+    def set(self, what: str, src: torch.Tensor):
+        src = src.to(device=self.device, dtype=torch.float64).contiguous()
+        assert tuple(src.shape) == self.field_shape(what)
+        self._check(self.L.ge_set(self.h, FIELDS[what], _ptr(src)))
+        self._keep = src  # keep alive until the stream has copied it
+
+    def particles(self, s: int) -> Dict[str, torch.Tensor]:
+        n = self.counts[s]
+        cell = torch.empty(n, dtype=torch.int32, device=self.device)
+        off = torch.empty((3, n), dtype=self.fdtype, device=self.device)
+        v = torch.empty((3, n), dtype=self.fdtype, device=self.device)
+        w = torch.empty(n, dtype=self.fdtype, device=self.device)
+        self._check(self.L.ge_get_particles(self.h, s, n, _ptr(cell), _ptr(off), _ptr(v), _ptr(w)))
+        return {"cell": cell, "off": off, "v": v, "w": w}
+
+    def apply_operator(self, x: torch.Tensor) -> torch.Tensor:
+        x = x.to(device=self.device, dtype=torch.float64).contiguous()
+        y = torch.empty_like(x)
+        self._check(self.L.ge_apply_operator(self.h, _ptr(x), _ptr(y)))
+        return y
+
+    def diagnostics(self) -> Dict:
+        dg = GEDiag()
+        self._check(self.L.ge_diagnostics(self.h, ctypes.byref(dg)))
+        return {"W_E": dg.W_E, "W_B": dg.W_B, "K": [dg.K[s] for s in range(self.nsp)],
+                "P": [[dg.P[s][d] for d in range(3)] for s in range(self.nsp)], "gauss": dg.gauss}
+
+    def timings(self):
+        out = (ctypes.c_double * 8)()
+        self._check(self.L.ge_timings(self.h, out))
+        return list(out)
