@@ -1,0 +1,194 @@
+#!/usr/bin/env python3
+"""Benchmark of the GL-ECSIM step on one MI355X.
+
+One step = the whole hot path on one batch of synthetic particles already
+resident in HBM: deposit (mass matrices, current, moments) -> grid pass
+(node assembly, smoothed bulk velocity, comoving current, limited LF
+coefficients, RHS) -> FP64 GMRES solve to 1e-8 -> field update -> implicit push
+with stable re-binning.  Prints one JSON line.
+
+Workload (default): the 3D3V reconnection case at HBM scale (256x128x128
+cells, 64 macro-particles per cell per species, m_i/m_e = 100, double Harris
+sheet with a 0.2c guide flow), FP32 particle path, FP64 field solve.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "particle-steps/s (push+deposit); GMRES s/step plain vs NN-precond at 1e-8"
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(wl, nsp, counts):
+    """Compulsory HBM bytes of one launch of the particle kernels (FP32, 3D):
+    deposit: particle state read once (28 B), the run table of each species
+    (27 x 8 B per cell), node-averaged B (12 B per node) and the per-cell sums
+    written once (558 x 4 B per cell with two species);
+    push (per species): particle state read and written once (2 x 28 B), run
+    table read and written (2 x 27 x 8 B per cell), segment offsets (4 B per
+    cell), E and B at nodes (24 B per node)."""
+    N = wl.ncells
+    nd = 3 ** wl.dim
+    nc = 2 ** wl.dim
+    es = 4 if wl.fp32 else 8
+    per_p = (wl.dim + 3 + 1) * es
+    q_used = 18 * nd + nc * (7 + nsp)
+    dep = sum(counts) * per_p + N * (nsp * nd * 8 + 3 * es + q_used * es)
+    push = sum(c * 2 * per_p for c in counts) + nsp * N * (2 * nd * 8 + 4 + 6 * es)
+    return {"deposit": dep, "push": push}
+
+
+def cpu_baseline(wl, box=32):
+    """The FP64 oracle, as it stands, timed on a bounded sample of the same
+    workload: one full step of a periodic box^3-cell sub-box built with the
+    same recipe (ppc, dx, dt, species)."""
+    import oracle as O
+    import synth
+    sub = synth.small("cpu_sample", dim=3, n=(box, box, box), ppc=wl.ppc, base="c5")
+    G = O.grid(3, sub.n, sub.dx)
+    E, B = synth.fields(sub)
+    sp = []
+    for s in range(sub.nsp):
+        p = synth.particles(sub, s, f32=True)
+        sp.append(O.Species(sub.q[s], sub.m[s], O.global_positions(G, p["cell"], p["off"].astype(np.float64)),
+                            p["v"].astype(np.float64).T, p["w"].astype(np.float64)))
+    npart = sum(s.w.size for s in sp)
+    t0 = time.perf_counter()
+    O.step(G, sp, E, B, dt=sub.dt, theta=sub.theta, comoving=True, lf_E=True, lf_B=True, beta_lim=sub.beta_lim,
+           a_mode=sub.a_mode, tol=1e-8, restart=30)
+    dt = time.perf_counter() - t0
+    return {"value": npart / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"1 full step (deposit, comoving current, GMRES to 1e-8, B/E update, push) of a "
+                      f"{box}^3-cell periodic sub-box with the same recipe ({npart} particles), "
+                      f"single-threaded FP64 C oracle, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="c5")
+    ap.add_argument("--precond", default="none", choices=["none", "jacobi"])
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--compare-precond", action="store_true", help="also time a Jacobi-preconditioned solve")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: this build has no multi-GPU path (got --gpus {args.gpus}); "
+              "the sharding design is described in DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    from paper_2506_11320_amd import Simulation
+
+    wl = synth.workloads()[args.workload]
+    log(f"workload {wl.name}: cells {wl.n[:wl.dim]}, ppc {wl.ppc}, species {wl.nsp}")
+    sim = Simulation(wl.dim, wl.n, wl.dx, theta=wl.theta, dt=wl.dt, lf_E=wl.lf_E, lf_B=wl.lf_B,
+                     beta_lim=wl.beta_lim, a_mode=wl.a_mode, comoving=wl.comoving, n_smooth_u=wl.n_smooth_u,
+                     fp32=wl.fp32)
+    counts = []
+    t0 = time.perf_counter()
+    for s in range(wl.nsp):
+        p = synth.particles(wl, s, f32=wl.fp32)
+        t = {k: torch.from_numpy(v).cuda() for k, v in p.items()}
+        del p
+        sim.add_species(wl.q[s], wl.m[s], t["cell"], t["off"], t["v"], t["w"])
+        counts.append(int(t["cell"].numel()))
+        del t
+        torch.cuda.synchronize()
+        log(f"species {s} loaded ({counts[-1]} particles)")
+    E, B = synth.fields(wl)
+    sim.set_fields(torch.from_numpy(E).cuda(), torch.from_numpy(B).cuda())
+    torch.cuda.synchronize()
+    log(f"setup {time.perf_counter() - t0:.1f} s")
+    pc = {"none": 0, "jacobi": 1}[args.precond]
+    for k in range(args.warmup):
+        r = sim.step(tol=args.tol, maxit=500, restart=30, precond=pc)
+        log(f"warmup step {k}: {r['iterations']} GMRES iterations, relres {r['relres']:.2e}")
+    sim.timings()  # reset the per-phase accumulators
+    iters = []
+    solve_s = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        r = sim.step(tol=args.tol, maxit=500, restart=30, precond=pc)
+        iters.append(r["iterations"])
+        solve_s.append(r["seconds"])
+        if not r["converged"]:
+            log(f"step {k}: GMRES did not converge (relres {r['relres']:.2e})")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    tm = sim.timings()
+    log(f"timed {args.steps} steps in {elapsed:.3f} s")
+    npart = sum(counts)
+    ms_step = elapsed / args.steps * 1e3
+    phase = {"push_rebin": tm[0] * 1e3, "deposit": tm[1] * 1e3, "assemble": tm[2] * 1e3, "grid_rest": tm[3] * 1e3,
+             "update": tm[4] * 1e3, "solve": tm[5] * 1e3}
+    pd_s = tm[0] + tm[1]
+    ab = algorithmic_bytes(wl, wl.nsp, counts)
+    dom = "deposit" if tm[1] >= tm[0] else "push"
+    dom_t = tm[1] if dom == "deposit" else tm[0]
+    achieved = ab[dom] / dom_t / 1e9
+    roof = {"bound": "hbm", "kernel": "k_deposit<float,3>" if dom == "deposit" else "k_push<float,3> (x2 species)",
+            "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "algorithmic_bytes_per_launch": ab[dom], "launch_ms": round(dom_t * 1e3, 4)}
+    precond_cmp = None
+    if args.compare_precond:
+        pcs = {}
+        for name, code in [("plain", 0), ("jacobi", 1)]:
+            sim.deposit()
+            rep = sim.solve(tol=args.tol, maxit=500, restart=30, precond=code)
+            pcs[name] = {"seconds": rep["seconds"], "iterations": rep["iterations"]}
+        precond_cmp = pcs
+    out = {
+        "metric": METRIC,
+        "value": npart * args.steps / elapsed,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if wl.fp32 else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{wl.name}: 3D3V double-Harris reconnection, {wl.n[0]}x{wl.n[1]}x{wl.n[2]} cells, "
+                               f"{wl.ppc} ppc/species, m_i/m_e={wl.m[1]:g}, guide flow {wl.u0[0]}c, "
+                               f"FP32 push/deposit, FP64 GMRES to {args.tol:g}, comoving current, limited LF",
+                   "cells": wl.ncells, "particles": npart, "precond": args.precond},
+        "push_deposit_particle_steps_per_s": npart / pd_s,
+        "gmres_s_per_step": {"plain" if pc == 0 else args.precond: float(np.mean(solve_s)), "nn": None},
+        "gmres_iterations": float(np.mean(iters)),
+        "phase_ms": {k: round(v, 3) for k, v in phase.items()},
+        "precond_compare": precond_cmp,
+        "roofline": roof,
+    }
+    sim.close()
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a sample")
+        out["cpu_baseline"] = cpu_baseline(wl)
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

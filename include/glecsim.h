@@ -215,8 +215,13 @@ int ge_apply_operator(ge_ctx* ctx, const double* x, double* y);
 /* FP64 energies, momenta and Gauss residual (host struct).  Synchronises. */
 int ge_diagnostics(ge_ctx* ctx, ge_diag* out);
 
-/* Seconds spent in each phase since the last call (device events), host
- * array of 8: sort-and-push, deposit, grid pass, solve, update, diag, 0, 0. */
+/* Mean seconds per ge_step() since the last call, from HIP events recorded on
+ * the context's stream around each kernel group; host array of 8:
+ *   [0] push + re-binning kernels (all species)   [1] deposit kernel
+ *   [2] node assembly kernel                      [3] rest of the grid pass
+ *   [4] field update kernels                      [5] solve (host wall time)
+ *   [6] 0                                         [7] number of steps averaged
+ * The accumulators are reset by the call. */
 int ge_timings(ge_ctx* ctx, double* out8);
 
 #ifdef __cplusplus

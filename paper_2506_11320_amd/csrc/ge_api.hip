@@ -41,7 +41,15 @@ int check_flags(ge_ctx* c) {
   return GE_OK;
 }
 
-void ev_begin(ge_ctx* c, int k) { (void)hipEventRecord(c->ev[2 * (k % 4)], c->stream); }
+// add the elapsed time of the event pairs of the last step (stream idle)
+void accumulate_timings(ge_ctx* c, double solve_s) {
+  float ms;
+  for (int k = 0; k < 5; ++k)
+    if (hipEventElapsedTime(&ms, c->ev[2 * k], c->ev[2 * k + 1]) == hipSuccess) c->tsum[k] += ms * 1e-3;
+  (void)hipGetLastError();
+  c->tsum[5] += solve_s;
+  c->tcnt += 1;
+}
 
 }  // namespace
 
@@ -116,7 +124,7 @@ int ge_create(const ge_grid* grid, const ge_params* params, void* hip_stream, ge
   if (!rc) rc = dalloc(c, &c->Mt, es * c->nh * 9 * N);
   if (!rc) rc = dalloc(c, &c->M0, es * c->nh * 9 * N);
   if (!rc) rc = dalloc(c, &c->cellQ, es * (size_t)c->Q * N);
-  if (!rc) rc = dalloc(c, &c->seg_next, sizeof(int32_t) * N);
+  if (!rc) rc = dalloc(c, &c->seg_next, sizeof(int32_t) * GE_MAX_SPECIES * N);
   c->scan_nblocks = (N + 1023) / 1024;
   if (!rc) rc = dalloc(c, &c->scan_blocks, sizeof(int32_t) * (c->scan_nblocks + 1));
   if (!rc) rc = dalloc(c, &c->V, sizeof(double) * 3 * N * (c->kr_m + 1));
@@ -134,10 +142,9 @@ int ge_create(const ge_grid* grid, const ge_params* params, void* hip_stream, ge
   (void)hipMemsetAsync(c->kB, 0, sizeof(double) * 9 * N, s);
   (void)hipMemsetAsync(c->rho, 0, sizeof(double) * GE_MAX_SPECIES * N, s);
   (void)hipMemsetAsync(c->flags, 0, sizeof(int) * 4, s);
-  for (int k = 0; k < 8; ++k) {
-    (void)hipEventCreate(&c->ev[k]);
-    c->tsum[k] = 0;
-  }
+  for (int k = 0; k < 10; ++k) (void)hipEventCreate(&c->ev[k]);
+  for (int k = 0; k < 8; ++k) c->tsum[k] = 0;
+  c->tcnt = 0;
   if (hipGetLastError() != hipSuccess) {
     ge_destroy(c);
     return GE_ERR_HIP;
@@ -169,7 +176,7 @@ void ge_destroy(ge_ctx* c) {
       dfree(c->sp[s].sub_start[b]);
       dfree(c->sp[s].sub_cnt[b]);
     }
-  for (int k = 0; k < 8; ++k)
+  for (int k = 0; k < 10; ++k)
     if (c->ev[k]) (void)hipEventDestroy(c->ev[k]);
   delete c;
 }
@@ -231,13 +238,12 @@ int ge_deposit(ge_ctx* c) {
   if (!c) return GE_ERR_ARG;
   if (c->nsp == 0) return ge_fail(c, GE_ERR_STATE, "no species");
   int rc;
-  (void)hipEventRecord(c->ev[2], c->stream);
   if ((rc = ge_launch_node_avg(c))) return rc;
+  (void)hipEventRecord(c->ev[2], c->stream);
   if ((rc = ge_launch_deposit(c))) return rc;
   (void)hipEventRecord(c->ev[3], c->stream);
   c->have_deposit = 1;
   if ((rc = ge_launch_grid_pass(c))) return rc;
-  (void)hipEventRecord(c->ev[4], c->stream);
   c->have_solve = 0;
   return GE_OK;
 }
@@ -258,9 +264,11 @@ int ge_push(ge_ctx* c) {
   if (!c) return GE_ERR_ARG;
   if (!c->have_solve) return ge_fail(c, GE_ERR_STATE, "ge_push needs E^{n+theta} (solve or ge_set GE_F_ETH)");
   int rc;
-  (void)hipEventRecord(c->ev[0], c->stream);
   if (c->P.precision == GE_FP32)
     if ((rc = ge_launch_to_f32(c, c->Eth, c->Eth32, 3 * c->G.N))) return rc;
+  for (int s = 0; s < c->nsp; ++s)
+    if ((rc = ge_launch_scan_counts(c, s))) return rc;
+  (void)hipEventRecord(c->ev[0], c->stream);
   for (int s = 0; s < c->nsp; ++s)
     if ((rc = ge_launch_push(c, s))) return rc;
   (void)hipEventRecord(c->ev[1], c->stream);
@@ -280,11 +288,15 @@ int ge_update_fields(ge_ctx* c) {
 int ge_step(ge_ctx* c, double tol, int maxit, int restart, int precond, ge_solve_report* rep) {
   int rc = ge_deposit(c);
   if (rc) return rc;
-  int sr = ge_solve_fields(c, tol, maxit, restart, precond, rep);
+  ge_solve_report r;
+  std::memset(&r, 0, sizeof(r));
+  int sr = ge_solve_fields(c, tol, maxit, restart, precond, &r);
   if (sr < 0) return sr;
+  if (rep) *rep = r;
   if ((rc = ge_push(c))) return rc;
   if ((rc = ge_update_fields(c))) return rc;
   rc = check_flags(c);
+  if (!rc) accumulate_timings(c, r.seconds);
   return rc ? rc : sr;
 }
 
@@ -373,13 +385,10 @@ int ge_diagnostics(ge_ctx* c, ge_diag* out) {
 
 int ge_timings(ge_ctx* c, double* out8) {
   if (!c || !out8) return GE_ERR_ARG;
-  GE_HIP(c, hipStreamSynchronize(c->stream));
-  float ms = 0;
-  for (int k = 0; k < 8; ++k) out8[k] = 0;
-  if (hipEventElapsedTime(&ms, c->ev[0], c->ev[1]) == hipSuccess) out8[0] = ms * 1e-3;
-  if (hipEventElapsedTime(&ms, c->ev[2], c->ev[3]) == hipSuccess) out8[1] = ms * 1e-3;
-  if (hipEventElapsedTime(&ms, c->ev[3], c->ev[4]) == hipSuccess) out8[2] = ms * 1e-3;
-  (void)hipGetLastError();
+  for (int k = 0; k < 8; ++k) out8[k] = c->tcnt ? c->tsum[k] / c->tcnt : 0.0;
+  out8[7] = c->tcnt;
+  for (int k = 0; k < 8; ++k) c->tsum[k] = 0;
+  c->tcnt = 0;
   return GE_OK;
 }
 

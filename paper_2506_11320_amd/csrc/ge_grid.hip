@@ -480,8 +480,11 @@ static void comoving_t(ge_ctx* c) {
 int ge_launch_grid_pass(ge_ctx* c) {
   const DGrid& G = c->G;
   const int64_t N = G.N;
+  (void)hipEventRecord(c->ev[4], c->stream);
   DISPATCH_TD(c, assemble_t);
   GE_HIP(c, hipGetLastError());
+  (void)hipEventRecord(c->ev[5], c->stream);
+  (void)hipEventRecord(c->ev[6], c->stream);
   hipLaunchKernelGGL(k_bulk_u, grid1(N), dim3(256), 0, c->stream, N, c->mm, c->mass, c->u);
   // filter passes: strides 1, 2, 1, 2, ...; each pass sweeps x, then y, then z
   for (int k = 0; k < c->P.n_smooth_u; ++k)
@@ -502,6 +505,7 @@ int ge_launch_grid_pass(ge_ctx* c) {
   const double ctd = c->P.c * c->P.theta * c->P.dt, ftd = 4.0 * M_PI * c->P.theta * c->P.dt;
   DISPATCH_DIM(c, k_rhs, grid1(N), dim3(256), 0, c->stream, G, c->E, c->B, c->Jeff, ctd, ftd, c->rhs);
   GE_HIP(c, hipGetLastError());
+  (void)hipEventRecord(c->ev[7], c->stream);
   return GE_OK;
 }
 
@@ -529,12 +533,14 @@ int ge_launch_apply_A(ge_ctx* c, const double* x, double* y) {
 
 int ge_launch_update(ge_ctx* c) {
   const int64_t N = c->G.N;
+  (void)hipEventRecord(c->ev[8], c->stream);
   DISPATCH_DIM(c, k_curl_nc, grid1(N), dim3(256), 0, c->stream, c->G, c->Eth, c->ccell);
   DISPATCH_DIM(c, k_update_B, grid1(N), dim3(256), 0, c->stream, c->G, c->B, c->ccell, c->P.lf_B ? c->kB : nullptr,
                c->P.c * c->P.dt, c->P.dt, c->Bnew);
   std::swap(c->B, c->Bnew);
   hipLaunchKernelGGL(k_update_E, grid1(3 * N), dim3(256), 0, c->stream, 3 * N, c->P.theta, c->Eth, c->E);
   GE_HIP(c, hipGetLastError());
+  (void)hipEventRecord(c->ev[9], c->stream);
   return GE_OK;
 }
 

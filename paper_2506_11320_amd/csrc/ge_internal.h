@@ -90,7 +90,7 @@ struct ge_ctx {
   // Jacobi blocks (double [9][N], inverted 3x3 per node)
   double* jac;
   // sort scratch
-  int32_t *seg_next, *scan_blocks;
+  int32_t *seg_next, *scan_blocks;  // seg_next: [GE_MAX_SPECIES][N]
   int64_t scan_nblocks;
   // Krylov workspace
   int kr_m;
@@ -98,8 +98,9 @@ struct ge_ctx {
   int64_t nred_blocks;
   int* flags;            // [0] CFL clamp, [1] run overflow, [2] load error
   int have_deposit, have_solve;
-  hipEvent_t ev[8];
-  double tsum[8];
+  hipEvent_t ev[10];   // pairs: push, deposit, assemble, grid rest, update
+  double tsum[8];      // accumulated per-phase seconds (see ge_timings)
+  int tcnt;
 };
 
 // error helpers
@@ -112,8 +113,8 @@ int ge_fail(ge_ctx* c, int code, const std::string& msg);
 
 // launchers (host side), each returns GE_OK or an error via ge_fail
 int ge_launch_load_species(ge_ctx* c, int s, const int32_t* cell, const void* off, const void* v, const void* w);
-int ge_launch_scan_counts(ge_ctx* c, int s);
-int ge_launch_push(ge_ctx* c, int s);
+int ge_launch_scan_counts(ge_ctx* c, int s);  // into seg_next + s*N
+int ge_launch_push(ge_ctx* c, int s);          // needs ge_launch_scan_counts(c, s) first
 int ge_launch_deposit(ge_ctx* c);
 int ge_launch_get_particles(ge_ctx* c, int s, int32_t* cell, void* off, void* v, void* w);
 int ge_launch_particle_moments(ge_ctx* c, int s, double* out4);  // K, P[3] (sync)

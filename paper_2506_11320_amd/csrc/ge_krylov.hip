@@ -116,6 +116,8 @@ static int precond_apply(ge_ctx* c, int precond, const double* x, double* y, int
 }
 
 int ge_gmres(ge_ctx* c, double tol, int maxit, int m, int precond, ge_solve_report* rep) {
+  // the solve's own wall time starts once the queued deposit work is done
+  GE_HIP(c, hipStreamSynchronize(c->stream));
   auto t0 = std::chrono::steady_clock::now();
   const int64_t n = 3 * c->G.N;
   if (m < 1 || m > c->kr_m) return ge_fail(c, GE_ERR_ARG, "restart out of range (1.." + std::to_string(c->kr_m) + ")");

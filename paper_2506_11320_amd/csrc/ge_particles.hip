@@ -641,7 +641,7 @@ int ge_launch_scan_counts(ge_ctx* c, int s) {
   SpeciesBuf& S = c->sp[s];
   const int64_t N = c->G.N;
   dim3 gb((N + 255) / 256);
-  int32_t* cnt = c->seg_next;  // counts first, scanned in place via a temp
+  int32_t* cnt = c->seg_next + (int64_t)s * N;  // counts, then scanned in place
   switch (c->G.dim) {
     case 1: hipLaunchKernelGGL(k_count<1>, gb, dim3(256), 0, c->stream, c->G, S.sub_cnt[S.cur], cnt); break;
     case 2: hipLaunchKernelGGL(k_count<2>, gb, dim3(256), 0, c->stream, c->G, S.sub_cnt[S.cur], cnt); break;
@@ -658,7 +658,7 @@ static void launch_push_t(ge_ctx* c, int s) {
   const int cur = S.cur, nxt = 1 - S.cur;
   A.off = (const T*)S.off[cur]; A.v = (const T*)S.v[cur]; A.w = (const T*)S.w[cur];
   A.off_o = (T*)S.off[nxt]; A.v_o = (T*)S.v[nxt]; A.w_o = (T*)S.w[nxt];
-  A.sub_start = S.sub_start[cur]; A.sub_cnt = S.sub_cnt[cur]; A.seg_next = c->seg_next;
+  A.sub_start = S.sub_start[cur]; A.sub_cnt = S.sub_cnt[cur]; A.seg_next = c->seg_next + (int64_t)s * c->G.N;
   A.sub_start_o = S.sub_start[nxt]; A.sub_cnt_o = S.sub_cnt[nxt];
   if (sizeof(T) == 4) { A.E = (const T*)c->Eth32; A.B = (const T*)c->Bn32; }
   else { A.E = (const T*)c->Eth; A.B = (const T*)c->Bn; }
@@ -671,8 +671,6 @@ static void launch_push_t(ge_ctx* c, int s) {
 }
 
 int ge_launch_push(ge_ctx* c, int s) {
-  int rc = ge_launch_scan_counts(c, s);
-  if (rc) return rc;
   const bool f32 = c->P.precision == GE_FP32;
   switch (c->G.dim * 2 + (f32 ? 1 : 0)) {
     case 2: launch_push_t<double, 1>(c, s); break;
@@ -751,7 +749,7 @@ static void launch_get_t(ge_ctx* c, int s, int32_t* cell, void* off, void* v, vo
   SpeciesBuf& S = c->sp[s];
   hipLaunchKernelGGL((k_get_particles<T, DIM>), dim3((c->G.N + 3) / 4), dim3(256), 0, c->stream, c->G,
                      (const T*)S.off[S.cur], (const T*)S.v[S.cur], (const T*)S.w[S.cur], S.sub_start[S.cur],
-                     S.sub_cnt[S.cur], c->seg_next, S.n, cell, (T*)off, (T*)v, (T*)w);
+                     S.sub_cnt[S.cur], c->seg_next + (int64_t)s * c->G.N, S.n, cell, (T*)off, (T*)v, (T*)w);
 }
 
 int ge_launch_get_particles(ge_ctx* c, int s, int32_t* cell, void* off, void* v, void* w) {

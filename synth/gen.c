@@ -12,8 +12,10 @@
  * (SC'11), written from its published definition.  Each particle is keyed by
  * (seed, stream) and counted by (cell, k, species, call), so any cell's
  * particles can be regenerated alone, in any order and on any thread.
- * Normal deviates: the Box-Muller transform, truncated at |n| <= NCLIP so
- * that no particle starts faster than the time step allows.
+ * Normal deviates: the Box-Muller transform; the thermal velocity vector is
+ * truncated at |n| <= RCLIP (its length, so that gyration cannot rotate a
+ * clipped tail into a faster component) so that no particle starts faster
+ * than the time step allows.
  */
 #include <math.h>
 #include <stdint.h>
@@ -23,7 +25,7 @@
 #define PHILOX_M1 0xCD9E8D57u
 #define PHILOX_W0 0x9E3779B9u
 #define PHILOX_W1 0xBB67AE85u
-#define NCLIP 5.0
+#define RCLIP 4.5
 #define TWO_PI 6.283185307179586476925286766559
 
 void synth_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t out[4]) {
@@ -116,10 +118,8 @@ static void normals4(const uint32_t r[4], double nout[4]) {
   for (int j = 0; j < 2; ++j) {
     double a = u01(r[2 * j]), b = u01(r[2 * j + 1]);
     double rad = sqrt(-2.0 * log(a));
-    double n0 = rad * cos(TWO_PI * b), n1 = rad * sin(TWO_PI * b);
-    if (n0 > NCLIP) n0 = NCLIP; if (n0 < -NCLIP) n0 = -NCLIP;
-    if (n1 > NCLIP) n1 = NCLIP; if (n1 < -NCLIP) n1 = -NCLIP;
-    nout[2 * j] = n0; nout[2 * j + 1] = n1;
+    nout[2 * j] = rad * cos(TWO_PI * b);
+    nout[2 * j + 1] = rad * sin(TWO_PI * b);
   }
 }
 
@@ -161,6 +161,11 @@ int64_t synth_particles(const synth_cfg* c, int s, int64_t cb, int64_t ce, int32
       }
       double u[3]; drift(c, s, x, u01(ra[3]), u);
       double nn[4]; normals4(rv, nn);
+      double r2 = nn[0] * nn[0] + nn[1] * nn[1] + nn[2] * nn[2];
+      if (r2 > RCLIP * RCLIP) {
+        double sc = RCLIP / sqrt(r2);
+        nn[0] *= sc; nn[1] *= sc; nn[2] *= sc;
+      }
       double vv[3];
       for (int d = 0; d < 3; ++d) vv[d] = u[d] + c->vth[s] * nn[d];
       double ww = synth_density(c, x) * dV / c->ppc;
