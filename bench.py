@@ -87,6 +87,8 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--compare-precond", action="store_true", help="also time a Jacobi-preconditioned solve")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain device copy of 4 GiB (reference for the HBM byte counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: this build has no multi-GPU path (got --gpus {args.gpus}); "
@@ -96,6 +98,14 @@ def main():
     import torch
     import synth
     from paper_2506_11320_amd import Simulation
+
+    if args.copy_probe:
+        a = torch.ones(1 << 29, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": a.numel() * 8, "copy_probe_bytes_written": b.numel() * 8}))
+        return
 
     wl = synth.workloads()[args.workload]
     log(f"workload {wl.name}: cells {wl.n[:wl.dim]}, ppc {wl.ppc}, species {wl.nsp}")

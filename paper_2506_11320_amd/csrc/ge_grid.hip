@@ -3,6 +3,7 @@
 // comoving current, limited Lax-Friedrichs coefficients, right-hand side, the
 // implicit E operator and the field updates.  Fields are FP64, [comp][N].
 #include <cmath>
+#include <cstring>
 
 #include "ge_internal.h"
 
@@ -35,49 +36,59 @@ __global__ void k_node_avg(DGrid G, const double* __restrict__ B, double* __rest
 
 // ----------------------------------------------------------------- assembly
 // Sum the per-cell quadratic-row sums into the node-pair half stencil and the
-// per-cell corner sums into nodes, in a fixed order (deterministic).
+// per-cell corner sums into nodes, in a fixed order (deterministic).  Node g
+// and g + o are corners a and a + o of the cells g - a; that pair's weight
+// product is quadratic row (2 a_d + o_d) along each axis d.
 template <typename T, int DIM>
-__global__ __launch_bounds__(256) void k_assemble(DGrid G, const T* __restrict__ Q, int nsp, int nh, T* __restrict__ Mt,
+__global__ __launch_bounds__(256) void k_assemble(DGrid G, const T* __restrict__ Q, int Qn, int nsp, T* __restrict__ Mt,
                                                   T* __restrict__ M0, double* __restrict__ Jlab, double* __restrict__ mm,
                                                   double* __restrict__ mass, double* __restrict__ rho) {
   constexpr int NC = Gd<DIM>::NC, NR = Gd<DIM>::NR;
-  int64_t g = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  using HS = HalfStencil<DIM>;
+  const int64_t g = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (g >= G.N) return;
   const int64_t N = G.N;
-  int64_t cells[8];
+  int gi, gj, gk;
+  unflat3(G, g, gi, gj, gk);
+  int64_t cells[NC];
+#pragma unroll
   for (int a = 0; a < NC; ++a)
-    cells[a] = nbr3(G, g, -ax_bit(a, 0), DIM >= 2 ? -ax_bit(a, 1) : 0, DIM >= 3 ? -ax_bit(a, 2) : 0);
-  for (int h = 0; h < nh; ++h) {
-    int o[3];
-    half_offset(DIM, h, o);
-    int rows[8], use[8];
+    cells[a] = flat3(G, gi - ax_bit(a, 0), gj - (DIM >= 2 ? ax_bit(a, 1) : 0), gk - (DIM >= 3 ? ax_bit(a, 2) : 0));
+#pragma unroll
+  for (int h = 0; h < HS::NH; ++h) {
+    double smt[9], sm0[9];
+#pragma unroll
+    for (int e = 0; e < 9; ++e) smt[e] = sm0[e] = 0.0;
+#pragma unroll
     for (int a = 0; a < NC; ++a) {
-      int ok = 1, r = 0, mul = 1;
+      bool ok = true;
+      int r = 0, mul = 1;
+#pragma unroll
       for (int d = 0; d < DIM; ++d) {
-        int b = ax_bit(a, d) + o[d];
-        if (b < 0 || b > 1) ok = 0;
-        r += (2 * ax_bit(a, d) + o[d]) * mul;
+        const int bd = ax_bit(a, d) + HS::o[h][d];
+        ok = ok && bd >= 0 && bd <= 1;
+        r += (2 * ax_bit(a, d) + HS::o[h][d]) * mul;
         mul *= 3;
       }
-      use[a] = ok;
-      rows[a] = r;
-    }
-    for (int e = 0; e < 9; ++e) {
-      double smt = 0, sm0 = 0;
-      for (int a = 0; a < NC; ++a) {
-        if (!use[a]) continue;
-        smt += (double)Q[(int64_t)(rows[a] * 9 + e) * N + cells[a]];
-        sm0 += (double)Q[(int64_t)(9 * NR + rows[a] * 9 + e) * N + cells[a]];
+      if (!ok) continue;
+#pragma unroll
+      for (int e = 0; e < 9; ++e) {
+        smt[e] += (double)Q[cq_index(cells[a], r * 9 + e, Qn)];
+        sm0[e] += (double)Q[cq_index(cells[a], 9 * NR + r * 9 + e, Qn)];
       }
-      Mt[(int64_t)(h * 9 + e) * N + g] = (T)smt;
-      M0[(int64_t)(h * 9 + e) * N + g] = (T)sm0;
+    }
+#pragma unroll
+    for (int e = 0; e < 9; ++e) {
+      Mt[(int64_t)(h * 9 + e) * N + g] = (T)smt[e];
+      M0[(int64_t)(h * 9 + e) * N + g] = (T)sm0[e];
     }
   }
   const double idV = 1.0 / G.dV;
   const int NK = 7 + nsp;
   for (int k = 0; k < NK; ++k) {
     double s = 0;
-    for (int a = 0; a < NC; ++a) s += (double)Q[(int64_t)(18 * NR + k * NC + a) * N + cells[a]];
+#pragma unroll
+    for (int a = 0; a < NC; ++a) s += (double)Q[cq_index(cells[a], 18 * NR + k * NC + a, Qn)];
     if (k < 3) Jlab[k * N + g] = s * idV;
     else if (k < 6) mm[(k - 3) * N + g] = s;
     else if (k == 6) mass[g] = s;
@@ -119,26 +130,27 @@ __global__ void k_motional(int64_t N, const double* __restrict__ u, const double
   anode[g] = a_mode == GE_A_LIGHT ? a_const : sqrt(ux * ux + uy * uy + uz * uz);
 }
 
-// y_g = sum over the 3^DIM neighbours g' of M_{g,g'} x_{g'}, half stencil.
+// y_g = sum over the 3^DIM neighbours g' of M_{g,g'} x_{g'}, half stencil:
+// the stored block at g serves offset +o, the block stored at g - o serves -o.
 template <typename T, int DIM>
 __device__ inline void apply_half(const DGrid& G, const T* __restrict__ M, const double* __restrict__ x, int64_t g,
-                                  int nh, double y[3]) {
+                                  double y[3]) {
+  using HS = HalfStencil<DIM>;
   const int64_t N = G.N;
   y[0] = y[1] = y[2] = 0;
   int gx, gy, gz;
   unflat3(G, g, gx, gy, gz);
-  for (int h = 0; h < nh; ++h) {
-    int o[3];
-    half_offset(DIM, h, o);
-    const int64_t gp = flat3(G, gx + o[0], gy + o[1], gz + o[2]);
-    double xp[3] = {x[gp], x[N + gp], x[2 * N + gp]};
+#pragma unroll
+  for (int h = 0; h < HS::NH; ++h) {
+    const int64_t gp = flat3(G, gx + HS::o[h][0], gy + HS::o[h][1], gz + HS::o[h][2]);
+    const double xp[3] = {x[gp], x[N + gp], x[2 * N + gp]};
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
       for (int j = 0; j < 3; ++j) y[i] += (double)M[(int64_t)(h * 9 + 3 * i + j) * N + g] * xp[j];
     if (h == 0) continue;
-    const int64_t gm = flat3(G, gx - o[0], gy - o[1], gz - o[2]);
-    double xm[3] = {x[gm], x[N + gm], x[2 * N + gm]};
+    const int64_t gm = flat3(G, gx - HS::o[h][0], gy - HS::o[h][1], gz - HS::o[h][2]);
+    const double xm[3] = {x[gm], x[N + gm], x[2 * N + gm]};
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
@@ -148,14 +160,14 @@ __device__ inline void apply_half(const DGrid& G, const T* __restrict__ M, const
 
 // J_eff = J_lab - (1/dV)(M0 u + Mtilde E_M)  (Sec. 3.1, comoving frame)
 template <typename T, int DIM>
-__global__ __launch_bounds__(256) void k_comoving(DGrid G, int nh, const T* __restrict__ Mt, const T* __restrict__ M0,
+__global__ __launch_bounds__(256) void k_comoving(DGrid G, const T* __restrict__ Mt, const T* __restrict__ M0,
                                                   const double* __restrict__ u, const double* __restrict__ EM,
                                                   const double* __restrict__ Jlab, double* __restrict__ Jeff) {
-  int64_t g = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  const int64_t g = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (g >= G.N) return;
   double a[3], b[3];
-  apply_half<T, DIM>(G, M0, u, g, nh, a);
-  apply_half<T, DIM>(G, Mt, EM, g, nh, b);
+  apply_half<T, DIM>(G, M0, u, g, a);
+  apply_half<T, DIM>(G, Mt, EM, g, b);
   const double idV = 1.0 / G.dV;
   for (int q = 0; q < 3; ++q) Jeff[q * G.N + g] = Jlab[q * G.N + g] - idV * (a[q] + b[q]);
 }
@@ -308,22 +320,62 @@ __global__ void k_rhs(DGrid G, const double* __restrict__ E, const double* __res
   for (int q = 0; q < 3; ++q) b[q * G.N + g] = E[q * G.N + g] + ctd * cb[q] - ftd * J[q * G.N + g];
 }
 
-// A x = x + (c theta dt)^2 curl_CN C + (4 pi theta dt / dV) Mtilde x - theta dt D_E x, C = curl_NC x
+// A x = x + (c theta dt)^2 curl_CN curl_NC x + (4 pi theta dt / dV) Mtilde x
+//       - theta dt D_E x, in one pass over the 3^DIM neighbours of each node.
+// curl_CN curl_NC is a constant 3^DIM-point stencil (a sum of tensor products
+// of 1D differences and averages), precomputed on the host into K:
+// K.k[o][3 m + j] multiplies x_j at offset o for output component m.
+struct CurlCurl {
+  double k[27][9];
+};
+
 template <typename T, int DIM>
-__global__ __launch_bounds__(256) void k_apply_A(DGrid G, int nh, const double* __restrict__ x, const double* __restrict__ C,
-                                                 const T* __restrict__ Mt, const double* __restrict__ kE, double k2,
-                                                 double mcoef, double tdt, double* __restrict__ y) {
-  int64_t g = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void k_apply_A(DGrid G, const double* __restrict__ x, const T* __restrict__ Mt,
+                                                 const double* __restrict__ kE, CurlCurl K, double k2, double mcoef,
+                                                 double tdt, double* __restrict__ y) {
+  using HS = HalfStencil<DIM>;
+  const int64_t g = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (g >= G.N) return;
-  double cc[3];
-  curl_cn_at<DIM>(G, C, g, cc);
-  double mx[3] = {0, 0, 0};
-  if (Mt) apply_half<T, DIM>(G, Mt, x, g, nh, mx);
-  for (int q = 0; q < 3; ++q) {
-    double v = x[q * G.N + g] + k2 * cc[q] + mcoef * mx[q];
-    if (kE) v -= tdt * diffusion_at<DIM>(G, kE, x, g, q);
-    y[q * G.N + g] = v;
+  const int64_t N = G.N;
+  int gx, gy, gz;
+  unflat3(G, g, gx, gy, gz);
+  double acc[3] = {x[g], x[N + g], x[2 * N + g]};
+  const double x0[3] = {acc[0], acc[1], acc[2]};
+  // curl-curl stencil
+  constexpr int RY = DIM >= 2 ? 1 : 0, RZ = DIM >= 3 ? 1 : 0;
+#pragma unroll
+  for (int oz = -RZ; oz <= RZ; ++oz)
+#pragma unroll
+    for (int oy = -RY; oy <= RY; ++oy)
+#pragma unroll
+      for (int ox = -1; ox <= 1; ++ox) {
+        const int oi = (ox + 1) + 3 * (oy + 1) + 9 * (oz + 1);
+        const int64_t h = flat3(G, gx + ox, gy + oy, gz + oz);
+        const double xv[3] = {x[h], x[N + h], x[2 * N + h]};
+#pragma unroll
+        for (int m = 0; m < 3; ++m)
+          acc[m] += k2 * (K.k[oi][3 * m] * xv[0] + K.k[oi][3 * m + 1] * xv[1] + K.k[oi][3 * m + 2] * xv[2]);
+      }
+  if (Mt) {
+    double mx[3];
+    apply_half<T, DIM>(G, Mt, x, g, mx);
+#pragma unroll
+    for (int m = 0; m < 3; ++m) acc[m] += mcoef * mx[m];
   }
+  if (kE) {
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      const int64_t gp = flat3(G, gx + (d == 0), gy + (d == 1), gz + (d == 2));
+      const int64_t gm = flat3(G, gx - (d == 0), gy - (d == 1), gz - (d == 2));
+#pragma unroll
+      for (int m = 0; m < 3; ++m) {
+        const double kp = kE[(d * 3 + m) * N + g], km = kE[(d * 3 + m) * N + gm];
+        acc[m] -= tdt * G.idx[d] * (kp * (x[m * N + gp] - x0[m]) - km * (x0[m] - x[m * N + gm]));
+      }
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < 3; ++m) y[m * N + g] = acc[m];
 }
 
 // B^{n+1} = B^n - c dt curl_NC E^{n+theta} + dt D_B B^n  (C holds curl_NC E^{n+theta})
@@ -458,12 +510,12 @@ int ge_launch_node_avg(ge_ctx* c) {
 
 template <typename T, int DIM>
 static void assemble_t(ge_ctx* c) {
-  hipLaunchKernelGGL((k_assemble<T, DIM>), grid1(c->G.N), dim3(256), 0, c->stream, c->G, (const T*)c->cellQ, c->nsp,
-                     c->nh, (T*)c->Mt, (T*)c->M0, c->Jlab, c->mm, c->mass, c->rho);
+  hipLaunchKernelGGL((k_assemble<T, DIM>), grid1(c->G.N), dim3(256), 0, c->stream, c->G, (const T*)c->cellQ, c->Q,
+                     c->nsp, (T*)c->Mt, (T*)c->M0, c->Jlab, c->mm, c->mass, c->rho);
 }
 template <typename T, int DIM>
 static void comoving_t(ge_ctx* c) {
-  hipLaunchKernelGGL((k_comoving<T, DIM>), grid1(c->G.N), dim3(256), 0, c->stream, c->G, c->nh, (const T*)c->Mt,
+  hipLaunchKernelGGL((k_comoving<T, DIM>), grid1(c->G.N), dim3(256), 0, c->stream, c->G, (const T*)c->Mt,
                      (const T*)c->M0, c->u, c->EM, c->Jlab, c->Jeff);
 }
 #define DISPATCH_TD(c, FN)                                          \
@@ -509,14 +561,46 @@ int ge_launch_grid_pass(ge_ctx* c) {
   return GE_OK;
 }
 
+// Stencil of curl_CN curl_NC: sum over d != m of D_CN,d D_NC,m (x_d) minus
+// D_CN,d D_NC,d (x_m).  Each D_CN,a D_NC,b is a tensor product of 1D stencils:
+// along a == b the second difference [1,-2,1]/dx^2; along a != b the centred
+// difference [-1,0,1]/(2 dx) on both axes a and b; the average [1,2,1]/4
+// along every other active axis.
+static CurlCurl curl_curl_stencil(const DGrid& G) {
+  CurlCurl K;
+  std::memset(&K, 0, sizeof(K));
+  const int dim = G.dim;
+  auto s1 = [&](int axis, int a, int b, int o) -> double {  // 1D factor of D_CN,a D_NC,b along axis
+    if (axis >= dim) return o == 0 ? 1.0 : 0.0;
+    const double ih = G.idx[axis];
+    if (axis == a && axis == b) return (o == 0 ? -2.0 : 1.0) * ih * ih;
+    if (axis == a || axis == b) return o == 0 ? 0.0 : 0.5 * o * ih;
+    return o == 0 ? 0.5 : 0.25;
+  };
+  auto prod = [&](int a, int b, int ox, int oy, int oz) {
+    return s1(0, a, b, ox) * s1(1, a, b, oy) * s1(2, a, b, oz);
+  };
+  for (int oz = -1; oz <= 1; ++oz)
+    for (int oy = -1; oy <= 1; ++oy)
+      for (int ox = -1; ox <= 1; ++ox) {
+        const int oi = (ox + 1) + 3 * (oy + 1) + 9 * (oz + 1);
+        for (int m = 0; m < 3; ++m)
+          for (int d = 0; d < dim; ++d) {
+            if (d == m) continue;
+            K.k[oi][3 * m + m] -= prod(d, d, ox, oy, oz);
+            if (m < dim) K.k[oi][3 * m + d] += prod(d, m, ox, oy, oz);
+          }
+      }
+  return K;
+}
+
 template <typename T, int DIM>
 static void apply_t(ge_ctx* c, const double* x, double* y) {
   const double ctd = c->P.c * c->P.theta * c->P.dt;
   const double mcoef = 4.0 * M_PI * c->P.theta * c->P.dt / c->G.dV;
-  hipLaunchKernelGGL(k_curl_nc<DIM>, grid1(c->G.N), dim3(256), 0, c->stream, c->G, x, c->ccell);
-  hipLaunchKernelGGL((k_apply_A<T, DIM>), grid1(c->G.N), dim3(256), 0, c->stream, c->G, c->nh, x, c->ccell,
-                     c->have_deposit ? (const T*)c->Mt : nullptr, c->P.lf_E ? c->kE : nullptr, ctd * ctd, mcoef,
-                     c->P.theta * c->P.dt, y);
+  hipLaunchKernelGGL((k_apply_A<T, DIM>), grid1(c->G.N), dim3(256), 0, c->stream, c->G, x,
+                     c->have_deposit ? (const T*)c->Mt : nullptr, c->P.lf_E ? c->kE : nullptr, curl_curl_stencil(c->G),
+                     ctd * ctd, mcoef, c->P.theta * c->P.dt, y);
 }
 int ge_launch_apply_A(ge_ctx* c, const double* x, double* y) {
   switch (c->G.dim * 2 + (c->P.precision == GE_FP32 ? 1 : 0)) {

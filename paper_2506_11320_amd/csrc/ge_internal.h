@@ -23,20 +23,27 @@ struct DGrid {
 __host__ __device__ inline int wrapi(int i, int n) {
   return i < 0 ? i + n : (i >= n ? i - n : i);
 }
+// Linear index <-> (i, j, k).  N < 2^31, so 32-bit arithmetic is exact.
 __device__ inline void unflat3(const DGrid& G, int64_t g, int& i, int& j, int& k) {
-  i = (int)(g % G.n[0]);
-  int64_t r = g / G.n[0];
-  j = (int)(r % G.n[1]);
-  k = (int)(r / G.n[1]);
+  const unsigned gg = (unsigned)g, nx = (unsigned)G.n[0], ny = (unsigned)G.n[1];
+  const unsigned r = gg / nx;
+  i = (int)(gg - r * nx);
+  k = (int)(r / ny);
+  j = (int)(r - (unsigned)k * ny);
 }
 __device__ inline int64_t flat3(const DGrid& G, int i, int j, int k) {
-  return (int64_t)wrapi(i, G.n[0]) + (int64_t)G.n[0] * ((int64_t)wrapi(j, G.n[1]) + (int64_t)G.n[1] * wrapi(k, G.n[2]));
+  return (int64_t)(wrapi(i, G.n[0]) + G.n[0] * (wrapi(j, G.n[1]) + G.n[1] * wrapi(k, G.n[2])));
 }
 __device__ inline int64_t nbr3(const DGrid& G, int64_t g, int ox, int oy, int oz) {
   int i, j, k;
   unflat3(G, g, i, j, k);
   return flat3(G, i + ox, j + oy, k + oz);
 }
+
+// Per-cell partial sums are stored in blocks of 4 consecutive cells,
+// [cell/4][Q][4], so that the 4 wavefronts of a deposit workgroup fill whole
+// cache lines together.
+__host__ __device__ inline int64_t cq_index(int64_t c, int k, int Q) { return ((c >> 2) * Q + k) * 4 + (c & 3); }
 
 // Workgroups are dispatched round-robin over the 8 XCDs; remap so that each
 // XCD (and its L2) receives one contiguous range of logical blocks.
@@ -45,22 +52,28 @@ __device__ inline int64_t xcd_block(int64_t b, int64_t nb) {
   return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
 }
 
-// Half-stencil offsets (see glecsim.h): index h -> (ox, oy, oz).
+// Half-stencil offsets (see glecsim.h), h -> (ox, oy, oz): o = 0 first, then
+// every o != 0 whose last nonzero component is +1, enumerated z-major.
 __host__ __device__ inline int half_count(int dim) { return dim == 3 ? 14 : (dim == 2 ? 5 : 2); }
-__host__ __device__ inline void half_offset(int dim, int h, int o[3]) {
-  // o = 0 first, then o != 0 with last nonzero component +1, z-major.
-  o[0] = o[1] = o[2] = 0;
-  if (h == 0) return;
-  int k = 0;
-  int rz = dim >= 3 ? 1 : 0, ry = dim >= 2 ? 1 : 0;
-  for (int oz = -rz; oz <= rz; ++oz)
-    for (int oy = -ry; oy <= ry; ++oy)
-      for (int ox = -1; ox <= 1; ++ox) {
-        int last = oz != 0 ? oz : (oy != 0 ? oy : ox);
-        if (last <= 0) continue;
-        if (++k == h) { o[0] = ox; o[1] = oy; o[2] = oz; return; }
-      }
-}
+template <int DIM>
+struct HalfStencil;
+template <>
+struct HalfStencil<1> {
+  static constexpr int NH = 2;
+  static constexpr int o[2][3] = {{0, 0, 0}, {1, 0, 0}};
+};
+template <>
+struct HalfStencil<2> {
+  static constexpr int NH = 5;
+  static constexpr int o[5][3] = {{0, 0, 0}, {1, 0, 0}, {-1, 1, 0}, {0, 1, 0}, {1, 1, 0}};
+};
+template <>
+struct HalfStencil<3> {
+  static constexpr int NH = 14;
+  static constexpr int o[14][3] = {{0, 0, 0},  {1, 0, 0},  {-1, 1, 0}, {0, 1, 0},  {1, 1, 0},
+                                   {-1, -1, 1}, {0, -1, 1}, {1, -1, 1}, {-1, 0, 1}, {0, 0, 1},
+                                   {1, 0, 1},  {-1, 1, 1}, {0, 1, 1},  {1, 1, 1}};
+};
 
 struct SpeciesBuf {
   double q, m, beta;     // beta = q dt / (2 m)

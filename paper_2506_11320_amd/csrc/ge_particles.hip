@@ -12,6 +12,8 @@
 // stable sort by present cell gives, so the re-binning is an integer,
 // deterministic, bit-exact stable sort that moves each particle once, inside
 // the push.
+#include <cstring>
+
 #include "ge_internal.h"
 
 namespace {
@@ -90,20 +92,16 @@ __device__ inline int run_index(int t, const int* s_start, const int* s_pre, int
   return s_start[k] + (t - s_pre[k]);
 }
 
-// Field values at the 2^DIM corner nodes of cell c, broadcast to every lane.
+// Field values at the 2^DIM corner nodes of cell c into the wavefront's LDS
+// slot fc[3 NC] (component-major); lanes < 3 NC each load one value.
 template <typename T, int DIM>
-__device__ void corner_fields(const DGrid& G, int64_t c, const T* __restrict__ F, int lane, T out[3][8]) {
+__device__ inline void corners_to_lds(const DGrid& G, int64_t c, const T* __restrict__ F, T* fc, int lane) {
   constexpr int NC = Dm<DIM>::NC;
-  T val = 0;
   if (lane < 3 * NC) {
-    int q = lane / NC, a = lane % NC;
-    int64_t g = nbr3(G, c, a & 1, DIM >= 2 ? (a >> 1) & 1 : 0, DIM >= 3 ? (a >> 2) & 1 : 0);
-    val = F[q * G.N + g];
+    const int q = lane / NC, a = lane % NC;
+    const int64_t g = nbr3(G, c, a & 1, DIM >= 2 ? (a >> 1) & 1 : 0, DIM >= 3 ? (a >> 2) & 1 : 0);
+    fc[lane] = F[q * G.N + g];
   }
-#pragma unroll
-  for (int q = 0; q < 3; ++q)
-#pragma unroll
-    for (int a = 0; a < NC; ++a) out[q][a] = rl(val, q * NC + a);
 }
 
 template <typename T, int DIM>
@@ -118,36 +116,39 @@ __device__ inline void lin_weights(const T f[3], T W[8]) {
   }
 }
 
+// out[q] = sum_a W_a F_q(corner a), corner values read from LDS (broadcast)
 template <typename T, int DIM>
-__device__ inline void gather3(const T W[8], const T F[3][8], T out[3]) {
+__device__ inline void gather_lds(const T W[8], const T* fc, T out[3]) {
+  constexpr int NC = Dm<DIM>::NC;
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
     T s = 0;
 #pragma unroll
-    for (int a = 0; a < Dm<DIM>::NC; ++a) s += W[a] * F[q][a];
+    for (int a = 0; a < NC; ++a) s += W[a] * fc[q * NC + a];
     out[q] = s;
   }
 }
 
 // The implicit mover (Sec. 3.1): vbar = alpha (v + beta E_p),
 // v^{n+1} = 2 vbar - v^n, x^{n+3/2} = x^{n+1/2} + dt v^{n+1}.  alpha applied
-// as (t + beta t x B + beta^2 (t.B) B) / (1 + beta^2 |B|^2).  Returns the
-// direction code of the cell move; clamps a move of one cell or more.
+// as (t + beta t x B + beta^2 (t.B) B) / (1 + beta^2 |B|^2).  fc holds the
+// corner values of E^{n+theta} then of B^n.  Returns the direction code of the
+// cell move; clamps a move of one cell or more.
 template <typename T, int DIM>
-__device__ inline int push_one(T f[3], T v[3], const T Ec[3][8], const T Bc[3][8], T beta, const T dtx[3],
-                               int& clamped) {
+__device__ inline int push_one(T f[3], T v[3], const T* fc, T beta, const T dtx[3], int& clamped) {
+  constexpr int NC = Dm<DIM>::NC;
   T W[8];
   lin_weights<T, DIM>(f, W);
   T Ep[3], Bp[3];
-  gather3<T, DIM>(W, Ec, Ep);
-  gather3<T, DIM>(W, Bc, Bp);
-  T t0 = v[0] + beta * Ep[0], t1 = v[1] + beta * Ep[1], t2 = v[2] + beta * Ep[2];
-  T b2 = Bp[0] * Bp[0] + Bp[1] * Bp[1] + Bp[2] * Bp[2];
-  T den = (T)1 / ((T)1 + beta * beta * b2);
-  T tb = beta * beta * (t0 * Bp[0] + t1 * Bp[1] + t2 * Bp[2]);
-  T vb0 = (t0 + beta * (t1 * Bp[2] - t2 * Bp[1]) + tb * Bp[0]) * den;
-  T vb1 = (t1 + beta * (t2 * Bp[0] - t0 * Bp[2]) + tb * Bp[1]) * den;
-  T vb2 = (t2 + beta * (t0 * Bp[1] - t1 * Bp[0]) + tb * Bp[2]) * den;
+  gather_lds<T, DIM>(W, fc, Ep);
+  gather_lds<T, DIM>(W, fc + 3 * NC, Bp);
+  const T t0 = v[0] + beta * Ep[0], t1 = v[1] + beta * Ep[1], t2 = v[2] + beta * Ep[2];
+  const T b2 = Bp[0] * Bp[0] + Bp[1] * Bp[1] + Bp[2] * Bp[2];
+  const T den = (T)1 / ((T)1 + beta * beta * b2);
+  const T tb = beta * beta * (t0 * Bp[0] + t1 * Bp[1] + t2 * Bp[2]);
+  const T vb0 = (t0 + beta * (t1 * Bp[2] - t2 * Bp[1]) + tb * Bp[0]) * den;
+  const T vb1 = (t1 + beta * (t2 * Bp[0] - t0 * Bp[2]) + tb * Bp[1]) * den;
+  const T vb2 = (t2 + beta * (t0 * Bp[1] - t1 * Bp[0]) + tb * Bp[2]) * den;
   v[0] = (T)2 * vb0 - v[0];
   v[1] = (T)2 * vb1 - v[1];
   v[2] = (T)2 * vb2 - v[2];
@@ -183,80 +184,131 @@ struct PushArgs {
   int* flags;
 };
 
+// Direction statistics of one chunk from five bit-ballots of the direction
+// code (< 27): 'same' is the mask of active lanes sharing this lane's
+// direction; lane k < 27 receives the chunk's count of direction k.
+struct DirStats {
+  uint64_t same;
+  int count_k;
+};
+__device__ inline DirStats dir_stats(bool act, int dir, int lane) {
+  const int d = act ? dir : 31;
+  uint64_t bm[5];
+#pragma unroll
+  for (int b = 0; b < 5; ++b) bm[b] = __ballot(act && ((d >> b) & 1));
+  const uint64_t am = __ballot(act);
+  uint64_t same = am, kk = am;
+#pragma unroll
+  for (int b = 0; b < 5; ++b) {
+    same &= ((d >> b) & 1) ? bm[b] : ~bm[b];
+    kk &= ((lane >> b) & 1) ? bm[b] : ~bm[b];
+  }
+  DirStats r;
+  r.same = same;
+  r.count_k = lane < 27 ? __popcll(kk) : 0;
+  return r;
+}
+__device__ inline int excl_scan32(int x, int lane) {
+  int incl = x;
+#pragma unroll
+  for (int d = 1; d < 32; d <<= 1) {
+    const int t = __shfl_up(incl, d, 64);
+    if (lane >= d) incl += t;
+  }
+  return incl - x;
+}
+
+template <typename T, int DIM>
+__device__ inline void load_particle(const PushArgs<T>& A, int i, T f[3], T v[3], T& w) {
+  const int64_t N = A.n;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) f[d] = d < DIM ? A.off[d * N + i] : (T)0;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) v[d] = A.v[d * N + i];
+  w = A.w[i];
+}
+template <typename T>
+__device__ inline void store_particle(const PushArgs<T>& A, int64_t o, const T f[3], const T v[3], T w) {
+  const int64_t N = A.n;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) A.off_o[d * N + o] = f[d];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) A.v_o[d * N + o] = v[d];
+  A.w_o[o] = w;
+}
+
+// One wavefront per cell: push every particle present in the cell and write
+// it into the cell's new segment, partitioned by the direction of its move.
+// Cells with up to 128 particles keep the pushed state in registers; larger
+// cells count in a first pass and push again in a second (same arithmetic).
 template <typename T, int DIM>
 __global__ __launch_bounds__(256) void k_push(DGrid G, PushArgs<T> A) {
-  constexpr int ND = Dm<DIM>::ND;
+  constexpr int ND = Dm<DIM>::ND, NC = Dm<DIM>::NC;
   __shared__ int s_start[4][32], s_pre[4][32];
+  __shared__ T s_fc[4][48];
   const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t c = xcd_block(blockIdx.x, gridDim.x) * 4 + wid;
   if (c >= G.N) return;
+  T* fc = s_fc[wid];
+  corners_to_lds<T, DIM>(G, c, A.E, fc, lane);
+  corners_to_lds<T, DIM>(G, c, A.B, fc + 3 * NC, lane);
   int nseg;
   const int total = runs_setup<DIM>(G, c, A.sub_start, A.sub_cnt, s_start[wid], s_pre[wid], lane, nseg);
-  T Ec[3][8], Bc[3][8];
-  corner_fields<T, DIM>(G, c, A.E, lane, Ec);
-  corner_fields<T, DIM>(G, c, A.B, lane, Bc);
   const int64_t base = A.seg_next[c];
-  const int64_t N = A.n;
-  int mycnt = 0, dir_off = 0, running = 0, clamped = 0, bad = 0;
-  // pass 0 counts the particles per direction, pass 1 writes them
+  int cnt = 0, dir_off = 0, clamped = 0, bad = 0;
+  if (total <= 128) {
+    T f0[3], v0[3], w0 = 0, f1[3], v1[3], w1 = 0;
+    const bool a0 = lane < total, a1 = 64 + lane < total;
+    int d0 = 31, d1 = 31;
+    if (a0) {
+      load_particle<T, DIM>(A, run_index(lane, s_start[wid], s_pre[wid], nseg), f0, v0, w0);
+      d0 = push_one<T, DIM>(f0, v0, fc, A.beta, A.dtx, clamped);
+    }
+    if (a1) {
+      load_particle<T, DIM>(A, run_index(64 + lane, s_start[wid], s_pre[wid], nseg), f1, v1, w1);
+      d1 = push_one<T, DIM>(f1, v1, fc, A.beta, A.dtx, clamped);
+    }
+    const DirStats q0 = dir_stats(a0, d0, lane), q1 = dir_stats(a1, d1, lane);
+    cnt = q0.count_k + q1.count_k;
+    dir_off = excl_scan32(cnt, lane);
+    const int b0 = __shfl(dir_off, d0 & 31, 64);
+    const int b1 = __shfl(dir_off + q0.count_k, d1 & 31, 64);
+    const uint64_t lt = lanemask_lt(lane);
+    if (a0) store_particle(A, base + b0 + __popcll(q0.same & lt), f0, v0, w0);
+    if (a1) store_particle(A, base + b1 + __popcll(q1.same & lt), f1, v1, w1);
+  } else {
+    int running = 0;
 #pragma clang loop unroll(disable)
-  for (int pass = 0; pass < 2; ++pass) {
-    for (int t0 = 0; t0 < total; t0 += 64) {
-      const int t = t0 + lane;
-      const bool act = t < total;
-      T f[3] = {0, 0, 0}, v[3] = {0, 0, 0}, w = 0;
-      int dir = -1;
-      if (act) {
-        const int i = run_index(t, s_start[wid], s_pre[wid], nseg);
-#pragma unroll
-        for (int d = 0; d < DIM; ++d) f[d] = A.off[d * N + i];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) v[d] = A.v[d * N + i];
-        w = A.w[i];
-        dir = push_one<T, DIM>(f, v, Ec, Bc, A.beta, A.dtx, clamped);
-      }
-      uint64_t rem = __ballot(act);
-      int pos = -1;
-      while (rem) {
-        const int l0 = __ffsll((unsigned long long)rem) - 1;
-        const int d0 = rl_i(dir, l0);
-        const uint64_t m = __ballot(act && dir == d0);
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int t0 = 0; t0 < total; t0 += 64) {
+        const int t = t0 + lane;
+        const bool act = t < total;
+        T f[3] = {0, 0, 0}, v[3] = {0, 0, 0}, w = 0;
+        int dir = 31;
+        if (act) {
+          load_particle<T, DIM>(A, run_index(t, s_start[wid], s_pre[wid], nseg), f, v, w);
+          dir = push_one<T, DIM>(f, v, fc, A.beta, A.dtx, clamped);
+        }
+        const DirStats q = dir_stats(act, dir, lane);
         if (pass == 0) {
-          if (lane == d0) mycnt += __popcll(m);
+          cnt += q.count_k;
         } else {
-          const int b0 = rl_i(dir_off, d0) + rl_i(running, d0);
-          if (act && dir == d0) pos = b0 + __popcll(m & lanemask_lt(lane));
-          if (lane == d0) running += __popcll(m);
-        }
-        rem &= ~m;
-      }
-      if (pass == 1 && act) {
-        if (pos >= 0 && pos < total) {
-          const int64_t o = base + pos;
-#pragma unroll
-          for (int d = 0; d < 3; ++d) A.off_o[d * N + o] = f[d];
-#pragma unroll
-          for (int d = 0; d < 3; ++d) A.v_o[d * N + o] = v[d];
-          A.w_o[o] = w;
-        } else {
-          bad = 1;
+          const int b = __shfl(dir_off + running, dir & 31, 64);
+          const int pos = b + __popcll(q.same & lanemask_lt(lane));
+          running += q.count_k;
+          if (act) {
+            if (pos >= 0 && pos < total) store_particle(A, base + pos, f, v, w);
+            else bad = 1;
+          }
         }
       }
+      if (pass == 0) dir_off = excl_scan32(cnt, lane);
     }
-    if (pass == 0) {
-      int incl = mycnt;
-#pragma unroll
-      for (int d = 1; d < 32; d <<= 1) {
-        int tt = __shfl_up(incl, d, 64);
-        if (lane >= d) incl += tt;
-      }
-      dir_off = incl - mycnt;
-    }
+    if (lane < ND && running != cnt) bad = 1;
   }
   if (lane < ND) {
     A.sub_start_o[(int64_t)lane * G.N + c] = (int32_t)(base + dir_off);
-    A.sub_cnt_o[(int64_t)lane * G.N + c] = mycnt;
-    if (running != mycnt) bad = 1;
+    A.sub_cnt_o[(int64_t)lane * G.N + c] = cnt;
   }
   if (clamped) atomicOr(&A.flags[0], 1);
   if (bad) atomicOr(&A.flags[1], 1);
@@ -354,7 +406,11 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_final(const int32_t* __rest
 // = (w alpha (9), w alpha v (3), w v (3), w).  Every node-pair product
 // W_a W_b of the cell is one of these rows, and every linear weight W_a is a
 // sum of them, so S = A B holds the whole cell's contribution to the mass
-// matrices, current and moments.
+// matrices, current and moments.  Each lane computes one particle's operands
+// and writes them to an LDS row laid out for the MFMA reads (one 8-byte read
+// of the two A rows and one 4-byte read of B per 4-particle step).  Each
+// species' S is scaled (beta_s q_s, q_s, m_s) into per-wave LDS accumulators
+// and the cell's sums are written once at the end.
 template <typename T>
 struct DepSpecies {
   const T *off, *v, *w;
@@ -367,7 +423,8 @@ struct DepArgs {
   DepSpecies<T> sp[GE_MAX_SPECIES];
   int nsp;
   const T* Bn;  // [3][N]
-  T* cellQ;     // [Q][N]
+  T* cellQ;     // per-cell sums, [N/4][Qn][4] (cq_index)
+  int Qn;
 };
 
 template <typename T>
@@ -387,37 +444,36 @@ struct Mfma<double> {
 
 template <typename T, int DIM>
 struct DepCfg {
-  static constexpr int WPB = sizeof(T) == 4 ? 4 : 2;          // waves per block
-  static constexpr int AW = 16 * Dm<DIM>::NRB;                 // A row width
-  static constexpr int STRIDE = AW + 16;                       // staged floats per particle
+  static constexpr int NR = Dm<DIM>::ND;
+  static constexpr int NRB = Dm<DIM>::NRB;
+  static constexpr int AW = 16 * NRB;            // A values per particle (row blocks interleaved)
+  static constexpr int ST = AW + 16;             // staged values per particle
+  static constexpr int WPB = 2;                  // wavefronts per workgroup
+  static constexpr int NACC = NR * (18 + 7 + GE_MAX_SPECIES);
 };
 
 template <typename T, int DIM>
-__global__ __launch_bounds__(256) void k_deposit(DGrid G, DepArgs<T> A) {
+__global__ __launch_bounds__(128) void k_deposit(DGrid G, DepArgs<T> A) {
   using M = Mfma<T>;
   typedef typename M::v4 v4;
-  constexpr int ND = Dm<DIM>::ND, NC = Dm<DIM>::NC, NRB = Dm<DIM>::NRB;
-  constexpr int WPB = DepCfg<T, DIM>::WPB, AW = DepCfg<T, DIM>::AW, ST = DepCfg<T, DIM>::STRIDE;
-  constexpr int NR = ND;
+  using C = DepCfg<T, DIM>;
+  constexpr int NC = Dm<DIM>::NC, NRB = C::NRB, NR = C::NR, AW = C::AW, ST = C::ST, WPB = C::WPB;
   __shared__ int s_start[WPB][32], s_pre[WPB][32];
-  __shared__ T s_stage[WPB][64 * ST];
+  __shared__ T s_fc[WPB][24];
+  __shared__ __attribute__((aligned(16))) T s_stage[WPB][64 * ST];
+  __shared__ T s_acc[WPB][C::NACC];
   const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  if (wid >= WPB) return;
   const int64_t c = xcd_block(blockIdx.x, gridDim.x) * WPB + wid;
   if (c >= G.N) return;
+  T* fc = s_fc[wid];
   T* stage = s_stage[wid];
-  T Bc[3][8];
-  corner_fields<T, DIM>(G, c, A.Bn, lane, Bc);
+  T* acc_mt = s_acc[wid];          // [NR][9]
+  T* acc_m0 = acc_mt + 9 * NR;     // [NR][9]
+  T* acc_lin = acc_m0 + 9 * NR;    // [NR][7]: q alpha v (3), m v (3), m w
+  T* acc_rho = acc_lin + 7 * NR;   // [NR][GE_MAX_SPECIES]
+  corners_to_lds<T, DIM>(G, c, A.Bn, fc, lane);
+  for (int k = lane; k < C::NACC; k += 64) s_acc[wid][k] = 0;
   const int col = lane & 15;
-  T Rmt[NRB][4], Rm0[NRB][4], Rlin[NRB][4], Rrho[GE_MAX_SPECIES][NRB][4];
-#pragma unroll
-  for (int rb = 0; rb < NRB; ++rb)
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      Rmt[rb][i] = Rm0[rb][i] = Rlin[rb][i] = 0;
-#pragma unroll
-      for (int s = 0; s < GE_MAX_SPECIES; ++s) Rrho[s][rb][i] = 0;
-    }
   for (int s = 0; s < A.nsp; ++s) {
     const DepSpecies<T>& S = A.sp[s];
     int nseg;
@@ -428,11 +484,7 @@ __global__ __launch_bounds__(256) void k_deposit(DGrid G, DepArgs<T> A) {
     const int64_t N = S.n;
     for (int t0 = 0; t0 < total; t0 += 64) {
       const int t = t0 + lane;
-      T arow[AW], bcol[16];
-#pragma unroll
-      for (int k = 0; k < AW; ++k) arow[k] = 0;
-#pragma unroll
-      for (int k = 0; k < 16; ++k) bcol[k] = 0;
+      T* my = stage + lane * ST;
       if (t < total) {
         const int i = run_index(t, s_start[wid], s_pre[wid], nseg);
         T f[3] = {0, 0, 0}, v[3];
@@ -444,29 +496,28 @@ __global__ __launch_bounds__(256) void k_deposit(DGrid G, DepArgs<T> A) {
         T W[8];
         lin_weights<T, DIM>(f, W);
         T Bp[3];
-        gather3<T, DIM>(W, Bc, Bp);
-        // alpha (Sec. 3.1), row-major
-        const T be = S.beta;
-        const T den = (T)1 / ((T)1 + be * be * (Bp[0] * Bp[0] + Bp[1] * Bp[1] + Bp[2] * Bp[2]));
-        const T bb = be * be;
-        T al[9];
-        al[0] = (1 + bb * Bp[0] * Bp[0]) * den;
-        al[1] = (be * Bp[2] + bb * Bp[0] * Bp[1]) * den;
-        al[2] = (-be * Bp[1] + bb * Bp[0] * Bp[2]) * den;
-        al[3] = (-be * Bp[2] + bb * Bp[1] * Bp[0]) * den;
-        al[4] = (1 + bb * Bp[1] * Bp[1]) * den;
-        al[5] = (be * Bp[0] + bb * Bp[1] * Bp[2]) * den;
-        al[6] = (be * Bp[1] + bb * Bp[2] * Bp[0]) * den;
-        al[7] = (-be * Bp[0] + bb * Bp[2] * Bp[1]) * den;
-        al[8] = (1 + bb * Bp[2] * Bp[2]) * den;
+        gather_lds<T, DIM>(W, fc, Bp);
+        const T be = S.beta, bb = be * be;
+        const T den = (T)1 / ((T)1 + bb * (Bp[0] * Bp[0] + Bp[1] * Bp[1] + Bp[2] * Bp[2]));
+        const T wd = w * den;
+        T al[9];  // w alpha (Sec. 3.1), row-major
+        al[0] = (1 + bb * Bp[0] * Bp[0]) * wd;
+        al[1] = (be * Bp[2] + bb * Bp[0] * Bp[1]) * wd;
+        al[2] = (-be * Bp[1] + bb * Bp[0] * Bp[2]) * wd;
+        al[3] = (-be * Bp[2] + bb * Bp[1] * Bp[0]) * wd;
+        al[4] = (1 + bb * Bp[1] * Bp[1]) * wd;
+        al[5] = (be * Bp[0] + bb * Bp[1] * Bp[2]) * wd;
+        al[6] = (be * Bp[1] + bb * Bp[2] * Bp[0]) * wd;
+        al[7] = (-be * Bp[0] + bb * Bp[2] * Bp[1]) * wd;
+        al[8] = (1 + bb * Bp[2] * Bp[2]) * wd;
+        T* bcol = my + AW;
 #pragma unroll
-        for (int k = 0; k < 9; ++k) bcol[k] = w * al[k];
+        for (int k = 0; k < 9; ++k) bcol[k] = al[k];
 #pragma unroll
-        for (int r = 0; r < 3; ++r) bcol[9 + r] = w * (al[3 * r] * v[0] + al[3 * r + 1] * v[1] + al[3 * r + 2] * v[2]);
+        for (int r = 0; r < 3; ++r) bcol[9 + r] = al[3 * r] * v[0] + al[3 * r + 1] * v[1] + al[3 * r + 2] * v[2];
 #pragma unroll
         for (int r = 0; r < 3; ++r) bcol[12 + r] = w * v[r];
         bcol[15] = w;
-        // quadratic weight products per axis
         T X[3][3];
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
@@ -479,83 +530,71 @@ __global__ __launch_bounds__(256) void k_deposit(DGrid G, DepArgs<T> A) {
             X[d][0] = 1; X[d][1] = 0; X[d][2] = 0;
           }
         }
+        // A rows r and 16 + r interleaved: my[NRB * k + rb] = A[16 rb + k]
 #pragma unroll
-        for (int r = 0; r < NR; ++r) {
-          const int ix = r % 3, iy = (r / 3) % 3, iz = r / 9;
-          arow[r] = X[0][ix] * X[1][iy] * X[2][iz];
-        }
+        for (int k = 0; k < 16; ++k)
+#pragma unroll
+          for (int rb = 0; rb < NRB; ++rb) {
+            const int r = 16 * rb + k;
+            my[NRB * k + rb] = r < NR ? X[0][r % 3] * X[1][(r / 3) % 3] * X[2][r / 9] : (T)0;
+          }
+      } else {
+#pragma unroll
+        for (int k = 0; k < ST; ++k) my[k] = 0;
       }
-      T* my = stage + lane * ST;
-#pragma unroll
-      for (int k = 0; k < AW; ++k) my[k] = arow[k];
-#pragma unroll
-      for (int k = 0; k < 16; ++k) my[AW + k] = bcol[k];
       wave_sync();
-      const int cnt = min(64, total - t0);
-      const int nsteps = (cnt + 3) >> 2;
+      const int nsteps = (min(64, total - t0) + 3) >> 2;
       for (int stp = 0; stp < nsteps; ++stp) {
-        const T* pr = stage + (4 * stp + (lane >> 4)) * ST;
-        const T b = pr[AW + col];
-#pragma unroll
-        for (int rb = 0; rb < NRB; ++rb) acc[rb] = M::op(pr[16 * rb + col], b, acc[rb]);
+        const T* prow = stage + (4 * stp + (lane >> 4)) * ST;
+        const T b = prow[AW + col];
+        if (NRB == 2) {
+          typedef T t2 __attribute__((ext_vector_type(2)));
+          const t2 a = *reinterpret_cast<const t2*>(prow + 2 * col);
+          acc[0] = M::op(a[0], b, acc[0]);
+          acc[NRB - 1] = M::op(a[1], b, acc[NRB - 1]);
+        } else {
+          acc[0] = M::op(prow[col], b, acc[0]);
+        }
       }
       wave_sync();
     }
-    // scale this species' sums into the cell totals
+    // scale this species' sums into the cell accumulators (each (row, col)
+    // belongs to one lane, so no two lanes touch the same LDS word)
     const T qs = S.q, ms = S.m, bq = S.beta * S.q;
 #pragma unroll
     for (int rb = 0; rb < NRB; ++rb)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
+        const int r = 16 * rb + M::row(lane, i);
+        if (r >= NR) continue;
         const T val = acc[rb][i];
         if (col < 9) {
-          Rmt[rb][i] += bq * val;
-          Rm0[rb][i] += qs * val;
+          acc_mt[r * 9 + col] += bq * val;
+          acc_m0[r * 9 + col] += qs * val;
         } else {
-          Rlin[rb][i] += (col < 12 ? qs : ms) * val;
+          acc_lin[r * 7 + col - 9] += (col < 12 ? qs : ms) * val;
+          if (col == 15) acc_rho[r * GE_MAX_SPECIES + s] += qs * val;
         }
-        if (col == 15) Rrho[s][rb][i] += qs * val;
       }
   }
-  // write the cell's quadratic-row sums of Mtilde and M0
-  const int64_t NN = G.N;
-  T* Q = A.cellQ;
-#pragma unroll
-  for (int rb = 0; rb < NRB; ++rb)
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int r = 16 * rb + M::row(lane, i);
-      if (col < 9 && r < NR) {
-        Q[(int64_t)(r * 9 + col) * NN + c] = Rmt[rb][i];
-        Q[(int64_t)(9 * NR + r * 9 + col) * NN + c] = Rm0[rb][i];
-      }
-    }
-  // corner sums of the linear quantities: W_a = prod_d (X_{a_d} + X_{a_d+1})
-  const int NK = 7 + A.nsp;
-  T* lin = stage;  // reuse: [NR][NK]
-#pragma unroll
-  for (int rb = 0; rb < NRB; ++rb)
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int r = 16 * rb + M::row(lane, i);
-      if (r < NR) {
-        if (col >= 9) lin[r * NK + (col - 9)] = Rlin[rb][i];
-        if (col == 15)
-          for (int s = 0; s < A.nsp; ++s) lin[r * NK + 7 + s] = Rrho[s][rb][i];
-      }
-    }
   wave_sync();
+  // write the cell: quadratic rows of Mtilde and M0, then corner sums of the
+  // linear quantities, W_a = prod_d (X_{a_d} + X_{a_d + 1})
+  T* Q = A.cellQ;
+  const int Qn = A.Qn;
+  for (int k = lane; k < 18 * NR; k += 64) Q[cq_index(c, k, Qn)] = acc_mt[k];
+  const int NK = 7 + A.nsp;
   for (int t = lane; t < NC * NK; t += 64) {
     const int a = t % NC, k = t / NC;
-    T s = 0;
+    T sum = 0;
 #pragma unroll
     for (int b = 0; b < NC; ++b) {
-      int r = ((a & 1) + (b & 1));
+      int r = (a & 1) + (b & 1);
       if (DIM >= 2) r += 3 * (((a >> 1) & 1) + ((b >> 1) & 1));
       if (DIM >= 3) r += 9 * (((a >> 2) & 1) + ((b >> 2) & 1));
-      s += lin[r * NK + k];
+      sum += k < 7 ? acc_lin[r * 7 + k] : acc_rho[r * GE_MAX_SPECIES + (k - 7)];
     }
-    Q[(int64_t)(18 * NR + k * NC + a) * NN + c] = s;
+    Q[cq_index(c, 18 * NR + k * NC + a, Qn)] = sum;
   }
 }
 
@@ -670,6 +709,7 @@ static void launch_push_t(ge_ctx* c, int s) {
   hipLaunchKernelGGL((k_push<T, DIM>), dim3(nb), dim3(256), 0, c->stream, c->G, A);
 }
 
+// Push species s; needs ge_launch_scan_counts(c, s) first.
 int ge_launch_push(ge_ctx* c, int s) {
   const bool f32 = c->P.precision == GE_FP32;
   switch (c->G.dim * 2 + (f32 ? 1 : 0)) {
@@ -688,6 +728,7 @@ int ge_launch_push(ge_ctx* c, int s) {
 template <typename T, int DIM>
 static void launch_deposit_t(ge_ctx* c) {
   DepArgs<T> A;
+  std::memset(&A, 0, sizeof(A));
   A.nsp = c->nsp;
   for (int s = 0; s < c->nsp; ++s) {
     SpeciesBuf& S = c->sp[s];
@@ -697,6 +738,7 @@ static void launch_deposit_t(ge_ctx* c) {
   }
   A.Bn = sizeof(T) == 4 ? (const T*)c->Bn32 : (const T*)c->Bn;
   A.cellQ = (T*)c->cellQ;
+  A.Qn = c->Q;
   constexpr int WPB = DepCfg<T, DIM>::WPB;
   const int64_t nb = (c->G.N + WPB - 1) / WPB;
   hipLaunchKernelGGL((k_deposit<T, DIM>), dim3(nb), dim3(64 * WPB), 0, c->stream, c->G, A);

@@ -23,6 +23,8 @@ CASES = [
     ("2d_fp32", 2, (7, 5, 1), 70, "c3", True),
     ("3d_fp64", 3, (5, 3, 3), 70, "c5", False),
     ("3d_fp32", 3, (5, 3, 3), 70, "c5", True),
+    # more than 128 particles per cell: the two-pass push and 3-chunk deposit
+    ("3d_fp32_dense", 3, (4, 3, 3), 150, "c5", True),
 ]
 
 
