@@ -16,6 +16,12 @@
  *
  * Each function names the passage of the paper it follows.  Readings of
  * passages that are silent or garbled are marked READING.
+ *
+ * Parity unpinned (no closed form, printed value or invariant fixes them;
+ * the GPU path implements the same reading): the node averaging of B used to
+ * interpolate B to the particles (or_node_avg), the multi-dimensional form of
+ * the LF coefficients and their diffusion speed (or_kappa_E / or_kappa_B
+ * beyond 1D), and the lag of the E limiter to E^n.
  */
 #include <math.h>
 #include <stdint.h>
