@@ -57,7 +57,7 @@ enum {
 
 enum { GE_FP64 = 0, GE_FP32 = 1 };           /* particle and mass-matrix precision */
 enum { GE_A_LIGHT = 0, GE_A_BULK = 1 };      /* diffusion speed a: c, or |u| */
-enum { GE_PC_NONE = 0, GE_PC_JACOBI = 1 };   /* GMRES preconditioner */
+enum { GE_PC_NONE = 0, GE_PC_JACOBI = 1, GE_PC_CNN = 2 };  /* GMRES preconditioner */
 
 typedef struct ge_ctx ge_ctx;
 
@@ -89,7 +89,8 @@ typedef struct {
   int converged;       /* 1 if ||b - A x|| <= tol ||b|| on the true residual */
   double relres;       /* final true relative residual */
   double bnorm;
-  double seconds;      /* host wall time of the solve */
+  double seconds;      /* host wall time of the solve (after queued work) */
+  int fallback;        /* 1 if the learned preconditioner failed and plain GMRES finished */
 } ge_solve_report;
 
 typedef struct {
@@ -144,7 +145,11 @@ int ge_deposit(ge_ctx* ctx);
 
 /* Solve A E^{n+theta} = b (Sec. 2.1/2.2/3.1) by restarted GMRES(restart) in
  * FP64, starting from E^n, until ||b - A x|| <= tol ||b||.  precond:
- * GE_PC_NONE or GE_PC_JACOBI (node 3x3 block diagonal, right-preconditioned).
+ * GE_PC_NONE, GE_PC_JACOBI (node 3x3 block diagonal, right-preconditioned) or
+ * GE_PC_CNN (flexible GMRES with the learned network of ge_cnn_*, 3D only;
+ * falls back to plain GMRES if the network returns NaN/Inf).  If harvesting is
+ * on (ge_cnn_harvest), a converged GE_PC_NONE/JACOBI solve also stores the
+ * pair (b - A E^n, E^{n+theta} - E^n) for training.
  * report: host struct, may be NULL.  Synchronises.  Returns GE_OK,
  * GE_WARN_NOT_CONVERGED, or an error (GE_ERR_STATE before ge_deposit). */
 int ge_solve_fields(ge_ctx* ctx, double tol, int maxit, int restart, int precond, ge_solve_report* report);
@@ -223,6 +228,50 @@ int ge_diagnostics(ge_ctx* ctx, ge_diag* out);
  *   [6] 0                                         [7] number of steps averaged
  * The accumulators are reset by the call. */
 int ge_timings(ge_ctx* ctx, double* out8);
+
+/* ------------------------------------------------ learned preconditioner */
+/* Not from the paper: a 3-layer 3x3x3 convolutional network z = N(r)
+ * (3 -> 32 -> 32 -> 3 channels, ReLU after the first two, no bias), BF16 MFMA
+ * with FP32 accumulation, trained on (residual, correction) pairs of the solves
+ * and used as a flexible right preconditioner; plain GMRES stays the judge:
+ * the solve must still reach ||b - A x|| <= tol ||b||. */
+typedef struct {
+  int crop;       /* output crop edge in nodes (input crop = crop + 6) */
+  int batch;      /* crops per step (1..64) */
+  int iters;      /* optimiser steps */
+  double lr, beta1, beta2, eps;  /* Adam */
+  uint32_t seed;  /* crop origins and pair mixing */
+} ge_train_cfg;
+typedef struct {
+  int steps, pairs;
+  double loss_first, loss_last;  /* mean squared error of the first and last step */
+  double seconds;
+} ge_train_report;
+
+/* Create the network with weights near the identity map plus small seeded
+ * noise (3D grids only). */
+int ge_cnn_init(ge_ctx* ctx, uint32_t seed);
+/* Number of FP32 master weights: layers [27 taps][cout][cin] for
+ * (cin, cout) = (3, 32), (32, 32), (32, 3), concatenated. */
+int ge_cnn_size(void);
+/* Copy the master weights to (set = 0) or from (set = 1) host_w[ge_cnn_size()]. */
+int ge_cnn_weights(ge_ctx* ctx, int set, float* host_w);
+/* z = N(r) on the whole periodic grid, r normalised by its RMS and the
+ * output scaled back (device double [3][N]).  Synchronises. */
+int ge_cnn_apply(ge_ctx* ctx, const double* r, double* z);
+/* Turn pair harvesting from converged solves on (1) or off (0). */
+int ge_cnn_harvest(ge_ctx* ctx, int on);
+/* Store a (residual, correction) pair (device double [3][N]); the store keeps
+ * the 16 newest pairs.  Synchronises. */
+int ge_cnn_add_pair(ge_ctx* ctx, const double* r, const double* e);
+/* Number of stored pairs. */
+int ge_cnn_npairs(const ge_ctx* ctx);
+/* Train with Adam on random crops of random unit-norm combinations of two
+ * stored pairs (mean squared error).  Synchronises. */
+int ge_cnn_train(ge_ctx* ctx, const ge_train_cfg* cfg, ge_train_report* report);
+/* Loss and gradient for caller crops (device FP32): in_crops [B][(n+6)^3][3],
+ * tgt [B][n^3][3]; grad [ge_cnn_size()] (device FP32); loss on the host. */
+int ge_cnn_loss_grad(ge_ctx* ctx, int B, int n, const float* in_crops, const float* tgt, float* grad, double* loss);
 
 #ifdef __cplusplus
 }

@@ -178,6 +178,8 @@ void ge_destroy(ge_ctx* c) {
     }
   for (int k = 0; k < 10; ++k)
     if (c->ev[k]) (void)hipEventDestroy(c->ev[k]);
+  ge_cnn_free(c);
+  dfree(c->Zb);
   delete c;
 }
 
@@ -253,9 +255,21 @@ int ge_solve_fields(ge_ctx* c, double tol, int maxit, int restart, int precond, 
   if (!c->have_deposit) return ge_fail(c, GE_ERR_STATE, "ge_solve_fields before ge_deposit");
   if (!(tol > 0) || maxit < 1) return ge_fail(c, GE_ERR_ARG, "tol/maxit");
   GE_HIP(c, hipMemcpyAsync(c->Eth, c->E, sizeof(double) * 3 * c->G.N, hipMemcpyDeviceToDevice, c->stream));
-  int rc = ge_gmres(c, tol, maxit, restart, precond, rep);
+  ge_solve_report r;
+  std::memset(&r, 0, sizeof(r));
+  int rc = ge_gmres(c, tol, maxit, restart, precond, &r);
+  if (rep) *rep = r;
   if (rc < 0) return rc;
   c->have_solve = 1;
+  // training data for the learned preconditioner: (r0 = b - A E^n, e = E^{n+theta} - E^n)
+  if (rc == GE_OK && precond != GE_PC_CNN && ge_cnn_harvesting(c)) {
+    const int64_t n3 = 3 * c->G.N;
+    int hr = ge_launch_apply_A(c, c->E, c->kw);
+    if (!hr) hr = ge_launch_sub(c, c->rhs, c->kw, c->kw, n3);
+    if (!hr) hr = ge_launch_sub(c, c->Eth, c->E, c->kx, n3);
+    if (!hr) hr = ge_cnn_add_pair(c, c->kw, c->kx);
+    if (hr) return hr;
+  }
   int fr = check_flags(c);
   return fr ? fr : rc;
 }

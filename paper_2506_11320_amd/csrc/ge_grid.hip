@@ -663,6 +663,18 @@ int ge_launch_jacobi_apply(ge_ctx* c, const double* x, double* y) {
   return GE_OK;
 }
 
+namespace {
+__global__ void k_sub_vec(int64_t n, const double* __restrict__ a, const double* __restrict__ b, double* __restrict__ o) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) o[i] = a[i] - b[i];
+}
+}  // namespace
+int ge_launch_sub(ge_ctx* c, const double* a, const double* b, double* out, int64_t n) {
+  hipLaunchKernelGGL(k_sub_vec, grid1(n), dim3(256), 0, c->stream, n, a, b, out);
+  GE_HIP(c, hipGetLastError());
+  return GE_OK;
+}
+
 int ge_launch_field_diag(ge_ctx* c, double* out) {
   const int nbk = 256;
   DISPATCH_DIM(c, k_field_diag, dim3(nbk), dim3(256), 0, c->stream, c->G, c->E, c->B, c->rho, c->nsp, c->partials);

@@ -8,6 +8,7 @@
 #include "glecsim.h"
 
 #define GE_MAX_SPECIES 4
+#define GE_CNN_MAX_PAIRS 16
 #define GE_WAVE 64
 
 // Device view of the periodic mesh.  Inactive axes have n = 1 and are never
@@ -111,6 +112,8 @@ struct ge_ctx {
   int64_t nred_blocks;
   int* flags;            // [0] CFL clamp, [1] run overflow, [2] load error
   int have_deposit, have_solve;
+  void* cnn;           // learned preconditioner state (ge_cnn.hip), lazily created
+  double* Zb;          // flexible-GMRES basis of preconditioned vectors (lazily allocated)
   hipEvent_t ev[10];   // pairs: push, deposit, assemble, grid rest, update
   double tsum[8];      // accumulated per-phase seconds (see ge_timings)
   int tcnt;
@@ -141,5 +144,10 @@ int ge_launch_to_f32(ge_ctx* c, const double* src, float* dst, int64_t n);
 int ge_launch_jacobi_setup(ge_ctx* c);
 int ge_launch_jacobi_apply(ge_ctx* c, const double* x, double* y);
 int ge_launch_field_diag(ge_ctx* c, double* out);  // W_E, W_B, gauss (sync)
+int ge_launch_sub(ge_ctx* c, const double* a, const double* b, double* out, int64_t n);  // out = a - b
 
 int ge_gmres(ge_ctx* c, double tol, int maxit, int restart, int precond, ge_solve_report* rep);
+int ge_cnn_apply_grid(ge_ctx* c, const double* v, double* z, double scale);  // z = N(v) with input scale
+void ge_cnn_free(ge_ctx* c);
+extern "C" int ge_cnn_add_pair(ge_ctx* c, const double* r, const double* e);
+int ge_cnn_harvesting(const ge_ctx* c);

@@ -121,7 +121,18 @@ int ge_gmres(ge_ctx* c, double tol, int maxit, int m, int precond, ge_solve_repo
   auto t0 = std::chrono::steady_clock::now();
   const int64_t n = 3 * c->G.N;
   if (m < 1 || m > c->kr_m) return ge_fail(c, GE_ERR_ARG, "restart out of range (1.." + std::to_string(c->kr_m) + ")");
-  if (precond != GE_PC_NONE && precond != GE_PC_JACOBI) return ge_fail(c, GE_ERR_ARG, "unknown preconditioner");
+  if (precond != GE_PC_NONE && precond != GE_PC_JACOBI && precond != GE_PC_CNN)
+    return ge_fail(c, GE_ERR_ARG, "unknown preconditioner");
+  if (precond == GE_PC_CNN && !c->Zb) {
+    // flexible GMRES keeps the preconditioned vectors z_j
+    if (hipMalloc((void**)&c->Zb, sizeof(double) * n * c->kr_m) != hipSuccess) {
+      c->Zb = nullptr;
+      (void)hipGetLastError();
+      return ge_fail(c, GE_ERR_OOM, "flexible GMRES basis allocation failed");
+    }
+  }
+  const double cnn_scale = std::sqrt((double)n);  // basis vectors have unit norm: RMS = 1/sqrt(n)
+  int fallback = 0;
   int rc;
   double* x = c->Eth;
   double* V = c->V;
@@ -161,7 +172,11 @@ int ge_gmres(ge_ctx* c, double tol, int maxit, int m, int precond, ge_solve_repo
       double* vj = V + (int64_t)j * n;
       double* vn = V + (int64_t)(j + 1) * n;
       const double* av_in = vj;
-      if (precond != GE_PC_NONE) {
+      if (precond == GE_PC_CNN) {
+        double* zj = c->Zb + (int64_t)j * n;
+        if ((rc = ge_cnn_apply_grid(c, vj, zj, cnn_scale))) return rc;
+        av_in = zj;
+      } else if (precond != GE_PC_NONE) {
         if ((rc = precond_apply(c, precond, vj, z, n))) return rc;
         av_in = z;
       }
@@ -180,7 +195,17 @@ int ge_gmres(ge_ctx* c, double tol, int maxit, int m, int precond, ge_solve_repo
       ++it;
       for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hh[i];
       const double hn = std::sqrt(hh[128]);
-      if (!std::isfinite(hn)) return ge_fail(c, GE_ERR_NONFINITE, "non-finite Arnoldi vector");
+      bool finite = std::isfinite(hn);
+      for (int i = 0; i <= j; ++i) finite = finite && std::isfinite(hh[i]);
+      if (!finite && precond == GE_PC_CNN) {
+        // the learned preconditioner produced NaN/Inf: drop this cycle and
+        // continue with plain GMRES from the current iterate
+        precond = GE_PC_NONE;
+        fallback = 1;
+        k = -1;
+        break;
+      }
+      if (!finite) return ge_fail(c, GE_ERR_NONFINITE, "non-finite Arnoldi vector");
       H[(size_t)(j + 1) * m + j] = hn;
       for (int i = 0; i < j; ++i) {
         const double a0 = cs[i] * H[(size_t)i * m + j] + sn[i] * H[(size_t)(i + 1) * m + j];
@@ -199,7 +224,8 @@ int ge_gmres(ge_ctx* c, double tol, int maxit, int m, int precond, ge_solve_repo
       k = j + 1;
       if (std::fabs(s[j + 1]) <= tol * bref || hn == 0.0) break;
     }
-    // y = H^{-1} s; x += M^{-1} (V y)
+    if (k < 0) continue;  // cycle abandoned (fallback)
+    // y = H^{-1} s; x += M^{-1} (V y)  (flexible: x += Z y)
     for (int i = k - 1; i >= 0; --i) {
       double t = s[i];
       for (int l = i + 1; l < k; ++l) t -= H[(size_t)i * m + l] * y[l];
@@ -208,6 +234,8 @@ int ge_gmres(ge_ctx* c, double tol, int maxit, int m, int precond, ge_solve_repo
     GE_HIP(c, hipMemcpyAsync(hd + 192, y.data(), sizeof(double) * k, hipMemcpyHostToDevice, c->stream));
     if (precond == GE_PC_NONE) {
       hipLaunchKernelGGL(k_multiaxpy, vgrid(n), dim3(KB), 0, c->stream, x, V, n, k, hd + 192, 1.0, n);
+    } else if (precond == GE_PC_CNN) {
+      hipLaunchKernelGGL(k_multiaxpy, vgrid(n), dim3(KB), 0, c->stream, x, c->Zb, n, k, hd + 192, 1.0, n);
     } else {
       GE_HIP(c, hipMemsetAsync(w, 0, sizeof(double) * n, c->stream));
       hipLaunchKernelGGL(k_multiaxpy, vgrid(n), dim3(KB), 0, c->stream, w, V, n, k, hd + 192, 1.0, n);
@@ -223,6 +251,7 @@ int ge_gmres(ge_ctx* c, double tol, int maxit, int m, int precond, ge_solve_repo
     rep->converged = conv;
     rep->relres = rel;
     rep->bnorm = bnorm;
+    rep->fallback = fallback;
     rep->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   }
   return conv ? GE_OK : GE_WARN_NOT_CONVERGED;

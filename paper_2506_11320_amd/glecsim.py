@@ -20,7 +20,7 @@ GE_ERR_ARG, GE_ERR_OOM, GE_ERR_HIP, GE_ERR_CFL, GE_ERR_NONFINITE, GE_ERR_STATE =
 GE_WARN_NOT_CONVERGED = 1
 GE_FP64, GE_FP32 = 0, 1
 GE_A_LIGHT, GE_A_BULK = 0, 1
-GE_PC_NONE, GE_PC_JACOBI = 0, 1
+GE_PC_NONE, GE_PC_JACOBI, GE_PC_CNN = 0, 1, 2
 FIELDS = {
     "E": 0, "B": 1, "Eth": 2, "Bn": 3, "J_lab": 4, "J_eff": 5, "rho": 6, "mm": 7, "mass": 8, "u": 9,
     "EM": 10, "Mt": 11, "M0": 12, "kappa_E": 13, "kappa_B": 14, "rhs": 15,
@@ -29,6 +29,8 @@ EXPORTS = [
     "ge_create", "ge_destroy", "ge_last_error", "ge_add_species", "ge_set_fields", "ge_deposit", "ge_solve_fields",
     "ge_push", "ge_update_fields", "ge_step", "ge_sync", "ge_gather", "ge_set", "ge_half_stencil",
     "ge_get_particles", "ge_apply_operator", "ge_diagnostics", "ge_timings",
+    "ge_cnn_init", "ge_cnn_size", "ge_cnn_weights", "ge_cnn_apply", "ge_cnn_harvest", "ge_cnn_add_pair",
+    "ge_cnn_npairs", "ge_cnn_train", "ge_cnn_loss_grad",
 ]
 
 
@@ -49,7 +51,19 @@ class GESpecies(ctypes.Structure):
 
 class GESolveReport(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int), ("restarts", ctypes.c_int), ("converged", ctypes.c_int),
-                ("relres", ctypes.c_double), ("bnorm", ctypes.c_double), ("seconds", ctypes.c_double)]
+                ("relres", ctypes.c_double), ("bnorm", ctypes.c_double), ("seconds", ctypes.c_double),
+                ("fallback", ctypes.c_int)]
+
+
+class GETrainCfg(ctypes.Structure):
+    _fields_ = [("crop", ctypes.c_int), ("batch", ctypes.c_int), ("iters", ctypes.c_int), ("lr", ctypes.c_double),
+                ("beta1", ctypes.c_double), ("beta2", ctypes.c_double), ("eps", ctypes.c_double),
+                ("seed", ctypes.c_uint32)]
+
+
+class GETrainReport(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int), ("pairs", ctypes.c_int), ("loss_first", ctypes.c_double),
+                ("loss_last", ctypes.c_double), ("seconds", ctypes.c_double)]
 
 
 class GEDiag(ctypes.Structure):
@@ -93,6 +107,15 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.ge_apply_operator.argtypes = [vp, vp, vp]
     L.ge_diagnostics.argtypes = [vp, ctypes.POINTER(GEDiag)]
     L.ge_timings.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+    L.ge_cnn_init.argtypes = [vp, ctypes.c_uint32]
+    L.ge_cnn_size.argtypes = []
+    L.ge_cnn_weights.argtypes = [vp, ctypes.c_int, vp]
+    L.ge_cnn_apply.argtypes = [vp, vp, vp]
+    L.ge_cnn_harvest.argtypes = [vp, ctypes.c_int]
+    L.ge_cnn_add_pair.argtypes = [vp, vp, vp]
+    L.ge_cnn_npairs.argtypes = [vp]
+    L.ge_cnn_train.argtypes = [vp, ctypes.POINTER(GETrainCfg), ctypes.POINTER(GETrainReport)]
+    L.ge_cnn_loss_grad.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, vp, vp, ctypes.POINTER(ctypes.c_double)]
     _lib = L
     return L
 
@@ -179,7 +202,7 @@ class Simulation:
         r = GESolveReport()
         rc = self._check(self.L.ge_solve_fields(self.h, tol, maxit, restart, precond, ctypes.byref(r)), True)
         return {"iterations": r.iterations, "restarts": r.restarts, "converged": bool(r.converged),
-                "relres": r.relres, "bnorm": r.bnorm, "seconds": r.seconds, "rc": rc}
+                "relres": r.relres, "bnorm": r.bnorm, "seconds": r.seconds, "fallback": bool(r.fallback), "rc": rc}
 
     def push(self):
         self._check(self.L.ge_push(self.h))
@@ -191,7 +214,7 @@ class Simulation:
         r = GESolveReport()
         rc = self._check(self.L.ge_step(self.h, tol, maxit, restart, precond, ctypes.byref(r)), True)
         return {"iterations": r.iterations, "converged": bool(r.converged), "relres": r.relres, "rc": rc,
-                "seconds": r.seconds}
+                "seconds": r.seconds, "fallback": bool(r.fallback)}
 
     def sync(self):
         self._check(self.L.ge_sync(self.h))
@@ -243,6 +266,64 @@ class Simulation:
         self._check(self.L.ge_diagnostics(self.h, ctypes.byref(dg)))
         return {"W_E": dg.W_E, "W_B": dg.W_B, "K": [dg.K[s] for s in range(self.nsp)],
                 "P": [[dg.P[s][d] for d in range(3)] for s in range(self.nsp)], "gauss": dg.gauss}
+
+    # -------------------------------------------------- learned preconditioner
+    def cnn_init(self, seed: int = 0):
+        self._check(self.L.ge_cnn_init(self.h, seed))
+
+    def cnn_size(self) -> int:
+        return int(self.L.ge_cnn_size())
+
+    def cnn_weights(self) -> "numpy.ndarray":
+        import numpy as np
+        w = np.empty(self.cnn_size(), dtype=np.float32)
+        self._check(self.L.ge_cnn_weights(self.h, 0, w.ctypes.data))
+        return w
+
+    def cnn_set_weights(self, w) -> None:
+        import numpy as np
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        assert w.shape == (self.cnn_size(),)
+        self._check(self.L.ge_cnn_weights(self.h, 1, w.ctypes.data))
+
+    def cnn_apply(self, r: torch.Tensor) -> torch.Tensor:
+        r = r.to(device=self.device, dtype=torch.float64).contiguous()
+        assert tuple(r.shape) == (3, self.N)
+        z = torch.empty_like(r)
+        self._check(self.L.ge_cnn_apply(self.h, _ptr(r), _ptr(z)))
+        return z
+
+    def cnn_harvest(self, on: bool = True):
+        self._check(self.L.ge_cnn_harvest(self.h, int(on)))
+
+    def cnn_add_pair(self, r: torch.Tensor, e: torch.Tensor):
+        r = r.to(device=self.device, dtype=torch.float64).contiguous()
+        e = e.to(device=self.device, dtype=torch.float64).contiguous()
+        assert tuple(r.shape) == (3, self.N) and tuple(e.shape) == (3, self.N)
+        self._check(self.L.ge_cnn_add_pair(self.h, _ptr(r), _ptr(e)))
+
+    def cnn_npairs(self) -> int:
+        return int(self.L.ge_cnn_npairs(self.h))
+
+    def cnn_train(self, crop: int = 16, batch: int = 8, iters: int = 200, lr: float = 1e-3, beta1: float = 0.9,
+                  beta2: float = 0.999, eps: float = 1e-8, seed: int = 1) -> Dict:
+        cfg = GETrainCfg(crop, batch, iters, lr, beta1, beta2, eps, seed)
+        rep = GETrainReport()
+        self._check(self.L.ge_cnn_train(self.h, ctypes.byref(cfg), ctypes.byref(rep)))
+        return {"steps": rep.steps, "pairs": rep.pairs, "loss_first": rep.loss_first, "loss_last": rep.loss_last,
+                "seconds": rep.seconds}
+
+    def cnn_loss_grad(self, in_crops: torch.Tensor, tgt: torch.Tensor):
+        """in_crops [B, (n+6)^3, 3], tgt [B, n^3, 3] (FP32, crop-local x-fastest order)."""
+        in_crops = in_crops.to(device=self.device, dtype=torch.float32).contiguous()
+        tgt = tgt.to(device=self.device, dtype=torch.float32).contiguous()
+        B, v6 = in_crops.shape[0], in_crops.shape[1]
+        n = round(v6 ** (1.0 / 3.0)) - 6
+        assert (n + 6) ** 3 == v6 and tuple(tgt.shape) == (B, n ** 3, 3)
+        g = torch.empty(self.cnn_size(), dtype=torch.float32, device=self.device)
+        loss = ctypes.c_double()
+        self._check(self.L.ge_cnn_loss_grad(self.h, B, n, _ptr(in_crops), _ptr(tgt), _ptr(g), ctypes.byref(loss)))
+        return loss.value, g
 
     def timings(self):
         out = (ctypes.c_double * 8)()

@@ -1,0 +1,221 @@
+"""GPU tests of the learned preconditioner through the C ABI.
+
+Parity bar: the BF16/FP32 GPU network against the FP64 reference fed the
+same BF16-rounded inputs, weights and activations (oracle/cnn.py with
+quant=True).  With dyadic inputs and weights (every sum exact in FP32) the
+forward pass must agree bit for bit.  With random inputs the FP32
+accumulation order alone gives ~1e-7, but a BF16 rounding that this order
+flips (probability ~1e-4 per activation) moves one activation by one BF16 ulp
+(2^-8 relative) and spreads through the next layers: the normwise bar is
+1e-3 for the forward pass and 3e-3 for the weight gradient.  Against the
+unrounded FP64 network the error is the BF16 error itself, <= 2e-2.  The preconditioned
+solve is judged like every solve: true relative residual <= tol, and the
+same field as plain GMRES."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import cnn as C
+from tests import harness as H
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _ctx(n):
+    from paper_2506_11320_amd import Simulation
+    return Simulation(3, n, (0.5, 0.5, 0.5), theta=0.5, dt=0.5)
+
+
+def _rand_w(rng, scale=1.0):
+    parts = []
+    for ci, co in C.LAYERS:
+        parts.append(rng.standard_normal(27 * ci * co) * scale * np.sqrt(2.0 / (27 * ci)))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def _layer_errs(g, ref):
+    offs = [0, 27 * 3 * 32, 27 * 3 * 32 + 27 * 32 * 32, C.NW]
+    return [H.relerr(g[offs[l]:offs[l + 1]], ref[offs[l]:offs[l + 1]]) for l in range(3)]
+
+
+# (12, 10, 9): 1080 nodes = 67.5 MFMA tiles (ragged); (3, 4, 5): the smallest periodic box
+@pytest.mark.parametrize("n", [(12, 10, 9), (3, 4, 5), (16, 16, 16)])
+def test_forward_matches_oracle(n):
+    print(f"[gpu] cnn forward {n}", flush=True)
+    N = n[0] * n[1] * n[2]
+    sim = _ctx(n)
+    sim.cnn_init(7)
+    rng = np.random.default_rng(11)
+    w = _rand_w(rng)
+    sim.cnn_set_weights(w)
+    assert np.array_equal(sim.cnn_weights(), w)
+    r = rng.standard_normal((3, N)) * 3e-3
+    z = sim.cnn_apply(torch.from_numpy(r).to(sim.device)).cpu().numpy()
+    ref = C.forward_apply(w.astype(np.float64), r, n, quant=True)
+    e = H.relerr(z, ref)
+    print(f"  rel err vs BF16-rounded FP64 reference {e:.2e}", flush=True)
+    assert e <= 1e-3
+    assert H.relerr(z, C.forward_apply(w.astype(np.float64), r, n)) <= 2e-2
+    # bit-identical on a second application
+    z2 = sim.cnn_apply(torch.from_numpy(r).to(sim.device)).cpu().numpy()
+    assert np.array_equal(z, z2)
+    sim.close()
+
+
+def _dyadic_w(rng):
+    """Sparse weights in {0, +-1/2, +-1/4}: every partial sum of the network
+    on +-1 inputs is a short dyadic number, exact in FP32."""
+    w = rng.choice([0.5, -0.5, 0.25, -0.25], size=C.NW) * (rng.random(C.NW) < 0.06)
+    return w.astype(np.float32)
+
+
+@pytest.mark.parametrize("n", [(12, 10, 9), (16, 16, 16)])
+def test_forward_bit_exact_on_dyadic_data(n):
+    print(f"[gpu] cnn dyadic forward {n}", flush=True)
+    N = n[0] * n[1] * n[2]
+    sim = _ctx(n)
+    sim.cnn_init(7)
+    rng = np.random.default_rng(21)
+    w = _dyadic_w(rng)
+    sim.cnn_set_weights(w)
+    r = rng.choice([-1.0, 1.0], size=(3, N))  # RMS exactly 1: no rescaling rounding
+    z = sim.cnn_apply(torch.from_numpy(r).to(sim.device)).cpu().numpy()
+    ref = C.forward_apply(w.astype(np.float64), r, n, quant=True)
+    assert np.abs(ref).max() > 0
+    assert np.array_equal(z, ref), np.abs(z - ref).max()
+    sim.close()
+
+
+def test_gradient_on_dyadic_data():
+    """Forward exact, so the loss agrees to FP32 summation order; the
+    backward sums are inexact in FP32 and may flip a BF16 rounding."""
+    print("[gpu] cnn dyadic loss/grad", flush=True)
+    sim = _ctx((8, 8, 8))
+    sim.cnn_init(5)
+    rng = np.random.default_rng(31)
+    w = _dyadic_w(rng)
+    sim.cnn_set_weights(w)
+    B, k = 4, 5
+    x = rng.choice([-1.0, 0.0, 1.0], size=(B, (k + 6) ** 3, 3)).astype(np.float32)
+    e = rng.choice([-0.5, 0.0, 0.5], size=(B, k ** 3, 3)).astype(np.float32)
+    L, g = sim.cnn_loss_grad(torch.from_numpy(x), torch.from_numpy(e))
+    Lr, gr = C.loss_grad(w.astype(np.float64), x.astype(np.float64), e.astype(np.float64), quant=True)
+    errs = _layer_errs(g.cpu().numpy().astype(np.float64), gr)
+    print(f"  loss {L:.9e} vs {Lr:.9e}; layer grad errs {errs}", flush=True)
+    assert abs(L - Lr) <= 1e-6 * Lr
+    assert max(errs) <= 1e-3
+    sim.close()
+
+
+def test_initial_weights_are_near_identity():
+    n = (8, 6, 5)
+    N = n[0] * n[1] * n[2]
+    sim = _ctx(n)
+    sim.cnn_init(3)
+    w = sim.cnn_weights().astype(np.float64)
+    rng = np.random.default_rng(2)
+    r = rng.standard_normal((3, N))
+    z = sim.cnn_apply(torch.from_numpy(r).to(sim.device)).cpu().numpy()
+    assert H.relerr(z, C.forward_apply(w, r, n, quant=True)) <= 1e-3
+    assert H.relerr(z, r) <= 0.1
+    sim.close()
+
+
+@pytest.mark.parametrize("B,k", [(3, 3), (4, 6)])
+def test_loss_and_gradient_match_oracle(B, k):
+    """(3, 3): 1029 layer-1 nodes (two 1024-node reduction chunks, ragged);
+    (4, 6): several chunks in every layer."""
+    print(f"[gpu] cnn loss/grad B={B} crop={k}", flush=True)
+    sim = _ctx((8, 8, 8))
+    sim.cnn_init(5)
+    rng = np.random.default_rng(100 + k)
+    w = _rand_w(rng)
+    sim.cnn_set_weights(w)
+    x = rng.standard_normal((B, (k + 6) ** 3, 3)).astype(np.float32)
+    e = (0.3 * rng.standard_normal((B, k ** 3, 3))).astype(np.float32)
+    L, g = sim.cnn_loss_grad(torch.from_numpy(x), torch.from_numpy(e))
+    g = g.cpu().numpy().astype(np.float64)
+    Lr, gr = C.loss_grad(w.astype(np.float64), x.astype(np.float64), e.astype(np.float64), quant=True)
+    errs = _layer_errs(g, gr)
+    print(f"  loss {L:.6e} vs {Lr:.6e}; layer grad errs {errs}", flush=True)
+    assert abs(L - Lr) <= 1e-4 * Lr
+    assert max(errs) <= 3e-3
+    L0, g0 = C.loss_grad(w.astype(np.float64), x.astype(np.float64), e.astype(np.float64))
+    assert abs(L - L0) <= 2e-2 * L0
+    assert max(_layer_errs(g, g0)) <= 5e-2
+    sim.close()
+
+
+def test_pair_store_keeps_the_newest_sixteen():
+    n = (6, 5, 4)
+    N = n[0] * n[1] * n[2]
+    sim = _ctx(n)
+    rng = np.random.default_rng(0)
+    for i in range(20):
+        r = torch.from_numpy(rng.standard_normal((3, N)))
+        sim.cnn_add_pair(r, 0.5 * r)
+        assert sim.cnn_npairs() == min(i + 1, 16)
+    sim.close()
+
+
+def _reconnection_case():
+    wl = synth.small("cnn", dim=3, n=(12, 10, 8), ppc=16, base="c4", fp32=True)
+    parts = H.species_arrays(wl, True)
+    E, B = synth.fields(wl)
+    return wl, parts, E, B
+
+
+def test_training_and_flexible_gmres():
+    from paper_2506_11320_amd import GE_PC_CNN
+    print("[gpu] cnn harvest/train/FGMRES", flush=True)
+    wl, parts, E, B = _reconnection_case()
+    sim = H.make_sim(wl, parts, E, B)
+    sim.cnn_init(3)
+    sim.cnn_harvest(True)
+    for _ in range(6):
+        rep = sim.step(tol=1e-10)
+        assert rep["converged"]
+    assert sim.cnn_npairs() == 6
+    tr = sim.cnn_train(crop=6, batch=8, iters=80, lr=2e-3, seed=5)
+    print(f"  train {tr}", flush=True)
+    assert tr["steps"] == 80 and tr["pairs"] == 6
+    assert np.isfinite(tr["loss_last"]) and tr["loss_last"] < tr["loss_first"]
+    w1 = sim.cnn_weights()
+    # training is deterministic: re-initialise and train again
+    sim.cnn_init(3)
+    sim.cnn_train(crop=6, batch=8, iters=80, lr=2e-3, seed=5)
+    assert np.array_equal(sim.cnn_weights(), w1)
+    sim.cnn_harvest(False)
+    sim.deposit()
+    tol = 1e-9
+    rp = sim.solve(tol=tol)
+    Ep = sim.gather("Eth").cpu().numpy()
+    rc = sim.solve(tol=tol, precond=GE_PC_CNN)
+    Ec = sim.gather("Eth").cpu().numpy()
+    print(f"  plain {rp['iterations']} it, cnn {rc['iterations']} it", flush=True)
+    assert rp["converged"] and rc["converged"] and not rc["fallback"]
+    assert rc["relres"] <= tol
+    assert H.relerr(Ec, Ep) <= 1e-6
+    # the true residual of the FGMRES answer, recomputed through the operator
+    b = sim.gather("rhs")
+    res = (b - sim.apply_operator(torch.from_numpy(Ec).to(sim.device))).cpu().numpy()
+    assert np.linalg.norm(res) <= 1.01 * tol * np.linalg.norm(b.cpu().numpy())
+    sim.close()
+
+
+def test_nonfinite_network_falls_back_to_plain_gmres():
+    from paper_2506_11320_amd import GE_PC_CNN
+    wl, parts, E, B = _reconnection_case()
+    sim = H.make_sim(wl, parts, E, B)
+    sim.cnn_init(1)
+    w = sim.cnn_weights()
+    w[27 * 3 * 32 + 5] = np.nan
+    sim.cnn_set_weights(w)
+    sim.deposit()
+    rp = sim.solve(tol=1e-9)
+    Ep = sim.gather("Eth").cpu().numpy()
+    rc = sim.solve(tol=1e-9, precond=GE_PC_CNN)
+    assert rc["fallback"] and rc["converged"] and rc["relres"] <= 1e-9
+    assert H.relerr(sim.gather("Eth").cpu().numpy(), Ep) <= 1e-6
+    sim.close()
