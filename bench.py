@@ -77,6 +77,50 @@ def cpu_baseline(wl, box=32):
                       f"single-threaded FP64 C oracle, {dt:.1f} s"}
 
 
+def nn_compare(sim, args):
+    """Learned preconditioner, after the timed steps: harvest (residual,
+    correction) pairs from plain solves, train on the GPU, then solve each of
+    the next steps both ways from the same state (plain GMRES, then
+    CNN-preconditioned FGMRES, both to the same true residual) and push with
+    the second answer."""
+    from paper_2506_11320_amd import GE_HARVEST_KRYLOV, GE_HARVEST_SOLUTION, GE_PC_CNN
+    sim.cnn_init(1, max_pairs=args.nn_pairs)
+    sim.cnn_harvest({"solution": GE_HARVEST_SOLUTION, "krylov": GE_HARVEST_KRYLOV,
+                     "both": GE_HARVEST_SOLUTION | GE_HARVEST_KRYLOV}[args.nn_data])
+    for k in range(args.nn_harvest):
+        r = sim.step(tol=args.tol, maxit=500, restart=30, precond=0)
+        log(f"harvest step {k}: {r['iterations']} iterations")
+    sim.cnn_harvest(0)
+    tr = sim.cnn_train(crop=args.nn_crop, batch=args.nn_batch, iters=args.nn_iters, lr=args.nn_lr, seed=7)
+    log(f"trained: {tr}")
+    res = {"plain": [], "nn": []}
+    for k in range(args.nn_eval):
+        sim.deposit()
+        rp = sim.solve(tol=args.tol, maxit=500, restart=30, precond=0)
+        rc = sim.solve(tol=args.tol, maxit=500, restart=30, precond=GE_PC_CNN)
+        if not (rp["converged"] and rc["converged"]):
+            log(f"eval step {k}: not converged (plain {rp['relres']:.2e}, nn {rc['relres']:.2e})")
+        res["plain"].append((rp["seconds"], rp["iterations"]))
+        res["nn"].append((rc["seconds"], rc["iterations"], rc["fallback"], rc["relres"]))
+        log(f"eval step {k}: plain {rp['iterations']} it {rp['seconds'] * 1e3:.2f} ms, "
+            f"nn {rc['iterations']} it {rc['seconds'] * 1e3:.2f} ms (relres {rc['relres']:.2e})")
+        sim.push()
+        sim.update_fields()
+    sim.sync()
+    return {
+        "plain": {"seconds": float(np.mean([a[0] for a in res["plain"]])),
+                  "iterations": float(np.mean([a[1] for a in res["plain"]]))},
+        "nn": {"seconds": float(np.mean([a[0] for a in res["nn"]])),
+               "iterations": float(np.mean([a[1] for a in res["nn"]])),
+               "fallbacks": int(sum(a[2] for a in res["nn"])),
+               "max_relres": float(max(a[3] for a in res["nn"]))},
+        "train": {"pairs": tr["pairs"], "data": args.nn_data, "steps": tr["steps"], "crop": args.nn_crop,
+                  "batch": args.nn_batch, "lr": args.nn_lr,
+                  "loss_first": tr["loss_first"], "loss_last": tr["loss_last"], "seconds": tr["seconds"]},
+        "eval_steps": args.nn_eval,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -87,6 +131,16 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--compare-precond", action="store_true", help="also time a Jacobi-preconditioned solve")
+    ap.add_argument("--no-nn", action="store_true", help="skip the learned-preconditioner comparison")
+    ap.add_argument("--nn-harvest", type=int, default=8, help="plain solves whose (residual, correction) pairs train")
+    ap.add_argument("--nn-iters", type=int, default=300, help="training steps")
+    ap.add_argument("--nn-crop", type=int, default=16)
+    ap.add_argument("--nn-batch", type=int, default=16)
+    ap.add_argument("--nn-lr", type=float, default=1e-3)
+    ap.add_argument("--nn-eval", type=int, default=4, help="steps solved both ways after training")
+    ap.add_argument("--nn-pairs", type=int, default=96, help="pair store capacity")
+    ap.add_argument("--nn-data", default="both", choices=["solution", "krylov", "both"],
+                    help="training pairs: (r0, e) of each solve, (A v_j, v_j) of its Arnoldi vectors, or both")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain device copy of 4 GiB (reference for the HBM byte counters) and exit")
     args = ap.parse_args()
@@ -167,6 +221,9 @@ def main():
             rep = sim.solve(tol=args.tol, maxit=500, restart=30, precond=code)
             pcs[name] = {"seconds": rep["seconds"], "iterations": rep["iterations"]}
         precond_cmp = pcs
+    nn = None
+    if not args.no_nn and wl.dim == 3:
+        nn = nn_compare(sim, args)
     out = {
         "metric": METRIC,
         "value": npart * args.steps / elapsed,
@@ -185,7 +242,9 @@ def main():
                                f"FP32 push/deposit, FP64 GMRES to {args.tol:g}, comoving current, limited LF",
                    "cells": wl.ncells, "particles": npart, "precond": args.precond},
         "push_deposit_particle_steps_per_s": npart / pd_s,
-        "gmres_s_per_step": {"plain" if pc == 0 else args.precond: float(np.mean(solve_s)), "nn": None},
+        "gmres_s_per_step": {"plain" if pc == 0 else args.precond: float(np.mean(solve_s)),
+                             "nn": nn["nn"]["seconds"] if nn else None},
+        "nn_precond": nn,
         "gmres_iterations": float(np.mean(iters)),
         "phase_ms": {k: round(v, 3) for k, v in phase.items()},
         "precond_compare": precond_cmp,

@@ -147,9 +147,11 @@ int ge_deposit(ge_ctx* ctx);
  * FP64, starting from E^n, until ||b - A x|| <= tol ||b||.  precond:
  * GE_PC_NONE, GE_PC_JACOBI (node 3x3 block diagonal, right-preconditioned) or
  * GE_PC_CNN (flexible GMRES with the learned network of ge_cnn_*, 3D only;
- * falls back to plain GMRES if the network returns NaN/Inf).  If harvesting is
- * on (ge_cnn_harvest), a converged GE_PC_NONE/JACOBI solve also stores the
- * pair (b - A E^n, E^{n+theta} - E^n) for training.
+ * falls back to plain GMRES from the current iterate if the network returns
+ * NaN/Inf or a restart cycle reduces the residual by less than a factor 2).  If harvesting is
+ * on (ge_cnn_harvest), a converged GE_PC_NONE/JACOBI solve also stores
+ * training pairs: (b - A E^n, E^{n+theta} - E^n) and/or (A v_j, v_j) for the
+ * Arnoldi vectors v_j of its last cycle.
  * report: host struct, may be NULL.  Synchronises.  Returns GE_OK,
  * GE_WARN_NOT_CONVERGED, or an error (GE_ERR_STATE before ge_deposit). */
 int ge_solve_fields(ge_ctx* ctx, double tol, int maxit, int restart, int precond, ge_solve_report* report);
@@ -248,9 +250,13 @@ typedef struct {
   double seconds;
 } ge_train_report;
 
-/* Create the network with weights near the identity map plus small seeded
- * noise (3D grids only). */
-int ge_cnn_init(ge_ctx* ctx, uint32_t seed);
+enum { GE_HARVEST_SOLUTION = 1, GE_HARVEST_KRYLOV = 2 };  /* ge_cnn_harvest flags */
+
+/* Create (or reset) the network with weights near the identity map plus
+ * small seeded noise, and reset the Adam state (3D grids only).  max_pairs:
+ * capacity of the pair store (1..1024, 0 = 64), fixed by the first call;
+ * each pair takes 24 N bytes of device memory. */
+int ge_cnn_init(ge_ctx* ctx, uint32_t seed, int max_pairs);
 /* Number of FP32 master weights: layers [27 taps][cout][cin] for
  * (cin, cout) = (3, 32), (32, 32), (32, 3), concatenated. */
 int ge_cnn_size(void);
@@ -259,10 +265,13 @@ int ge_cnn_weights(ge_ctx* ctx, int set, float* host_w);
 /* z = N(r) on the whole periodic grid, r normalised by its RMS and the
  * output scaled back (device double [3][N]).  Synchronises. */
 int ge_cnn_apply(ge_ctx* ctx, const double* r, double* z);
-/* Turn pair harvesting from converged solves on (1) or off (0). */
-int ge_cnn_harvest(ge_ctx* ctx, int on);
+/* Pair harvesting from converged solves: 0 = off, else an OR of
+ * GE_HARVEST_SOLUTION (the pair (b - A E^n, E^{n+theta} - E^n)) and
+ * GE_HARVEST_KRYLOV (the exact pairs (A v_j, v_j) of the last cycle's Arnoldi
+ * vectors, one extra matvec each). */
+int ge_cnn_harvest(ge_ctx* ctx, int flags);
 /* Store a (residual, correction) pair (device double [3][N]); the store keeps
- * the 16 newest pairs.  Synchronises. */
+ * the newest max_pairs pairs (ge_cnn_init).  Synchronises. */
 int ge_cnn_add_pair(ge_ctx* ctx, const double* r, const double* e);
 /* Number of stored pairs. */
 int ge_cnn_npairs(const ge_ctx* ctx);

@@ -261,14 +261,26 @@ int ge_solve_fields(ge_ctx* c, double tol, int maxit, int restart, int precond, 
   if (rep) *rep = r;
   if (rc < 0) return rc;
   c->have_solve = 1;
-  // training data for the learned preconditioner: (r0 = b - A E^n, e = E^{n+theta} - E^n)
-  if (rc == GE_OK && precond != GE_PC_CNN && ge_cnn_harvesting(c)) {
+  // training data for the learned preconditioner
+  const int hv = (rc == GE_OK && precond != GE_PC_CNN) ? ge_cnn_harvesting(c) : 0;
+  if (hv & GE_HARVEST_SOLUTION) {
+    // (r0 = b - A E^n, e = E^{n+theta} - E^n)
     const int64_t n3 = 3 * c->G.N;
     int hr = ge_launch_apply_A(c, c->E, c->kw);
     if (!hr) hr = ge_launch_sub(c, c->rhs, c->kw, c->kw, n3);
     if (!hr) hr = ge_launch_sub(c, c->Eth, c->E, c->kx, n3);
     if (!hr) hr = ge_cnn_add_pair(c, c->kw, c->kx);
     if (hr) return hr;
+  }
+  if (hv & GE_HARVEST_KRYLOV) {
+    // (A v_j, v_j) for the unit Arnoldi vectors of the last cycle (v_0 holds
+    // the final residual by now and is skipped)
+    for (int j = 1; j < c->kr_last; ++j) {
+      const double* vj = c->V + (int64_t)j * 3 * c->G.N;
+      int hr = ge_launch_apply_A(c, vj, c->kw);
+      if (!hr) hr = ge_cnn_add_pair(c, c->kw, vj);
+      if (hr) return hr;
+    }
   }
   int fr = check_flags(c);
   return fr ? fr : rc;

@@ -4,12 +4,12 @@
 // gfx950 with BF16 MFMA (v_mfma_f32_16x16x32_bf16) and FP32 accumulation.
 //
 // Activations are channels-last BF16 ([box nodes][C]).  A convolution is an
-// implicit GEMM: one wavefront computes 16 consecutive output nodes (the MFMA
-// rows) for 16 output channels per accumulator; K runs over (tap, input
-// channel) in chunks of 32, each lane loading 8 consecutive channels (16 B) of
-// one tapped node.  Three geometries share the kernel: periodic (inference on
-// the whole grid), valid (training crops, output = input - 2) and full
-// (backward pass of the data gradient, output = input + 2, zero padding).
+// implicit GEMM with K running over (tap, input channel) in chunks of 32, each
+// lane holding 8 consecutive channels (16 B) of one tapped node.  The
+// whole-grid periodic layers (inference inside the solver) use an LDS-tiled
+// kernel; the training crops use a simpler kernel with two geometries: valid
+// (output = input - 2) and full (backward pass of the data gradient, output =
+// input + 2, zero padding).
 // Weight gradients are a GEMM over nodes per tap, also on MFMA, reduced over
 // node chunks in a fixed order.  Training data are (residual, correction)
 // pairs harvested from converged solves, normalised by the residual's RMS;
@@ -27,7 +27,7 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 
 namespace {
 
-enum { CONV_PERIODIC = 0, CONV_VALID = 1, CONV_FULL = 2 };
+enum { CONV_VALID = 1, CONV_FULL = 2 };
 
 struct ConvArgs {
   const __bf16* in;    // [B][in box][CIN]
@@ -52,9 +52,7 @@ __device__ inline bf8 zero8() {
 template <int MODE>
 __device__ inline int64_t tap_src(const ConvArgs& A, int b, int x, int y, int z, int tx, int ty, int tz) {
   int xi, yi, zi;
-  if (MODE == CONV_PERIODIC) {
-    xi = wrapi(x + tx - 1, A.ix); yi = wrapi(y + ty - 1, A.iy); zi = wrapi(z + tz - 1, A.iz);
-  } else if (MODE == CONV_VALID) {
+  if (MODE == CONV_VALID) {
     xi = x + tx; yi = y + ty; zi = z + tz;
   } else {
     xi = x + tx - 2; yi = y + ty - 2; zi = z + tz - 2;
@@ -120,6 +118,162 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs A) {
         if (A.out_bf) A.out_bf[on * COUT + co] = (__bf16)val;
         if (A.out_f32) A.out_f32[on * COUT + co] = val;
       }
+  }
+}
+
+// Whole-grid (periodic) layer, the one that runs inside every FGMRES
+// iteration.  A workgroup of 8 waves owns an output tile of 16 x 8 x 4 nodes;
+// its input halo (18 x 10 x 6 nodes) and the layer's weights sit in LDS, so
+// each input node is fetched from memory about twice instead of 27 times.
+// MFMA operands: A = weights (rows = 16 output channels), B = activations
+// (columns = 16 x-consecutive nodes), K = 32 (taps x input channels), so an
+// accumulator lane holds 4 consecutive channels of one node and stores them
+// as one 8-byte write.  Rows of 64 bytes (32 channels) are XOR-swizzled in
+// 16-byte chunks so that the 16 lanes of an LDS phase hit distinct banks.
+// Blocks are persistent; each prefetches its next tile's halo into registers
+// while it computes the current one, and the block -> tile order keeps
+// neighbouring tiles (shared halos) on one XCD.
+// IN_F64: the layer reads the FP64 grid vector v[3][N] times s (first layer);
+// OUT_F64: the layer writes z[c][N] = out[c] / s for c < 3 (last layer).
+constexpr int TLX = 16, TLY = 8, TLZ = 4, THX = TLX + 2, THY = TLY + 2, THZ = TLZ + 2, THN = THX * THY * THZ;
+constexpr int TNT = 512;
+
+struct TileArgs {
+  const __bf16* in;  // [N][CIN] (unless IN_F64)
+  const double* v;   // [3][N] (IN_F64)
+  double s;
+  const __bf16* w;   // [27][COUT][CIN]
+  __bf16* out;       // [N][COUT] (unless OUT_F64)
+  double* z;         // [3][N] (OUT_F64)
+  int nx, ny, nz, ntx, nty, ntiles;
+  int64_t N;
+};
+
+__device__ inline int pmod(int a, int n) {
+  const int r = a % n;
+  return r < 0 ? r + n : r;
+}
+// 16-byte chunk c of LDS row r (CH chunks per row)
+template <int CH>
+__device__ inline int swz(int r, int c) {
+  return CH == 4 ? r * 4 + (c ^ ((r >> 2) & 3)) : r * CH + c;
+}
+
+template <int CIN, int COUT, bool IN_F64, bool OUT_F64>
+__global__ __launch_bounds__(TNT) void k_conv_tile(TileArgs A) {
+  constexpr int NB = COUT / 16, TPK = 32 / CIN, NK = (27 + TPK - 1) / TPK, CH = CIN / 8;
+  constexpr int NLD = (THN * CH + TNT - 1) / TNT;
+  static_assert(!IN_F64 || CIN == 8, "FP64 input feeds the 8-channel first layer");
+  static_assert(!OUT_F64 || COUT == 16, "FP64 output comes from the 16-channel last layer");
+  __shared__ __attribute__((aligned(16))) bf8 sw[27 * COUT * CH];
+  __shared__ __attribute__((aligned(16))) bf8 sh[THN * CH];
+  for (int i = threadIdx.x; i < 27 * COUT * CH; i += TNT)
+    sw[swz<CH>(i / CH, i % CH)] = reinterpret_cast<const bf8*>(A.w)[i];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, row = lane & 15, kq = lane >> 4;
+  const int nblk = (int)gridDim.x;
+  int tile = (int)xcd_block(blockIdx.x, nblk);
+
+  bf8 pre[NLD];
+  double pd[IN_F64 ? NLD : 1][3];
+  auto fetch = [&](int tl) {
+    const int tx = tl % A.ntx, ty = (tl / A.ntx) % A.nty, tz = tl / (A.ntx * A.nty);
+    const int x0 = tx * TLX - 1, y0 = ty * TLY - 1, z0 = tz * TLZ - 1;
+#pragma unroll
+    for (int i = 0; i < NLD; ++i) {
+      const int c = threadIdx.x + i * TNT;
+      if (c < THN * CH) {
+        const int h = c / CH, part = c % CH;
+        const int hx = h % THX, hy = (h / THX) % THY, hz = h / (THX * THY);
+        const int64_t g = pmod(x0 + hx, A.nx) + (int64_t)A.nx * (pmod(y0 + hy, A.ny) + (int64_t)A.ny * pmod(z0 + hz, A.nz));
+        if constexpr (IN_F64) {
+          pd[i][0] = A.v[g];
+          pd[i][1] = A.v[A.N + g];
+          pd[i][2] = A.v[2 * A.N + g];
+        } else {
+          pre[i] = reinterpret_cast<const bf8*>(A.in)[g * CH + part];
+        }
+      }
+    }
+  };
+  auto stage = [&]() {
+#pragma unroll
+    for (int i = 0; i < NLD; ++i) {
+      const int c = threadIdx.x + i * TNT;
+      if (c < THN * CH) {
+        const int h = c / CH, part = c % CH;
+        bf8 x;
+        if constexpr (IN_F64) {
+          x = zero8();
+          x[0] = (__bf16)(float)(A.s * pd[i][0]);
+          x[1] = (__bf16)(float)(A.s * pd[i][1]);
+          x[2] = (__bf16)(float)(A.s * pd[i][2]);
+        } else {
+          x = pre[i];
+        }
+        sh[swz<CH>(h, part)] = x;
+      }
+    }
+  };
+
+  if (tile < A.ntiles) fetch(tile);
+  for (; tile < A.ntiles; tile += nblk) {
+    __syncthreads();  // the previous tile's readers are done (and the weights are in)
+    stage();
+    __syncthreads();
+    if (tile + nblk < A.ntiles) fetch(tile + nblk);  // in flight during the MFMA work
+    f4 acc[4][NB];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) acc[m][nb] = f4{0, 0, 0, 0};
+#pragma unroll 3
+    for (int q = 0; q < NK; ++q) {
+      const int traw = q * TPK + (8 * kq) / CIN;
+      const int c = ((8 * kq) % CIN) / 8;  // this lane's 16-byte chunk of the input channels
+      const bool tv = traw < 27;
+      const int t = tv ? traw : 26;
+      const int tx = t % 3, ty = (t / 3) % 3, tz = t / 9;
+      bf8 a[NB];
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) a[nb] = tv ? sw[swz<CH>(t * COUT + 16 * nb + row, c)] : zero8();
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const int r = 4 * wv + m, yy = r % TLY, zz = r / TLY;
+        const bf8 b = sh[swz<CH>(((zz + tz) * THY + yy + ty) * THX + row + tx, c)];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) acc[m][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[nb], b, acc[m][nb], 0, 0, 0);
+      }
+    }
+    // C[channel 16 nb + 4 kq + i][node row]
+    const int tx = tile % A.ntx, ty = (tile / A.ntx) % A.nty, tz = tile / (A.ntx * A.nty);
+    const int gx = tx * TLX + row;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int r = 4 * wv + m;
+      const int gy = ty * TLY + r % TLY, gz = tz * TLZ + r / TLY;
+      if (gx >= A.nx || gy >= A.ny || gz >= A.nz) continue;
+      const int64_t g = gx + (int64_t)A.nx * (gy + (int64_t)A.ny * gz);
+      if constexpr (OUT_F64) {
+        if (kq == 0) {
+          const double inv = 1.0 / A.s;
+          A.z[g] = (double)acc[m][0][0] * inv;
+          A.z[A.N + g] = (double)acc[m][0][1] * inv;
+          A.z[2 * A.N + g] = (double)acc[m][0][2] * inv;
+        }
+      } else {
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+          typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
+          bf4 o;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const float val = acc[m][nb][i];
+            o[i] = (__bf16)(val <= 0.0f ? 0.0f : val);  // ReLU that keeps NaN
+          }
+          *reinterpret_cast<bf4*>(A.out + g * COUT + 16 * nb + 4 * kq) = o;
+        }
+      }
+    }
   }
 }
 
@@ -201,23 +355,6 @@ __global__ void k_reduce_chunks(const float* __restrict__ part, int nchunk, int6
 }
 
 // ----------------------------------------------------------------- data movement
-// whole-grid input: in[g][0..2] = s * v[c][g], channels 3..7 zero
-__global__ void k_grid_to_bf16(int64_t N, const double* __restrict__ v, double s, __bf16* __restrict__ in) {
-  int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (g >= N) return;
-  bf8 x = zero8();
-  x[0] = (__bf16)(float)(s * v[g]);
-  x[1] = (__bf16)(float)(s * v[N + g]);
-  x[2] = (__bf16)(float)(s * v[2 * N + g]);
-  reinterpret_cast<bf8*>(in)[g] = x;
-}
-// z[c][g] = out[g][c] / s
-__global__ void k_grid_from_f32(int64_t N, const float* __restrict__ out, double s, double* __restrict__ z) {
-  int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (g >= N) return;
-  for (int c = 0; c < 3; ++c) z[c * N + g] = (double)out[g * 16 + c] / s;
-}
-
 // Training crops: crop b has origin org[b] (periodic), pairs (p0, p1) with
 // weights (w0, w1).  Input box (n+6)^3 of the residual combination (BF16, 8
 // channels), target box n^3 (offset 3) of the correction combination (FP32).
@@ -357,8 +494,7 @@ static const int LCIN[3] = {3, 32, 32}, LCOUT[3] = {32, 32, 3}, LCIP[3] = {8, 32
 struct ge_cnn_state {
   float *w, *g, *m, *v;            // master weights, gradient, Adam moments (CNN_NW floats)
   __bf16 *wf[3], *wb[3];           // packed forward / backward weights
-  __bf16 *act0, *act1, *act2;      // whole-grid activations
-  float* out;                      // whole-grid output [N][16]
+  __bf16 *act1, *act2;             // whole-grid activations [N][32]
   int64_t grid_cap;
   // training buffers
   __bf16 *t_in, *t_a1, *t_a2, *t_dz, *t_d2, *t_d1;
@@ -393,8 +529,8 @@ static ge_cnn_state* cnn(ge_ctx* c) { return (ge_cnn_state*)c->cnn; }
 void ge_cnn_free(ge_ctx* c) {
   ge_cnn_state* s = cnn(c);
   if (!s) return;
-  void* ptrs[] = {s->w, s->g, s->m, s->v, s->wf[0], s->wf[1], s->wf[2], s->wb[0], s->wb[1], s->wb[2], s->act0, s->act1,
-                  s->act2, s->out, s->t_in, s->t_a1, s->t_a2, s->t_dz, s->t_d2, s->t_d1, s->t_z, s->t_tgt, s->t_part,
+  void* ptrs[] = {s->w, s->g, s->m, s->v, s->wf[0], s->wf[1], s->wf[2], s->wb[0], s->wb[1], s->wb[2], s->act1,
+                  s->act2, s->t_in, s->t_a1, s->t_a2, s->t_dz, s->t_d2, s->t_d1, s->t_z, s->t_tgt, s->t_part,
                   s->t_gpad, s->t_loss, s->t_meta, s->t_wts, s->pr, s->pe};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -488,31 +624,40 @@ static void conv(ge_ctx* c, const ConvArgs& A) {
   hipLaunchKernelGGL((k_conv<CIN, COUT, MODE>), dim3((unsigned)nb), dim3(256), 0, c->stream, A);
 }
 
-// z = N(v) on the whole periodic grid (v, z: device double [3][N]).
+template <int CIN, int COUT, bool IN_F64, bool OUT_F64>
+static void conv_tile(ge_ctx* c, TileArgs A) {
+  A.ntx = (A.nx + TLX - 1) / TLX;
+  A.nty = (A.ny + TLY - 1) / TLY;
+  A.ntiles = A.ntx * A.nty * ((A.nz + TLZ - 1) / TLZ);
+  // resident workgroups per CU from the LDS footprint (160 KB per CU), 256 CUs
+  constexpr int lds = (27 * COUT * CIN + THN * CIN) * 2;
+  constexpr int per_cu = (160 * 1024) / lds < 4 ? (160 * 1024) / lds : 4;
+  const int nb = A.ntiles < 256 * per_cu ? A.ntiles : 256 * per_cu;
+  hipLaunchKernelGGL((k_conv_tile<CIN, COUT, IN_F64, OUT_F64>), dim3(nb), dim3(TNT), 0, c->stream, A);
+}
+
+// z = N(s v) / s on the whole periodic grid (v, z: device double [3][N]).
 int ge_cnn_apply_grid(ge_ctx* c, const double* v, double* z, double scale) {
   ge_cnn_state* s = cnn(c);
   if (!s || !s->ready) return ge_fail(c, GE_ERR_STATE, "CNN weights not initialised");
   const int64_t N = c->G.N;
   if (s->grid_cap < N) {
-    int rc = calloc_dev(c, &s->act0, sizeof(__bf16) * 8 * N);
-    if (!rc) rc = calloc_dev(c, &s->act1, sizeof(__bf16) * 32 * N);
+    if (s->act1) { (void)hipFree(s->act1); s->act1 = nullptr; }
+    if (s->act2) { (void)hipFree(s->act2); s->act2 = nullptr; }
+    int rc = calloc_dev(c, &s->act1, sizeof(__bf16) * 32 * N);
     if (!rc) rc = calloc_dev(c, &s->act2, sizeof(__bf16) * 32 * N);
-    if (!rc) rc = calloc_dev(c, &s->out, sizeof(float) * 16 * N);
     if (rc) return rc;
     s->grid_cap = N;
   }
-  hipLaunchKernelGGL(k_grid_to_bf16, g1(N), dim3(256), 0, c->stream, N, v, scale, s->act0);
-  ConvArgs A;
+  TileArgs A;
   std::memset(&A, 0, sizeof(A));
-  A.B = 1;
-  A.ix = A.ox = c->G.n[0]; A.iy = A.oy = c->G.n[1]; A.iz = A.oz = c->G.n[2];
-  A.in = s->act0; A.w = s->wf[0]; A.out_bf = s->act1; A.relu = 1;
-  conv<8, 32, CONV_PERIODIC>(c, A);
-  A.in = s->act1; A.w = s->wf[1]; A.out_bf = s->act2;
-  conv<32, 32, CONV_PERIODIC>(c, A);
-  A.in = s->act2; A.w = s->wf[2]; A.out_bf = nullptr; A.out_f32 = s->out; A.relu = 0;
-  conv<32, 16, CONV_PERIODIC>(c, A);
-  hipLaunchKernelGGL(k_grid_from_f32, g1(N), dim3(256), 0, c->stream, N, s->out, scale, z);
+  A.nx = c->G.n[0]; A.ny = c->G.n[1]; A.nz = c->G.n[2]; A.N = N; A.s = scale;
+  A.v = v; A.w = s->wf[0]; A.out = s->act1;
+  conv_tile<8, 32, true, false>(c, A);
+  A.v = nullptr; A.in = s->act1; A.w = s->wf[1]; A.out = s->act2;
+  conv_tile<32, 32, false, false>(c, A);
+  A.in = s->act2; A.w = s->wf[2]; A.out = nullptr; A.z = z;
+  conv_tile<32, 16, false, true>(c, A);
   GE_HIP(c, hipGetLastError());
   return GE_OK;
 }
@@ -609,16 +754,19 @@ static int train_step_grad(ge_ctx* c, double* loss) {
   return GE_OK;
 }
 
-int ge_cnn_harvesting(const ge_ctx* c) { return c && c->cnn && ((ge_cnn_state*)c->cnn)->harvest; }
+int ge_cnn_harvesting(const ge_ctx* c) { return (c && c->cnn) ? ((ge_cnn_state*)c->cnn)->harvest : 0; }
 
 // ----------------------------------------------------------------- C ABI
 extern "C" {
 
-int ge_cnn_init(ge_ctx* c, uint32_t seed) {
+int ge_cnn_init(ge_ctx* c, uint32_t seed, int max_pairs) {
   if (!c) return GE_ERR_ARG;
   if (c->G.dim != 3) return ge_fail(c, GE_ERR_ARG, "the CNN preconditioner is built for 3D grids");
+  if (max_pairs < 0 || max_pairs > 1024) return ge_fail(c, GE_ERR_ARG, "max_pairs out of range (0..1024)");
   int rc = cnn_setup(c);
   if (rc) return rc;
+  ge_cnn_state* s = cnn(c);
+  if (!s->pr) s->cap_pairs = max_pairs ? max_pairs : 64;
   return cnn_init_weights(c, seed, 0.02);
 }
 
@@ -662,7 +810,7 @@ int ge_cnn_add_pair(ge_ctx* c, const double* r, const double* e) {
   ge_cnn_state* s = cnn(c);
   const int64_t n3 = 3 * c->G.N;
   if (!s->pr) {
-    s->cap_pairs = GE_CNN_MAX_PAIRS;
+    if (s->cap_pairs < 1) s->cap_pairs = 64;
     rc = calloc_dev(c, &s->pr, sizeof(float) * n3 * s->cap_pairs);
     if (!rc) rc = calloc_dev(c, &s->pe, sizeof(float) * n3 * s->cap_pairs);
     if (rc) return rc;
@@ -683,11 +831,12 @@ int ge_cnn_add_pair(ge_ctx* c, const double* r, const double* e) {
   return GE_OK;
 }
 
-int ge_cnn_harvest(ge_ctx* c, int on) {
+int ge_cnn_harvest(ge_ctx* c, int flags) {
   if (!c) return GE_ERR_ARG;
+  if (flags & ~(GE_HARVEST_SOLUTION | GE_HARVEST_KRYLOV)) return ge_fail(c, GE_ERR_ARG, "unknown harvest flags");
   int rc = cnn_setup(c);
   if (rc) return rc;
-  cnn(c)->harvest = on;
+  cnn(c)->harvest = flags;
   return GE_OK;
 }
 

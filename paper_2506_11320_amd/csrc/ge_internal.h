@@ -8,7 +8,6 @@
 #include "glecsim.h"
 
 #define GE_MAX_SPECIES 4
-#define GE_CNN_MAX_PAIRS 16
 #define GE_WAVE 64
 
 // Device view of the periodic mesh.  Inactive axes have n = 1 and are never
@@ -108,6 +107,7 @@ struct ge_ctx {
   int64_t scan_nblocks;
   // Krylov workspace
   int kr_m;
+  int kr_last;  // Arnoldi vectors built in the last GMRES cycle
   double *V, *Zp, *kw, *kr, *kx, *hdev, *partials, *scal;
   int64_t nred_blocks;
   int* flags;            // [0] CFL clamp, [1] run overflow, [2] load error

@@ -134,6 +134,7 @@ int ge_gmres(ge_ctx* c, double tol, int maxit, int m, int precond, ge_solve_repo
   const double cnn_scale = std::sqrt((double)n);  // basis vectors have unit norm: RMS = 1/sqrt(n)
   int fallback = 0;
   int rc;
+  c->kr_last = 0;
   double* x = c->Eth;
   double* V = c->V;
   double* w = c->kw;
@@ -161,9 +162,16 @@ int ge_gmres(ge_ctx* c, double tol, int maxit, int m, int precond, ge_solve_repo
     GE_HIP(c, hipStreamSynchronize(c->stream));
     const double beta = std::sqrt(b2);
     if (!std::isfinite(beta)) return ge_fail(c, GE_ERR_NONFINITE, "non-finite residual in GMRES");
+    const double rel_prev = rel;
     rel = beta / bref;
     if (rel <= tol) { conv = 1; break; }
     if (it >= maxit) break;
+    if (precond == GE_PC_CNN && restarts > 0 && rel > 0.5 * rel_prev) {
+      // a whole flexible cycle gained less than a factor 2: the network does
+      // not help on this system; finish with plain GMRES from here
+      precond = GE_PC_NONE;
+      fallback = 1;
+    }
     hipLaunchKernelGGL(k_normalize, vgrid(n), dim3(KB), 0, c->stream, V, V, hd + 128, n);
     std::fill(s.begin(), s.end(), 0.0);
     s[0] = beta;
@@ -225,11 +233,22 @@ int ge_gmres(ge_ctx* c, double tol, int maxit, int m, int precond, ge_solve_repo
       if (std::fabs(s[j + 1]) <= tol * bref || hn == 0.0) break;
     }
     if (k < 0) continue;  // cycle abandoned (fallback)
+    c->kr_last = k;
     // y = H^{-1} s; x += M^{-1} (V y)  (flexible: x += Z y)
+    bool yfinite = true;
     for (int i = k - 1; i >= 0; --i) {
       double t = s[i];
       for (int l = i + 1; l < k; ++l) t -= H[(size_t)i * m + l] * y[l];
       y[i] = t / H[(size_t)i * m + i];
+      yfinite = yfinite && std::isfinite(y[i]);
+    }
+    if (!yfinite) {
+      // singular least-squares system: only a preconditioner that maps some
+      // v_j to zero (or a null direction of A) gets here
+      if (precond != GE_PC_CNN) return ge_fail(c, GE_ERR_NONFINITE, "singular GMRES least-squares system");
+      precond = GE_PC_NONE;
+      fallback = 1;
+      continue;
     }
     GE_HIP(c, hipMemcpyAsync(hd + 192, y.data(), sizeof(double) * k, hipMemcpyHostToDevice, c->stream));
     if (precond == GE_PC_NONE) {

@@ -21,6 +21,7 @@ GE_WARN_NOT_CONVERGED = 1
 GE_FP64, GE_FP32 = 0, 1
 GE_A_LIGHT, GE_A_BULK = 0, 1
 GE_PC_NONE, GE_PC_JACOBI, GE_PC_CNN = 0, 1, 2
+GE_HARVEST_SOLUTION, GE_HARVEST_KRYLOV = 1, 2
 FIELDS = {
     "E": 0, "B": 1, "Eth": 2, "Bn": 3, "J_lab": 4, "J_eff": 5, "rho": 6, "mm": 7, "mass": 8, "u": 9,
     "EM": 10, "Mt": 11, "M0": 12, "kappa_E": 13, "kappa_B": 14, "rhs": 15,
@@ -107,7 +108,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.ge_apply_operator.argtypes = [vp, vp, vp]
     L.ge_diagnostics.argtypes = [vp, ctypes.POINTER(GEDiag)]
     L.ge_timings.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
-    L.ge_cnn_init.argtypes = [vp, ctypes.c_uint32]
+    L.ge_cnn_init.argtypes = [vp, ctypes.c_uint32, ctypes.c_int]
     L.ge_cnn_size.argtypes = []
     L.ge_cnn_weights.argtypes = [vp, ctypes.c_int, vp]
     L.ge_cnn_apply.argtypes = [vp, vp, vp]
@@ -268,8 +269,8 @@ class Simulation:
                 "P": [[dg.P[s][d] for d in range(3)] for s in range(self.nsp)], "gauss": dg.gauss}
 
     # -------------------------------------------------- learned preconditioner
-    def cnn_init(self, seed: int = 0):
-        self._check(self.L.ge_cnn_init(self.h, seed))
+    def cnn_init(self, seed: int = 0, max_pairs: int = 0):
+        self._check(self.L.ge_cnn_init(self.h, seed, max_pairs))
 
     def cnn_size(self) -> int:
         return int(self.L.ge_cnn_size())
@@ -293,8 +294,8 @@ class Simulation:
         self._check(self.L.ge_cnn_apply(self.h, _ptr(r), _ptr(z)))
         return z
 
-    def cnn_harvest(self, on: bool = True):
-        self._check(self.L.ge_cnn_harvest(self.h, int(on)))
+    def cnn_harvest(self, flags: int = GE_HARVEST_SOLUTION):
+        self._check(self.L.ge_cnn_harvest(self.h, int(flags)))
 
     def cnn_add_pair(self, r: torch.Tensor, e: torch.Tensor):
         r = r.to(device=self.device, dtype=torch.float64).contiguous()

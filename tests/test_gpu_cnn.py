@@ -151,6 +151,7 @@ def test_pair_store_keeps_the_newest_sixteen():
     n = (6, 5, 4)
     N = n[0] * n[1] * n[2]
     sim = _ctx(n)
+    sim.cnn_init(0, max_pairs=16)
     rng = np.random.default_rng(0)
     for i in range(20):
         r = torch.from_numpy(rng.standard_normal((3, N)))
@@ -167,26 +168,30 @@ def _reconnection_case():
 
 
 def test_training_and_flexible_gmres():
-    from paper_2506_11320_amd import GE_PC_CNN
+    from paper_2506_11320_amd import GE_HARVEST_KRYLOV, GE_HARVEST_SOLUTION, GE_PC_CNN
     print("[gpu] cnn harvest/train/FGMRES", flush=True)
     wl, parts, E, B = _reconnection_case()
     sim = H.make_sim(wl, parts, E, B)
     sim.cnn_init(3)
-    sim.cnn_harvest(True)
+    sim.cnn_harvest(GE_HARVEST_SOLUTION)
     for _ in range(6):
         rep = sim.step(tol=1e-10)
         assert rep["converged"]
     assert sim.cnn_npairs() == 6
+    # Krylov pairs: (A v_j, v_j) for the Arnoldi vectors 1..k-1 of the last cycle
+    sim.cnn_harvest(GE_HARVEST_SOLUTION | GE_HARVEST_KRYLOV)
+    rep = sim.step(tol=1e-10)
+    assert sim.cnn_npairs() == 6 + 1 + (rep["iterations"] - 1)
     tr = sim.cnn_train(crop=6, batch=8, iters=80, lr=2e-3, seed=5)
     print(f"  train {tr}", flush=True)
-    assert tr["steps"] == 80 and tr["pairs"] == 6
+    assert tr["steps"] == 80 and tr["pairs"] == sim.cnn_npairs()
     assert np.isfinite(tr["loss_last"]) and tr["loss_last"] < tr["loss_first"]
     w1 = sim.cnn_weights()
     # training is deterministic: re-initialise and train again
     sim.cnn_init(3)
     sim.cnn_train(crop=6, batch=8, iters=80, lr=2e-3, seed=5)
     assert np.array_equal(sim.cnn_weights(), w1)
-    sim.cnn_harvest(False)
+    sim.cnn_harvest(0)
     sim.deposit()
     tol = 1e-9
     rp = sim.solve(tol=tol)
@@ -212,6 +217,23 @@ def test_nonfinite_network_falls_back_to_plain_gmres():
     w = sim.cnn_weights()
     w[27 * 3 * 32 + 5] = np.nan
     sim.cnn_set_weights(w)
+    sim.deposit()
+    rp = sim.solve(tol=1e-9)
+    Ep = sim.gather("Eth").cpu().numpy()
+    rc = sim.solve(tol=1e-9, precond=GE_PC_CNN)
+    assert rc["fallback"] and rc["converged"] and rc["relres"] <= 1e-9
+    assert H.relerr(sim.gather("Eth").cpu().numpy(), Ep) <= 1e-6
+    sim.close()
+
+
+def test_zero_network_falls_back_to_plain_gmres():
+    """A network that maps everything to zero makes the flexible least-squares
+    problem singular; the solve must finish with plain GMRES."""
+    from paper_2506_11320_amd import GE_PC_CNN
+    wl, parts, E, B = _reconnection_case()
+    sim = H.make_sim(wl, parts, E, B)
+    sim.cnn_init(1)
+    sim.cnn_set_weights(np.zeros(sim.cnn_size(), dtype=np.float32))
     sim.deposit()
     rp = sim.solve(tol=1e-9)
     Ep = sim.gather("Eth").cpu().numpy()
