@@ -83,5 +83,6 @@ def oracle_grid_pass(wl, G, sp, E, B, comoving=None, beta_lim=None, a_mode=None,
     for s in sp:
         a = O.deposit_species(G, s.q, s.m, O.beta_s(s.q, s.m, wl.dt), s.x, s.v, s.w, dep["Bn"])
         Js.append(a["J"])
+    dep["J_s"] = Js
     dep["J_scale"] = sum(np.linalg.norm(j) for j in Js)
     return dep
