@@ -105,6 +105,15 @@ int ge_create(const ge_grid* grid, const ge_params* params, void* hip_stream, ge
   c->NR = c->ND;
   c->Q = 18 * c->NR + c->NC * (7 + GE_MAX_SPECIES);
   c->kr_m = 64;
+  {
+    int dev = 0;
+    c->n_cu = 256;
+    if (hipGetDevice(&dev) == hipSuccess) {
+      int n = 0;
+      if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0) c->n_cu = n;
+    }
+    (void)hipGetLastError();
+  }
   const size_t es = params->precision == GE_FP32 ? 4 : 8;
   int rc = GE_OK;
   double** f3[] = {&c->E, &c->B, &c->Eth, &c->Bn, &c->Jlab, &c->Jeff, &c->mm, &c->u, &c->utmp, &c->EM, &c->rhs, &c->Bnew,

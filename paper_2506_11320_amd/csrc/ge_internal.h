@@ -107,6 +107,7 @@ struct ge_ctx {
   int64_t scan_nblocks;
   // Krylov workspace
   int kr_m;
+  int n_cu;     // compute units of the device (persistent launches)
   int kr_last;  // Arnoldi vectors built in the last GMRES cycle
   double *V, *Zp, *kw, *kr, *kx, *hdev, *partials, *scal;
   int64_t nred_blocks;

@@ -38,6 +38,9 @@ __device__ inline double rl(double x, int l) {
   int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
   return __longlong_as_double(((int64_t)hi << 32) | (uint32_t)lo);
 }
+// 1/x: the hardware reciprocal (1 ulp) in FP32, a true division in FP64
+__device__ inline float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ inline double recip(double x) { return 1.0 / x; }
 __device__ inline uint64_t lanemask_lt(int lane) { return lane == 0 ? 0ull : ((~0ull) >> (64 - lane)); }
 
 // Offset e (neighbour h = c + e along one axis) of rank j in ascending order
@@ -144,7 +147,7 @@ __device__ inline int push_one(T f[3], T v[3], const T* fc, T beta, const T dtx[
   gather_lds<T, DIM>(W, fc + 3 * NC, Bp);
   const T t0 = v[0] + beta * Ep[0], t1 = v[1] + beta * Ep[1], t2 = v[2] + beta * Ep[2];
   const T b2 = Bp[0] * Bp[0] + Bp[1] * Bp[1] + Bp[2] * Bp[2];
-  const T den = (T)1 / ((T)1 + beta * beta * b2);
+  const T den = recip((T)1 + beta * beta * b2);
   const T tb = beta * beta * (t0 * Bp[0] + t1 * Bp[1] + t2 * Bp[2]);
   const T vb0 = (t0 + beta * (t1 * Bp[2] - t2 * Bp[1]) + tb * Bp[0]) * den;
   const T vb1 = (t1 + beta * (t2 * Bp[0] - t0 * Bp[2]) + tb * Bp[1]) * den;
@@ -446,155 +449,376 @@ template <typename T, int DIM>
 struct DepCfg {
   static constexpr int NR = Dm<DIM>::ND;
   static constexpr int NRB = Dm<DIM>::NRB;
-  static constexpr int AW = 16 * NRB;            // A values per particle (row blocks interleaved)
-  static constexpr int ST = AW + 16;             // staged values per particle
-  static constexpr int WPB = 2;                  // wavefronts per workgroup
-  static constexpr int NACC = NR * (18 + 7 + GE_MAX_SPECIES);
+  // staged row of a particle: its NR A values (quadratic rows), then the 16 B
+  // columns, padded to a multiple of 4.  ST / 4 is odd (3D: 11, 2D: 7, 1D: 5),
+  // so the 16 lanes of a 16-byte write phase hit 16 different bank groups.
+  static constexpr int AW = NR;
+  static constexpr int ST = (NR + 16 + 3) / 4 * 4;
+  static constexpr int NACC = NR * (7 + GE_MAX_SPECIES);  // linear sums only (quadratic ones stay in registers)
 };
 
+// Run table of one cell for two species at once: lanes 0..26 hold the runs
+// of species 0 (and 2), lanes 32..58 those of species 1 (and 3).
+struct RunRegs {
+  int cnt[2], st[2];
+};
+// All loads below are issued unconditionally (out-of-range lanes read a valid
+// dummy address and drop the value): a load under a branch makes the
+// compiler's wait-count analysis fall back to "wait for everything" at the
+// join, which would stall on the prefetched data of the next cell.
 template <typename T, int DIM>
-__global__ __launch_bounds__(128) void k_deposit(DGrid G, DepArgs<T> A) {
+__device__ inline RunRegs load_runs(const DGrid& G, int64_t c, const DepArgs<T>& A, int lane) {
+  RunRegs R;
+  const int r0 = lane & 31, half = lane >> 5;
+  const int r = r0 < Dm<DIM>::ND ? r0 : 0;
+  int cx, cy, cz;
+  unflat3(G, c, cx, cy, cz);
+  const int ex = axis_order(cx, G.n[0], r % 3);
+  const int ey = DIM >= 2 ? axis_order(cy, G.n[1], (r / 3) % 3) : 0;
+  const int ez = DIM >= 3 ? axis_order(cz, G.n[2], r / 9) : 0;
+  const int64_t h = flat3(G, cx + ex, cy + ey, cz + ez);
+  const int dir = (1 - ex) + (DIM >= 2 ? 3 * (1 - ey) : 0) + (DIM >= 3 ? 9 * (1 - ez) : 0);
+  const int64_t o = (int64_t)dir * G.N + h;
+  // species (half) and (half + 2): base pointer of the even species plus a
+  // uniform byte distance to the odd one, so the address is base + select
+  const int nsp = A.nsp;
+  const uintptr_t c0 = (uintptr_t)A.sp[0].sub_cnt, s0 = (uintptr_t)A.sp[0].sub_start;
+  const uintptr_t c1 = nsp > 1 ? (uintptr_t)A.sp[1].sub_cnt : c0, s1 = nsp > 1 ? (uintptr_t)A.sp[1].sub_start : s0;
+  const uintptr_t c2 = nsp > 2 ? (uintptr_t)A.sp[2].sub_cnt : c0, s2 = nsp > 2 ? (uintptr_t)A.sp[2].sub_start : s0;
+  const uintptr_t c3 = nsp > 3 ? (uintptr_t)A.sp[3].sub_cnt : c2, s3 = nsp > 3 ? (uintptr_t)A.sp[3].sub_start : s2;
+  const int64_t ob = o * (int64_t)sizeof(int32_t);
+  typedef const __attribute__((address_space(1))) int32_t* gptr;  // global, not flat
+  const int32_t v0 = *(gptr)(c0 + (half ? c1 - c0 : 0) + ob);
+  const int32_t w0 = *(gptr)(s0 + (half ? s1 - s0 : 0) + ob);
+  const int32_t v1 = *(gptr)(c2 + (half ? c3 - c2 : 0) + ob);
+  const int32_t w1 = *(gptr)(s2 + (half ? s3 - s2 : 0) + ob);
+  // raw values: lanes without a run are masked where the values are used, so
+  // that nothing touches the loaded registers before the data are needed
+  R.cnt[0] = v0;
+  R.st[0] = w0;
+  R.cnt[1] = v1;
+  R.st[1] = w1;
+  return R;
+}
+
+// Wavefront scans on DPP lane moves (no LDS round trips): row_shr:1,2,4,8
+// within each row of 16 lanes (sources outside the row read 0), then
+// row_bcast:15 / row_bcast:31 carry the row totals forward.  0 must be the
+// identity of the operation (sums, or maxima of non-negative values).
+template <bool MAX, bool HALVES>
+__device__ inline int dpp_scan(int x) {
+#define GE_DPP_STEP(CTRL, RMASK)                                              \
+  {                                                                         \
+    const int y = __builtin_amdgcn_update_dpp(0, x, CTRL, RMASK, 0xf, true); \
+    x = MAX ? max(x, y) : x + y;                                            \
+  }
+  GE_DPP_STEP(0x111, 0xf)  // row_shr:1
+  GE_DPP_STEP(0x112, 0xf)  // row_shr:2
+  GE_DPP_STEP(0x114, 0xf)  // row_shr:4
+  GE_DPP_STEP(0x118, 0xf)  // row_shr:8
+  GE_DPP_STEP(0x142, 0xa)  // row_bcast:15 into rows 1 and 3
+  if (!HALVES) GE_DPP_STEP(0x143, 0xc)  // row_bcast:31 into rows 2 and 3
+#undef GE_DPP_STEP
+  return x;
+}
+
+// Per-wave LDS of the deposit: compacted run tables of the current and the
+// next cell, the run-start markers, corner values, MFMA staging, accumulators.
+template <typename T, int DIM, int NSLOT>
+struct DepLds {
+  int runs[NSLOT][GE_MAX_SPECIES][2][32];  // [slot][species][start, pre][run]
+  int nseg[NSLOT][GE_MAX_SPECIES];
+  int total[NSLOT][GE_MAX_SPECIES];
+  T fc[24];
+  union {  // the run-start markers are dead before the staging starts
+    int mark[2][128];
+    __attribute__((aligned(16))) T stage[64 * DepCfg<T, DIM>::ST];
+  };
+  T acc[DepCfg<T, DIM>::NACC];
+};
+
+// Compact the run tables R (of one cell) into slot sl and find the source
+// index of the particles t = lane and t = 64 + lane of species 0 and 1
+// (-1 where t is past the species' count).
+template <typename T, int DIM, int NSLOT>
+__device__ inline void runs_locate(RunRegs R, DepLds<T, DIM, NSLOT>& L, int sl, int nsp, int lane, int idx[2][2]) {
+  const int half = lane >> 5, r = lane & 31;
+  {
+    const bool ok = r < Dm<DIM>::ND;
+    if (!(ok && half < nsp)) { R.cnt[0] = 0; R.st[0] = 0; }
+    if (!(ok && half + 2 < nsp)) { R.cnt[1] = 0; R.st[1] = 0; }
+  }
+  int pre[2];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int incl = dpp_scan<false, true>(R.cnt[k]);  // within each half
+    pre[k] = incl - R.cnt[k];
+    const int t0 = __builtin_amdgcn_readlane(incl, 31), t1 = __builtin_amdgcn_readlane(incl, 63);
+    const int tot = half ? t1 : t0;
+    const uint64_t m = __ballot(R.cnt[k] > 0);
+    const uint32_t mh = (uint32_t)(m >> (32 * half));
+    const int sp = half + 2 * k;
+    if (R.cnt[k] > 0) {
+      const int pos = __popc(mh & ((1u << r) - 1u));
+      L.runs[sl][sp][0][pos] = R.st[k];
+      L.runs[sl][sp][1][pos] = pre[k];
+    }
+    if (r == 0) {
+      L.nseg[sl][sp] = __popc(mh);
+      L.total[sl][sp] = sp < nsp ? tot : 0;
+    }
+  }
+  // run-start markers hold lane + 1 (0 = no run starts here)
+  L.mark[0][lane] = 0; L.mark[0][64 + lane] = 0;
+  L.mark[1][lane] = 0; L.mark[1][64 + lane] = 0;
+  wave_sync();
+  if (R.cnt[0] > 0 && pre[0] < 128) L.mark[half][pre[0]] = lane + 1;
+  wave_sync();
+  const int basev = R.st[0] - pre[0];
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    const int tot = L.total[sl][s];
+    const int s0 = dpp_scan<true, false>(L.mark[s][lane]);
+    const int m0 = s0 - 1;
+    const int m1 = max(dpp_scan<true, false>(L.mark[s][64 + lane]), __builtin_amdgcn_readlane(s0, 63)) - 1;
+    const int b0 = __shfl(basev, m0 & 63, 64), b1 = __shfl(basev, m1 & 63, 64);
+    idx[s][0] = lane < tot ? b0 + lane : -1;
+    idx[s][1] = 64 + lane < tot ? b1 + 64 + lane : -1;
+  }
+}
+
+template <typename T>
+struct PState {
+  T f[3], v[3], w;
+};
+template <typename T, int DIM>
+__device__ inline void load_p(const DepSpecies<T>& S, int i, PState<T>& P) {
+  i = i < 0 ? 0 : i;  // every buffer holds at least one element
+  const int64_t N = S.n;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) P.f[d] = d < DIM ? S.off[d * N + i] : (T)0;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) P.v[d] = S.v[d * N + i];
+  P.w = S.w[i];
+}
+
+// Persistent wavefronts, each owning a contiguous range of cells.  While a
+// wave computes cell c, the particles and corner fields of cell c+1 and the
+// run table of cell c+2 are already on their way (two-stage software
+// pipeline), so the dependent loads of a cell (run table -> particles) never
+// stall the wave.
+template <typename T, int DIM, bool PIPE, int WPB>
+__global__ __launch_bounds__(64 * WPB) void k_deposit(DGrid G, DepArgs<T> A, int64_t nwaves) {
   using M = Mfma<T>;
   typedef typename M::v4 v4;
   using C = DepCfg<T, DIM>;
-  constexpr int NC = Dm<DIM>::NC, NRB = C::NRB, NR = C::NR, AW = C::AW, ST = C::ST, WPB = C::WPB;
-  __shared__ int s_start[WPB][32], s_pre[WPB][32];
-  __shared__ T s_fc[WPB][24];
-  __shared__ __attribute__((aligned(16))) T s_stage[WPB][64 * ST];
-  __shared__ T s_acc[WPB][C::NACC];
+  constexpr int NC = Dm<DIM>::NC, NRB = C::NRB, NR = C::NR, AW = C::AW, ST = C::ST;
+  __shared__ DepLds<T, DIM, PIPE ? 2 : 1> s_l[WPB];
   const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t c = xcd_block(blockIdx.x, gridDim.x) * WPB + wid;
-  if (c >= G.N) return;
-  T* fc = s_fc[wid];
-  T* stage = s_stage[wid];
-  T* acc_mt = s_acc[wid];          // [NR][9]
-  T* acc_m0 = acc_mt + 9 * NR;     // [NR][9]
-  T* acc_lin = acc_m0 + 9 * NR;    // [NR][7]: q alpha v (3), m v (3), m w
-  T* acc_rho = acc_lin + 7 * NR;   // [NR][GE_MAX_SPECIES]
-  corners_to_lds<T, DIM>(G, c, A.Bn, fc, lane);
-  for (int k = lane; k < C::NACC; k += 64) s_acc[wid][k] = 0;
+  const int64_t gw = xcd_block(blockIdx.x, gridDim.x) * WPB + wid;
+  // PIPE: persistent waves over contiguous cell ranges; else one cell per wave
+  const int64_t cb = PIPE ? gw * G.N / nwaves : gw, ce = PIPE ? (gw + 1) * G.N / nwaves : gw + 1;
+  if (!PIPE && cb >= G.N) return;
+  if (cb >= ce) return;
+  DepLds<T, DIM, PIPE ? 2 : 1>& L = s_l[wid];
+  T* acc_lin = L.acc;             // [NR][7]: q alpha v (3), m v (3), m w
+  T* acc_rho = acc_lin + 7 * NR;  // [NR][GE_MAX_SPECIES]
   const int col = lane & 15;
-  for (int s = 0; s < A.nsp; ++s) {
-    const DepSpecies<T>& S = A.sp[s];
-    int nseg;
-    const int total = runs_setup<DIM>(G, c, S.sub_start, S.sub_cnt, s_start[wid], s_pre[wid], lane, nseg);
-    v4 acc[NRB];
+  const int cq = lane / NC, ca = lane % NC;  // corner value loaded by this lane
+  // MFMA operand reads of a step: row 4 stp + lane/16, A row col (and 16 +
+  // col), B column col.  A rows past NR read other values of the row: their
+  // products land in accumulator rows that are never used.
+  const int rofsA0 = (lane >> 4) * ST + col, rofsA1 = rofsA0 + 16, rofsB = (lane >> 4) * ST + AW + col;
+
+  auto corner = [&](int64_t c) -> T {
+    const bool ok = lane < 3 * NC;
+    const int q = ok ? cq : 0, a = ok ? ca : 0;
+    const int64_t g = nbr3(G, c, a & 1, DIM >= 2 ? (a >> 1) & 1 : 0, DIM >= 3 ? (a >> 2) & 1 : 0);
+    const T val = A.Bn[q * G.N + g];
+    return ok ? val : (T)0;
+  };
+  const DepSpecies<T>& S1 = A.nsp > 1 ? A.sp[1] : A.sp[0];  // a valid buffer even without species 1
+
+  // pipeline prologue
+  PState<T> Pn[2][2];
+  int idx[2][2];
+  RunRegs R = load_runs<T, DIM>(G, cb, A, lane);
+  runs_locate(R, L, 0, A.nsp, lane, idx);
 #pragma unroll
-    for (int rb = 0; rb < NRB; ++rb) acc[rb] = v4{0, 0, 0, 0};
-    const int64_t N = S.n;
-    for (int t0 = 0; t0 < total; t0 += 64) {
-      const int t = t0 + lane;
-      T* my = stage + lane * ST;
-      if (t < total) {
-        const int i = run_index(t, s_start[wid], s_pre[wid], nseg);
-        T f[3] = {0, 0, 0}, v[3];
+  for (int j = 0; j < 2; ++j) load_p<T, DIM>(A.sp[0], idx[0][j], Pn[0][j]);
 #pragma unroll
-        for (int d = 0; d < DIM; ++d) f[d] = S.off[d * N + i];
+  for (int j = 0; j < 2; ++j) load_p<T, DIM>(S1, idx[1][j], Pn[1][j]);
+  T cv = corner(cb);
+  if constexpr (PIPE) R = load_runs<T, DIM>(G, cb + 1 < ce ? cb + 1 : cb, A, lane);
+
+  for (int64_t c = cb; c < ce; ++c) {
+    const int sl = (int)((c - cb) & 1);
+    PState<T> P[2][2];
 #pragma unroll
-        for (int d = 0; d < 3; ++d) v[d] = S.v[d * N + i];
-        const T w = S.w[i];
-        T W[8];
-        lin_weights<T, DIM>(f, W);
-        T Bp[3];
-        gather_lds<T, DIM>(W, fc, Bp);
-        const T be = S.beta, bb = be * be;
-        const T den = (T)1 / ((T)1 + bb * (Bp[0] * Bp[0] + Bp[1] * Bp[1] + Bp[2] * Bp[2]));
-        const T wd = w * den;
-        T al[9];  // w alpha (Sec. 3.1), row-major
-        al[0] = (1 + bb * Bp[0] * Bp[0]) * wd;
-        al[1] = (be * Bp[2] + bb * Bp[0] * Bp[1]) * wd;
-        al[2] = (-be * Bp[1] + bb * Bp[0] * Bp[2]) * wd;
-        al[3] = (-be * Bp[2] + bb * Bp[1] * Bp[0]) * wd;
-        al[4] = (1 + bb * Bp[1] * Bp[1]) * wd;
-        al[5] = (be * Bp[0] + bb * Bp[1] * Bp[2]) * wd;
-        al[6] = (be * Bp[1] + bb * Bp[2] * Bp[0]) * wd;
-        al[7] = (-be * Bp[0] + bb * Bp[2] * Bp[1]) * wd;
-        al[8] = (1 + bb * Bp[2] * Bp[2]) * wd;
-        T* bcol = my + AW;
+    for (int s = 0; s < 2; ++s)
 #pragma unroll
-        for (int k = 0; k < 9; ++k) bcol[k] = al[k];
+      for (int j = 0; j < 2; ++j) P[s][j] = Pn[s][j];
+    if (lane < 3 * NC) L.fc[lane] = cv;
+    for (int k = lane; k < C::NACC; k += 64) L.acc[k] = 0;
+    // stage 1: run table of c+1 -> particle and corner loads of c+1; stage 2:
+    // run table of c+2 (past the range end the last cell is loaded again and
+    // ignored, so that the loads stay unconditional)
+    if constexpr (PIPE) {
+      const int64_t c1 = c + 1 < ce ? c + 1 : c, c2 = c + 2 < ce ? c + 2 : ce - 1;
+      runs_locate(R, L, sl ^ 1, A.nsp, lane, idx);
 #pragma unroll
-        for (int r = 0; r < 3; ++r) bcol[9 + r] = al[3 * r] * v[0] + al[3 * r + 1] * v[1] + al[3 * r + 2] * v[2];
+      for (int j = 0; j < 2; ++j) load_p<T, DIM>(A.sp[0], idx[0][j], Pn[0][j]);
 #pragma unroll
-        for (int r = 0; r < 3; ++r) bcol[12 + r] = w * v[r];
-        bcol[15] = w;
-        T X[3][3];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-          if (d < DIM) {
-            const T g0 = (T)1 - f[d];
-            X[d][0] = g0 * g0;
-            X[d][1] = f[d] * g0;
-            X[d][2] = f[d] * f[d];
-          } else {
-            X[d][0] = 1; X[d][1] = 0; X[d][2] = 0;
-          }
-        }
-        // A rows r and 16 + r interleaved: my[NRB * k + rb] = A[16 rb + k]
-#pragma unroll
-        for (int k = 0; k < 16; ++k)
-#pragma unroll
-          for (int rb = 0; rb < NRB; ++rb) {
-            const int r = 16 * rb + k;
-            my[NRB * k + rb] = r < NR ? X[0][r % 3] * X[1][(r / 3) % 3] * X[2][r / 9] : (T)0;
-          }
-      } else {
-#pragma unroll
-        for (int k = 0; k < ST; ++k) my[k] = 0;
-      }
-      wave_sync();
-      const int nsteps = (min(64, total - t0) + 3) >> 2;
-      for (int stp = 0; stp < nsteps; ++stp) {
-        const T* prow = stage + (4 * stp + (lane >> 4)) * ST;
-        const T b = prow[AW + col];
-        if (NRB == 2) {
-          typedef T t2 __attribute__((ext_vector_type(2)));
-          const t2 a = *reinterpret_cast<const t2*>(prow + 2 * col);
-          acc[0] = M::op(a[0], b, acc[0]);
-          acc[NRB - 1] = M::op(a[1], b, acc[NRB - 1]);
-        } else {
-          acc[0] = M::op(prow[col], b, acc[0]);
-        }
-      }
-      wave_sync();
+      for (int j = 0; j < 2; ++j) load_p<T, DIM>(S1, idx[1][j], Pn[1][j]);
+      cv = corner(c1);
+      R = load_runs<T, DIM>(G, c2, A, lane);
     }
-    // scale this species' sums into the cell accumulators (each (row, col)
-    // belongs to one lane, so no two lanes touch the same LDS word)
-    const T qs = S.q, ms = S.m, bq = S.beta * S.q;
+    wave_sync();
+    // Mtilde and M0 rows (B columns 0..8) accumulate over species in registers
+    v4 aMt[NRB], aM0[NRB];
 #pragma unroll
-    for (int rb = 0; rb < NRB; ++rb)
+    for (int rb = 0; rb < NRB; ++rb) aMt[rb] = aM0[rb] = v4{0, 0, 0, 0};
+    for (int s = 0; s < A.nsp; ++s) {
+      const DepSpecies<T>& S = A.sp[s];
+      const int total = L.total[sl][s];
+      v4 acc[NRB];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int r = 16 * rb + M::row(lane, i);
-        if (r >= NR) continue;
-        const T val = acc[rb][i];
-        if (col < 9) {
-          acc_mt[r * 9 + col] += bq * val;
-          acc_m0[r * 9 + col] += qs * val;
+      for (int rb = 0; rb < NRB; ++rb) acc[rb] = v4{0, 0, 0, 0};
+      // one chunk of up to 64 particles: operands to LDS, then the MFMA sweep
+      auto chunk = [&](const PState<T>& q, int t0) {
+        const int t = t0 + lane;
+        T vals[ST];  // A rows 0..NR-1, then the 16 B columns
+        if (t < total) {
+          const T* f = q.f;
+          const T* v = q.v;
+          const T w = q.w;
+          T W[8];
+          lin_weights<T, DIM>(f, W);
+          T Bp[3];
+          gather_lds<T, DIM>(W, L.fc, Bp);
+          const T be = S.beta, bb = be * be;
+          const T den = recip((T)1 + bb * (Bp[0] * Bp[0] + Bp[1] * Bp[1] + Bp[2] * Bp[2]));
+          const T wd = w * den;
+          T al[9];  // w alpha (Sec. 3.1), row-major
+          al[0] = (1 + bb * Bp[0] * Bp[0]) * wd;
+          al[1] = (be * Bp[2] + bb * Bp[0] * Bp[1]) * wd;
+          al[2] = (-be * Bp[1] + bb * Bp[0] * Bp[2]) * wd;
+          al[3] = (-be * Bp[2] + bb * Bp[1] * Bp[0]) * wd;
+          al[4] = (1 + bb * Bp[1] * Bp[1]) * wd;
+          al[5] = (be * Bp[0] + bb * Bp[1] * Bp[2]) * wd;
+          al[6] = (be * Bp[1] + bb * Bp[2] * Bp[0]) * wd;
+          al[7] = (-be * Bp[0] + bb * Bp[2] * Bp[1]) * wd;
+          al[8] = (1 + bb * Bp[2] * Bp[2]) * wd;
+          T* bcol = vals + AW;
+#pragma unroll
+          for (int k = 0; k < 9; ++k) bcol[k] = al[k];
+#pragma unroll
+          for (int r = 0; r < 3; ++r) bcol[9 + r] = al[3 * r] * v[0] + al[3 * r + 1] * v[1] + al[3 * r + 2] * v[2];
+#pragma unroll
+          for (int r = 0; r < 3; ++r) bcol[12 + r] = w * v[r];
+          bcol[15] = w;
+          T X[3][3];
+#pragma unroll
+          for (int d = 0; d < 3; ++d) {
+            if (d < DIM) {
+              const T g0 = (T)1 - f[d];
+              X[d][0] = g0 * g0;
+              X[d][1] = f[d] * g0;
+              X[d][2] = f[d] * f[d];
+            } else {
+              X[d][0] = 1; X[d][1] = 0; X[d][2] = 0;
+            }
+          }
+          T YZ[9];
+#pragma unroll
+          for (int k = 0; k < 9; ++k) YZ[k] = X[1][k % 3] * X[2][k / 3];
+#pragma unroll
+          for (int r = 0; r < NR; ++r) vals[r] = X[0][r % 3] * YZ[r / 3];
+#pragma unroll
+          for (int k = NR + 16; k < ST; ++k) vals[k] = 0;
         } else {
+#pragma unroll
+          for (int k = 0; k < ST; ++k) vals[k] = 0;
+        }
+        {
+          typedef T t4 __attribute__((ext_vector_type(4)));
+          t4* row = reinterpret_cast<t4*>(L.stage + lane * ST);
+#pragma unroll
+          for (int j = 0; j < ST / 4; ++j) row[j] = t4{vals[4 * j], vals[4 * j + 1], vals[4 * j + 2], vals[4 * j + 3]};
+        }
+        wave_sync();
+        const int nsteps = (min(64, total - t0) + 3) >> 2;
+        // fully unrolled: the step's row offset is an immediate of the LDS read,
+        // the lane's column offsets are precomputed (rofs*)
+#pragma unroll
+        for (int stp = 0; stp < 16; ++stp) {
+          if (stp < nsteps) {
+            const T* rows = L.stage + 4 * stp * ST;
+            const T b = rows[rofsB];
+            acc[0] = M::op(rows[rofsA0], b, acc[0]);
+            if (NRB == 2) acc[NRB - 1] = M::op(rows[rofsA1], b, acc[NRB - 1]);
+          }
+        }
+        wave_sync();
+      };
+      // particles 0..127 of species 0 and 1 come from the prefetched registers
+      // (selected with compile-time indices: a dynamic index would send the
+      // arrays to scratch memory); the rest are loaded here
+      const int nfast = s < 2 ? min(total, 128) : 0;
+      if (nfast > 0) chunk(s == 0 ? P[0][0] : P[1][0], 0);
+      if (nfast > 64) chunk(s == 0 ? P[0][1] : P[1][1], 64);
+      for (int t0 = nfast; t0 < total; t0 += 64) {
+        PState<T> q;
+        const int t = t0 + lane;
+        load_p<T, DIM>(S, t < total ? run_index(t, L.runs[sl][s][0], L.runs[sl][s][1], L.nseg[sl][s]) : -1, q);
+        chunk(q, t0);
+      }
+      // scale this species' sums into the cell accumulators (each (row, col)
+      // belongs to one lane, so no two lanes touch the same LDS word)
+      const T qs = S.q, ms = S.m, bq = S.beta * S.q;
+#pragma unroll
+      for (int rb = 0; rb < NRB; ++rb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const T val = acc[rb][i];
+          aMt[rb][i] += bq * val;
+          aM0[rb][i] += qs * val;
+          const int r = 16 * rb + M::row(lane, i);
+          if (r >= NR || col < 9) continue;
           acc_lin[r * 7 + col - 9] += (col < 12 ? qs : ms) * val;
           if (col == 15) acc_rho[r * GE_MAX_SPECIES + s] += qs * val;
         }
-      }
-  }
-  wave_sync();
-  // write the cell: quadratic rows of Mtilde and M0, then corner sums of the
-  // linear quantities, W_a = prod_d (X_{a_d} + X_{a_d + 1})
-  T* Q = A.cellQ;
-  const int Qn = A.Qn;
-  for (int k = lane; k < 18 * NR; k += 64) Q[cq_index(c, k, Qn)] = acc_mt[k];
-  const int NK = 7 + A.nsp;
-  for (int t = lane; t < NC * NK; t += 64) {
-    const int a = t % NC, k = t / NC;
-    T sum = 0;
-#pragma unroll
-    for (int b = 0; b < NC; ++b) {
-      int r = (a & 1) + (b & 1);
-      if (DIM >= 2) r += 3 * (((a >> 1) & 1) + ((b >> 1) & 1));
-      if (DIM >= 3) r += 9 * (((a >> 2) & 1) + ((b >> 2) & 1));
-      sum += k < 7 ? acc_lin[r * 7 + k] : acc_rho[r * GE_MAX_SPECIES + (k - 7)];
     }
-    Q[cq_index(c, 18 * NR + k * NC + a, Qn)] = sum;
+    wave_sync();
+    // write the cell: quadratic rows of Mtilde and M0, then corner sums of the
+    // linear quantities, W_a = prod_d (X_{a_d} + X_{a_d + 1})
+    T* Qc = A.cellQ + cq_index(c, 0, A.Qn);  // value k of this cell at Qc[4 k]
+    if (col < 9) {
+#pragma unroll
+      for (int rb = 0; rb < NRB; ++rb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int r = 16 * rb + M::row(lane, i);
+          if (r < NR) {
+            Qc[4 * (r * 9 + col)] = aMt[rb][i];
+            Qc[4 * (9 * NR + r * 9 + col)] = aM0[rb][i];
+          }
+        }
+    }
+    const int NK = 7 + A.nsp;
+    for (int t = lane; t < NC * NK; t += 64) {
+      const int a = t % NC, k = t / NC;
+      T sum = 0;
+#pragma unroll
+      for (int b = 0; b < NC; ++b) {
+        int r = (a & 1) + (b & 1);
+        if (DIM >= 2) r += 3 * (((a >> 1) & 1) + ((b >> 1) & 1));
+        if (DIM >= 3) r += 9 * (((a >> 2) & 1) + ((b >> 2) & 1));
+        sum += k < 7 ? acc_lin[r * 7 + k] : acc_rho[r * GE_MAX_SPECIES + (k - 7)];
+      }
+      Qc[4 * (18 * NR + k * NC + a)] = sum;
+    }
+    wave_sync();
   }
 }
 
@@ -725,6 +949,11 @@ int ge_launch_push(ge_ctx* c, int s) {
   return GE_OK;
 }
 
+// deposit launch shape: persistent pipelined waves or one wave per cell, and
+// wavefronts per workgroup
+constexpr bool DEP_PIPE = false;
+constexpr int DEP_WPB = 1;
+
 template <typename T, int DIM>
 static void launch_deposit_t(ge_ctx* c) {
   DepArgs<T> A;
@@ -739,9 +968,26 @@ static void launch_deposit_t(ge_ctx* c) {
   A.Bn = sizeof(T) == 4 ? (const T*)c->Bn32 : (const T*)c->Bn;
   A.cellQ = (T*)c->cellQ;
   A.Qn = c->Q;
-  constexpr int WPB = DepCfg<T, DIM>::WPB;
-  const int64_t nb = (c->G.N + WPB - 1) / WPB;
-  hipLaunchKernelGGL((k_deposit<T, DIM>), dim3(nb), dim3(64 * WPB), 0, c->stream, c->G, A);
+  if (DEP_PIPE) {
+    // persistent grid: as many workgroups as fit on the device at once
+    static int per_cu[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
+    int& occ = per_cu[sizeof(T) == 4][DIM];
+    if (!occ) {
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+              &occ, reinterpret_cast<const void*>(&k_deposit<T, DIM, true, DEP_WPB>), 64 * DEP_WPB, 0) != hipSuccess ||
+          occ < 1)
+        occ = 1;
+    }
+    int64_t nb = (int64_t)occ * c->n_cu;
+    const int64_t need = (c->G.N + DEP_WPB - 1) / DEP_WPB;  // at least one cell per wave
+    if (nb > need) nb = need;
+    hipLaunchKernelGGL((k_deposit<T, DIM, true, DEP_WPB>), dim3((unsigned)nb), dim3(64 * DEP_WPB), 0, c->stream, c->G, A,
+                       nb * DEP_WPB);
+  } else {
+    const int64_t nb = (c->G.N + DEP_WPB - 1) / DEP_WPB;
+    hipLaunchKernelGGL((k_deposit<T, DIM, false, DEP_WPB>), dim3((unsigned)nb), dim3(64 * DEP_WPB), 0, c->stream, c->G,
+                       A, c->G.N);
+  }
 }
 
 int ge_launch_deposit(ge_ctx* c) {
