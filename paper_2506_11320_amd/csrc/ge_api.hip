@@ -126,10 +126,7 @@ int ge_create(const ge_grid* grid, const ge_params* params, void* hip_stream, ge
   if (!rc) rc = dalloc(c, &c->kE, sizeof(double) * 9 * N);
   if (!rc) rc = dalloc(c, &c->kB, sizeof(double) * 9 * N);
   if (!rc) rc = dalloc(c, &c->jac, sizeof(double) * 9 * N);
-  if (!rc && params->precision == GE_FP32) {
-    rc = dalloc(c, &c->Eth32, sizeof(float) * 3 * N);
-    if (!rc) rc = dalloc(c, &c->Bn32, sizeof(float) * 3 * N);
-  }
+  if (!rc) rc = dalloc(c, &c->node8, es * 8 * N);
   if (!rc) rc = dalloc(c, &c->Mt, es * c->nh * 9 * N);
   if (!rc) rc = dalloc(c, &c->M0, es * c->nh * 9 * N);
   if (!rc) rc = dalloc(c, &c->cellQ, es * (size_t)c->Q * ((N + 3) / 4 * 4));
@@ -169,8 +166,7 @@ void ge_destroy(ge_ctx* c) {
                   &c->EM, &c->anode, &c->kE, &c->kB, &c->rhs, &c->Bnew, &c->ccell, &c->jac, &c->V, &c->Zp,
                   &c->kw, &c->kr, &c->kx, &c->hdev, &c->partials, &c->scal};
   for (auto p : f) dfree(*p);
-  dfree(c->Eth32);
-  dfree(c->Bn32);
+  dfree(c->node8);
   dfree(c->Mt);
   dfree(c->M0);
   dfree(c->cellQ);
@@ -179,9 +175,7 @@ void ge_destroy(ge_ctx* c) {
   dfree(c->flags);
   for (int s = 0; s < c->nsp; ++s)
     for (int b = 0; b < 2; ++b) {
-      dfree(c->sp[s].off[b]);
-      dfree(c->sp[s].v[b]);
-      dfree(c->sp[s].w[b]);
+      dfree(c->sp[s].rec[b]);
       dfree(c->sp[s].sub_start[b]);
       dfree(c->sp[s].sub_cnt[b]);
     }
@@ -210,16 +204,14 @@ int ge_add_species(ge_ctx* c, const ge_species* sp, int64_t n, const int32_t* ce
   const size_t es = c->P.precision == GE_FP32 ? 4 : 8;
   int rc = GE_OK;
   for (int b = 0; b < 2 && !rc; ++b) {
-    rc = dalloc(c, &S.off[b], es * 3 * n);
-    if (!rc) rc = dalloc(c, &S.v[b], es * 3 * n);
-    if (!rc) rc = dalloc(c, &S.w[b], es * n);
+    rc = dalloc(c, &S.rec[b], es * 8 * n);
     if (!rc) rc = dalloc(c, &S.sub_start[b], sizeof(int32_t) * c->ND * c->G.N);
     if (!rc) rc = dalloc(c, &S.sub_cnt[b], sizeof(int32_t) * c->ND * c->G.N);
   }
   c->nsp = s + 1;  // so that ge_destroy frees partial allocations
   if (rc) {
     for (int b = 0; b < 2; ++b) {
-      dfree(S.off[b]); dfree(S.v[b]); dfree(S.w[b]); dfree(S.sub_start[b]); dfree(S.sub_cnt[b]);
+      dfree(S.rec[b]); dfree(S.sub_start[b]); dfree(S.sub_cnt[b]);
     }
     c->nsp = s;
     return rc;
@@ -229,7 +221,7 @@ int ge_add_species(ge_ctx* c, const ge_species* sp, int64_t n, const int32_t* ce
   rc = check_flags(c);
   if (rc) {
     for (int b = 0; b < 2; ++b) {
-      dfree(S.off[b]); dfree(S.v[b]); dfree(S.w[b]); dfree(S.sub_start[b]); dfree(S.sub_cnt[b]);
+      dfree(S.rec[b]); dfree(S.sub_start[b]); dfree(S.sub_cnt[b]);
     }
     c->nsp = s;
     return rc;
@@ -299,8 +291,7 @@ int ge_push(ge_ctx* c) {
   if (!c) return GE_ERR_ARG;
   if (!c->have_solve) return ge_fail(c, GE_ERR_STATE, "ge_push needs E^{n+theta} (solve or ge_set GE_F_ETH)");
   int rc;
-  if (c->P.precision == GE_FP32)
-    if ((rc = ge_launch_to_f32(c, c->Eth, c->Eth32, 3 * c->G.N))) return rc;
+  if ((rc = ge_launch_pack_node8(c, 0))) return rc;
   for (int s = 0; s < c->nsp; ++s)
     if ((rc = ge_launch_scan_counts(c, s))) return rc;
   (void)hipEventRecord(c->ev[0], c->stream);
@@ -382,7 +373,7 @@ int ge_set(ge_ctx* c, int what, const double* src) {
   }
   GE_HIP(c, hipMemcpyAsync(dst, src, sizeof(double) * 3 * N, hipMemcpyDeviceToDevice, c->stream));
   if (what == GE_F_ETH) c->have_solve = 1;
-  if (what == GE_F_BN && c->P.precision == GE_FP32) return ge_launch_to_f32(c, c->Bn, c->Bn32, 3 * N);
+  if (what == GE_F_BN) return ge_launch_pack_node8(c, 1);
   return GE_OK;
 }
 

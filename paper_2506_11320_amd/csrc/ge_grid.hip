@@ -21,7 +21,7 @@ __device__ inline int ax_bit(int a, int d) { return (a >> d) & 1; }
 
 // ----------------------------------------------------------------- node average of B
 template <int DIM>
-__global__ void k_node_avg(DGrid G, const double* __restrict__ B, double* __restrict__ Bn, float* __restrict__ Bn32) {
+__global__ void k_node_avg(DGrid G, const double* __restrict__ B, double* __restrict__ Bn) {
   int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (g >= G.N) return;
   for (int q = 0; q < 3; ++q) {
@@ -30,8 +30,16 @@ __global__ void k_node_avg(DGrid G, const double* __restrict__ B, double* __rest
       s += B[q * G.N + nbr3(G, g, -ax_bit(a, 0), DIM >= 2 ? -ax_bit(a, 1) : 0, DIM >= 3 ? -ax_bit(a, 2) : 0)];
     s /= Gd<DIM>::NC;
     Bn[q * G.N + g] = s;
-    if (Bn32) Bn32[q * G.N + g] = (float)s;
   }
+}
+
+// node8[g][4 half + q] = src[q][g] in the particle precision, [4 half + 3] = 0
+template <typename T>
+__global__ void k_pack_node8(int64_t N, const double* __restrict__ src, int half, T* __restrict__ node8) {
+  int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (g >= N) return;
+  typedef T t4 __attribute__((ext_vector_type(4)));
+  reinterpret_cast<t4*>(node8)[2 * g + half] = t4{(T)src[g], (T)src[N + g], (T)src[2 * N + g], (T)0};
 }
 
 // ----------------------------------------------------------------- assembly
@@ -502,8 +510,18 @@ inline dim3 grid1(int64_t n) { return dim3((unsigned)((n + 255) / 256)); }
   }
 
 int ge_launch_node_avg(ge_ctx* c) {
-  float* b32 = c->P.precision == GE_FP32 ? c->Bn32 : nullptr;
-  DISPATCH_DIM(c, k_node_avg, grid1(c->G.N), dim3(256), 0, c->stream, c->G, c->B, c->Bn, b32);
+  DISPATCH_DIM(c, k_node_avg, grid1(c->G.N), dim3(256), 0, c->stream, c->G, c->B, c->Bn);
+  GE_HIP(c, hipGetLastError());
+  return ge_launch_pack_node8(c, 1);
+}
+
+int ge_launch_pack_node8(ge_ctx* c, int half) {
+  const double* src = half ? c->Bn : c->Eth;
+  if (c->P.precision == GE_FP32)
+    hipLaunchKernelGGL(k_pack_node8<float>, grid1(c->G.N), dim3(256), 0, c->stream, c->G.N, src, half, (float*)c->node8);
+  else
+    hipLaunchKernelGGL(k_pack_node8<double>, grid1(c->G.N), dim3(256), 0, c->stream, c->G.N, src, half,
+                       (double*)c->node8);
   GE_HIP(c, hipGetLastError());
   return GE_OK;
 }
@@ -634,12 +652,6 @@ int ge_launch_widen_M(ge_ctx* c, const void* M, double* dst) {
     hipLaunchKernelGGL((k_convert<float, double>), grid1(n), dim3(256), 0, c->stream, (const float*)M, dst, n);
   else
     GE_HIP(c, hipMemcpyAsync(dst, M, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
-  GE_HIP(c, hipGetLastError());
-  return GE_OK;
-}
-
-int ge_launch_to_f32(ge_ctx* c, const double* src, float* dst, int64_t n) {
-  hipLaunchKernelGGL((k_convert<double, float>), grid1(n), dim3(256), 0, c->stream, src, dst, n);
   GE_HIP(c, hipGetLastError());
   return GE_OK;
 }

@@ -78,9 +78,7 @@ struct HalfStencil<3> {
 struct SpeciesBuf {
   double q, m, beta;     // beta = q dt / (2 m)
   int64_t n;
-  void* off[2];          // T[3][n]
-  void* v[2];            // T[3][n]
-  void* w[2];            // T[n]
+  void* rec[2];          // T[n][8]: offset in the cell (3), w, velocity (3), 0
   int32_t* sub_start[2]; // [ND][Ncell]: start of the run (home cell, direction)
   int32_t* sub_cnt[2];   // [ND][Ncell]
   int cur;
@@ -97,7 +95,7 @@ struct ge_ctx {
   // fields (double)
   double *E, *B, *Eth, *Bn, *Jlab, *Jeff, *rho, *mm, *mass, *u, *utmp, *EM, *anode, *kE, *kB, *rhs, *Bnew, *ccell;
   // FP32 copies for particle gathers
-  float *Eth32, *Bn32;
+  void* node8;  // T[N][8] in the particle precision: E^{n+theta} (3), 0, node-averaged B^n (3), 0
   // mass matrices (T) and per-cell partial sums (T)
   void *Mt, *M0, *cellQ;
   // Jacobi blocks (double [9][N], inverted 3x3 per node)
@@ -141,7 +139,7 @@ int ge_launch_node_avg(ge_ctx* c);
 int ge_launch_apply_A(ge_ctx* c, const double* x, double* y);
 int ge_launch_update(ge_ctx* c);
 int ge_launch_widen_M(ge_ctx* c, const void* M, double* dst);
-int ge_launch_to_f32(ge_ctx* c, const double* src, float* dst, int64_t n);
+int ge_launch_pack_node8(ge_ctx* c, int half);  // half 0: E^{n+theta} from Eth, 1: B from Bn
 int ge_launch_jacobi_setup(ge_ctx* c);
 int ge_launch_jacobi_apply(ge_ctx* c, const double* x, double* y);
 int ge_launch_field_diag(ge_ctx* c, double* out);  // W_E, W_B, gauss (sync)

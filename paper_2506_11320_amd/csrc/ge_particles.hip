@@ -43,6 +43,28 @@ __device__ inline float recip(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ inline double recip(double x) { return 1.0 / x; }
 __device__ inline uint64_t lanemask_lt(int lane) { return lane == 0 ? 0ull : ((~0ull) >> (64 - lane)); }
 
+// Wavefront scans on DPP lane moves (no LDS round trips): row_shr:1,2,4,8
+// within each row of 16 lanes (sources outside the row read 0), then
+// row_bcast:15 / row_bcast:31 carry the row totals forward.  0 must be the
+// identity of the operation (sums, or maxima of non-negative values).
+template <bool MAX, bool HALVES>
+__device__ inline int dpp_scan(int x) {
+#define GE_DPP_STEP(CTRL, RMASK)                                              \
+  {                                                                         \
+    const int y = __builtin_amdgcn_update_dpp(0, x, CTRL, RMASK, 0xf, true); \
+    x = MAX ? max(x, y) : x + y;                                            \
+  }
+  GE_DPP_STEP(0x111, 0xf)  // row_shr:1
+  GE_DPP_STEP(0x112, 0xf)  // row_shr:2
+  GE_DPP_STEP(0x114, 0xf)  // row_shr:4
+  GE_DPP_STEP(0x118, 0xf)  // row_shr:8
+  GE_DPP_STEP(0x142, 0xa)  // row_bcast:15 into rows 1 and 3
+  if (!HALVES) GE_DPP_STEP(0x143, 0xc)  // row_bcast:31 into rows 2 and 3
+#undef GE_DPP_STEP
+  return x;
+}
+
+
 // Offset e (neighbour h = c + e along one axis) of rank j in ascending order
 // of the neighbour's coordinate, on a periodic axis of n >= 3 cells.
 __device__ inline int axis_order(int ci, int n, int j) {
@@ -70,13 +92,8 @@ __device__ int runs_setup(const DGrid& G, int64_t c, const int32_t* __restrict__
     cnt = sub_cnt[(int64_t)dir * G.N + h];
     st = sub_start[(int64_t)dir * G.N + h];
   }
-  int incl = cnt;
-#pragma unroll
-  for (int d = 1; d < 32; d <<= 1) {
-    int t = __shfl_up(incl, d, 64);
-    if (lane >= d) incl += t;
-  }
-  int total = rl_i(incl, 31);
+  const int incl = dpp_scan<false, false>(cnt);
+  const int total = rl_i(incl, 31);
   uint64_t m = __ballot(cnt > 0);
   if (cnt > 0) {
     int pos = __popcll(m & lanemask_lt(lane));
@@ -95,15 +112,22 @@ __device__ inline int run_index(int t, const int* s_start, const int* s_pre, int
   return s_start[k] + (t - s_pre[k]);
 }
 
-// Field values at the 2^DIM corner nodes of cell c into the wavefront's LDS
-// slot fc[3 NC] (component-major); lanes < 3 NC each load one value.
+// E and B at the 2^DIM corner nodes of cell c, from the node records ([N][8]:
+// E (3), 0, B (3), 0), into the wavefront's LDS slot, component-major:
+// fc[q NC + a] = E_q and fc[(3 + q) NC + a] = B_q at corner a.  Lane 2a + h
+// loads half h of corner a as one vector.
 template <typename T, int DIM>
-__device__ inline void corners_to_lds(const DGrid& G, int64_t c, const T* __restrict__ F, T* fc, int lane) {
+__device__ inline void corners_to_lds(const DGrid& G, int64_t c, const T* __restrict__ NF, T* fc, int lane) {
   constexpr int NC = Dm<DIM>::NC;
-  if (lane < 3 * NC) {
-    const int q = lane / NC, a = lane % NC;
+  typedef T t4 __attribute__((ext_vector_type(4)));
+  if (lane < 2 * NC) {
+    const int a = lane >> 1, h = lane & 1;
     const int64_t g = nbr3(G, c, a & 1, DIM >= 2 ? (a >> 1) & 1 : 0, DIM >= 3 ? (a >> 2) & 1 : 0);
-    fc[lane] = F[q * G.N + g];
+    const t4 x = reinterpret_cast<const t4*>(NF)[2 * g + h];
+    T* dst = fc + 3 * h * NC + a;
+    dst[0] = x[0];
+    dst[NC] = x[1];
+    dst[2 * NC] = x[2];
   }
 }
 
@@ -176,11 +200,11 @@ __device__ inline int push_one(T f[3], T v[3], const T* fc, T beta, const T dtx[
 // ------------------------------------------------------------------ push
 template <typename T>
 struct PushArgs {
-  const T *off, *v, *w;
-  T *off_o, *v_o, *w_o;
+  const T* rec;  // particle records [n][8], read
+  T* rec_o;      // written
   const int32_t *sub_start, *sub_cnt, *seg_next;
   int32_t *sub_start_o, *sub_cnt_o;
-  const T *E, *B;  // E^{n+theta} and node-averaged B^n, [3][N]
+  const T* NF;   // node fields [N][8]: E^{n+theta}, node-averaged B^n
   T beta;
   T dtx[3];
   int64_t n;
@@ -211,33 +235,31 @@ __device__ inline DirStats dir_stats(bool act, int dir, int lane) {
   r.count_k = lane < 27 ? __popcll(kk) : 0;
   return r;
 }
-__device__ inline int excl_scan32(int x, int lane) {
-  int incl = x;
-#pragma unroll
-  for (int d = 1; d < 32; d <<= 1) {
-    const int t = __shfl_up(incl, d, 64);
-    if (lane >= d) incl += t;
-  }
-  return incl - x;
-}
+__device__ inline int excl_scan(int x) { return dpp_scan<false, false>(x) - x; }
 
+// Particle record i: two vectors of 4, (offset x, y, z, w) and (v x, y, z, 0).
+template <typename T, int DIM>
+__device__ inline void read_rec(const T* __restrict__ rec, int64_t i, T f[3], T v[3], T& w) {
+  typedef T t4 __attribute__((ext_vector_type(4)));
+  const t4 a = reinterpret_cast<const t4*>(rec)[2 * i], b = reinterpret_cast<const t4*>(rec)[2 * i + 1];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) f[d] = d < DIM ? a[d] : (T)0;
+  v[0] = b[0]; v[1] = b[1]; v[2] = b[2];
+  w = a[3];
+}
+template <typename T>
+__device__ inline void write_rec(T* __restrict__ rec, int64_t o, const T f[3], const T v[3], T w) {
+  typedef T t4 __attribute__((ext_vector_type(4)));
+  reinterpret_cast<t4*>(rec)[2 * o] = t4{f[0], f[1], f[2], w};
+  reinterpret_cast<t4*>(rec)[2 * o + 1] = t4{v[0], v[1], v[2], (T)0};
+}
 template <typename T, int DIM>
 __device__ inline void load_particle(const PushArgs<T>& A, int i, T f[3], T v[3], T& w) {
-  const int64_t N = A.n;
-#pragma unroll
-  for (int d = 0; d < 3; ++d) f[d] = d < DIM ? A.off[d * N + i] : (T)0;
-#pragma unroll
-  for (int d = 0; d < 3; ++d) v[d] = A.v[d * N + i];
-  w = A.w[i];
+  read_rec<T, DIM>(A.rec, i, f, v, w);
 }
 template <typename T>
 __device__ inline void store_particle(const PushArgs<T>& A, int64_t o, const T f[3], const T v[3], T w) {
-  const int64_t N = A.n;
-#pragma unroll
-  for (int d = 0; d < 3; ++d) A.off_o[d * N + o] = f[d];
-#pragma unroll
-  for (int d = 0; d < 3; ++d) A.v_o[d * N + o] = v[d];
-  A.w_o[o] = w;
+  write_rec<T>(A.rec_o, o, f, v, w);
 }
 
 // One wavefront per cell: push every particle present in the cell and write
@@ -248,32 +270,50 @@ template <typename T, int DIM>
 __global__ __launch_bounds__(256) void k_push(DGrid G, PushArgs<T> A) {
   constexpr int ND = Dm<DIM>::ND, NC = Dm<DIM>::NC;
   __shared__ int s_start[4][32], s_pre[4][32];
+  __shared__ int s_mark[4][128];
   __shared__ T s_fc[4][48];
   const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t c = xcd_block(blockIdx.x, gridDim.x) * 4 + wid;
+  // the cell is uniform over the wave: keep its index (and coordinates) scalar
+  const int64_t c = __builtin_amdgcn_readfirstlane((int)(xcd_block(blockIdx.x, gridDim.x) * 4 + wid));
   if (c >= G.N) return;
   T* fc = s_fc[wid];
-  corners_to_lds<T, DIM>(G, c, A.E, fc, lane);
-  corners_to_lds<T, DIM>(G, c, A.B, fc + 3 * NC, lane);
+  corners_to_lds<T, DIM>(G, c, A.NF, fc, lane);
   int nseg;
-  const int total = runs_setup<DIM>(G, c, A.sub_start, A.sub_cnt, s_start[wid], s_pre[wid], lane, nseg);
+  int* sst = s_start[wid];
+  int* spr = s_pre[wid];
+  const int total = runs_setup<DIM>(G, c, A.sub_start, A.sub_cnt, sst, spr, lane, nseg);
   const int64_t base = A.seg_next[c];
   int cnt = 0, dir_off = 0, clamped = 0, bad = 0;
   if (total <= 128) {
+    // particle t = lane and t = 64 + lane: run k from a max-scan of run-start
+    // markers (k + 1 at position s_pre[k], 0 elsewhere)
+    int* mk = s_mark[wid];
+    mk[lane] = 0;
+    mk[64 + lane] = 0;
+    wave_sync();
+    if (lane < nseg) {
+      const int p0 = spr[lane];
+      if (p0 < 128) mk[p0] = lane + 1;
+    }
+    wave_sync();
+    const int m0 = dpp_scan<true, false>(mk[lane]);
+    const int m1 = max(dpp_scan<true, false>(mk[64 + lane]), rl_i(m0, 63));
     T f0[3], v0[3], w0 = 0, f1[3], v1[3], w1 = 0;
     const bool a0 = lane < total, a1 = 64 + lane < total;
+    const int k0 = a0 ? m0 - 1 : 0, k1 = a1 ? m1 - 1 : 0;
+    const int i0 = sst[k0] + lane - spr[k0], i1 = sst[k1] + 64 + lane - spr[k1];
     int d0 = 31, d1 = 31;
     if (a0) {
-      load_particle<T, DIM>(A, run_index(lane, s_start[wid], s_pre[wid], nseg), f0, v0, w0);
+      load_particle<T, DIM>(A, i0, f0, v0, w0);
       d0 = push_one<T, DIM>(f0, v0, fc, A.beta, A.dtx, clamped);
     }
     if (a1) {
-      load_particle<T, DIM>(A, run_index(64 + lane, s_start[wid], s_pre[wid], nseg), f1, v1, w1);
+      load_particle<T, DIM>(A, i1, f1, v1, w1);
       d1 = push_one<T, DIM>(f1, v1, fc, A.beta, A.dtx, clamped);
     }
     const DirStats q0 = dir_stats(a0, d0, lane), q1 = dir_stats(a1, d1, lane);
     cnt = q0.count_k + q1.count_k;
-    dir_off = excl_scan32(cnt, lane);
+    dir_off = excl_scan(cnt);
     const int b0 = __shfl(dir_off, d0 & 31, 64);
     const int b1 = __shfl(dir_off + q0.count_k, d1 & 31, 64);
     const uint64_t lt = lanemask_lt(lane);
@@ -305,7 +345,7 @@ __global__ __launch_bounds__(256) void k_push(DGrid G, PushArgs<T> A) {
           }
         }
       }
-      if (pass == 0) dir_off = excl_scan32(cnt, lane);
+      if (pass == 0) dir_off = excl_scan(cnt);
     }
     if (lane < ND && running != cnt) bad = 1;
   }
@@ -416,7 +456,7 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_final(const int32_t* __rest
 // and the cell's sums are written once at the end.
 template <typename T>
 struct DepSpecies {
-  const T *off, *v, *w;
+  const T* rec;  // particle records [n][8]
   const int32_t *sub_start, *sub_cnt;
   T q, m, beta;
   int64_t n;
@@ -425,7 +465,7 @@ template <typename T>
 struct DepArgs {
   DepSpecies<T> sp[GE_MAX_SPECIES];
   int nsp;
-  const T* Bn;  // [3][N]
+  const T* NF;  // node records [N][8] (the B half is used)
   T* cellQ;     // per-cell sums, [N/4][Qn][4] (cq_index)
   int Qn;
 };
@@ -501,27 +541,6 @@ __device__ inline RunRegs load_runs(const DGrid& G, int64_t c, const DepArgs<T>&
   return R;
 }
 
-// Wavefront scans on DPP lane moves (no LDS round trips): row_shr:1,2,4,8
-// within each row of 16 lanes (sources outside the row read 0), then
-// row_bcast:15 / row_bcast:31 carry the row totals forward.  0 must be the
-// identity of the operation (sums, or maxima of non-negative values).
-template <bool MAX, bool HALVES>
-__device__ inline int dpp_scan(int x) {
-#define GE_DPP_STEP(CTRL, RMASK)                                              \
-  {                                                                         \
-    const int y = __builtin_amdgcn_update_dpp(0, x, CTRL, RMASK, 0xf, true); \
-    x = MAX ? max(x, y) : x + y;                                            \
-  }
-  GE_DPP_STEP(0x111, 0xf)  // row_shr:1
-  GE_DPP_STEP(0x112, 0xf)  // row_shr:2
-  GE_DPP_STEP(0x114, 0xf)  // row_shr:4
-  GE_DPP_STEP(0x118, 0xf)  // row_shr:8
-  GE_DPP_STEP(0x142, 0xa)  // row_bcast:15 into rows 1 and 3
-  if (!HALVES) GE_DPP_STEP(0x143, 0xc)  // row_bcast:31 into rows 2 and 3
-#undef GE_DPP_STEP
-  return x;
-}
-
 // Per-wave LDS of the deposit: compacted run tables of the current and the
 // next cell, the run-start markers, corner values, MFMA staging, accumulators.
 template <typename T, int DIM, int NSLOT>
@@ -593,13 +612,8 @@ struct PState {
 };
 template <typename T, int DIM>
 __device__ inline void load_p(const DepSpecies<T>& S, int i, PState<T>& P) {
-  i = i < 0 ? 0 : i;  // every buffer holds at least one element
-  const int64_t N = S.n;
-#pragma unroll
-  for (int d = 0; d < 3; ++d) P.f[d] = d < DIM ? S.off[d * N + i] : (T)0;
-#pragma unroll
-  for (int d = 0; d < 3; ++d) P.v[d] = S.v[d * N + i];
-  P.w = S.w[i];
+  i = i < 0 ? 0 : i;  // every buffer holds at least one record
+  read_rec<T, DIM>(S.rec, i, P.f, P.v, P.w);
 }
 
 // Persistent wavefronts, each owning a contiguous range of cells.  While a
@@ -624,18 +638,17 @@ __global__ __launch_bounds__(64 * WPB) void k_deposit(DGrid G, DepArgs<T> A, int
   T* acc_lin = L.acc;             // [NR][7]: q alpha v (3), m v (3), m w
   T* acc_rho = acc_lin + 7 * NR;  // [NR][GE_MAX_SPECIES]
   const int col = lane & 15;
-  const int cq = lane / NC, ca = lane % NC;  // corner value loaded by this lane
   // MFMA operand reads of a step: row 4 stp + lane/16, A row col (and 16 +
   // col), B column col.  A rows past NR read other values of the row: their
   // products land in accumulator rows that are never used.
   const int rofsA0 = (lane >> 4) * ST + col, rofsA1 = rofsA0 + 16, rofsB = (lane >> 4) * ST + AW + col;
 
-  auto corner = [&](int64_t c) -> T {
-    const bool ok = lane < 3 * NC;
-    const int q = ok ? cq : 0, a = ok ? ca : 0;
+  typedef T t4 __attribute__((ext_vector_type(4)));
+  // B at corner lane (lanes past the corners reload corner 0)
+  auto corner = [&](int64_t c) -> t4 {
+    const int a = lane < NC ? lane : 0;
     const int64_t g = nbr3(G, c, a & 1, DIM >= 2 ? (a >> 1) & 1 : 0, DIM >= 3 ? (a >> 2) & 1 : 0);
-    const T val = A.Bn[q * G.N + g];
-    return ok ? val : (T)0;
+    return reinterpret_cast<const t4*>(A.NF)[2 * g + 1];
   };
   const DepSpecies<T>& S1 = A.nsp > 1 ? A.sp[1] : A.sp[0];  // a valid buffer even without species 1
 
@@ -648,7 +661,7 @@ __global__ __launch_bounds__(64 * WPB) void k_deposit(DGrid G, DepArgs<T> A, int
   for (int j = 0; j < 2; ++j) load_p<T, DIM>(A.sp[0], idx[0][j], Pn[0][j]);
 #pragma unroll
   for (int j = 0; j < 2; ++j) load_p<T, DIM>(S1, idx[1][j], Pn[1][j]);
-  T cv = corner(cb);
+  t4 cv = corner(cb);
   if constexpr (PIPE) R = load_runs<T, DIM>(G, cb + 1 < ce ? cb + 1 : cb, A, lane);
 
   for (int64_t c = cb; c < ce; ++c) {
@@ -658,7 +671,11 @@ __global__ __launch_bounds__(64 * WPB) void k_deposit(DGrid G, DepArgs<T> A, int
     for (int s = 0; s < 2; ++s)
 #pragma unroll
       for (int j = 0; j < 2; ++j) P[s][j] = Pn[s][j];
-    if (lane < 3 * NC) L.fc[lane] = cv;
+    if (lane < NC) {
+      L.fc[lane] = cv[0];
+      L.fc[NC + lane] = cv[1];
+      L.fc[2 * NC + lane] = cv[2];
+    }
     for (int k = lane; k < C::NACC; k += 64) L.acc[k] = 0;
     // stage 1: run table of c+1 -> particle and corner loads of c+1; stage 2:
     // run table of c+2 (past the range end the last cell is loaded again and
@@ -842,8 +859,8 @@ __global__ void k_load_fix(int64_t N, const int32_t* __restrict__ st, int32_t* _
 }
 
 template <typename T, int DIM>
-__global__ __launch_bounds__(256) void k_get_particles(DGrid G, const T* __restrict__ off, const T* __restrict__ v,
-                                                       const T* __restrict__ w, const int32_t* __restrict__ sub_start,
+__global__ __launch_bounds__(256) void k_get_particles(DGrid G, const T* __restrict__ rec,
+                                                       const int32_t* __restrict__ sub_start,
                                                        const int32_t* __restrict__ sub_cnt, const int32_t* __restrict__ seg,
                                                        int64_t n, int32_t* __restrict__ cell_o, T* __restrict__ off_o,
                                                        T* __restrict__ v_o, T* __restrict__ w_o) {
@@ -857,21 +874,35 @@ __global__ __launch_bounds__(256) void k_get_particles(DGrid G, const T* __restr
   for (int t = lane; t < total; t += 64) {
     const int i = run_index(t, s_start[wid], s_pre[wid], nseg);
     const int64_t o = base + t;
+    T f[3], v[3], w;
+    read_rec<T, 3>(rec, i, f, v, w);
     cell_o[o] = (int32_t)c;
-    for (int d = 0; d < 3; ++d) off_o[d * n + o] = off[d * n + i];
-    for (int d = 0; d < 3; ++d) v_o[d * n + o] = v[d * n + i];
-    w_o[o] = w[i];
+    for (int d = 0; d < 3; ++d) off_o[d * n + o] = f[d];
+    for (int d = 0; d < 3; ++d) v_o[d * n + o] = v[d];
+    w_o[o] = w;
   }
+}
+
+// Particle records from the caller's structure-of-arrays input.
+template <typename T>
+__global__ void k_pack_particles(int64_t n, const T* __restrict__ off, const T* __restrict__ v, const T* __restrict__ w,
+                                 T* __restrict__ rec) {
+  const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const T f[3] = {off[p], off[n + p], off[2 * n + p]};
+  const T u[3] = {v[p], v[n + p], v[2 * n + p]};
+  write_rec<T>(rec, p, f, u, w[p]);
 }
 
 // Kinetic energy and momentum of one species, deterministic block partials.
 template <typename T>
-__global__ __launch_bounds__(256) void k_particle_moments(const T* __restrict__ v, const T* __restrict__ w, int64_t n,
-                                                          double* __restrict__ part) {
+__global__ __launch_bounds__(256) void k_particle_moments(const T* __restrict__ rec, int64_t n, double* __restrict__ part) {
   __shared__ double sh[4][256];
   double a[4] = {0, 0, 0, 0};
   for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
-    double vx = v[p], vy = v[n + p], vz = v[2 * n + p], ww = w[p];
+    T f[3], v[3], w;
+    read_rec<T, 3>(rec, p, f, v, w);
+    const double vx = v[0], vy = v[1], vz = v[2], ww = w;
     a[0] += ww * (vx * vx + vy * vy + vz * vz);
     a[1] += ww * vx; a[2] += ww * vy; a[3] += ww * vz;
   }
@@ -919,12 +950,11 @@ static void launch_push_t(ge_ctx* c, int s) {
   SpeciesBuf& S = c->sp[s];
   PushArgs<T> A;
   const int cur = S.cur, nxt = 1 - S.cur;
-  A.off = (const T*)S.off[cur]; A.v = (const T*)S.v[cur]; A.w = (const T*)S.w[cur];
-  A.off_o = (T*)S.off[nxt]; A.v_o = (T*)S.v[nxt]; A.w_o = (T*)S.w[nxt];
+  A.rec = (const T*)S.rec[cur];
+  A.rec_o = (T*)S.rec[nxt];
   A.sub_start = S.sub_start[cur]; A.sub_cnt = S.sub_cnt[cur]; A.seg_next = c->seg_next + (int64_t)s * c->G.N;
   A.sub_start_o = S.sub_start[nxt]; A.sub_cnt_o = S.sub_cnt[nxt];
-  if (sizeof(T) == 4) { A.E = (const T*)c->Eth32; A.B = (const T*)c->Bn32; }
-  else { A.E = (const T*)c->Eth; A.B = (const T*)c->Bn; }
+  A.NF = (const T*)c->node8;
   A.beta = (T)S.beta;
   for (int d = 0; d < 3; ++d) A.dtx[d] = (T)(c->P.dt * c->G.idx[d]);
   A.n = S.n;
@@ -961,11 +991,11 @@ static void launch_deposit_t(ge_ctx* c) {
   A.nsp = c->nsp;
   for (int s = 0; s < c->nsp; ++s) {
     SpeciesBuf& S = c->sp[s];
-    A.sp[s].off = (const T*)S.off[S.cur]; A.sp[s].v = (const T*)S.v[S.cur]; A.sp[s].w = (const T*)S.w[S.cur];
+    A.sp[s].rec = (const T*)S.rec[S.cur];
     A.sp[s].sub_start = S.sub_start[S.cur]; A.sp[s].sub_cnt = S.sub_cnt[S.cur];
     A.sp[s].q = (T)S.q; A.sp[s].m = (T)S.m; A.sp[s].beta = (T)S.beta; A.sp[s].n = S.n;
   }
-  A.Bn = sizeof(T) == 4 ? (const T*)c->Bn32 : (const T*)c->Bn;
+  A.NF = (const T*)c->node8;
   A.cellQ = (T*)c->cellQ;
   A.Qn = c->Q;
   if (DEP_PIPE) {
@@ -1008,9 +1038,14 @@ int ge_launch_load_species(ge_ctx* c, int s, const int32_t* cell, const void* of
   SpeciesBuf& S = c->sp[s];
   const int64_t N = c->G.N, n = S.n;
   const size_t es = c->P.precision == GE_FP32 ? 4 : 8;
-  GE_HIP(c, hipMemcpyAsync(S.off[0], off, 3 * n * es, hipMemcpyDeviceToDevice, c->stream));
-  GE_HIP(c, hipMemcpyAsync(S.v[0], v, 3 * n * es, hipMemcpyDeviceToDevice, c->stream));
-  GE_HIP(c, hipMemcpyAsync(S.w[0], w, n * es, hipMemcpyDeviceToDevice, c->stream));
+  if (n > 0) {
+    if (es == 4)
+      hipLaunchKernelGGL(k_pack_particles<float>, dim3((n + 255) / 256), dim3(256), 0, c->stream, n, (const float*)off,
+                         (const float*)v, (const float*)w, (float*)S.rec[0]);
+    else
+      hipLaunchKernelGGL(k_pack_particles<double>, dim3((n + 255) / 256), dim3(256), 0, c->stream, n, (const double*)off,
+                         (const double*)v, (const double*)w, (double*)S.rec[0]);
+  }
   for (int b = 0; b < 2; ++b) {
     GE_HIP(c, hipMemsetAsync(S.sub_start[b], 0, sizeof(int32_t) * c->ND * N, c->stream));
     GE_HIP(c, hipMemsetAsync(S.sub_cnt[b], 0, sizeof(int32_t) * c->ND * N, c->stream));
@@ -1036,7 +1071,7 @@ template <typename T, int DIM>
 static void launch_get_t(ge_ctx* c, int s, int32_t* cell, void* off, void* v, void* w) {
   SpeciesBuf& S = c->sp[s];
   hipLaunchKernelGGL((k_get_particles<T, DIM>), dim3((c->G.N + 3) / 4), dim3(256), 0, c->stream, c->G,
-                     (const T*)S.off[S.cur], (const T*)S.v[S.cur], (const T*)S.w[S.cur], S.sub_start[S.cur],
+                     (const T*)S.rec[S.cur], S.sub_start[S.cur],
                      S.sub_cnt[S.cur], c->seg_next + (int64_t)s * c->G.N, S.n, cell, (T*)off, (T*)v, (T*)w);
 }
 
@@ -1061,11 +1096,11 @@ int ge_launch_particle_moments(ge_ctx* c, int s, double* out4) {
   const int nbk = 256;
   double* part = c->partials;  // needs 4 * nbk
   if (c->P.precision == GE_FP32)
-    hipLaunchKernelGGL(k_particle_moments<float>, dim3(nbk), dim3(256), 0, c->stream, (const float*)S.v[S.cur],
-                       (const float*)S.w[S.cur], S.n, part);
+    hipLaunchKernelGGL(k_particle_moments<float>, dim3(nbk), dim3(256), 0, c->stream, (const float*)S.rec[S.cur], S.n,
+                       part);
   else
-    hipLaunchKernelGGL(k_particle_moments<double>, dim3(nbk), dim3(256), 0, c->stream, (const double*)S.v[S.cur],
-                       (const double*)S.w[S.cur], S.n, part);
+    hipLaunchKernelGGL(k_particle_moments<double>, dim3(nbk), dim3(256), 0, c->stream, (const double*)S.rec[S.cur], S.n,
+                       part);
   GE_HIP(c, hipGetLastError());
   double h[4 * 256];
   GE_HIP(c, hipMemcpyAsync(h, part, sizeof(double) * 4 * nbk, hipMemcpyDeviceToHost, c->stream));
