@@ -176,8 +176,7 @@ void ge_destroy(ge_ctx* c) {
   for (int s = 0; s < c->nsp; ++s)
     for (int b = 0; b < 2; ++b) {
       dfree(c->sp[s].rec[b]);
-      dfree(c->sp[s].sub_start[b]);
-      dfree(c->sp[s].sub_cnt[b]);
+      dfree(c->sp[s].runs[b]);
     }
   for (int k = 0; k < 10; ++k)
     if (c->ev[k]) (void)hipEventDestroy(c->ev[k]);
@@ -205,13 +204,12 @@ int ge_add_species(ge_ctx* c, const ge_species* sp, int64_t n, const int32_t* ce
   int rc = GE_OK;
   for (int b = 0; b < 2 && !rc; ++b) {
     rc = dalloc(c, &S.rec[b], es * 8 * n);
-    if (!rc) rc = dalloc(c, &S.sub_start[b], sizeof(int32_t) * c->ND * c->G.N);
-    if (!rc) rc = dalloc(c, &S.sub_cnt[b], sizeof(int32_t) * c->ND * c->G.N);
+    if (!rc) rc = dalloc(c, &S.runs[b], sizeof(int32_t) * 2 * c->ND * c->G.N);
   }
   c->nsp = s + 1;  // so that ge_destroy frees partial allocations
   if (rc) {
     for (int b = 0; b < 2; ++b) {
-      dfree(S.rec[b]); dfree(S.sub_start[b]); dfree(S.sub_cnt[b]);
+      dfree(S.rec[b]); dfree(S.runs[b]);
     }
     c->nsp = s;
     return rc;
@@ -221,7 +219,7 @@ int ge_add_species(ge_ctx* c, const ge_species* sp, int64_t n, const int32_t* ce
   rc = check_flags(c);
   if (rc) {
     for (int b = 0; b < 2; ++b) {
-      dfree(S.rec[b]); dfree(S.sub_start[b]); dfree(S.sub_cnt[b]);
+      dfree(S.rec[b]); dfree(S.runs[b]);
     }
     c->nsp = s;
     return rc;

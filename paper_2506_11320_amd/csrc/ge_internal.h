@@ -79,8 +79,7 @@ struct SpeciesBuf {
   double q, m, beta;     // beta = q dt / (2 m)
   int64_t n;
   void* rec[2];          // T[n][8]: offset in the cell (3), w, velocity (3), 0
-  int32_t* sub_start[2]; // [ND][Ncell]: start of the run (home cell, direction)
-  int32_t* sub_cnt[2];   // [ND][Ncell]
+  int32_t* runs[2];      // [Ncell][ND][2]: (start, count) of the run entering cell c by move d
   int cur;
 };
 

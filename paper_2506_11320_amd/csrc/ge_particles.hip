@@ -1,12 +1,13 @@
 // Particle-side kernels of the GL-ECSIM pass on gfx950: loading, the
 // implicit mover with stable re-binning, and the mass-matrix/current deposit.
 //
-// Particle storage.  Each species keeps two buffers (ping-pong) of
-// structure-of-arrays data (offset in the cell [3][n], velocity [3][n],
-// weight [n]).  A buffer is ordered by "home" cell h (the cell a particle
-// occupied before the last push) and, inside a home segment, partitioned by
-// the direction d in {-1,0,1}^dim to the particle's present cell h + d.  The
-// run of (h, d) starts at sub_start[d][h] and holds sub_cnt[d][h] particles.
+// Particle storage.  Each species keeps two buffers (ping-pong) of particle
+// records, two 4-vectors per particle: (offset in the cell x, y, z, weight)
+// and (velocity x, y, z, 0).  A buffer is ordered by "home" cell h (the cell a
+// particle occupied before the last push) and, inside a home segment,
+// partitioned by the direction d in {-1,0,1}^dim to the particle's present
+// cell h + d.  The run of (h, d) is recorded at its destination: runs[c][d] =
+// (start, count) for c = h + d, so the ND runs a cell receives sit together.
 // The particles now in cell c are the runs (c - d, d) taken in ascending
 // linear order of the home cell: that concatenation is exactly the order a
 // stable sort by present cell gives, so the re-binning is an integer,
@@ -17,6 +18,8 @@
 #include "ge_internal.h"
 
 namespace {
+
+typedef int i2 __attribute__((ext_vector_type(2)));  // (start, count) of a run
 
 template <int DIM>
 struct Dm {
@@ -76,21 +79,26 @@ __device__ inline int axis_order(int ci, int n, int j) {
 // Collect the runs of particles present in cell c, ascending by home cell.
 // Lane j < ND loads run j; the non-empty runs are compacted into s_start /
 // s_pre (exclusive prefix of counts).  Returns the total; nseg the run count.
+// Move direction of the run that lane r (< ND) of cell c reads: lanes take the
+// runs in ascending order of their home cell c + e, whose move is -e.
 template <int DIM>
-__device__ int runs_setup(const DGrid& G, int64_t c, const int32_t* __restrict__ sub_start,
-                          const int32_t* __restrict__ sub_cnt, int* s_start, int* s_pre, int lane, int& nseg) {
+__device__ inline int run_dir(const DGrid& G, int cx, int cy, int cz, int r) {
+  const int ex = axis_order(cx, G.n[0], r % 3);
+  const int ey = DIM >= 2 ? axis_order(cy, G.n[1], (r / 3) % 3) : 0;
+  const int ez = DIM >= 3 ? axis_order(cz, G.n[2], r / 9) : 0;
+  return (1 - ex) + (DIM >= 2 ? 3 * (1 - ey) : 0) + (DIM >= 3 ? 9 * (1 - ez) : 0);
+}
+
+template <int DIM>
+__device__ int runs_setup(const DGrid& G, int64_t c, const int32_t* __restrict__ runs, int* s_start, int* s_pre,
+                          int lane, int& nseg) {
   int cx, cy, cz;
   unflat3(G, c, cx, cy, cz);
   int cnt = 0, st = 0;
   if (lane < Dm<DIM>::ND) {
-    int jx = lane % 3, jy = (lane / 3) % 3, jz = lane / 9;
-    int ex = axis_order(cx, G.n[0], jx);
-    int ey = DIM >= 2 ? axis_order(cy, G.n[1], jy) : 0;
-    int ez = DIM >= 3 ? axis_order(cz, G.n[2], jz) : 0;
-    int64_t h = flat3(G, cx + ex, cy + ey, cz + ez);
-    int dir = (1 - ex) + (DIM >= 2 ? 3 * (1 - ey) : 0) + (DIM >= 3 ? 9 * (1 - ez) : 0);
-    cnt = sub_cnt[(int64_t)dir * G.N + h];
-    st = sub_start[(int64_t)dir * G.N + h];
+    const i2 rv = reinterpret_cast<const i2*>(runs)[c * Dm<DIM>::ND + run_dir<DIM>(G, cx, cy, cz, lane)];
+    st = rv.x;
+    cnt = rv.y;
   }
   const int incl = dpp_scan<false, false>(cnt);
   const int total = rl_i(incl, 31);
@@ -202,8 +210,8 @@ template <typename T>
 struct PushArgs {
   const T* rec;  // particle records [n][8], read
   T* rec_o;      // written
-  const int32_t *sub_start, *sub_cnt, *seg_next;
-  int32_t *sub_start_o, *sub_cnt_o;
+  const int32_t *runs, *seg_next;
+  int32_t* runs_o;
   const T* NF;   // node fields [N][8]: E^{n+theta}, node-averaged B^n
   T beta;
   T dtx[3];
@@ -281,7 +289,7 @@ __global__ __launch_bounds__(256) void k_push(DGrid G, PushArgs<T> A) {
   int nseg;
   int* sst = s_start[wid];
   int* spr = s_pre[wid];
-  const int total = runs_setup<DIM>(G, c, A.sub_start, A.sub_cnt, sst, spr, lane, nseg);
+  const int total = runs_setup<DIM>(G, c, A.runs, sst, spr, lane, nseg);
   const int64_t base = A.seg_next[c];
   int cnt = 0, dir_off = 0, clamped = 0, bad = 0;
   if (total <= 128) {
@@ -350,8 +358,11 @@ __global__ __launch_bounds__(256) void k_push(DGrid G, PushArgs<T> A) {
     if (lane < ND && running != cnt) bad = 1;
   }
   if (lane < ND) {
-    A.sub_start_o[(int64_t)lane * G.N + c] = (int32_t)(base + dir_off);
-    A.sub_cnt_o[(int64_t)lane * G.N + c] = cnt;
+    // run (c, lane) is recorded at its destination cell
+    int cx, cy, cz;
+    unflat3(G, c, cx, cy, cz);
+    const int64_t dst = flat3(G, cx + lane % 3 - 1, DIM >= 2 ? cy + (lane / 3) % 3 - 1 : cy, DIM >= 3 ? cz + lane / 9 - 1 : cz);
+    reinterpret_cast<i2*>(A.runs_o)[dst * ND + lane] = i2{(int)(base + dir_off), cnt};
   }
   if (clamped) atomicOr(&A.flags[0], 1);
   if (bad) atomicOr(&A.flags[1], 1);
@@ -360,18 +371,11 @@ __global__ __launch_bounds__(256) void k_push(DGrid G, PushArgs<T> A) {
 // ------------------------------------------------------------------ scan
 // cnt[c] = particles now in cell c; seg[c] = exclusive prefix over cells.
 template <int DIM>
-__global__ __launch_bounds__(256) void k_count(DGrid G, const int32_t* __restrict__ sub_cnt, int32_t* __restrict__ cnt) {
+__global__ __launch_bounds__(256) void k_count(DGrid G, const int32_t* __restrict__ runs, int32_t* __restrict__ cnt) {
   int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (c >= G.N) return;
-  int cx, cy, cz;
-  unflat3(G, c, cx, cy, cz);
   int s = 0;
-  for (int j = 0; j < Dm<DIM>::ND; ++j) {
-    int ex = j % 3 - 1, ey = DIM >= 2 ? (j / 3) % 3 - 1 : 0, ez = DIM >= 3 ? j / 9 - 1 : 0;
-    int64_t h = flat3(G, cx + ex, cy + ey, cz + ez);
-    int dir = (1 - ex) + (DIM >= 2 ? 3 * (1 - ey) : 0) + (DIM >= 3 ? 9 * (1 - ez) : 0);
-    s += sub_cnt[(int64_t)dir * G.N + h];
-  }
+  for (int j = 0; j < Dm<DIM>::ND; ++j) s += runs[2 * (c * Dm<DIM>::ND + j) + 1];
   cnt[c] = s;
 }
 
@@ -457,7 +461,7 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_final(const int32_t* __rest
 template <typename T>
 struct DepSpecies {
   const T* rec;  // particle records [n][8]
-  const int32_t *sub_start, *sub_cnt;
+  const int32_t* runs;  // [N][ND][2]
   T q, m, beta;
   int64_t n;
 };
@@ -513,31 +517,23 @@ __device__ inline RunRegs load_runs(const DGrid& G, int64_t c, const DepArgs<T>&
   const int r = r0 < Dm<DIM>::ND ? r0 : 0;
   int cx, cy, cz;
   unflat3(G, c, cx, cy, cz);
-  const int ex = axis_order(cx, G.n[0], r % 3);
-  const int ey = DIM >= 2 ? axis_order(cy, G.n[1], (r / 3) % 3) : 0;
-  const int ez = DIM >= 3 ? axis_order(cz, G.n[2], r / 9) : 0;
-  const int64_t h = flat3(G, cx + ex, cy + ey, cz + ez);
-  const int dir = (1 - ex) + (DIM >= 2 ? 3 * (1 - ey) : 0) + (DIM >= 3 ? 9 * (1 - ez) : 0);
-  const int64_t o = (int64_t)dir * G.N + h;
+  const int64_t ob = (c * Dm<DIM>::ND + run_dir<DIM>(G, cx, cy, cz, r)) * (int64_t)sizeof(i2);
   // species (half) and (half + 2): base pointer of the even species plus a
   // uniform byte distance to the odd one, so the address is base + select
   const int nsp = A.nsp;
-  const uintptr_t c0 = (uintptr_t)A.sp[0].sub_cnt, s0 = (uintptr_t)A.sp[0].sub_start;
-  const uintptr_t c1 = nsp > 1 ? (uintptr_t)A.sp[1].sub_cnt : c0, s1 = nsp > 1 ? (uintptr_t)A.sp[1].sub_start : s0;
-  const uintptr_t c2 = nsp > 2 ? (uintptr_t)A.sp[2].sub_cnt : c0, s2 = nsp > 2 ? (uintptr_t)A.sp[2].sub_start : s0;
-  const uintptr_t c3 = nsp > 3 ? (uintptr_t)A.sp[3].sub_cnt : c2, s3 = nsp > 3 ? (uintptr_t)A.sp[3].sub_start : s2;
-  const int64_t ob = o * (int64_t)sizeof(int32_t);
-  typedef const __attribute__((address_space(1))) int32_t* gptr;  // global, not flat
-  const int32_t v0 = *(gptr)(c0 + (half ? c1 - c0 : 0) + ob);
-  const int32_t w0 = *(gptr)(s0 + (half ? s1 - s0 : 0) + ob);
-  const int32_t v1 = *(gptr)(c2 + (half ? c3 - c2 : 0) + ob);
-  const int32_t w1 = *(gptr)(s2 + (half ? s3 - s2 : 0) + ob);
+  const uintptr_t p0 = (uintptr_t)A.sp[0].runs;
+  const uintptr_t p1 = nsp > 1 ? (uintptr_t)A.sp[1].runs : p0;
+  const uintptr_t p2 = nsp > 2 ? (uintptr_t)A.sp[2].runs : p0;
+  const uintptr_t p3 = nsp > 3 ? (uintptr_t)A.sp[3].runs : p2;
+  typedef const __attribute__((address_space(1))) i2* gptr;  // global, not flat
+  const i2 a = *(gptr)(p0 + (half ? p1 - p0 : 0) + ob);
+  const i2 b = *(gptr)(p2 + (half ? p3 - p2 : 0) + ob);
   // raw values: lanes without a run are masked where the values are used, so
   // that nothing touches the loaded registers before the data are needed
-  R.cnt[0] = v0;
-  R.st[0] = w0;
-  R.cnt[1] = v1;
-  R.st[1] = w1;
+  R.st[0] = a.x;
+  R.cnt[0] = a.y;
+  R.st[1] = b.x;
+  R.cnt[1] = b.y;
   return R;
 }
 
@@ -840,28 +836,29 @@ __global__ __launch_bounds__(64 * WPB) void k_deposit(DGrid G, DepArgs<T> A, int
 }
 
 // ------------------------------------------------------------------ load / read back
+// Initial run table: the particles of cell c, sorted by cell, form the run
+// "no move" of cell c: r[c stride] = start, r[c stride + 1] = end, then count.
 template <int DIM>
-__global__ void k_load_bounds(DGrid G, const int32_t* __restrict__ cell, int64_t n, int32_t* __restrict__ st,
-                              int32_t* __restrict__ en, int* flags) {
+__global__ void k_load_bounds(DGrid G, const int32_t* __restrict__ cell, int64_t n, int32_t* __restrict__ r,
+                              int64_t stride, int* flags) {
   int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (p >= n) return;
   int32_t c = cell[p];
   if (c < 0 || c >= G.N) { atomicOr(&flags[2], 1); return; }
   if (p > 0 && cell[p - 1] > c) atomicOr(&flags[2], 1);
-  if (p == 0 || cell[p - 1] != c) st[c] = (int32_t)p;
-  if (p == n - 1 || cell[p + 1] != c) en[c] = (int32_t)(p + 1);
+  if (p == 0 || cell[p - 1] != c) r[c * stride] = (int32_t)p;
+  if (p == n - 1 || cell[p + 1] != c) r[c * stride + 1] = (int32_t)(p + 1);
 }
-__global__ void k_load_fix(int64_t N, const int32_t* __restrict__ st, int32_t* __restrict__ en) {
+__global__ void k_load_fix(int64_t N, int32_t* __restrict__ r, int64_t stride) {
   int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (c >= N) return;
-  int32_t e = en[c];
-  en[c] = e > 0 ? e - st[c] : 0;
+  int32_t e = r[c * stride + 1];
+  r[c * stride + 1] = e > 0 ? e - r[c * stride] : 0;
 }
 
 template <typename T, int DIM>
 __global__ __launch_bounds__(256) void k_get_particles(DGrid G, const T* __restrict__ rec,
-                                                       const int32_t* __restrict__ sub_start,
-                                                       const int32_t* __restrict__ sub_cnt, const int32_t* __restrict__ seg,
+                                                       const int32_t* __restrict__ runs, const int32_t* __restrict__ seg,
                                                        int64_t n, int32_t* __restrict__ cell_o, T* __restrict__ off_o,
                                                        T* __restrict__ v_o, T* __restrict__ w_o) {
   __shared__ int s_start[4][32], s_pre[4][32];
@@ -869,7 +866,7 @@ __global__ __launch_bounds__(256) void k_get_particles(DGrid G, const T* __restr
   const int64_t c = blockIdx.x * 4 + wid;
   if (c >= G.N) return;
   int nseg;
-  const int total = runs_setup<DIM>(G, c, sub_start, sub_cnt, s_start[wid], s_pre[wid], lane, nseg);
+  const int total = runs_setup<DIM>(G, c, runs, s_start[wid], s_pre[wid], lane, nseg);
   const int64_t base = seg[c];
   for (int t = lane; t < total; t += 64) {
     const int i = run_index(t, s_start[wid], s_pre[wid], nseg);
@@ -937,9 +934,9 @@ int ge_launch_scan_counts(ge_ctx* c, int s) {
   dim3 gb((N + 255) / 256);
   int32_t* cnt = c->seg_next + (int64_t)s * N;  // counts, then scanned in place
   switch (c->G.dim) {
-    case 1: hipLaunchKernelGGL(k_count<1>, gb, dim3(256), 0, c->stream, c->G, S.sub_cnt[S.cur], cnt); break;
-    case 2: hipLaunchKernelGGL(k_count<2>, gb, dim3(256), 0, c->stream, c->G, S.sub_cnt[S.cur], cnt); break;
-    default: hipLaunchKernelGGL(k_count<3>, gb, dim3(256), 0, c->stream, c->G, S.sub_cnt[S.cur], cnt); break;
+    case 1: hipLaunchKernelGGL(k_count<1>, gb, dim3(256), 0, c->stream, c->G, S.runs[S.cur], cnt); break;
+    case 2: hipLaunchKernelGGL(k_count<2>, gb, dim3(256), 0, c->stream, c->G, S.runs[S.cur], cnt); break;
+    default: hipLaunchKernelGGL(k_count<3>, gb, dim3(256), 0, c->stream, c->G, S.runs[S.cur], cnt); break;
   }
   GE_HIP(c, hipGetLastError());
   return scan_into(c, cnt, cnt);
@@ -952,8 +949,8 @@ static void launch_push_t(ge_ctx* c, int s) {
   const int cur = S.cur, nxt = 1 - S.cur;
   A.rec = (const T*)S.rec[cur];
   A.rec_o = (T*)S.rec[nxt];
-  A.sub_start = S.sub_start[cur]; A.sub_cnt = S.sub_cnt[cur]; A.seg_next = c->seg_next + (int64_t)s * c->G.N;
-  A.sub_start_o = S.sub_start[nxt]; A.sub_cnt_o = S.sub_cnt[nxt];
+  A.runs = S.runs[cur]; A.seg_next = c->seg_next + (int64_t)s * c->G.N;
+  A.runs_o = S.runs[nxt];
   A.NF = (const T*)c->node8;
   A.beta = (T)S.beta;
   for (int d = 0; d < 3; ++d) A.dtx[d] = (T)(c->P.dt * c->G.idx[d]);
@@ -992,7 +989,7 @@ static void launch_deposit_t(ge_ctx* c) {
   for (int s = 0; s < c->nsp; ++s) {
     SpeciesBuf& S = c->sp[s];
     A.sp[s].rec = (const T*)S.rec[S.cur];
-    A.sp[s].sub_start = S.sub_start[S.cur]; A.sp[s].sub_cnt = S.sub_cnt[S.cur];
+    A.sp[s].runs = S.runs[S.cur];
     A.sp[s].q = (T)S.q; A.sp[s].m = (T)S.m; A.sp[s].beta = (T)S.beta; A.sp[s].n = S.n;
   }
   A.NF = (const T*)c->node8;
@@ -1047,22 +1044,21 @@ int ge_launch_load_species(ge_ctx* c, int s, const int32_t* cell, const void* of
                          (const double*)v, (const double*)w, (double*)S.rec[0]);
   }
   for (int b = 0; b < 2; ++b) {
-    GE_HIP(c, hipMemsetAsync(S.sub_start[b], 0, sizeof(int32_t) * c->ND * N, c->stream));
-    GE_HIP(c, hipMemsetAsync(S.sub_cnt[b], 0, sizeof(int32_t) * c->ND * N, c->stream));
+    GE_HIP(c, hipMemsetAsync(S.runs[b], 0, sizeof(int32_t) * 2 * c->ND * N, c->stream));
   }
   S.cur = 0;
   const int center = (c->ND - 1) / 2;
-  int32_t* st = S.sub_start[0] + (int64_t)center * N;
-  int32_t* en = S.sub_cnt[0] + (int64_t)center * N;
+  int32_t* r0 = S.runs[0] + 2 * center;
+  const int64_t stride = 2 * c->ND;
   if (n > 0) {
     dim3 gp((n + 255) / 256);
     switch (c->G.dim) {
-      case 1: hipLaunchKernelGGL(k_load_bounds<1>, gp, dim3(256), 0, c->stream, c->G, cell, n, st, en, c->flags); break;
-      case 2: hipLaunchKernelGGL(k_load_bounds<2>, gp, dim3(256), 0, c->stream, c->G, cell, n, st, en, c->flags); break;
-      default: hipLaunchKernelGGL(k_load_bounds<3>, gp, dim3(256), 0, c->stream, c->G, cell, n, st, en, c->flags); break;
+      case 1: hipLaunchKernelGGL(k_load_bounds<1>, gp, dim3(256), 0, c->stream, c->G, cell, n, r0, stride, c->flags); break;
+      case 2: hipLaunchKernelGGL(k_load_bounds<2>, gp, dim3(256), 0, c->stream, c->G, cell, n, r0, stride, c->flags); break;
+      default: hipLaunchKernelGGL(k_load_bounds<3>, gp, dim3(256), 0, c->stream, c->G, cell, n, r0, stride, c->flags); break;
     }
   }
-  hipLaunchKernelGGL(k_load_fix, dim3((N + 255) / 256), dim3(256), 0, c->stream, N, st, en);
+  hipLaunchKernelGGL(k_load_fix, dim3((N + 255) / 256), dim3(256), 0, c->stream, N, r0, stride);
   GE_HIP(c, hipGetLastError());
   return GE_OK;
 }
@@ -1071,8 +1067,7 @@ template <typename T, int DIM>
 static void launch_get_t(ge_ctx* c, int s, int32_t* cell, void* off, void* v, void* w) {
   SpeciesBuf& S = c->sp[s];
   hipLaunchKernelGGL((k_get_particles<T, DIM>), dim3((c->G.N + 3) / 4), dim3(256), 0, c->stream, c->G,
-                     (const T*)S.rec[S.cur], S.sub_start[S.cur],
-                     S.sub_cnt[S.cur], c->seg_next + (int64_t)s * c->G.N, S.n, cell, (T*)off, (T*)v, (T*)w);
+                     (const T*)S.rec[S.cur], S.runs[S.cur], c->seg_next + (int64_t)s * c->G.N, S.n, cell, (T*)off, (T*)v, (T*)w);
 }
 
 int ge_launch_get_particles(ge_ctx* c, int s, int32_t* cell, void* off, void* v, void* w) {
