@@ -52,7 +52,22 @@ def algorithmic_bytes(wl, nsp, counts):
     return {"deposit": dep, "push": push}
 
 
-def cpu_baseline(wl, box=32):
+def measured_traffic(kernel_file, record):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    record (profiles/), or None when the kernel source changed since the
+    counters were taken (the record holds the source's SHA-256)."""
+    import hashlib
+    try:
+        rec = json.load(open(os.path.join(ROOT, record)))
+        src = open(os.path.join(ROOT, kernel_file), "rb").read()
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_sha256") != hashlib.sha256(src).hexdigest():
+        return None
+    return float(rec["traffic_bytes"])
+
+
+def cpu_baseline(wl, box=24):
     """The FP64 oracle, as it stands, timed on a bounded sample of the same
     workload: one full step of a periodic box^3-cell sub-box built with the
     same recipe (ppc, dx, dt, species)."""
@@ -211,7 +226,9 @@ def main():
     achieved = ab[dom] / dom_t / 1e9
     roof = {"bound": "hbm", "kernel": "k_deposit<float,3>" if dom == "deposit" else "k_push<float,3> (x2 species)",
             "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic("paper_2506_11320_amd/csrc/ge_particles.hip", "profiles/c5_deposit_traffic.json")
+            if (dom == "deposit" and args.workload == "c5") else None,
             "algorithmic_bytes_per_launch": ab[dom], "launch_ms": round(dom_t * 1e3, 4)}
     precond_cmp = None
     if args.compare_precond:
