@@ -249,7 +249,11 @@ __device__ inline int excl_scan(int x) { return dpp_scan<false, false>(x) - x; }
 template <typename T, int DIM>
 __device__ inline void read_rec(const T* __restrict__ rec, int64_t i, T f[3], T v[3], T& w) {
   typedef T t4 __attribute__((ext_vector_type(4)));
-  const t4 a = reinterpret_cast<const t4*>(rec)[2 * i], b = reinterpret_cast<const t4*>(rec)[2 * i + 1];
+  typedef T t3 __attribute__((ext_vector_type(3)));
+  // the velocity half is read as three values: a fourth, unused register
+  // would be reused by the compiler, which then waits for the load to land
+  const t4 a = reinterpret_cast<const t4*>(rec)[2 * i];
+  const t3 b = *reinterpret_cast<const t3*>(rec + 8 * i + 4);
 #pragma unroll
   for (int d = 0; d < 3; ++d) f[d] = d < DIM ? a[d] : (T)0;
   v[0] = b[0]; v[1] = b[1]; v[2] = b[2];
@@ -641,14 +645,17 @@ __global__ __launch_bounds__(64 * WPB) void k_deposit(DGrid G, DepArgs<T> A, int
 
   typedef T t4 __attribute__((ext_vector_type(4)));
   // B at corner lane (lanes past the corners reload corner 0)
-  auto corner = [&](int64_t c) -> t4 {
+  typedef T t3 __attribute__((ext_vector_type(3)));
+  auto corner = [&](int64_t c) -> t3 {
     const int a = lane < NC ? lane : 0;
     const int64_t g = nbr3(G, c, a & 1, DIM >= 2 ? (a >> 1) & 1 : 0, DIM >= 3 ? (a >> 2) & 1 : 0);
-    return reinterpret_cast<const t4*>(A.NF)[2 * g + 1];
+    return *reinterpret_cast<const t3*>(A.NF + 8 * g + 4);
   };
   const DepSpecies<T>& S1 = A.nsp > 1 ? A.sp[1] : A.sp[0];  // a valid buffer even without species 1
 
-  // pipeline prologue
+  // pipeline prologue (the corner fields do not depend on the run table:
+  // their load goes first)
+  t3 cv = corner(cb);
   PState<T> Pn[2][2];
   int idx[2][2];
   RunRegs R = load_runs<T, DIM>(G, cb, A, lane);
@@ -657,7 +664,6 @@ __global__ __launch_bounds__(64 * WPB) void k_deposit(DGrid G, DepArgs<T> A, int
   for (int j = 0; j < 2; ++j) load_p<T, DIM>(A.sp[0], idx[0][j], Pn[0][j]);
 #pragma unroll
   for (int j = 0; j < 2; ++j) load_p<T, DIM>(S1, idx[1][j], Pn[1][j]);
-  t4 cv = corner(cb);
   if constexpr (PIPE) R = load_runs<T, DIM>(G, cb + 1 < ce ? cb + 1 : cb, A, lane);
 
   for (int64_t c = cb; c < ce; ++c) {
@@ -699,12 +705,19 @@ __global__ __launch_bounds__(64 * WPB) void k_deposit(DGrid G, DepArgs<T> A, int
       for (int rb = 0; rb < NRB; ++rb) acc[rb] = v4{0, 0, 0, 0};
       // one chunk of up to 64 particles: operands to LDS, then the MFMA sweep
       auto chunk = [&](const PState<T>& q, int t0) {
-        const int t = t0 + lane;
+        // lanes past the count take a zero weight (all B columns vanish) at
+        // the corner-0 position with zero velocity, so every staged value is
+        // finite and the MFMA adds exact zeros for them
+        const bool ok = t0 + lane < total;
         T vals[ST];  // A rows 0..NR-1, then the 16 B columns
-        if (t < total) {
-          const T* f = q.f;
-          const T* v = q.v;
-          const T w = q.w;
+        {
+          T f[3], v[3];
+#pragma unroll
+          for (int d = 0; d < 3; ++d) {
+            f[d] = ok ? q.f[d] : (T)0;
+            v[d] = ok ? q.v[d] : (T)0;
+          }
+          const T w = ok ? q.w : (T)0;
           T W[8];
           lin_weights<T, DIM>(f, W);
           T Bp[3];
@@ -749,9 +762,6 @@ __global__ __launch_bounds__(64 * WPB) void k_deposit(DGrid G, DepArgs<T> A, int
           for (int r = 0; r < NR; ++r) vals[r] = X[0][r % 3] * YZ[r / 3];
 #pragma unroll
           for (int k = NR + 16; k < ST; ++k) vals[k] = 0;
-        } else {
-#pragma unroll
-          for (int k = 0; k < ST; ++k) vals[k] = 0;
         }
         {
           typedef T t4 __attribute__((ext_vector_type(4)));
@@ -760,16 +770,44 @@ __global__ __launch_bounds__(64 * WPB) void k_deposit(DGrid G, DepArgs<T> A, int
           for (int j = 0; j < ST / 4; ++j) row[j] = t4{vals[4 * j], vals[4 * j + 1], vals[4 * j + 2], vals[4 * j + 3]};
         }
         wave_sync();
-        const int nsteps = (min(64, total - t0) + 3) >> 2;
-        // fully unrolled: the step's row offset is an immediate of the LDS read,
-        // the lane's column offsets are precomputed (rofs*)
+        // groups of 4 MFMA steps (16 particles; rows past the count are
+        // zero); the group count is wave-uniform, and the operands of group
+        // g + 1 are read from LDS while the MFMAs of group g run.  Row offsets
+        // are immediates of the LDS reads, the lane's column offsets are
+        // precomputed (rofs*).
+        const int ngrp = __builtin_amdgcn_readfirstlane((min(64, total - t0) + 15) >> 4);
+        T ca[2][4], cb[4];
+        auto rd = [&](int g, T (&a)[2][4], T (&b)[4]) {
 #pragma unroll
-        for (int stp = 0; stp < 16; ++stp) {
-          if (stp < nsteps) {
-            const T* rows = L.stage + 4 * stp * ST;
-            const T b = rows[rofsB];
-            acc[0] = M::op(rows[rofsA0], b, acc[0]);
-            if (NRB == 2) acc[NRB - 1] = M::op(rows[rofsA1], b, acc[NRB - 1]);
+          for (int i = 0; i < 4; ++i) {
+            const T* rows = L.stage + (16 * g + 4 * i) * ST;
+            b[i] = rows[rofsB];
+            a[0][i] = rows[rofsA0];
+            a[1][i] = NRB == 2 ? rows[rofsA1] : (T)0;
+          }
+        };
+        rd(0, ca, cb);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+          if (g >= ngrp) break;
+          T na[2][4], nb[4];
+          if (g < 3) rd(g + 1, na, nb);
+          // keep the scheduler from sinking the reads next to their MFMAs
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            acc[0] = M::op(ca[0][i], cb[i], acc[0]);
+            if (NRB == 2) acc[NRB - 1] = M::op(ca[1][i], cb[i], acc[NRB - 1]);
+          }
+          __builtin_amdgcn_sched_barrier(0);
+          if (g < 3) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              ca[0][i] = na[0][i];
+              ca[1][i] = na[1][i];
+              cb[i] = nb[i];
+            }
           }
         }
         wave_sync();
