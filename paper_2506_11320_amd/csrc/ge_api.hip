@@ -84,7 +84,7 @@ int ge_create(const ge_grid* grid, const ge_params* params, void* hip_stream, ge
       return bad("inactive axes need n = 1");
     }
   }
-  if (N > (int64_t)1 << 31) return bad("grid too large");
+  if (N >= (int64_t)1 << 31) return bad("grid too large");
   if (!(params->theta >= 0.5 && params->theta <= 1.0) || !(params->dt > 0) || !(params->c > 0)) return bad("theta/dt/c");
   if (params->precision != GE_FP64 && params->precision != GE_FP32) return bad("precision");
   if (params->n_smooth_u < 0 || params->beta_lim < 0) return bad("n_smooth_u/beta_lim");
@@ -98,6 +98,7 @@ int ge_create(const ge_grid* grid, const ge_params* params, void* hip_stream, ge
     G.idx[d] = 1.0 / G.dx[d];
     if (d < dim) G.dV *= G.dx[d];
   }
+  grid_div_magic(G);
   c->nsp = 0;
   c->nh = half_count(dim);
   c->ND = dim == 3 ? 27 : (dim == 2 ? 9 : 3);

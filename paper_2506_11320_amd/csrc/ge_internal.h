@@ -18,7 +18,27 @@ struct DGrid {
   int64_t N;
   double dx[3], idx[3];
   double dV;
+  // division by n[0] and n[1] as a multiply-shift (set by grid_div_magic):
+  // q = (x * dm[a]) >> ds[a] for every 0 <= x < 2^31
+  uint32_t dm[2];
+  int ds[2];
 };
+
+// Multiplier m = ceil(2^(31+s) / n), s = ceil(log2 n): for x < 2^31 the error
+// of x m / 2^(31+s) against x / n is below 2^-s <= 1/n, so the floor is exact
+// (division by invariant integers, Granlund and Montgomery 1994); m < 2^32.
+inline void grid_div_magic(DGrid& G) {
+  for (int a = 0; a < 2; ++a) {
+    const uint64_t n = (uint64_t)G.n[a];
+    int s = 0;
+    while (((uint64_t)1 << s) < n) ++s;
+    G.dm[a] = (uint32_t)((((uint64_t)1 << (31 + s)) + n - 1) / n);
+    G.ds[a] = 31 + s;
+  }
+}
+__device__ inline unsigned grid_div(const DGrid& G, unsigned x, int a) {
+  return (unsigned)(((uint64_t)x * G.dm[a]) >> G.ds[a]);
+}
 
 __host__ __device__ inline int wrapi(int i, int n) {
   return i < 0 ? i + n : (i >= n ? i - n : i);
@@ -26,9 +46,9 @@ __host__ __device__ inline int wrapi(int i, int n) {
 // Linear index <-> (i, j, k).  N < 2^31, so 32-bit arithmetic is exact.
 __device__ inline void unflat3(const DGrid& G, int64_t g, int& i, int& j, int& k) {
   const unsigned gg = (unsigned)g, nx = (unsigned)G.n[0], ny = (unsigned)G.n[1];
-  const unsigned r = gg / nx;
+  const unsigned r = grid_div(G, gg, 0);
   i = (int)(gg - r * nx);
-  k = (int)(r / ny);
+  k = (int)grid_div(G, r, 1);
   j = (int)(r - (unsigned)k * ny);
 }
 __device__ inline int64_t flat3(const DGrid& G, int i, int j, int k) {

@@ -541,13 +541,13 @@ __device__ inline RunRegs load_runs(const DGrid& G, int64_t c, const DepArgs<T>&
   return R;
 }
 
-// Per-wave LDS of the deposit: compacted run tables of the current and the
-// next cell, the run-start markers, corner values, MFMA staging, accumulators.
-template <typename T, int DIM, int NSLOT>
+// Per-wave LDS of the deposit: compacted run tables of the cell, the
+// run-start markers, corner values, MFMA staging, accumulators.
+template <typename T, int DIM>
 struct DepLds {
-  int runs[NSLOT][GE_MAX_SPECIES][2][32];  // [slot][species][start, pre][run]
-  int nseg[NSLOT][GE_MAX_SPECIES];
-  int total[NSLOT][GE_MAX_SPECIES];
+  int runs[GE_MAX_SPECIES][2][32];  // [species][start, pre][run]
+  int nseg[GE_MAX_SPECIES];
+  int total[GE_MAX_SPECIES];
   T fc[24];
   union {  // the run-start markers are dead before the staging starts
     int mark[2][128];
@@ -556,11 +556,11 @@ struct DepLds {
   T acc[DepCfg<T, DIM>::NACC];
 };
 
-// Compact the run tables R (of one cell) into slot sl and find the source
-// index of the particles t = lane and t = 64 + lane of species 0 and 1
-// (-1 where t is past the species' count).
-template <typename T, int DIM, int NSLOT>
-__device__ inline void runs_locate(RunRegs R, DepLds<T, DIM, NSLOT>& L, int sl, int nsp, int lane, int idx[2][2]) {
+// Compact the run tables R (of one cell) and find the source index of the
+// particles t = lane and t = 64 + lane of species 0 and 1 (-1 where t is past
+// the species' count).
+template <typename T, int DIM>
+__device__ inline void runs_locate(RunRegs R, DepLds<T, DIM>& L, int nsp, int lane, int idx[2][2]) {
   const int half = lane >> 5, r = lane & 31;
   {
     const bool ok = r < Dm<DIM>::ND;
@@ -570,6 +570,10 @@ __device__ inline void runs_locate(RunRegs R, DepLds<T, DIM, NSLOT>& L, int sl, 
   int pre[2];
 #pragma unroll
   for (int k = 0; k < 2; ++k) {
+    if (k == 1 && nsp <= 2) {  // no species 2 and 3 (wave-uniform)
+      pre[1] = 0;
+      break;
+    }
     const int incl = dpp_scan<false, true>(R.cnt[k]);  // within each half
     pre[k] = incl - R.cnt[k];
     const int t0 = __builtin_amdgcn_readlane(incl, 31), t1 = __builtin_amdgcn_readlane(incl, 63);
@@ -579,12 +583,12 @@ __device__ inline void runs_locate(RunRegs R, DepLds<T, DIM, NSLOT>& L, int sl, 
     const int sp = half + 2 * k;
     if (R.cnt[k] > 0) {
       const int pos = __popc(mh & ((1u << r) - 1u));
-      L.runs[sl][sp][0][pos] = R.st[k];
-      L.runs[sl][sp][1][pos] = pre[k];
+      L.runs[sp][0][pos] = R.st[k];
+      L.runs[sp][1][pos] = pre[k];
     }
     if (r == 0) {
-      L.nseg[sl][sp] = __popc(mh);
-      L.total[sl][sp] = sp < nsp ? tot : 0;
+      L.nseg[sp] = __popc(mh);
+      L.total[sp] = sp < nsp ? tot : 0;
     }
   }
   // run-start markers hold lane + 1 (0 = no run starts here)
@@ -596,7 +600,7 @@ __device__ inline void runs_locate(RunRegs R, DepLds<T, DIM, NSLOT>& L, int sl, 
   const int basev = R.st[0] - pre[0];
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
-    const int tot = L.total[sl][s];
+    const int tot = L.total[s];
     const int s0 = dpp_scan<true, false>(L.mark[s][lane]);
     const int m0 = s0 - 1;
     const int m1 = max(dpp_scan<true, false>(L.mark[s][64 + lane]), __builtin_amdgcn_readlane(s0, 63)) - 1;
@@ -616,25 +620,20 @@ __device__ inline void load_p(const DepSpecies<T>& S, int i, PState<T>& P) {
   read_rec<T, DIM>(S.rec, i, P.f, P.v, P.w);
 }
 
-// Persistent wavefronts, each owning a contiguous range of cells.  While a
-// wave computes cell c, the particles and corner fields of cell c+1 and the
-// run table of cell c+2 are already on their way (two-stage software
-// pipeline), so the dependent loads of a cell (run table -> particles) never
-// stall the wave.
-template <typename T, int DIM, bool PIPE, int WPB>
-__global__ __launch_bounds__(64 * WPB) void k_deposit(DGrid G, DepArgs<T> A, int64_t nwaves) {
+// One wavefront per cell (the cell index is wave-uniform and lives in scalar
+// registers).  The corner fields and the run table are loaded first; the run
+// table gives the particle indices, whose loads are then all in flight
+// together before the first chunk is staged.
+template <typename T, int DIM>
+__global__ __launch_bounds__(64) void k_deposit(DGrid G, DepArgs<T> A) {
   using M = Mfma<T>;
   typedef typename M::v4 v4;
   using C = DepCfg<T, DIM>;
   constexpr int NC = Dm<DIM>::NC, NRB = C::NRB, NR = C::NR, AW = C::AW, ST = C::ST;
-  __shared__ DepLds<T, DIM, PIPE ? 2 : 1> s_l[WPB];
-  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t gw = xcd_block(blockIdx.x, gridDim.x) * WPB + wid;
-  // PIPE: persistent waves over contiguous cell ranges; else one cell per wave
-  const int64_t cb = PIPE ? gw * G.N / nwaves : gw, ce = PIPE ? (gw + 1) * G.N / nwaves : gw + 1;
-  if (!PIPE && cb >= G.N) return;
-  if (cb >= ce) return;
-  DepLds<T, DIM, PIPE ? 2 : 1>& L = s_l[wid];
+  __shared__ DepLds<T, DIM> L;
+  const int lane = threadIdx.x;
+  const int64_t c = __builtin_amdgcn_readfirstlane((int)xcd_block(blockIdx.x, gridDim.x));
+  if (c >= G.N) return;
   T* acc_lin = L.acc;             // [NR][7]: q alpha v (3), m v (3), m w
   T* acc_rho = acc_lin + 7 * NR;  // [NR][GE_MAX_SPECIES]
   const int col = lane & 15;
@@ -643,63 +642,40 @@ __global__ __launch_bounds__(64 * WPB) void k_deposit(DGrid G, DepArgs<T> A, int
   // products land in accumulator rows that are never used.
   const int rofsA0 = (lane >> 4) * ST + col, rofsA1 = rofsA0 + 16, rofsB = (lane >> 4) * ST + AW + col;
 
-  typedef T t4 __attribute__((ext_vector_type(4)));
   // B at corner lane (lanes past the corners reload corner 0)
   typedef T t3 __attribute__((ext_vector_type(3)));
-  auto corner = [&](int64_t c) -> t3 {
+  t3 cv;
+  {
     const int a = lane < NC ? lane : 0;
     const int64_t g = nbr3(G, c, a & 1, DIM >= 2 ? (a >> 1) & 1 : 0, DIM >= 3 ? (a >> 2) & 1 : 0);
-    return *reinterpret_cast<const t3*>(A.NF + 8 * g + 4);
-  };
+    cv = *reinterpret_cast<const t3*>(A.NF + 8 * g + 4);
+  }
   const DepSpecies<T>& S1 = A.nsp > 1 ? A.sp[1] : A.sp[0];  // a valid buffer even without species 1
-
-  // pipeline prologue (the corner fields do not depend on the run table:
-  // their load goes first)
-  t3 cv = corner(cb);
-  PState<T> Pn[2][2];
-  int idx[2][2];
-  RunRegs R = load_runs<T, DIM>(G, cb, A, lane);
-  runs_locate(R, L, 0, A.nsp, lane, idx);
+  PState<T> P[2][2];
+  {
+    int idx[2][2];
+    RunRegs R = load_runs<T, DIM>(G, c, A, lane);
+    runs_locate(R, L, A.nsp, lane, idx);
 #pragma unroll
-  for (int j = 0; j < 2; ++j) load_p<T, DIM>(A.sp[0], idx[0][j], Pn[0][j]);
+    for (int j = 0; j < 2; ++j) load_p<T, DIM>(A.sp[0], idx[0][j], P[0][j]);
 #pragma unroll
-  for (int j = 0; j < 2; ++j) load_p<T, DIM>(S1, idx[1][j], Pn[1][j]);
-  if constexpr (PIPE) R = load_runs<T, DIM>(G, cb + 1 < ce ? cb + 1 : cb, A, lane);
-
-  for (int64_t c = cb; c < ce; ++c) {
-    const int sl = (int)((c - cb) & 1);
-    PState<T> P[2][2];
-#pragma unroll
-    for (int s = 0; s < 2; ++s)
-#pragma unroll
-      for (int j = 0; j < 2; ++j) P[s][j] = Pn[s][j];
-    if (lane < NC) {
-      L.fc[lane] = cv[0];
-      L.fc[NC + lane] = cv[1];
-      L.fc[2 * NC + lane] = cv[2];
-    }
-    for (int k = lane; k < C::NACC; k += 64) L.acc[k] = 0;
-    // stage 1: run table of c+1 -> particle and corner loads of c+1; stage 2:
-    // run table of c+2 (past the range end the last cell is loaded again and
-    // ignored, so that the loads stay unconditional)
-    if constexpr (PIPE) {
-      const int64_t c1 = c + 1 < ce ? c + 1 : c, c2 = c + 2 < ce ? c + 2 : ce - 1;
-      runs_locate(R, L, sl ^ 1, A.nsp, lane, idx);
-#pragma unroll
-      for (int j = 0; j < 2; ++j) load_p<T, DIM>(A.sp[0], idx[0][j], Pn[0][j]);
-#pragma unroll
-      for (int j = 0; j < 2; ++j) load_p<T, DIM>(S1, idx[1][j], Pn[1][j]);
-      cv = corner(c1);
-      R = load_runs<T, DIM>(G, c2, A, lane);
-    }
-    wave_sync();
+    for (int j = 0; j < 2; ++j) load_p<T, DIM>(S1, idx[1][j], P[1][j]);
+  }
+  if (lane < NC) {
+    L.fc[lane] = cv[0];
+    L.fc[NC + lane] = cv[1];
+    L.fc[2 * NC + lane] = cv[2];
+  }
+  for (int k = lane; k < C::NACC; k += 64) L.acc[k] = 0;
+  wave_sync();
+  {
     // Mtilde and M0 rows (B columns 0..8) accumulate over species in registers
     v4 aMt[NRB], aM0[NRB];
 #pragma unroll
     for (int rb = 0; rb < NRB; ++rb) aMt[rb] = aM0[rb] = v4{0, 0, 0, 0};
     for (int s = 0; s < A.nsp; ++s) {
       const DepSpecies<T>& S = A.sp[s];
-      const int total = L.total[sl][s];
+      const int total = L.total[s];
       v4 acc[NRB];
 #pragma unroll
       for (int rb = 0; rb < NRB; ++rb) acc[rb] = v4{0, 0, 0, 0};
@@ -821,7 +797,7 @@ __global__ __launch_bounds__(64 * WPB) void k_deposit(DGrid G, DepArgs<T> A, int
       for (int t0 = nfast; t0 < total; t0 += 64) {
         PState<T> q;
         const int t = t0 + lane;
-        load_p<T, DIM>(S, t < total ? run_index(t, L.runs[sl][s][0], L.runs[sl][s][1], L.nseg[sl][s]) : -1, q);
+        load_p<T, DIM>(S, t < total ? run_index(t, L.runs[s][0], L.runs[s][1], L.nseg[s]) : -1, q);
         chunk(q, t0);
       }
       // scale this species' sums into the cell accumulators (each (row, col)
@@ -869,7 +845,6 @@ __global__ __launch_bounds__(64 * WPB) void k_deposit(DGrid G, DepArgs<T> A, int
       }
       Qc[4 * (18 * NR + k * NC + a)] = sum;
     }
-    wave_sync();
   }
 }
 
@@ -1014,11 +989,6 @@ int ge_launch_push(ge_ctx* c, int s) {
   return GE_OK;
 }
 
-// deposit launch shape: persistent pipelined waves or one wave per cell, and
-// wavefronts per workgroup
-constexpr bool DEP_PIPE = false;
-constexpr int DEP_WPB = 1;
-
 template <typename T, int DIM>
 static void launch_deposit_t(ge_ctx* c) {
   DepArgs<T> A;
@@ -1033,26 +1003,8 @@ static void launch_deposit_t(ge_ctx* c) {
   A.NF = (const T*)c->node8;
   A.cellQ = (T*)c->cellQ;
   A.Qn = c->Q;
-  if (DEP_PIPE) {
-    // persistent grid: as many workgroups as fit on the device at once
-    static int per_cu[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
-    int& occ = per_cu[sizeof(T) == 4][DIM];
-    if (!occ) {
-      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-              &occ, reinterpret_cast<const void*>(&k_deposit<T, DIM, true, DEP_WPB>), 64 * DEP_WPB, 0) != hipSuccess ||
-          occ < 1)
-        occ = 1;
-    }
-    int64_t nb = (int64_t)occ * c->n_cu;
-    const int64_t need = (c->G.N + DEP_WPB - 1) / DEP_WPB;  // at least one cell per wave
-    if (nb > need) nb = need;
-    hipLaunchKernelGGL((k_deposit<T, DIM, true, DEP_WPB>), dim3((unsigned)nb), dim3(64 * DEP_WPB), 0, c->stream, c->G, A,
-                       nb * DEP_WPB);
-  } else {
-    const int64_t nb = (c->G.N + DEP_WPB - 1) / DEP_WPB;
-    hipLaunchKernelGGL((k_deposit<T, DIM, false, DEP_WPB>), dim3((unsigned)nb), dim3(64 * DEP_WPB), 0, c->stream, c->G,
-                       A, c->G.N);
-  }
+  // one wavefront (one workgroup) per cell
+  hipLaunchKernelGGL((k_deposit<T, DIM>), dim3((unsigned)c->G.N), dim3(64), 0, c->stream, c->G, A);
 }
 
 int ge_launch_deposit(ge_ctx* c) {
