@@ -139,6 +139,26 @@ __device__ inline void corners_to_lds(const DGrid& G, int64_t c, const T* __rest
   }
 }
 
+// The same corner values with wave-uniform scalar loads into registers (the
+// node records are read-only during the push): fc[q NC + a] as above.
+template <typename T, int DIM>
+__device__ inline void corners_scalar(const DGrid& G, int64_t c, const T* NF, T fc[6 * 8]) {
+  constexpr int NC = Dm<DIM>::NC;
+  typedef T t4 __attribute__((ext_vector_type(4)));
+  typedef const __attribute__((address_space(4))) t4* cptr;  // constant address space: scalar loads
+  const cptr nf = reinterpret_cast<cptr>(reinterpret_cast<uintptr_t>(NF));
+#pragma unroll
+  for (int a = 0; a < NC; ++a) {
+    const int64_t g = nbr3(G, c, a & 1, DIM >= 2 ? (a >> 1) & 1 : 0, DIM >= 3 ? (a >> 2) & 1 : 0);
+    const t4 e = nf[2 * g], b = nf[2 * g + 1];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      fc[q * NC + a] = e[q];
+      fc[(3 + q) * NC + a] = b[q];
+    }
+  }
+}
+
 template <typename T, int DIM>
 __device__ inline void lin_weights(const T f[3], T W[8]) {
   constexpr int NC = Dm<DIM>::NC;
@@ -279,27 +299,36 @@ __device__ inline void store_particle(const PushArgs<T>& A, int64_t o, const T f
 // Cells with up to 128 particles keep the pushed state in registers; larger
 // cells count in a first pass and push again in a second (same arithmetic).
 template <typename T, int DIM>
-__global__ __launch_bounds__(256) void k_push(DGrid G, PushArgs<T> A) {
+__global__ __launch_bounds__(64) void k_push(DGrid G, PushArgs<T> A) {
   constexpr int ND = Dm<DIM>::ND, NC = Dm<DIM>::NC;
-  __shared__ int s_start[4][32], s_pre[4][32];
-  __shared__ int s_mark[4][128];
-  __shared__ T s_fc[4][48];
-  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  // the cell is uniform over the wave: keep its index (and coordinates) scalar
-  const int64_t c = __builtin_amdgcn_readfirstlane((int)(xcd_block(blockIdx.x, gridDim.x) * 4 + wid));
+  __shared__ int s_start[32], s_pre[32];
+  __shared__ int s_mark[128];
+  __shared__ T s_fc[48];
+  const int lane = threadIdx.x;
+  // one wavefront (one workgroup) per cell; the cell is uniform over the
+  // wave: keep its index (and coordinates) scalar
+  const int64_t c = __builtin_amdgcn_readfirstlane((int)xcd_block(blockIdx.x, gridDim.x));
   if (c >= G.N) return;
-  T* fc = s_fc[wid];
-  corners_to_lds<T, DIM>(G, c, A.NF, fc, lane);
+  // corner E and B: FP32 in scalar registers, FP64 (twice the registers) in LDS
+  T fcr[6 * 8];
+  const T* fc;
+  if constexpr (sizeof(T) == 4) {
+    corners_scalar<T, DIM>(G, c, A.NF, fcr);
+    fc = fcr;
+  } else {
+    corners_to_lds<T, DIM>(G, c, A.NF, s_fc, lane);
+    fc = s_fc;
+  }
   int nseg;
-  int* sst = s_start[wid];
-  int* spr = s_pre[wid];
+  int* sst = s_start;
+  int* spr = s_pre;
   const int total = runs_setup<DIM>(G, c, A.runs, sst, spr, lane, nseg);
   const int64_t base = A.seg_next[c];
   int cnt = 0, dir_off = 0, clamped = 0, bad = 0;
   if (total <= 128) {
     // particle t = lane and t = 64 + lane: run k from a max-scan of run-start
     // markers (k + 1 at position s_pre[k], 0 elsewhere)
-    int* mk = s_mark[wid];
+    int* mk = s_mark;
     mk[lane] = 0;
     mk[64 + lane] = 0;
     wave_sync();
@@ -341,7 +370,7 @@ __global__ __launch_bounds__(256) void k_push(DGrid G, PushArgs<T> A) {
         T f[3] = {0, 0, 0}, v[3] = {0, 0, 0}, w = 0;
         int dir = 31;
         if (act) {
-          load_particle<T, DIM>(A, run_index(t, s_start[wid], s_pre[wid], nseg), f, v, w);
+          load_particle<T, DIM>(A, run_index(t, sst, spr, nseg), f, v, w);
           dir = push_one<T, DIM>(f, v, fc, A.beta, A.dtx, clamped);
         }
         const DirStats q = dir_stats(act, dir, lane);
@@ -969,8 +998,7 @@ static void launch_push_t(ge_ctx* c, int s) {
   for (int d = 0; d < 3; ++d) A.dtx[d] = (T)(c->P.dt * c->G.idx[d]);
   A.n = S.n;
   A.flags = c->flags;
-  const int64_t nb = (c->G.N + 3) / 4;
-  hipLaunchKernelGGL((k_push<T, DIM>), dim3(nb), dim3(256), 0, c->stream, c->G, A);
+  hipLaunchKernelGGL((k_push<T, DIM>), dim3((unsigned)c->G.N), dim3(64), 0, c->stream, c->G, A);
 }
 
 // Push species s; needs ge_launch_scan_counts(c, s) first.
