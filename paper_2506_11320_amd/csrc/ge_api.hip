@@ -104,7 +104,7 @@ int ge_create(const ge_grid* grid, const ge_params* params, void* hip_stream, ge
   c->ND = dim == 3 ? 27 : (dim == 2 ? 9 : 3);
   c->NC = 1 << dim;
   c->NR = c->ND;
-  c->Q = 18 * c->NR + c->NC * (7 + GE_MAX_SPECIES);
+  c->Q = (18 * c->NR + c->NC * (7 + GE_MAX_SPECIES) + 3) / 4 * 4;  // a multiple of 4 (cq_index)
   c->kr_m = 64;
   {
     int dev = 0;

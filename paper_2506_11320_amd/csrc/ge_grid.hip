@@ -47,6 +47,21 @@ __global__ void k_pack_node8(int64_t N, const double* __restrict__ src, int half
 // per-cell corner sums into nodes, in a fixed order (deterministic).  Node g
 // and g + o are corners a and a + o of the cells g - a; that pair's weight
 // product is quadratic row (2 a_d + o_d) along each axis d.
+// Values k0 .. k0 + 8 of one cell's sums (qc = the cell's value 0), read as
+// the 3 or 4 aligned 4-value vectors that hold them (k0 is a compile-time
+// constant at every call, so the picks below are fixed register moves).
+template <typename T>
+__device__ inline void load_run9(const T* __restrict__ qc, int k0, T out[9]) {
+  typedef T t4 __attribute__((ext_vector_type(4)));
+  const int kb0 = k0 >> 2, nb = ((k0 + 8) >> 2) - kb0 + 1;
+  t4 blk[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+    if (j < nb) blk[j] = *reinterpret_cast<const t4*>(qc + cq_off(4 * (kb0 + j)));
+#pragma unroll
+  for (int e = 0; e < 9; ++e) out[e] = blk[((k0 + e) >> 2) - kb0][(k0 + e) & 3];
+}
+
 template <typename T, int DIM>
 __global__ __launch_bounds__(256) void k_assemble(DGrid G, const T* __restrict__ Q, int Qn, int nsp, T* __restrict__ Mt,
                                                   T* __restrict__ M0, double* __restrict__ Jlab, double* __restrict__ mm,
@@ -79,11 +94,14 @@ __global__ __launch_bounds__(256) void k_assemble(DGrid G, const T* __restrict__
         mul *= 3;
       }
       if (!ok) continue;
+      const T* qc = Q + cq_index(cells[a], 0, Qn);
+      T v[9];
+      load_run9(qc, r * 9, v);
 #pragma unroll
-      for (int e = 0; e < 9; ++e) {
-        smt[e] += (double)Q[cq_index(cells[a], r * 9 + e, Qn)];
-        sm0[e] += (double)Q[cq_index(cells[a], 9 * NR + r * 9 + e, Qn)];
-      }
+      for (int e = 0; e < 9; ++e) smt[e] += (double)v[e];
+      load_run9(qc, 9 * NR + r * 9, v);
+#pragma unroll
+      for (int e = 0; e < 9; ++e) sm0[e] += (double)v[e];
     }
 #pragma unroll
     for (int e = 0; e < 9; ++e) {

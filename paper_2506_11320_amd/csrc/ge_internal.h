@@ -60,10 +60,15 @@ __device__ inline int64_t nbr3(const DGrid& G, int64_t g, int ox, int oy, int oz
   return flat3(G, i + ox, j + oy, k + oz);
 }
 
-// Per-cell partial sums are stored in blocks of 4 consecutive cells,
-// [cell/4][Q][4], so that the 4 wavefronts of a deposit workgroup fill whole
-// cache lines together.
-__host__ __device__ inline int64_t cq_index(int64_t c, int k, int Q) { return ((c >> 2) * Q + k) * 4 + (c & 3); }
+// Per-cell partial sums: value k of cell c at cq_index(c, k, Q), laid out as
+// [cell/4][Q/4][4 cells][4 values] (Q a multiple of 4).  The 4 cells of a
+// group share cache lines (their deposit waves run side by side), and 4
+// consecutive values of one cell form one 16-byte vector, which the node
+// assembly reads with a single load.
+__host__ __device__ inline int cq_off(int k) { return (k >> 2) * 16 + (k & 3); }
+__host__ __device__ inline int64_t cq_index(int64_t c, int k, int Q) {
+  return ((c >> 2) * (Q >> 2) * 4 + (c & 3)) * 4 + cq_off(k);
+}
 
 // Workgroups are dispatched round-robin over the 8 XCDs; remap so that each
 // XCD (and its L2) receives one contiguous range of logical blocks.

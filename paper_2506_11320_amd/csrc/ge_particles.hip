@@ -140,9 +140,10 @@ __device__ inline void corners_to_lds(const DGrid& G, int64_t c, const T* __rest
 }
 
 // The same corner values with wave-uniform scalar loads into registers (the
-// node records are read-only during the push): fc[q NC + a] as above.
-template <typename T, int DIM>
-__device__ inline void corners_scalar(const DGrid& G, int64_t c, const T* NF, T fc[6 * 8]) {
+// node records are read-only in the particle kernels): fc[q NC + a] as above,
+// E then B (WITH_E), or B alone from fc[0].
+template <typename T, int DIM, bool WITH_E>
+__device__ inline void corners_scalar(const DGrid& G, int64_t c, const T* NF, T* fc) {
   constexpr int NC = Dm<DIM>::NC;
   typedef T t4 __attribute__((ext_vector_type(4)));
   typedef const __attribute__((address_space(4))) t4* cptr;  // constant address space: scalar loads
@@ -150,12 +151,14 @@ __device__ inline void corners_scalar(const DGrid& G, int64_t c, const T* NF, T 
 #pragma unroll
   for (int a = 0; a < NC; ++a) {
     const int64_t g = nbr3(G, c, a & 1, DIM >= 2 ? (a >> 1) & 1 : 0, DIM >= 3 ? (a >> 2) & 1 : 0);
-    const t4 e = nf[2 * g], b = nf[2 * g + 1];
+    const t4 b = nf[2 * g + 1];
+    if constexpr (WITH_E) {
+      const t4 e = nf[2 * g];
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      fc[q * NC + a] = e[q];
-      fc[(3 + q) * NC + a] = b[q];
+      for (int q = 0; q < 3; ++q) fc[q * NC + a] = e[q];
     }
+#pragma unroll
+    for (int q = 0; q < 3; ++q) fc[((WITH_E ? 3 : 0) + q) * NC + a] = b[q];
   }
 }
 
@@ -313,7 +316,7 @@ __global__ __launch_bounds__(64) void k_push(DGrid G, PushArgs<T> A) {
   T fcr[6 * 8];
   const T* fc;
   if constexpr (sizeof(T) == 4) {
-    corners_scalar<T, DIM>(G, c, A.NF, fcr);
+    corners_scalar<T, DIM, true>(G, c, A.NF, fcr);
     fc = fcr;
   } else {
     corners_to_lds<T, DIM>(G, c, A.NF, s_fc, lane);
@@ -503,7 +506,7 @@ struct DepArgs {
   DepSpecies<T> sp[GE_MAX_SPECIES];
   int nsp;
   const T* NF;  // node records [N][8] (the B half is used)
-  T* cellQ;     // per-cell sums, [N/4][Qn][4] (cq_index)
+  T* cellQ;     // per-cell sums (cq_index)
   int Qn;
 };
 
@@ -671,13 +674,21 @@ __global__ __launch_bounds__(64) void k_deposit(DGrid G, DepArgs<T> A) {
   // products land in accumulator rows that are never used.
   const int rofsA0 = (lane >> 4) * ST + col, rofsA1 = rofsA0 + 16, rofsB = (lane >> 4) * ST + AW + col;
 
-  // B at corner lane (lanes past the corners reload corner 0)
+  // B at the corners: FP32 in scalar registers (wave-uniform loads); FP64 (twice
+  // the registers) one corner per lane (lanes past the corners reload corner 0)
+  // into LDS
   typedef T t3 __attribute__((ext_vector_type(3)));
+  T fbr[3 * 8];
+  const T* fb;
   t3 cv;
-  {
+  if constexpr (sizeof(T) == 4) {
+    corners_scalar<T, DIM, false>(G, c, A.NF, fbr);
+    fb = fbr;
+  } else {
     const int a = lane < NC ? lane : 0;
     const int64_t g = nbr3(G, c, a & 1, DIM >= 2 ? (a >> 1) & 1 : 0, DIM >= 3 ? (a >> 2) & 1 : 0);
     cv = *reinterpret_cast<const t3*>(A.NF + 8 * g + 4);
+    fb = L.fc;
   }
   const DepSpecies<T>& S1 = A.nsp > 1 ? A.sp[1] : A.sp[0];  // a valid buffer even without species 1
   PState<T> P[2][2];
@@ -690,10 +701,12 @@ __global__ __launch_bounds__(64) void k_deposit(DGrid G, DepArgs<T> A) {
 #pragma unroll
     for (int j = 0; j < 2; ++j) load_p<T, DIM>(S1, idx[1][j], P[1][j]);
   }
-  if (lane < NC) {
-    L.fc[lane] = cv[0];
-    L.fc[NC + lane] = cv[1];
-    L.fc[2 * NC + lane] = cv[2];
+  if constexpr (sizeof(T) != 4) {
+    if (lane < NC) {
+      L.fc[lane] = cv[0];
+      L.fc[NC + lane] = cv[1];
+      L.fc[2 * NC + lane] = cv[2];
+    }
   }
   for (int k = lane; k < C::NACC; k += 64) L.acc[k] = 0;
   wave_sync();
@@ -726,7 +739,7 @@ __global__ __launch_bounds__(64) void k_deposit(DGrid G, DepArgs<T> A) {
           T W[8];
           lin_weights<T, DIM>(f, W);
           T Bp[3];
-          gather_lds<T, DIM>(W, L.fc, Bp);
+          gather_lds<T, DIM>(W, fb, Bp);
           const T be = S.beta, bb = be * be;
           const T den = recip((T)1 + bb * (Bp[0] * Bp[0] + Bp[1] * Bp[1] + Bp[2] * Bp[2]));
           const T wd = w * den;
@@ -848,7 +861,7 @@ __global__ __launch_bounds__(64) void k_deposit(DGrid G, DepArgs<T> A) {
     wave_sync();
     // write the cell: quadratic rows of Mtilde and M0, then corner sums of the
     // linear quantities, W_a = prod_d (X_{a_d} + X_{a_d + 1})
-    T* Qc = A.cellQ + cq_index(c, 0, A.Qn);  // value k of this cell at Qc[4 k]
+    T* Qc = A.cellQ + cq_index(c, 0, A.Qn);  // value k of this cell at Qc[cq_off(k)]
     if (col < 9) {
 #pragma unroll
       for (int rb = 0; rb < NRB; ++rb)
@@ -856,8 +869,8 @@ __global__ __launch_bounds__(64) void k_deposit(DGrid G, DepArgs<T> A) {
         for (int i = 0; i < 4; ++i) {
           const int r = 16 * rb + M::row(lane, i);
           if (r < NR) {
-            Qc[4 * (r * 9 + col)] = aMt[rb][i];
-            Qc[4 * (9 * NR + r * 9 + col)] = aM0[rb][i];
+            Qc[cq_off(r * 9 + col)] = aMt[rb][i];
+            Qc[cq_off(9 * NR + r * 9 + col)] = aM0[rb][i];
           }
         }
     }
@@ -872,7 +885,7 @@ __global__ __launch_bounds__(64) void k_deposit(DGrid G, DepArgs<T> A) {
         if (DIM >= 3) r += 9 * (((a >> 2) & 1) + ((b >> 2) & 1));
         sum += k < 7 ? acc_lin[r * 7 + k] : acc_rho[r * GE_MAX_SPECIES + (k - 7)];
       }
-      Qc[4 * (18 * NR + k * NC + a)] = sum;
+      Qc[cq_off(18 * NR + k * NC + a)] = sum;
     }
   }
 }
