@@ -136,7 +136,7 @@ int ge_create(const ge_grid* grid, const ge_params* params, void* hip_stream, ge
   if (!rc) rc = dalloc(c, &c->scan_blocks, sizeof(int32_t) * (c->scan_nblocks + 1));
   if (!rc) rc = dalloc(c, &c->V, sizeof(double) * 3 * N * (c->kr_m + 1));
   if (!rc) rc = dalloc(c, &c->hdev, sizeof(double) * 256);
-  if (!rc) rc = dalloc(c, &c->partials, sizeof(double) * 8 * 512);
+  if (!rc) rc = dalloc(c, &c->partials, sizeof(double) * 16 * 512);  // 16 dots x 512 blocks
   if (!rc) rc = dalloc(c, &c->flags, sizeof(int) * 4);
   if (rc) {
     ge_destroy(c);

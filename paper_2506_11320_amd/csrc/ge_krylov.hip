@@ -1,7 +1,9 @@
 // Restarted GMRES in FP64 for the implicit E system.  The Arnoldi basis is
 // orthogonalised by classical Gram-Schmidt applied twice (CGS2): each pass is
 // one fused multi-dot (block partial sums, reduced in a fixed order, so every
-// run gives the same bits) and one fused multi-axpy.  The Hessenberg column
+// run gives the same bits) and one fused multi-axpy; for up to 16 basis
+// vectors the first pass's update and the second pass's dots share one read
+// of the basis, and the second update carries the norm.  The Hessenberg column
 // travels to the host once per iteration for the Givens update.
 #include <chrono>
 #include <cmath>
@@ -68,6 +70,71 @@ __global__ __launch_bounds__(KB) void k_multiaxpy(double* __restrict__ w, const 
   }
 }
 
+// The second CGS pass fused into the first pass's update: w[k] -= sum_i h[i]
+// V_i[k], then part[i * KRED + b] = block b's share of V_i . w (new w), with
+// V_i[k] read once for both.  Same grid, element order and per-element
+// arithmetic as k_multiaxpy followed by k_multidot, so the results are the
+// same bits.
+template <int NV>
+__global__ __launch_bounds__(KB) void k_axpy_dot(double* __restrict__ w, const double* __restrict__ V, int64_t ld,
+                                                 const double* __restrict__ h, int64_t n, double* __restrict__ part) {
+  __shared__ double sh[NV][KB];
+  __shared__ double hs[NV];
+  if (threadIdx.x < NV) hs[threadIdx.x] = h[threadIdx.x];
+  __syncthreads();
+  double a[NV];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) a[i] = 0;
+  for (int64_t k = blockIdx.x * (int64_t)KB + threadIdx.x; k < n; k += (int64_t)gridDim.x * KB) {
+    double v[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) v[i] = V[i * ld + k];
+    double s = 0;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) s += hs[i] * v[i];
+    const double wk = w[k] + (-1.0) * s;
+    w[k] = wk;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) a[i] += v[i] * wk;
+  }
+#pragma unroll
+  for (int i = 0; i < NV; ++i) sh[i][threadIdx.x] = a[i];
+  __syncthreads();
+  for (int s2 = KB / 2; s2 > 0; s2 >>= 1) {
+    if (threadIdx.x < s2)
+#pragma unroll
+      for (int i = 0; i < NV; ++i) sh[i][threadIdx.x] += sh[i][threadIdx.x + s2];
+    __syncthreads();
+  }
+  if (threadIdx.x < NV) part[threadIdx.x * KRED + blockIdx.x] = sh[threadIdx.x][0];
+}
+
+// The second pass's update fused with the squared norm of its result:
+// w[k] -= sum_{i<nv} h[i] V_i[k]; part[b] = block b's share of w . w.
+__global__ __launch_bounds__(KB) void k_axpy_norm(double* __restrict__ w, const double* __restrict__ V, int64_t ld,
+                                                  int nv, const double* __restrict__ h, int64_t n,
+                                                  double* __restrict__ part) {
+  __shared__ double hs[HSTRIDE];
+  __shared__ double sh[KB];
+  if (threadIdx.x < nv) hs[threadIdx.x] = h[threadIdx.x];
+  __syncthreads();
+  double a = 0;
+  for (int64_t k = blockIdx.x * (int64_t)KB + threadIdx.x; k < n; k += (int64_t)gridDim.x * KB) {
+    double s = 0;
+    for (int i = 0; i < nv; ++i) s += hs[i] * V[i * ld + k];
+    const double wk = w[k] + (-1.0) * s;
+    w[k] = wk;
+    a += wk * wk;
+  }
+  sh[threadIdx.x] = a;
+  __syncthreads();
+  for (int s2 = KB / 2; s2 > 0; s2 >>= 1) {
+    if (threadIdx.x < s2) sh[threadIdx.x] += sh[threadIdx.x + s2];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
 // v = w / sqrt(*nrm2)
 __global__ void k_normalize(double* __restrict__ v, const double* __restrict__ w, const double* __restrict__ nrm2, int64_t n) {
   const double inv = 1.0 / sqrt(*nrm2);
@@ -105,6 +172,24 @@ static int multidot(ge_ctx* c, const double* V, int64_t ld, int nv, const double
     }
     hipLaunchKernelGGL(k_reduce, dim3(k), dim3(KB), 0, c->stream, part, dots + i0);
   }
+  GE_HIP(c, hipGetLastError());
+  return GE_OK;
+}
+
+// Passes 1b and 2 of CGS2 for nv <= 16 vectors (h1 from the first multi-dot):
+// w -= V h1, h2 = V^T w, w -= V h2, |w|^2, with V read twice instead of three times.
+static int cgs2_fused(ge_ctx* c, double* w, const double* V, int64_t ld, int nv, const double* h1, double* h2,
+                      double* nrm2, int64_t n) {
+  double* part = c->partials;
+  switch (nv) {
+#define AD(K) case K: hipLaunchKernelGGL(k_axpy_dot<K>, dim3(KRED), dim3(KB), 0, c->stream, w, V, ld, h1, n, part); break;
+    AD(1) AD(2) AD(3) AD(4) AD(5) AD(6) AD(7) AD(8) AD(9) AD(10) AD(11) AD(12) AD(13) AD(14) AD(15) AD(16)
+#undef AD
+    default: return ge_fail(c, GE_ERR_ARG, "fused Gram-Schmidt takes at most 16 vectors");
+  }
+  hipLaunchKernelGGL(k_reduce, dim3(nv), dim3(KB), 0, c->stream, part, h2);
+  hipLaunchKernelGGL(k_axpy_norm, dim3(KRED), dim3(KB), 0, c->stream, w, V, ld, nv, h2, n, part);
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(KB), 0, c->stream, part, nrm2);
   GE_HIP(c, hipGetLastError());
   return GE_OK;
 }
@@ -191,11 +276,16 @@ int ge_gmres(ge_ctx* c, double tol, int maxit, int m, int precond, ge_solve_repo
       if ((rc = ge_launch_apply_A(c, av_in, w))) return rc;
       // CGS2
       if ((rc = multidot(c, V, n, j + 1, w, n, hd))) return rc;
-      hipLaunchKernelGGL(k_multiaxpy, vgrid(n), dim3(KB), 0, c->stream, w, V, n, j + 1, hd, -1.0, n);
-      if ((rc = multidot(c, V, n, j + 1, w, n, hd + HSTRIDE))) return rc;
-      hipLaunchKernelGGL(k_multiaxpy, vgrid(n), dim3(KB), 0, c->stream, w, V, n, j + 1, hd + HSTRIDE, -1.0, n);
-      hipLaunchKernelGGL(k_sum2, dim3(1), dim3(HSTRIDE), 0, c->stream, hd, hd + HSTRIDE, j + 1);
-      if ((rc = multidot(c, w, n, 1, w, n, hd + 128))) return rc;
+      if (j + 1 <= 16) {
+        if ((rc = cgs2_fused(c, w, V, n, j + 1, hd, hd + HSTRIDE, hd + 128, n))) return rc;
+        hipLaunchKernelGGL(k_sum2, dim3(1), dim3(HSTRIDE), 0, c->stream, hd, hd + HSTRIDE, j + 1);
+      } else {
+        hipLaunchKernelGGL(k_multiaxpy, vgrid(n), dim3(KB), 0, c->stream, w, V, n, j + 1, hd, -1.0, n);
+        if ((rc = multidot(c, V, n, j + 1, w, n, hd + HSTRIDE))) return rc;
+        hipLaunchKernelGGL(k_multiaxpy, vgrid(n), dim3(KB), 0, c->stream, w, V, n, j + 1, hd + HSTRIDE, -1.0, n);
+        hipLaunchKernelGGL(k_sum2, dim3(1), dim3(HSTRIDE), 0, c->stream, hd, hd + HSTRIDE, j + 1);
+        if ((rc = multidot(c, w, n, 1, w, n, hd + 128))) return rc;
+      }
       hipLaunchKernelGGL(k_normalize, vgrid(n), dim3(KB), 0, c->stream, vn, w, hd + 128, n);
       GE_HIP(c, hipGetLastError());
       GE_HIP(c, hipMemcpyAsync(hh.data(), hd, sizeof(double) * (2 * HSTRIDE + 1), hipMemcpyDeviceToHost, c->stream));
