@@ -204,7 +204,7 @@ int ge_add_species(ge_ctx* c, const ge_species* sp, int64_t n, const int32_t* ce
   const size_t es = c->P.precision == GE_FP32 ? 4 : 8;
   int rc = GE_OK;
   for (int b = 0; b < 2 && !rc; ++b) {
-    rc = dalloc(c, &S.rec[b], es * 8 * n);
+    rc = dalloc(c, &S.rec[b], es * GE_REC * (n > 0 ? n : 1));  // a valid record 0 even when empty
     if (!rc) rc = dalloc(c, &S.runs[b], sizeof(int32_t) * 2 * c->ND * c->G.N);
   }
   c->nsp = s + 1;  // so that ge_destroy frees partial allocations

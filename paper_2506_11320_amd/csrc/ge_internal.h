@@ -100,10 +100,13 @@ struct HalfStencil<3> {
                                    {1, 0, 1},  {-1, 1, 1}, {0, 1, 1},  {1, 1, 1}};
 };
 
+// values per particle record: offset in the cell (3), weight, velocity (3)
+constexpr int GE_REC = 7;
+
 struct SpeciesBuf {
   double q, m, beta;     // beta = q dt / (2 m)
   int64_t n;
-  void* rec[2];          // T[n][8]: offset in the cell (3), w, velocity (3), 0
+  void* rec[2];          // T[max(n,1)][GE_REC]: offset in the cell (3), w, velocity (3)
   int32_t* runs[2];      // [Ncell][ND][2]: (start, count) of the run entering cell c by move d
   int cur;
 };

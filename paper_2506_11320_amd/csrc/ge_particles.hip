@@ -231,7 +231,7 @@ __device__ inline int push_one(T f[3], T v[3], const T* fc, T beta, const T dtx[
 // ------------------------------------------------------------------ push
 template <typename T>
 struct PushArgs {
-  const T* rec;  // particle records [n][8], read
+  const T* rec;  // particle records [n][GE_REC], read
   T* rec_o;      // written
   const int32_t *runs, *seg_next;
   int32_t* runs_o;
@@ -268,15 +268,18 @@ __device__ inline DirStats dir_stats(bool act, int dir, int lane) {
 }
 __device__ inline int excl_scan(int x) { return dpp_scan<false, false>(x) - x; }
 
-// Particle record i: two vectors of 4, (offset x, y, z, w) and (v x, y, z, 0).
+// Particle record i: GE_REC = 7 consecutive values, offset x, y, z, w, then
+// velocity x, y, z (28 bytes in FP32), read and written as one 4-vector and
+// three values that the compiler merges into one 3-wide access (a vec3 type
+// is avoided: its FP64 store writes a fourth, padding element over the next
+// record).  Consecutive records are contiguous, so a wave's records are read
+// and written as whole cache lines without padding.
+template <typename T>
+using rec4 = T __attribute__((ext_vector_type(4), aligned(sizeof(T))));
 template <typename T, int DIM>
 __device__ inline void read_rec(const T* __restrict__ rec, int64_t i, T f[3], T v[3], T& w) {
-  typedef T t4 __attribute__((ext_vector_type(4)));
-  typedef T t3 __attribute__((ext_vector_type(3)));
-  // the velocity half is read as three values: a fourth, unused register
-  // would be reused by the compiler, which then waits for the load to land
-  const t4 a = reinterpret_cast<const t4*>(rec)[2 * i];
-  const t3 b = *reinterpret_cast<const t3*>(rec + 8 * i + 4);
+  const rec4<T> a = *reinterpret_cast<const rec4<T>*>(rec + GE_REC * i);
+  const T* b = rec + GE_REC * i + 4;
 #pragma unroll
   for (int d = 0; d < 3; ++d) f[d] = d < DIM ? a[d] : (T)0;
   v[0] = b[0]; v[1] = b[1]; v[2] = b[2];
@@ -284,9 +287,9 @@ __device__ inline void read_rec(const T* __restrict__ rec, int64_t i, T f[3], T 
 }
 template <typename T>
 __device__ inline void write_rec(T* __restrict__ rec, int64_t o, const T f[3], const T v[3], T w) {
-  typedef T t4 __attribute__((ext_vector_type(4)));
-  reinterpret_cast<t4*>(rec)[2 * o] = t4{f[0], f[1], f[2], w};
-  reinterpret_cast<t4*>(rec)[2 * o + 1] = t4{v[0], v[1], v[2], (T)0};
+  *reinterpret_cast<rec4<T>*>(rec + GE_REC * o) = rec4<T>{f[0], f[1], f[2], w};
+  T* b = rec + GE_REC * o + 4;
+  b[0] = v[0]; b[1] = v[1]; b[2] = v[2];
 }
 template <typename T, int DIM>
 __device__ inline void load_particle(const PushArgs<T>& A, int i, T f[3], T v[3], T& w) {
@@ -496,7 +499,7 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_final(const int32_t* __rest
 // and the cell's sums are written once at the end.
 template <typename T>
 struct DepSpecies {
-  const T* rec;  // particle records [n][8]
+  const T* rec;  // particle records [n][GE_REC]
   const int32_t* runs;  // [N][ND][2]
   T q, m, beta;
   int64_t n;
