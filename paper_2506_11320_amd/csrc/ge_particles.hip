@@ -711,13 +711,14 @@ __global__ __launch_bounds__(64) void k_deposit(DGrid G, DepArgs<T> A) {
       L.fc[2 * NC + lane] = cv[2];
     }
   }
-  for (int k = lane; k < C::NACC; k += 64) L.acc[k] = 0;
   wave_sync();
   {
-    // Mtilde and M0 rows (B columns 0..8) accumulate over species in registers
-    v4 aMt[NRB], aM0[NRB];
+    // Mtilde and M0 rows (B columns 0..8) and the linear sums (columns 9..15)
+    // accumulate over species in registers; the charge density of each
+    // species goes to LDS as it is completed
+    v4 aMt[NRB], aM0[NRB], aLin[NRB];
 #pragma unroll
-    for (int rb = 0; rb < NRB; ++rb) aMt[rb] = aM0[rb] = v4{0, 0, 0, 0};
+    for (int rb = 0; rb < NRB; ++rb) aMt[rb] = aM0[rb] = aLin[rb] = v4{0, 0, 0, 0};
     for (int s = 0; s < A.nsp; ++s) {
       const DepSpecies<T>& S = A.sp[s];
       const int total = L.total[s];
@@ -846,8 +847,8 @@ __global__ __launch_bounds__(64) void k_deposit(DGrid G, DepArgs<T> A) {
         chunk(q, t0);
       }
       // scale this species' sums into the cell accumulators (each (row, col)
-      // belongs to one lane, so no two lanes touch the same LDS word)
-      const T qs = S.q, ms = S.m, bq = S.beta * S.q;
+      // belongs to one lane)
+      const T qs = S.q, ms = S.m, bq = S.beta * S.q, ls = col < 12 ? qs : ms;
 #pragma unroll
       for (int rb = 0; rb < NRB; ++rb)
 #pragma unroll
@@ -855,12 +856,19 @@ __global__ __launch_bounds__(64) void k_deposit(DGrid G, DepArgs<T> A) {
           const T val = acc[rb][i];
           aMt[rb][i] += bq * val;
           aM0[rb][i] += qs * val;
+          aLin[rb][i] += ls * val;
           const int r = 16 * rb + M::row(lane, i);
-          if (r >= NR || col < 9) continue;
-          acc_lin[r * 7 + col - 9] += (col < 12 ? qs : ms) * val;
-          if (col == 15) acc_rho[r * GE_MAX_SPECIES + s] += qs * val;
+          if (col == 15 && r < NR) acc_rho[r * GE_MAX_SPECIES + s] = qs * val;
         }
     }
+    // linear sums to LDS for the corner sums (rows < NR, columns 9..15)
+#pragma unroll
+    for (int rb = 0; rb < NRB; ++rb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = 16 * rb + M::row(lane, i);
+        if (r < NR && col >= 9) acc_lin[r * 7 + col - 9] = aLin[rb][i];
+      }
     wave_sync();
     // write the cell: quadratic rows of Mtilde and M0, then corner sums of the
     // linear quantities, W_a = prod_d (X_{a_d} + X_{a_d + 1})
