@@ -205,6 +205,61 @@ def smooth(G: Grid, f, npass: int, phi: float = 0.5) -> np.ndarray:
     return f
 
 
+def smooth_current(G: Grid, J, npass: int, phi: float = 0.5) -> np.ndarray:
+    """Current smoothing (Sec. 3.2): npass passes of the digital filter of
+    Sec. 2.4 at its default stride d = 1, each pass sweeping x, then y, then z
+    (the sweep order is the reading used for the u smoothing as well)."""
+    J = _f64(J).copy()
+    for _ in range(npass):
+        for axis in range(G.dim):
+            J = filter_axis(G, J, phi, 1, axis)
+    return J
+
+
+def _cell_view(G: Grid, f):
+    """[ncomp][N] (x fastest) -> [ncomp, nz, ny, nx] view."""
+    f = np.asarray(f, dtype=np.float64)
+    return f.reshape(f.shape[0], G.n[2], G.n[1], G.n[0])
+
+
+def div_cc(G: Grid, Bc) -> np.ndarray:
+    """Divergence of a cell-centred vector at the cell centres, central
+    differences on the periodic mesh (READING for the divergence cleaning of
+    Sec. 2.3, whose discretisation the paper takes from a reference that is
+    not available): sum_d (B_d(c + e_d) - B_d(c - e_d)) / (2 dx_d)."""
+    B = _cell_view(G, Bc)
+    out = np.zeros(B.shape[1:])
+    for d in range(G.dim):
+        ax = 2 - d  # array axis of mesh axis d in [z, y, x]
+        out += (np.roll(B[d], -1, axis=ax) - np.roll(B[d], 1, axis=ax)) / (2.0 * G.dx[d])
+    return out.reshape(-1)
+
+
+def grad_cc(G: Grid, psi) -> np.ndarray:
+    """Gradient of a cell-centred scalar at the cell centres, central
+    differences: the negative adjoint of div_cc on the periodic mesh."""
+    f = np.asarray(psi, dtype=np.float64).reshape(G.n[2], G.n[1], G.n[0])
+    out = np.zeros((3,) + f.shape)
+    for d in range(G.dim):
+        ax = 2 - d
+        out[d] = (np.roll(f, -1, axis=ax) - np.roll(f, 1, axis=ax)) / (2.0 * G.dx[d])
+    return out.reshape(3, -1)
+
+
+def cleaning_speed(G: Grid, dt: float, ch_frac: float = 0.8) -> float:
+    """c_h = ch_frac * dx / dt (Sec. 2.3 uses 0.8), dx the smallest active spacing."""
+    return ch_frac * min(G.dx[d] for d in range(G.dim)) / dt
+
+
+def dedner_psi(G: Grid, dt: float, psi, Bc, ch: float, damp: float = 0.1) -> np.ndarray:
+    """One step of the cleaning scalar (Sec. 2.3): d psi/dt + c_h^2 div B =
+    -(c_h^2/c_p^2) psi, READING: explicit in div B^n, then the damping term
+    integrated exactly over the step, psi^{n+1} = (psi^n - dt c_h^2 div B^n)
+    exp(-damp) with damp = dt c_h^2 / c_p^2 (0.1 in Sec. 2.3)."""
+    psi = np.asarray(psi, dtype=np.float64).reshape(-1)
+    return (psi - dt * ch * ch * div_cc(G, Bc)) * math.exp(-damp)
+
+
 def motional(G: Grid, u, Bn) -> np.ndarray:
     u, Bn = _f64(u), _f64(Bn)
     out = np.empty_like(u)
@@ -384,11 +439,13 @@ def beta_s(q: float, m: float, dt: float) -> float:
 
 
 def deposit(G: Grid, species: List[Species], dt: float, Bc, comoving: bool, n_smooth_u: int = 5,
-            phi_u: float = 0.5) -> Dict[str, np.ndarray]:
+            phi_u: float = 0.5, n_smooth_j: int = 0) -> Dict[str, np.ndarray]:
     """Particle-to-grid quantities of one step (Sec. 3.1).
 
     Returns J_lab, M_s (per species, 27-offset), Mt = sum beta_s M_s,
-    M0 = sum M_s, rho_s, mm, mass, u (smoothed), EM, J_C and J_eff."""
+    M0 = sum M_s, rho_s, mm, mass, u (smoothed), EM, J_C and J_eff.
+    n_smooth_j > 0 smooths the comoving-frame current J_C (the lab current when
+    the comoving frame is off) before the E_M term is added (Sec. 3.2)."""
     N = nnodes(G)
     dV = cellvol(G)
     Bn = node_avg(G, Bc)
@@ -419,11 +476,14 @@ def deposit(G: Grid, species: List[Species], dt: float, Bc, comoving: bool, n_sm
             b = beta_s(sp.q, sp.m, dt)
             a = deposit_species(G, sp.q, sp.m, b, sp.x, sp.v, sp.w, Bn, u_node=u)
             JC += a["J"]
+        if n_smooth_j > 0:
+            JC = smooth_current(G, JC, n_smooth_j, phi_u)
         out["J_C"] = JC
         out["J_eff"] = current_eff(G, JC, out["Mt"], out["EM"])
     else:
-        out["J_C"] = out["J_lab"]
-        out["J_eff"] = out["J_lab"]
+        JC = smooth_current(G, out["J_lab"], n_smooth_j, phi_u) if n_smooth_j > 0 else out["J_lab"]
+        out["J_C"] = JC
+        out["J_eff"] = JC
     return out
 
 
@@ -449,11 +509,14 @@ def diagnostics(G: Grid, species: List[Species], E, Bc) -> Dict[str, object]:
 def step(G: Grid, species: List[Species], E, Bc, *, dt: float, theta: float, c: float = 1.0,
          comoving: bool = False, lf_E: bool = False, lf_B: bool = False, beta_lim: float = 1.0,
          a_mode: int = 1, n_smooth_u: int = 5, tol: float = 1e-12, restart: int = 30,
-         solve: str = "gmres") -> Dict[str, object]:
+         solve: str = "gmres", n_smooth_j: int = 0, dedner: bool = False, ch_frac: float = 0.8,
+         dedner_damp: float = 0.1, psi=None) -> Dict[str, object]:
     """One full GL-ECSIM step without the Gauss's-law correction:
-    deposit -> implicit E solve -> B and E update -> particle push."""
+    deposit -> implicit E solve -> B and E update -> particle push.
+    With dedner, the cleaning scalar psi (cells, zero if None) is advanced
+    from B^n first and B^{n+1} gets -dt grad psi^{n+1} (Sec. 2.3)."""
     P = params(theta, dt, c)
-    dep = deposit(G, species, dt, Bc, comoving, n_smooth_u)
+    dep = deposit(G, species, dt, Bc, comoving, n_smooth_u, n_smooth_j=n_smooth_j)
     a_node = diffusion_speed(G, dep["u"], a_mode, c)
     kE = kappa_E(G, E, a_node, beta_lim) if lf_E else None
     kB = kappa_B(G, Bc, a_node, beta_lim) if lf_B else None
@@ -464,10 +527,15 @@ def step(G: Grid, species: List[Species], E, Bc, *, dt: float, theta: float, c: 
     else:
         Eth, its, rel = gmres(G, P, dep["Mt"], kE, b, E, tol=tol, maxit=5000, restart=restart)
     Bnew = update_B(G, P, Bc, Eth, kB)
+    psi_new = None
+    if dedner:
+        psi0 = np.zeros(nnodes(G)) if psi is None else psi
+        psi_new = dedner_psi(G, dt, psi0, Bc, cleaning_speed(G, dt, ch_frac), dedner_damp)
+        Bnew = Bnew - dt * grad_cc(G, psi_new)
     Enew = update_E(theta, E, Eth)
     new_species = []
     for sp in species:
         xn, vn = push_species(G, beta_s(sp.q, sp.m, dt), dt, sp.x, sp.v, Eth, dep["Bn"])
         new_species.append(Species(sp.q, sp.m, xn, vn, sp.w))
     return {"dep": dep, "kE": kE, "kB": kB, "b": b, "Eth": Eth, "E": Enew, "B": Bnew,
-            "species": new_species, "iters": its, "relres": rel, "a_node": a_node}
+            "species": new_species, "iters": its, "relres": rel, "a_node": a_node, "psi": psi_new}

@@ -68,9 +68,10 @@ def half_from_full(M27, dim):
     return np.stack([M27[O.off27(o)] for o in O.half_offsets(dim)])
 
 
-def oracle_grid_pass(wl, G, sp, E, B, comoving=None, beta_lim=None, a_mode=None, lf_E=None, lf_B=None):
+def oracle_grid_pass(wl, G, sp, E, B, comoving=None, beta_lim=None, a_mode=None, lf_E=None, lf_B=None,
+                     n_smooth_j=0):
     comoving = wl.comoving if comoving is None else comoving
-    dep = O.deposit(G, sp, wl.dt, B, comoving, wl.n_smooth_u)
+    dep = O.deposit(G, sp, wl.dt, B, comoving, wl.n_smooth_u, n_smooth_j=n_smooth_j)
     a_node = O.diffusion_speed(G, dep["u"], wl.a_mode if a_mode is None else a_mode, 1.0)
     bl = wl.beta_lim if beta_lim is None else beta_lim
     dep["kE"] = O.kappa_E(G, E, a_node, bl) if (wl.lf_E if lf_E is None else lf_E) else None
