@@ -156,6 +156,8 @@ def main():
     ap.add_argument("--nn-pairs", type=int, default=96, help="pair store capacity")
     ap.add_argument("--nn-data", default="both", choices=["solution", "krylov", "both"],
                     help="training pairs: (r0, e) of each solve, (A v_j, v_j) of its Arnoldi vectors, or both")
+    ap.add_argument("--ns-j", type=int, default=0, help="current smoothing passes (Sec. 3.2); 0 = off")
+    ap.add_argument("--dedner", action="store_true", help="divergence cleaning of B (Sec. 2.3)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain device copy of 4 GiB (reference for the HBM byte counters) and exit")
     args = ap.parse_args()
@@ -180,7 +182,7 @@ def main():
     log(f"workload {wl.name}: cells {wl.n[:wl.dim]}, ppc {wl.ppc}, species {wl.nsp}")
     sim = Simulation(wl.dim, wl.n, wl.dx, theta=wl.theta, dt=wl.dt, lf_E=wl.lf_E, lf_B=wl.lf_B,
                      beta_lim=wl.beta_lim, a_mode=wl.a_mode, comoving=wl.comoving, n_smooth_u=wl.n_smooth_u,
-                     fp32=wl.fp32)
+                     fp32=wl.fp32, ns_j=args.ns_j, dedner=args.dedner)
     counts = []
     t0 = time.perf_counter()
     for s in range(wl.nsp):
@@ -257,7 +259,8 @@ def main():
         "config": {"workload": f"{wl.name}: 3D3V double-Harris reconnection, {wl.n[0]}x{wl.n[1]}x{wl.n[2]} cells, "
                                f"{wl.ppc} ppc/species, m_i/m_e={wl.m[1]:g}, guide flow {wl.u0[0]}c, "
                                f"FP32 push/deposit, FP64 GMRES to {args.tol:g}, comoving current, limited LF",
-                   "cells": wl.ncells, "particles": npart, "precond": args.precond},
+                   "cells": wl.ncells, "particles": npart, "precond": args.precond, "ns_j": args.ns_j,
+                   "dedner": bool(args.dedner)},
         "push_deposit_particle_steps_per_s": npart / pd_s,
         "gmres_s_per_step": {"plain" if pc == 0 else args.precond: float(np.mean(solve_s)),
                              "nn": nn["nn"]["seconds"] if nn else None},

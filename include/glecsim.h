@@ -79,6 +79,19 @@ typedef struct {
   int n_smooth_u;     /* filter passes for u (Sec. 3.1 uses 5) */
   double phi_u;       /* filter weight (0.5) */
   int precision;      /* GE_FP64 or GE_FP32 (particles, deposit, mass matrices) */
+  /* Current smoothing (Sec. 3.2): ns_j passes of the Sec. 2.4 filter (stride 1,
+   * weight phi_u, each pass sweeping x, y, z) on the comoving-frame current
+   * J_C = J_lab - (1/dV) M0 u (J_lab in the lab frame) before the E_M term is
+   * added.  0 = off; the paper uses 1 to 3. */
+  int ns_j;
+  /* Hyperbolic/parabolic divergence cleaning of B (Sec. 2.3): a cell-centred
+   * scalar psi with psi^{n+1} = (psi^n - dt c_h^2 div B^n) exp(-dedner_damp)
+   * and B^{n+1} -= dt grad psi^{n+1} (central differences at cell centres),
+   * c_h = ch_frac * min dx / dt.  The paper uses ch_frac = 0.8 and
+   * dedner_damp = dt c_h^2 / c_p^2 = 0.1.  0 = off. */
+  int dedner;
+  double ch_frac;
+  double dedner_damp;
 } ge_params;
 
 typedef struct { double q, m; } ge_species;   /* charge and mass per physical particle */
@@ -191,7 +204,8 @@ enum {
   GE_F_M0 = 12,      /* sum_s M_s, half stencil [nh][9][N] */
   GE_F_KAPPA_E = 13, /* E diffusion coefficients [3 axes][3 comps][N] */
   GE_F_KAPPA_B = 14, /* B diffusion coefficients [3 axes][3 comps][N] */
-  GE_F_RHS = 15      /* right-hand side b       [3][N] */
+  GE_F_RHS = 15,     /* right-hand side b       [3][N] */
+  GE_F_PSI = 16      /* divergence-cleaning scalar at cells [N] */
 };
 /* Half stencil: nh = 14 (3D), 5 (2D), 2 (1D) offsets o with M_{g,g+o}
  * stored at node g: o = 0 first, then every o != 0 whose last nonzero

@@ -88,6 +88,7 @@ int ge_create(const ge_grid* grid, const ge_params* params, void* hip_stream, ge
   if (!(params->theta >= 0.5 && params->theta <= 1.0) || !(params->dt > 0) || !(params->c > 0)) return bad("theta/dt/c");
   if (params->precision != GE_FP64 && params->precision != GE_FP32) return bad("precision");
   if (params->n_smooth_u < 0 || params->beta_lim < 0) return bad("n_smooth_u/beta_lim");
+  if (params->ns_j < 0 || !(params->ch_frac >= 0) || !(params->dedner_damp >= 0)) return bad("ns_j/ch_frac/dedner_damp");
   DGrid& G = c->G;
   G.dim = dim;
   G.N = N;
@@ -124,6 +125,7 @@ int ge_create(const ge_grid* grid, const ge_params* params, void* hip_stream, ge
   if (!rc) rc = dalloc(c, &c->rho, sizeof(double) * GE_MAX_SPECIES * N);
   if (!rc) rc = dalloc(c, &c->mass, sizeof(double) * N);
   if (!rc) rc = dalloc(c, &c->anode, sizeof(double) * N);
+  if (!rc) rc = dalloc(c, &c->psi, sizeof(double) * N);
   if (!rc) rc = dalloc(c, &c->kE, sizeof(double) * 9 * N);
   if (!rc) rc = dalloc(c, &c->kB, sizeof(double) * 9 * N);
   if (!rc) rc = dalloc(c, &c->jac, sizeof(double) * 9 * N);
@@ -148,6 +150,7 @@ int ge_create(const ge_grid* grid, const ge_params* params, void* hip_stream, ge
   (void)hipMemsetAsync(c->kE, 0, sizeof(double) * 9 * N, s);
   (void)hipMemsetAsync(c->kB, 0, sizeof(double) * 9 * N, s);
   (void)hipMemsetAsync(c->rho, 0, sizeof(double) * GE_MAX_SPECIES * N, s);
+  (void)hipMemsetAsync(c->psi, 0, sizeof(double) * N, s);
   (void)hipMemsetAsync(c->flags, 0, sizeof(int) * 4, s);
   for (int k = 0; k < 10; ++k) (void)hipEventCreate(&c->ev[k]);
   for (int k = 0; k < 8; ++k) c->tsum[k] = 0;
@@ -164,7 +167,7 @@ void ge_destroy(ge_ctx* c) {
   if (!c) return;
   if (c->stream || true) (void)hipStreamSynchronize(c->stream);
   double** f[] = {&c->E, &c->B, &c->Eth, &c->Bn, &c->Jlab, &c->Jeff, &c->rho, &c->mm, &c->mass, &c->u, &c->utmp,
-                  &c->EM, &c->anode, &c->kE, &c->kB, &c->rhs, &c->Bnew, &c->ccell, &c->jac, &c->V, &c->Zp,
+                  &c->EM, &c->anode, &c->psi, &c->kE, &c->kB, &c->rhs, &c->Bnew, &c->ccell, &c->jac, &c->V, &c->Zp,
                   &c->kw, &c->kr, &c->kx, &c->hdev, &c->partials, &c->scal};
   for (auto p : f) dfree(*p);
   dfree(c->node8);
@@ -352,6 +355,7 @@ int ge_gather(ge_ctx* c, int what, double* dst) {
     case GE_F_KAPPA_E: src = c->kE; cnt = 9 * N; break;
     case GE_F_KAPPA_B: src = c->kB; cnt = 9 * N; break;
     case GE_F_RHS: src = c->rhs; break;
+    case GE_F_PSI: src = c->psi; cnt = N; break;
     default: return ge_fail(c, GE_ERR_ARG, "unknown field id");
   }
   GE_HIP(c, hipMemcpyAsync(dst, src, sizeof(double) * cnt, hipMemcpyDeviceToDevice, c->stream));
@@ -368,9 +372,11 @@ int ge_set(ge_ctx* c, int what, const double* src) {
     case GE_F_ETH: dst = c->Eth; break;
     case GE_F_BN: dst = c->Bn; break;
     case GE_F_RHS: dst = c->rhs; break;
+    case GE_F_PSI: dst = c->psi; break;
     default: return ge_fail(c, GE_ERR_ARG, "field id cannot be set");
   }
-  GE_HIP(c, hipMemcpyAsync(dst, src, sizeof(double) * 3 * N, hipMemcpyDeviceToDevice, c->stream));
+  GE_HIP(c, hipMemcpyAsync(dst, src, sizeof(double) * (what == GE_F_PSI ? 1 : 3) * N, hipMemcpyDeviceToDevice,
+                           c->stream));
   if (what == GE_F_ETH) c->have_solve = 1;
   if (what == GE_F_BN) return ge_launch_pack_node8(c, 1);
   return GE_OK;

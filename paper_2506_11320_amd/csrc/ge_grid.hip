@@ -184,18 +184,40 @@ __device__ inline void apply_half(const DGrid& G, const T* __restrict__ M, const
   }
 }
 
-// J_eff = J_lab - (1/dV)(M0 u + Mtilde E_M)  (Sec. 3.1, comoving frame)
-template <typename T, int DIM>
+// J_eff = J_lab - (1/dV)(M0 u + Mtilde E_M)  (Sec. 3.1, comoving frame).
+// PART 0: both terms, Jout = Jin - (1/dV)(M0 u + Mtilde E_M); PART 1: the
+// comoving-frame current J_C = Jin - (1/dV) M0 u; PART 2: the E_M term alone,
+// Jout = Jin - (1/dV) Mtilde E_M (J_C is smoothed between parts 1 and 2).
+template <typename T, int DIM, int PART>
 __global__ __launch_bounds__(256) void k_comoving(DGrid G, const T* __restrict__ Mt, const T* __restrict__ M0,
                                                   const double* __restrict__ u, const double* __restrict__ EM,
-                                                  const double* __restrict__ Jlab, double* __restrict__ Jeff) {
+                                                  const double* __restrict__ Jin, double* __restrict__ Jout) {
   const int64_t g = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (g >= G.N) return;
-  double a[3], b[3];
-  apply_half<T, DIM>(G, M0, u, g, a);
-  apply_half<T, DIM>(G, Mt, EM, g, b);
+  double a[3] = {0, 0, 0}, b[3] = {0, 0, 0};
+  if (PART != 2) apply_half<T, DIM>(G, M0, u, g, a);
+  if (PART != 1) apply_half<T, DIM>(G, Mt, EM, g, b);
   const double idV = 1.0 / G.dV;
-  for (int q = 0; q < 3; ++q) Jeff[q * G.N + g] = Jlab[q * G.N + g] - idV * (a[q] + b[q]);
+  for (int q = 0; q < 3; ++q) {
+    const double corr = PART == 0 ? a[q] + b[q] : (PART == 1 ? a[q] : b[q]);
+    Jout[q * G.N + g] = Jin[q * G.N + g] - idV * corr;
+  }
+}
+
+// Divergence cleaning (Sec. 2.3): psi = (psi - dt c_h^2 div B) decay with the
+// central-difference divergence of the cell-centred B at cell centres.
+template <int DIM>
+__global__ void k_dedner_psi(DGrid G, const double* __restrict__ B, double* __restrict__ psi, double dtch2,
+                             double decay) {
+  const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (c >= G.N) return;
+  double div = 0;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    const int64_t cp = nbr3(G, c, d == 0, d == 1, d == 2), cm = nbr3(G, c, -(d == 0), -(d == 1), -(d == 2));
+    div += (B[d * G.N + cp] - B[d * G.N + cm]) / (2.0 * G.dx[d]);
+  }
+  psi[c] = (psi[c] - dtch2 * div) * decay;
 }
 
 // ----------------------------------------------------------------- limited LF coefficients
@@ -407,12 +429,18 @@ __global__ __launch_bounds__(256) void k_apply_A(DGrid G, const double* __restri
 // B^{n+1} = B^n - c dt curl_NC E^{n+theta} + dt D_B B^n  (C holds curl_NC E^{n+theta})
 template <int DIM>
 __global__ void k_update_B(DGrid G, const double* __restrict__ B, const double* __restrict__ C,
-                           const double* __restrict__ kB, double cdt, double dt, double* __restrict__ Bnew) {
+                           const double* __restrict__ kB, const double* __restrict__ psi, double cdt, double dt,
+                           double* __restrict__ Bnew) {
   int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (c >= G.N) return;
   for (int q = 0; q < 3; ++q) {
     double v = B[q * G.N + c] - cdt * C[q * G.N + c];
     if (kB) v += dt * diffusion_at<DIM>(G, kB, B, c, q);
+    if (psi && q < DIM) {
+      // - dt grad psi^{n+1} (central difference at the cell centre)
+      const int64_t cp = nbr3(G, c, q == 0, q == 1, q == 2), cm = nbr3(G, c, -(q == 0), -(q == 1), -(q == 2));
+      v -= dt * ((psi[cp] - psi[cm]) / (2.0 * G.dx[q]));
+    }
     Bnew[q * G.N + c] = v;
   }
 }
@@ -549,10 +577,29 @@ static void assemble_t(ge_ctx* c) {
   hipLaunchKernelGGL((k_assemble<T, DIM>), grid1(c->G.N), dim3(256), 0, c->stream, c->G, (const T*)c->cellQ, c->Q,
                      c->nsp, (T*)c->Mt, (T*)c->M0, c->Jlab, c->mm, c->mass, c->rho);
 }
+// ns_j filter passes (stride 1, weight phi_u; x, then y, then z) on c->Jeff,
+// ping-ponging with c->utmp (free once u is smoothed)
+static void smooth_current(ge_ctx* c) {
+  for (int k = 0; k < c->P.ns_j; ++k)
+    for (int ax = 0; ax < c->G.dim; ++ax) {
+      hipLaunchKernelGGL(k_filter, grid1(c->G.N), dim3(256), 0, c->stream, c->G, c->Jeff, c->utmp, ax, 1, c->P.phi_u);
+      std::swap(c->Jeff, c->utmp);
+    }
+}
+
 template <typename T, int DIM>
 static void comoving_t(ge_ctx* c) {
-  hipLaunchKernelGGL((k_comoving<T, DIM>), grid1(c->G.N), dim3(256), 0, c->stream, c->G, (const T*)c->Mt,
+  if (c->P.ns_j == 0) {
+    hipLaunchKernelGGL((k_comoving<T, DIM, 0>), grid1(c->G.N), dim3(256), 0, c->stream, c->G, (const T*)c->Mt,
+                       (const T*)c->M0, c->u, c->EM, c->Jlab, c->Jeff);
+    return;
+  }
+  hipLaunchKernelGGL((k_comoving<T, DIM, 1>), grid1(c->G.N), dim3(256), 0, c->stream, c->G, (const T*)c->Mt,
                      (const T*)c->M0, c->u, c->EM, c->Jlab, c->Jeff);
+  smooth_current(c);
+  hipLaunchKernelGGL((k_comoving<T, DIM, 2>), grid1(c->G.N), dim3(256), 0, c->stream, c->G, (const T*)c->Mt,
+                     (const T*)c->M0, c->u, c->EM, c->Jeff, c->utmp);
+  std::swap(c->Jeff, c->utmp);
 }
 #define DISPATCH_TD(c, FN)                                          \
   switch ((c)->G.dim * 2 + ((c)->P.precision == GE_FP32 ? 1 : 0)) { \
@@ -587,6 +634,7 @@ int ge_launch_grid_pass(ge_ctx* c) {
     DISPATCH_TD(c, comoving_t);
   } else {
     GE_HIP(c, hipMemcpyAsync(c->Jeff, c->Jlab, sizeof(double) * 3 * N, hipMemcpyDeviceToDevice, c->stream));
+    smooth_current(c);
   }
   if (c->P.lf_E) DISPATCH_DIM(c, k_kappa_E, grid1(N), dim3(256), 0, c->stream, G, c->E, c->anode, c->P.beta_lim, c->kE);
   if (c->P.lf_B) DISPATCH_DIM(c, k_kappa_B, grid1(N), dim3(256), 0, c->stream, G, c->B, c->anode, c->P.beta_lim, c->kB);
@@ -655,8 +703,15 @@ int ge_launch_update(ge_ctx* c) {
   const int64_t N = c->G.N;
   (void)hipEventRecord(c->ev[8], c->stream);
   DISPATCH_DIM(c, k_curl_nc, grid1(N), dim3(256), 0, c->stream, c->G, c->Eth, c->ccell);
+  if (c->P.dedner) {
+    double dxmin = c->G.dx[0];
+    for (int d = 1; d < c->G.dim; ++d) dxmin = std::min(dxmin, c->G.dx[d]);
+    const double ch = c->P.ch_frac * dxmin / c->P.dt;
+    DISPATCH_DIM(c, k_dedner_psi, grid1(N), dim3(256), 0, c->stream, c->G, c->B, c->psi, c->P.dt * ch * ch,
+                 std::exp(-c->P.dedner_damp));
+  }
   DISPATCH_DIM(c, k_update_B, grid1(N), dim3(256), 0, c->stream, c->G, c->B, c->ccell, c->P.lf_B ? c->kB : nullptr,
-               c->P.c * c->P.dt, c->P.dt, c->Bnew);
+               c->P.dedner ? c->psi : nullptr, c->P.c * c->P.dt, c->P.dt, c->Bnew);
   std::swap(c->B, c->Bnew);
   hipLaunchKernelGGL(k_update_E, grid1(3 * N), dim3(256), 0, c->stream, 3 * N, c->P.theta, c->Eth, c->E);
   GE_HIP(c, hipGetLastError());

@@ -121,6 +121,7 @@ struct ge_ctx {
   SpeciesBuf sp[GE_MAX_SPECIES];
   // fields (double)
   double *E, *B, *Eth, *Bn, *Jlab, *Jeff, *rho, *mm, *mass, *u, *utmp, *EM, *anode, *kE, *kB, *rhs, *Bnew, *ccell;
+  double* psi;  // divergence-cleaning scalar at cells [N]
   // FP32 copies for particle gathers
   void* node8;  // T[N][8] in the particle precision: E^{n+theta} (3), 0, node-averaged B^n (3), 0
   // mass matrices (T) and per-cell partial sums (T)

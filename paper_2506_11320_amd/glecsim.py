@@ -24,7 +24,7 @@ GE_PC_NONE, GE_PC_JACOBI, GE_PC_CNN = 0, 1, 2
 GE_HARVEST_SOLUTION, GE_HARVEST_KRYLOV = 1, 2
 FIELDS = {
     "E": 0, "B": 1, "Eth": 2, "Bn": 3, "J_lab": 4, "J_eff": 5, "rho": 6, "mm": 7, "mass": 8, "u": 9,
-    "EM": 10, "Mt": 11, "M0": 12, "kappa_E": 13, "kappa_B": 14, "rhs": 15,
+    "EM": 10, "Mt": 11, "M0": 12, "kappa_E": 13, "kappa_B": 14, "rhs": 15, "psi": 16,
 }
 EXPORTS = [
     "ge_create", "ge_destroy", "ge_last_error", "ge_add_species", "ge_set_fields", "ge_deposit", "ge_solve_fields",
@@ -43,7 +43,9 @@ class GEParams(ctypes.Structure):
     _fields_ = [("theta", ctypes.c_double), ("c", ctypes.c_double), ("dt", ctypes.c_double),
                 ("lf_E", ctypes.c_int), ("lf_B", ctypes.c_int), ("beta_lim", ctypes.c_double),
                 ("a_mode", ctypes.c_int), ("a_const", ctypes.c_double), ("comoving", ctypes.c_int),
-                ("n_smooth_u", ctypes.c_int), ("phi_u", ctypes.c_double), ("precision", ctypes.c_int)]
+                ("n_smooth_u", ctypes.c_int), ("phi_u", ctypes.c_double), ("precision", ctypes.c_int),
+                ("ns_j", ctypes.c_int), ("dedner", ctypes.c_int), ("ch_frac", ctypes.c_double),
+                ("dedner_damp", ctypes.c_double)]
 
 
 class GESpecies(ctypes.Structure):
@@ -132,6 +134,7 @@ class Simulation:
     def __init__(self, dim: int, n, dx, *, theta: float, dt: float, c: float = 1.0, lf_E: bool = True,
                  lf_B: bool = True, beta_lim: float = 1.0, a_mode: int = GE_A_BULK, a_const: float = 1.0,
                  comoving: bool = True, n_smooth_u: int = 5, phi_u: float = 0.5, fp32: bool = False,
+                 ns_j: int = 0, dedner: bool = False, ch_frac: float = 0.8, dedner_damp: float = 0.1,
                  device: str = "cuda:0", stream: Optional[torch.cuda.Stream] = None):
         if not torch.cuda.is_available():
             raise RuntimeError("glecsim needs a GPU (no CPU fallback)")
@@ -150,7 +153,7 @@ class Simulation:
             g.n[d] = self.n[d]
             g.dx[d] = float(dx[d]) if d < dim else 1.0
         p = GEParams(theta, c, dt, int(lf_E), int(lf_B), beta_lim, a_mode, a_const, int(comoving), n_smooth_u,
-                     phi_u, GE_FP32 if fp32 else GE_FP64)
+                     phi_u, GE_FP32 if fp32 else GE_FP64, int(ns_j), int(dedner), ch_frac, dedner_damp)
         self.params = p
         with torch.cuda.device(self.device):
             self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
@@ -228,7 +231,7 @@ class Simulation:
         N = self.N
         if what in ("rho",):
             return (self.nsp, N)
-        if what == "mass":
+        if what in ("mass", "psi"):
             return (N,)
         if what in ("Mt", "M0"):
             return (self.half_stencil(), 9, N)
