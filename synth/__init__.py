@@ -223,6 +223,22 @@ def workloads() -> Dict[str, Workload]:
         comoving=True, fp32=True)
     # C5: 3D3V reconnection at HBM scale with a guide flow.
     W["c5"] = _harris("c5_harris_3d", 3, (256, 128, 128), 100.0, 64, 0.2, 50, True)
+    # Sec. 4.2 uniform fast flow (solar wind at 1 AU) in code units c = 1,
+    # d_e = 1, 4 pi n0 = 1, with the reduced light speed c = 3000 km/s of the
+    # paper's shock test (the fast-flow passage gives none): u = 400/3000,
+    # V_A = 49/3000 => B = V_A sqrt(m_i).  The quoted ion thermal speed 32 km/s
+    # is sqrt(5/3 k T_i / m_p) for T_i = 72,000 K, so the per-component spread
+    # is 32 / sqrt(5/3) km/s for the ions and sqrt(2 m_i/m_e) times that for the
+    # electrons (T_e = 2 T_i); d_e = d_i/10 = 10.2 km => dx = 8 km = 0.784,
+    # L = 20 cells, dt = 0.0038 s times omega_pe = c/d_e.  Particles per cell
+    # are not given: 200.
+    _VS_FF = 32.0 / 3000.0 / math.sqrt(5.0 / 3.0)
+    W["ff1d"] = Workload(
+        name="ff1d_fast_flow_1d", dim=1, n=(20, 1, 1), dx=(8.0 / 10.2, 1, 1), ppc=200,
+        q=(-1.0, 1.0), m=(1.0, 100.0), vth=(math.sqrt(200.0) * _VS_FF, _VS_FF), paired=False,
+        seed=6, profile=PROF_UNIFORM, u0=(400.0 / 3000.0, 0.0, 0.0), B0=(0.0, 0.0, 49.0 / 3000.0 * 10.0),
+        dt=0.0038 * 3000.0 / 10.2, theta=0.5, steps=200, lf_E=True, lf_B=True, beta_lim=1.0, a_mode=1,
+        comoving=True, fp32=False)
     return W
 
 
