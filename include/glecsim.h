@@ -92,6 +92,11 @@ typedef struct {
   int dedner;
   double ch_frac;
   double dedner_damp;
+  /* Electric-field smoothing, the alternative to the LF diffusion that Sec. 4.1
+   * compares against (filter of Sec. 2.4): ns_e passes on E^{n+1} right after
+   * its update, strides 1, 2, 1, ..., weight phi_u, each pass sweeping x, y,
+   * z.  0 = off (the method itself uses the LF diffusion instead). */
+  int ns_e;
 } ge_params;
 
 typedef struct { double q, m; } ge_species;   /* charge and mass per physical particle */

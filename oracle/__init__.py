@@ -510,11 +510,13 @@ def step(G: Grid, species: List[Species], E, Bc, *, dt: float, theta: float, c: 
          comoving: bool = False, lf_E: bool = False, lf_B: bool = False, beta_lim: float = 1.0,
          a_mode: int = 1, n_smooth_u: int = 5, tol: float = 1e-12, restart: int = 30,
          solve: str = "gmres", n_smooth_j: int = 0, dedner: bool = False, ch_frac: float = 0.8,
-         dedner_damp: float = 0.1, psi=None) -> Dict[str, object]:
+         dedner_damp: float = 0.1, psi=None, n_smooth_e: int = 0) -> Dict[str, object]:
     """One full GL-ECSIM step without the Gauss's-law correction:
     deposit -> implicit E solve -> B and E update -> particle push.
     With dedner, the cleaning scalar psi (cells, zero if None) is advanced
-    from B^n first and B^{n+1} gets -dt grad psi^{n+1} (Sec. 2.3)."""
+    from B^n first and B^{n+1} gets -dt grad psi^{n+1} (Sec. 2.3).
+    n_smooth_e > 0 smooths E^{n+1} with that many filter passes (Sec. 2.4,
+    strides 1, 2, 1, ...), the alternative to the LF diffusion of Sec. 4.1."""
     P = params(theta, dt, c)
     dep = deposit(G, species, dt, Bc, comoving, n_smooth_u, n_smooth_j=n_smooth_j)
     a_node = diffusion_speed(G, dep["u"], a_mode, c)
@@ -533,6 +535,8 @@ def step(G: Grid, species: List[Species], E, Bc, *, dt: float, theta: float, c: 
         psi_new = dedner_psi(G, dt, psi0, Bc, cleaning_speed(G, dt, ch_frac), dedner_damp)
         Bnew = Bnew - dt * grad_cc(G, psi_new)
     Enew = update_E(theta, E, Eth)
+    if n_smooth_e:
+        Enew = smooth(G, Enew, n_smooth_e)
     new_species = []
     for sp in species:
         xn, vn = push_species(G, beta_s(sp.q, sp.m, dt), dt, sp.x, sp.v, Eth, dep["Bn"])

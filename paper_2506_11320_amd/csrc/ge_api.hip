@@ -89,6 +89,7 @@ int ge_create(const ge_grid* grid, const ge_params* params, void* hip_stream, ge
   if (params->precision != GE_FP64 && params->precision != GE_FP32) return bad("precision");
   if (params->n_smooth_u < 0 || params->beta_lim < 0) return bad("n_smooth_u/beta_lim");
   if (params->ns_j < 0 || !(params->ch_frac >= 0) || !(params->dedner_damp >= 0)) return bad("ns_j/ch_frac/dedner_damp");
+  if (params->ns_e < 0) return bad("ns_e");
   DGrid& G = c->G;
   G.dim = dim;
   G.N = N;

@@ -714,6 +714,14 @@ int ge_launch_update(ge_ctx* c) {
                c->P.dedner ? c->psi : nullptr, c->P.c * c->P.dt, c->P.dt, c->Bnew);
   std::swap(c->B, c->Bnew);
   hipLaunchKernelGGL(k_update_E, grid1(3 * N), dim3(256), 0, c->stream, 3 * N, c->P.theta, c->Eth, c->E);
+  // optional E smoothing: strides 1, 2, 1, ...; x, then y, then z per pass;
+  // c->utmp is free between grid passes
+  for (int k = 0; k < c->P.ns_e; ++k)
+    for (int ax = 0; ax < c->G.dim; ++ax) {
+      hipLaunchKernelGGL(k_filter, grid1(N), dim3(256), 0, c->stream, c->G, c->E, c->utmp, ax, (k % 2 == 0) ? 1 : 2,
+                         c->P.phi_u);
+      std::swap(c->E, c->utmp);
+    }
   GE_HIP(c, hipGetLastError());
   (void)hipEventRecord(c->ev[9], c->stream);
   return GE_OK;

@@ -45,7 +45,7 @@ class GEParams(ctypes.Structure):
                 ("a_mode", ctypes.c_int), ("a_const", ctypes.c_double), ("comoving", ctypes.c_int),
                 ("n_smooth_u", ctypes.c_int), ("phi_u", ctypes.c_double), ("precision", ctypes.c_int),
                 ("ns_j", ctypes.c_int), ("dedner", ctypes.c_int), ("ch_frac", ctypes.c_double),
-                ("dedner_damp", ctypes.c_double)]
+                ("dedner_damp", ctypes.c_double), ("ns_e", ctypes.c_int)]
 
 
 class GESpecies(ctypes.Structure):
@@ -135,7 +135,7 @@ class Simulation:
                  lf_B: bool = True, beta_lim: float = 1.0, a_mode: int = GE_A_BULK, a_const: float = 1.0,
                  comoving: bool = True, n_smooth_u: int = 5, phi_u: float = 0.5, fp32: bool = False,
                  ns_j: int = 0, dedner: bool = False, ch_frac: float = 0.8, dedner_damp: float = 0.1,
-                 device: str = "cuda:0", stream: Optional[torch.cuda.Stream] = None):
+                 ns_e: int = 0, device: str = "cuda:0", stream: Optional[torch.cuda.Stream] = None):
         if not torch.cuda.is_available():
             raise RuntimeError("glecsim needs a GPU (no CPU fallback)")
         self.L = load_library()
@@ -153,7 +153,8 @@ class Simulation:
             g.n[d] = self.n[d]
             g.dx[d] = float(dx[d]) if d < dim else 1.0
         p = GEParams(theta, c, dt, int(lf_E), int(lf_B), beta_lim, a_mode, a_const, int(comoving), n_smooth_u,
-                     phi_u, GE_FP32 if fp32 else GE_FP64, int(ns_j), int(dedner), ch_frac, dedner_damp)
+                     phi_u, GE_FP32 if fp32 else GE_FP64, int(ns_j), int(dedner), ch_frac, dedner_damp,
+                     int(ns_e))
         self.params = p
         with torch.cuda.device(self.device):
             self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)

@@ -17,7 +17,7 @@ def _overshoot(f):
     return max(f.max() - 1.0, -f.min(), 0.0)
 
 
-def _oracle_light_wave(lf_E, lf_B, beta, cfl, nsteps, n=80, dx=0.01):
+def _oracle_light_wave(lf_E, lf_B, beta, cfl, nsteps, n=80, dx=0.01, ns_e=0):
     G = O.grid(1, (n, 1, 1), (dx, 1, 1))
     dt = cfl * dx
     xn = -0.4 + np.arange(n) * dx
@@ -34,15 +34,17 @@ def _oracle_light_wave(lf_E, lf_B, beta, cfl, nsteps, n=80, dx=0.01):
         Eth, _, _ = O.gmres(G, P, None, kE, b, E, tol=1e-13)
         B = O.update_B(G, P, B, Eth, kB)
         E = O.update_E(0.5, E, Eth)
+        if ns_e:
+            E = O.smooth(G, E, ns_e)
     return E, B
 
 
-def _gpu_light_wave(lf_E, lf_B, beta, cfl, nsteps, n=80, dx=0.01):
+def _gpu_light_wave(lf_E, lf_B, beta, cfl, nsteps, n=80, dx=0.01, ns_e=0):
     """Vacuum on the particle path: one weightless particle per cell, so the
     current and the mass matrices vanish; a = c (Sec. 4.1)."""
     from paper_2506_11320_amd import Simulation, GE_A_LIGHT
     sim = Simulation(1, (n, 1, 1), (dx, 1, 1), theta=0.5, dt=cfl * dx, lf_E=lf_E, lf_B=lf_B, beta_lim=beta,
-                     a_mode=GE_A_LIGHT, a_const=1.0, comoving=False, n_smooth_u=0)
+                     a_mode=GE_A_LIGHT, a_const=1.0, comoving=False, n_smooth_u=0, ns_e=ns_e)
     dev = sim.device
     cell = torch.arange(n, dtype=torch.int32, device=dev)
     off = torch.full((3, n), 0.5, dtype=torch.float64, device=dev)
@@ -71,6 +73,34 @@ def test_light_wave_matches_oracle(lf_E, lf_B, beta, cfl, steps):
     Eg, Bg = _gpu_light_wave(lf_E, lf_B, beta, cfl, steps)
     Eo, Bo = _oracle_light_wave(lf_E, lf_B, beta, cfl, steps)
     assert H.relerr(Eg, Eo) < 1e-10 and H.relerr(Bg, Bo) < 1e-10
+
+
+@pytest.mark.parametrize("ns_e", [1, 3])
+def test_light_wave_E_filter_matches_oracle(ns_e):
+    """Sec. 4.1's E-filter variant (LF on B only), 100 steps to t = 0.4."""
+    print(f"[gpu] light wave E filter ns_e={ns_e}", flush=True)
+    Eg, Bg = _gpu_light_wave(False, True, 1.0, 0.4, 100, ns_e=ns_e)
+    Eo, Bo = _oracle_light_wave(False, True, 1.0, 0.4, 100, ns_e=ns_e)
+    assert H.relerr(Eg, Eo) < 1e-10 and H.relerr(Bg, Bo) < 1e-10
+
+
+@pytest.mark.parametrize("dim,n,base,fp32", [(2, (7, 5, 1), "c2", False), (3, (5, 4, 3), "c5", True)])
+def test_E_filter_full_step_matches_oracle(dim, n, base, fp32):
+    """A full multi-D step with ns_e = 2 (strides 1, 2; x, y, z per pass)."""
+    print(f"[gpu] E filter full step dim={dim} fp32={fp32}", flush=True)
+    wl = synth.small("efilt", dim=dim, n=n, ppc=40, base=base, fp32=fp32).replace(lf_E=False, lf_B=True)
+    parts = H.species_arrays(wl, fp32)
+    E, B = H.perturbed_fields(wl)
+    G, sp = H.oracle_species(wl, parts)
+    r = O.step(G, sp, E, B, dt=wl.dt, theta=wl.theta, comoving=wl.comoving, lf_E=False, lf_B=True,
+               beta_lim=wl.beta_lim, a_mode=wl.a_mode, n_smooth_u=wl.n_smooth_u, tol=1e-13, restart=40,
+               n_smooth_e=2)
+    sim = H.make_sim(wl, parts, E, B, ns_e=2)
+    assert sim.step(tol=1e-13, maxit=2000, restart=40)["converged"]
+    tol = 1e-5 if fp32 else 1e-10
+    assert H.relerr(sim.gather("E").cpu().numpy(), r["E"]) < tol
+    assert H.relerr(sim.gather("B").cpu().numpy(), r["B"]) < tol
+    sim.close()
 
 
 def test_light_wave_claims_on_gpu():
