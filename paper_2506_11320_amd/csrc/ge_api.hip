@@ -101,6 +101,7 @@ int ge_create(const ge_grid* grid, const ge_params* params, void* hip_stream, ge
     if (d < dim) G.dV *= G.dx[d];
   }
   grid_div_magic(G);
+  G.colsh = visit_colsh(G);
   c->nsp = 0;
   c->nh = half_count(dim);
   c->ND = dim == 3 ? 27 : (dim == 2 ? 9 : 3);

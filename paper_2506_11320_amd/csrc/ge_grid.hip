@@ -68,11 +68,11 @@ __global__ __launch_bounds__(256) void k_assemble(DGrid G, const T* __restrict__
                                                   double* __restrict__ mass, double* __restrict__ rho) {
   constexpr int NC = Gd<DIM>::NC, NR = Gd<DIM>::NR;
   using HS = HalfStencil<DIM>;
-  const int64_t g = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-  if (g >= G.N) return;
+  const int64_t t = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  if (t >= G.N) return;
   const int64_t N = G.N;
   int gi, gj, gk;
-  unflat3(G, g, gi, gj, gk);
+  const int64_t g = visit_order(G, (unsigned)t, gi, gj, gk);
   int64_t cells[NC];
 #pragma unroll
   for (int a = 0; a < NC; ++a)
@@ -160,12 +160,10 @@ __global__ void k_motional(int64_t N, const double* __restrict__ u, const double
 // the stored block at g serves offset +o, the block stored at g - o serves -o.
 template <typename T, int DIM>
 __device__ inline void apply_half(const DGrid& G, const T* __restrict__ M, const double* __restrict__ x, int64_t g,
-                                  double y[3]) {
+                                  int gx, int gy, int gz, double y[3]) {
   using HS = HalfStencil<DIM>;
   const int64_t N = G.N;
   y[0] = y[1] = y[2] = 0;
-  int gx, gy, gz;
-  unflat3(G, g, gx, gy, gz);
 #pragma unroll
   for (int h = 0; h < HS::NH; ++h) {
     const int64_t gp = flat3(G, gx + HS::o[h][0], gy + HS::o[h][1], gz + HS::o[h][2]);
@@ -192,11 +190,13 @@ template <typename T, int DIM, int PART>
 __global__ __launch_bounds__(256) void k_comoving(DGrid G, const T* __restrict__ Mt, const T* __restrict__ M0,
                                                   const double* __restrict__ u, const double* __restrict__ EM,
                                                   const double* __restrict__ Jin, double* __restrict__ Jout) {
-  const int64_t g = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-  if (g >= G.N) return;
+  const int64_t t = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  if (t >= G.N) return;
+  int gx, gy, gz;
+  const int64_t g = visit_order(G, (unsigned)t, gx, gy, gz);
   double a[3] = {0, 0, 0}, b[3] = {0, 0, 0};
-  if (PART != 2) apply_half<T, DIM>(G, M0, u, g, a);
-  if (PART != 1) apply_half<T, DIM>(G, Mt, EM, g, b);
+  if (PART != 2) apply_half<T, DIM>(G, M0, u, g, gx, gy, gz, a);
+  if (PART != 1) apply_half<T, DIM>(G, Mt, EM, g, gx, gy, gz, b);
   const double idV = 1.0 / G.dV;
   for (int q = 0; q < 3; ++q) {
     const double corr = PART == 0 ? a[q] + b[q] : (PART == 1 ? a[q] : b[q]);
@@ -382,11 +382,11 @@ __global__ __launch_bounds__(256) void k_apply_A(DGrid G, const double* __restri
                                                  const double* __restrict__ kE, CurlCurl K, double k2, double mcoef,
                                                  double tdt, double* __restrict__ y) {
   using HS = HalfStencil<DIM>;
-  const int64_t g = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-  if (g >= G.N) return;
+  const int64_t t = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  if (t >= G.N) return;
   const int64_t N = G.N;
   int gx, gy, gz;
-  unflat3(G, g, gx, gy, gz);
+  const int64_t g = visit_order(G, (unsigned)t, gx, gy, gz);
   double acc[3] = {x[g], x[N + g], x[2 * N + g]};
   const double x0[3] = {acc[0], acc[1], acc[2]};
   // curl-curl stencil
@@ -406,7 +406,7 @@ __global__ __launch_bounds__(256) void k_apply_A(DGrid G, const double* __restri
       }
   if (Mt) {
     double mx[3];
-    apply_half<T, DIM>(G, Mt, x, g, mx);
+    apply_half<T, DIM>(G, Mt, x, g, gx, gy, gz, mx);
 #pragma unroll
     for (int m = 0; m < 3; ++m) acc[m] += mcoef * mx[m];
   }

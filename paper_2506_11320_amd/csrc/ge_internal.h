@@ -22,6 +22,8 @@ struct DGrid {
   // q = (x * dm[a]) >> ds[a] for every 0 <= x < 2^31
   uint32_t dm[2];
   int ds[2];
+  // visiting order of the stencil kernels (visit_order); < 0: storage order
+  int colsh;
 };
 
 // Multiplier m = ceil(2^(31+s) / n), s = ceil(log2 n): for x < 2^31 the error
@@ -53,6 +55,32 @@ __device__ inline void unflat3(const DGrid& G, int64_t g, int& i, int& j, int& k
 }
 __device__ inline int64_t flat3(const DGrid& G, int i, int j, int k) {
   return (int64_t)(wrapi(i, G.n[0]) + G.n[0] * (wrapi(j, G.n[1]) + G.n[1] * wrapi(k, G.n[2])));
+}
+// Visiting order of the node- and cell-wise stencil kernels in 3D: rows of
+// n[0] points taken in columns of 2^colsh y-rows that march in z, so the row
+// one step down in z was visited 2^colsh rows earlier and its data is still in
+// the L2 (in storage order it lies a whole plane back).  t is the logical
+// thread index (< N); returns the point and its (i, j, k).
+constexpr int GE_COLSH = 4;
+__device__ inline int64_t visit_order(const DGrid& G, unsigned t, int& i, int& j, int& k) {
+  const unsigned nx = (unsigned)G.n[0], R = grid_div(G, t, 0);
+  i = (int)(t - R * nx);
+  if (G.colsh < 0) {
+    k = (int)grid_div(G, R, 1);
+    j = (int)(R - (unsigned)k * (unsigned)G.n[1]);
+  } else {
+    const unsigned cz = (unsigned)G.n[2] << G.colsh, c = R / cz, rem = R - c * cz;
+    k = (int)(rem >> G.colsh);
+    j = (int)((c << G.colsh) + (rem & ((1u << G.colsh) - 1u)));
+  }
+  return (int64_t)i + (int64_t)G.n[0] * ((int64_t)j + (int64_t)G.n[1] * k);
+}
+// colsh for a grid: the widest column up to 2^GE_COLSH rows that divides n[1]
+inline int visit_colsh(const DGrid& G) {
+  if (G.dim < 3) return -1;
+  int s = GE_COLSH;
+  while (s > 0 && G.n[1] % (1 << s) != 0) --s;
+  return s;
 }
 __device__ inline int64_t nbr3(const DGrid& G, int64_t g, int ox, int oy, int oz) {
   int i, j, k;
