@@ -110,18 +110,24 @@ __global__ __launch_bounds__(KB) void k_axpy_dot(double* __restrict__ w, const d
 }
 
 // The second pass's update fused with the squared norm of its result:
-// w[k] -= sum_{i<nv} h[i] V_i[k]; part[b] = block b's share of w . w.
+// w[k] -= sum_{i<NV} h[i] V_i[k]; part[b] = block b's share of w . w.  The
+// vector count is a template argument so that the NV loads of an element are
+// issued together.
+template <int NV>
 __global__ __launch_bounds__(KB) void k_axpy_norm(double* __restrict__ w, const double* __restrict__ V, int64_t ld,
-                                                  int nv, const double* __restrict__ h, int64_t n,
-                                                  double* __restrict__ part) {
-  __shared__ double hs[HSTRIDE];
+                                                  const double* __restrict__ h, int64_t n, double* __restrict__ part) {
+  __shared__ double hs[NV];
   __shared__ double sh[KB];
-  if (threadIdx.x < nv) hs[threadIdx.x] = h[threadIdx.x];
+  if (threadIdx.x < NV) hs[threadIdx.x] = h[threadIdx.x];
   __syncthreads();
   double a = 0;
   for (int64_t k = blockIdx.x * (int64_t)KB + threadIdx.x; k < n; k += (int64_t)gridDim.x * KB) {
+    double v[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) v[i] = V[i * ld + k];
     double s = 0;
-    for (int i = 0; i < nv; ++i) s += hs[i] * V[i * ld + k];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) s += hs[i] * v[i];
     const double wk = w[k] + (-1.0) * s;
     w[k] = wk;
     a += wk * wk;
@@ -188,7 +194,11 @@ static int cgs2_fused(ge_ctx* c, double* w, const double* V, int64_t ld, int nv,
     default: return ge_fail(c, GE_ERR_ARG, "fused Gram-Schmidt takes at most 16 vectors");
   }
   hipLaunchKernelGGL(k_reduce, dim3(nv), dim3(KB), 0, c->stream, part, h2);
-  hipLaunchKernelGGL(k_axpy_norm, dim3(KRED), dim3(KB), 0, c->stream, w, V, ld, nv, h2, n, part);
+  switch (nv) {
+#define AN(K) case K: hipLaunchKernelGGL(k_axpy_norm<K>, dim3(KRED), dim3(KB), 0, c->stream, w, V, ld, h2, n, part); break;
+    AN(1) AN(2) AN(3) AN(4) AN(5) AN(6) AN(7) AN(8) AN(9) AN(10) AN(11) AN(12) AN(13) AN(14) AN(15) AN(16)
+#undef AN
+  }
   hipLaunchKernelGGL(k_reduce, dim3(1), dim3(KB), 0, c->stream, part, nrm2);
   GE_HIP(c, hipGetLastError());
   return GE_OK;
