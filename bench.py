@@ -158,6 +158,8 @@ def main():
                     help="training pairs: (r0, e) of each solve, (A v_j, v_j) of its Arnoldi vectors, or both")
     ap.add_argument("--ns-j", type=int, default=0, help="current smoothing passes (Sec. 3.2); 0 = off")
     ap.add_argument("--dedner", action="store_true", help="divergence cleaning of B (Sec. 2.3)")
+    ap.add_argument("--explicit-current", type=int, default=0, metavar="K",
+                    help="also time K calls of the explicit-PIC current (Sec. 3.1) at the final particle state")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain device copy of 4 GiB (reference for the HBM byte counters) and exit")
     args = ap.parse_args()
@@ -243,6 +245,16 @@ def main():
     nn = None
     if not args.no_nn and wl.dim == 3:
         nn = nn_compare(sim, args)
+    expl = None
+    if args.explicit_current > 0:
+        sim.explicit_current()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(sim.stream)
+        for _ in range(args.explicit_current):
+            sim.explicit_current()
+        ev1.record(sim.stream)
+        ev1.synchronize()
+        expl = {"calls": args.explicit_current, "ms_per_call": round(ev0.elapsed_time(ev1) / args.explicit_current, 3)}
     out = {
         "metric": METRIC,
         "value": npart * args.steps / elapsed,
@@ -268,6 +280,7 @@ def main():
         "gmres_iterations": float(np.mean(iters)),
         "phase_ms": {k: round(v, 3) for k, v in phase.items()},
         "precond_compare": precond_cmp,
+        "explicit_current": expl,
         "roofline": roof,
     }
     sim.close()

@@ -487,6 +487,30 @@ def deposit(G: Grid, species: List[Species], dt: float, Bc, comoving: bool, n_sm
     return out
 
 
+def explicit_current(G: Grid, species: List[Species], comoving: bool, n_smooth_u: int = 5, phi_u: float = 0.5,
+                     n_smooth_j: int = 0) -> np.ndarray:
+    """Current of an explicit PIC step (Sec. 3.1, explicit form): with the
+    comoving frame, (1/dV) sum_{s,p} q w (v - u(x_p)) W(x_p - x_g), u the
+    mass-weighted bulk velocity after n_smooth_u filter passes (strides 1, 2,
+    ...) interpolated to x_p with the weights W; else the lab current
+    (1/dV) sum q w v W.  Then n_smooth_j passes (Sec. 3.2).  The particle
+    velocity enters unrotated, i.e. the deposit of this module with beta = 0,
+    whose comoving branch deposits v - u(x_p) particle by particle."""
+    N = nnodes(G)
+    Bn = np.zeros((3, N))
+    tot = {"J": np.zeros((3, N)), "M": np.zeros((27, 9, N)), "rho": np.zeros(N),
+           "mm": np.zeros((3, N)), "mass": np.zeros(N)}
+    for sp in species:
+        deposit_species(G, sp.q, sp.m, 0.0, sp.x, sp.v, sp.w, Bn, acc=tot)
+    J = tot["J"]
+    if comoving:
+        u = smooth(G, bulk_velocity(G, tot["mm"], tot["mass"]), n_smooth_u, phi_u)
+        J = np.zeros((3, N))
+        for sp in species:
+            J += deposit_species(G, sp.q, sp.m, 0.0, sp.x, sp.v, sp.w, Bn, u_node=u)["J"]
+    return smooth_current(G, J, n_smooth_j, phi_u) if n_smooth_j > 0 else J
+
+
 def diffusion_speed(G: Grid, u, a_mode: int, c: float = 1.0) -> np.ndarray:
     """a at nodes (Sec. 2.2): c (a_mode 0) or the bulk speed |u| (a_mode 1)."""
     N = nnodes(G)

@@ -255,6 +255,22 @@ int ge_deposit(ge_ctx* c) {
   return GE_OK;
 }
 
+int ge_explicit_current(ge_ctx* c, double* J) {
+  if (!c) return GE_ERR_ARG;
+  if (c->nsp == 0) return ge_fail(c, GE_ERR_STATE, "no species");
+  int rc;
+  if ((rc = ge_launch_node_avg(c))) return rc;
+  c->unrotated = 1;
+  rc = ge_launch_deposit(c);
+  c->unrotated = 0;
+  if (rc) return rc;
+  c->have_deposit = 0;
+  c->have_solve = 0;
+  if ((rc = ge_launch_grid_pass(c))) return rc;
+  if (J) GE_HIP(c, hipMemcpyAsync(J, c->Jeff, sizeof(double) * 3 * c->G.N, hipMemcpyDeviceToDevice, c->stream));
+  return GE_OK;
+}
+
 int ge_solve_fields(ge_ctx* c, double tol, int maxit, int restart, int precond, ge_solve_report* rep) {
   if (!c) return GE_ERR_ARG;
   if (!c->have_deposit) return ge_fail(c, GE_ERR_STATE, "ge_solve_fields before ge_deposit");
