@@ -260,9 +260,15 @@ int ge_explicit_current(ge_ctx* c, double* J) {
   if (c->nsp == 0) return ge_fail(c, GE_ERR_STATE, "no species");
   int rc;
   if ((rc = ge_launch_node_avg(c))) return rc;
-  c->unrotated = 1;
+  // the deposit with beta_s = 0 (alpha = I); the launch copies beta into the
+  // kernel arguments, so the species' own values are restored right after
+  double beta[GE_MAX_SPECIES];
+  for (int s = 0; s < c->nsp; ++s) {
+    beta[s] = c->sp[s].beta;
+    c->sp[s].beta = 0.0;
+  }
   rc = ge_launch_deposit(c);
-  c->unrotated = 0;
+  for (int s = 0; s < c->nsp; ++s) c->sp[s].beta = beta[s];
   if (rc) return rc;
   c->have_deposit = 0;
   c->have_solve = 0;

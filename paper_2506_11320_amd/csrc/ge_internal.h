@@ -167,7 +167,6 @@ struct ge_ctx {
   int64_t nred_blocks;
   int* flags;            // [0] CFL clamp, [1] run overflow, [2] load error
   int have_deposit, have_solve;
-  int unrotated;       // deposit with beta_s = 0 (alpha = I), for ge_explicit_current
   void* cnn;           // learned preconditioner state (ge_cnn.hip), lazily created
   double* Zb;          // flexible-GMRES basis of preconditioned vectors (lazily allocated)
   hipEvent_t ev[10];   // pairs: push, deposit, assemble, grid rest, update

@@ -1050,7 +1050,7 @@ static void launch_deposit_t(ge_ctx* c) {
     SpeciesBuf& S = c->sp[s];
     A.sp[s].rec = (const T*)S.rec[S.cur];
     A.sp[s].runs = S.runs[S.cur];
-    A.sp[s].q = (T)S.q; A.sp[s].m = (T)S.m; A.sp[s].beta = c->unrotated ? (T)0 : (T)S.beta; A.sp[s].n = S.n;
+    A.sp[s].q = (T)S.q; A.sp[s].m = (T)S.m; A.sp[s].beta = (T)S.beta; A.sp[s].n = S.n;
   }
   A.NF = (const T*)c->node8;
   A.cellQ = (T*)c->cellQ;
