@@ -245,7 +245,8 @@ int ge_half_stencil(const ge_ctx* ctx);
 
 /* Particles of species s in sorted order (by cell, stable), into device
  * arrays: cell[n] int32, off[3][n], v[3][n], w[n] (double for GE_FP64,
- * float for GE_FP32).  n must equal the species' count. */
+ * float for GE_FP32).  n must equal the species' count; for an empty species
+ * (n = 0) it returns GE_OK at once and the pointers may be null. */
 int ge_get_particles(ge_ctx* ctx, int s, int64_t n, int32_t* cell, void* off, void* v, void* w);
 
 /* y = A x for the current operator (device double [3][N]); the matvec of the

@@ -409,6 +409,7 @@ int ge_set(ge_ctx* c, int what, const double* src) {
 int ge_get_particles(ge_ctx* c, int s, int64_t n, int32_t* cell, void* off, void* v, void* w) {
   if (!c || s < 0 || s >= c->nsp) return GE_ERR_ARG;
   if (n != c->sp[s].n) return ge_fail(c, GE_ERR_ARG, "particle count mismatch");
+  if (n == 0) return GE_OK;  // an empty species: nothing to copy, the pointers may be null
   if (!cell || !off || !v || !w) return ge_fail(c, GE_ERR_ARG, "null output");
   return ge_launch_get_particles(c, s, cell, off, v, w);
 }
