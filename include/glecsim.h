@@ -269,7 +269,7 @@ int ge_timings(ge_ctx* ctx, double* out8);
 /* Not from the paper: a 3-layer 3x3x3 convolutional network z = N(r)
  * (3 -> 32 -> 32 -> 3 channels, ReLU after the first two, no bias), BF16 MFMA
  * with FP32 accumulation, trained on (residual, correction) pairs of the solves
- * and used as a flexible right preconditioner; plain GMRES stays the judge:
+ * and used as a flexible right preconditioner; the GMRES residual decides:
  * the solve must still reach ||b - A x|| <= tol ||b||. */
 typedef struct {
   int crop;       /* output crop edge in nodes (input crop = crop + 6) */

@@ -7,7 +7,7 @@ never imports it and it shares no code with the GPU library.
 The network is not part of the paper's method: the paper solves the implicit
 field system (Sec. 2.1, with the mass-matrix term of Sec. 3.1) by a Krylov
 method and says nothing of how.  Here a learned right preconditioner is tried
-inside flexible GMRES; GMRES stays the judge of convergence, so the network
+inside flexible GMRES; the GMRES residual decides convergence, so the network
 can only change the iteration count, never the converged field.
 
 Definition (readings stated once here and used everywhere):
