@@ -140,6 +140,11 @@ int ge_create(const ge_grid* grid, const ge_params* params, void* hip_stream, ge
   if (!rc) rc = dalloc(c, &c->scan_blocks, sizeof(int32_t) * (c->scan_nblocks + 1));
   if (!rc) rc = dalloc(c, &c->V, sizeof(double) * 3 * N * (c->kr_m + 1));
   if (!rc) rc = dalloc(c, &c->hdev, sizeof(double) * 256);
+  if (!rc && hipHostMalloc((void**)&c->hhost, sizeof(double) * 256, hipHostMallocDefault) != hipSuccess) {
+    c->hhost = nullptr;
+    (void)hipGetLastError();
+    rc = ge_fail(c, GE_ERR_OOM, "pinned host buffer allocation failed");
+  }
   if (!rc) rc = dalloc(c, &c->partials, sizeof(double) * 16 * 512);  // 16 dots x 512 blocks
   if (!rc) rc = dalloc(c, &c->flags, sizeof(int) * 4);
   if (rc) {
@@ -172,6 +177,7 @@ void ge_destroy(ge_ctx* c) {
                   &c->EM, &c->anode, &c->psi, &c->kE, &c->kB, &c->rhs, &c->Bnew, &c->ccell, &c->jac, &c->V, &c->Zp,
                   &c->kw, &c->kr, &c->kx, &c->hdev, &c->partials, &c->scal};
   for (auto p : f) dfree(*p);
+  if (c->hhost) (void)hipHostFree(c->hhost);
   dfree(c->node8);
   dfree(c->Mt);
   dfree(c->M0);

@@ -164,6 +164,7 @@ struct ge_ctx {
   int n_cu;     // compute units of the device (persistent launches)
   int kr_last;  // Arnoldi vectors built in the last GMRES cycle
   double *V, *Zp, *kw, *kr, *kx, *hdev, *partials, *scal;
+  double* hhost;  // pinned host copy of hdev (per-iteration read-backs of the solve)
   int64_t nred_blocks;
   int* flags;            // [0] CFL clamp, [1] run overflow, [2] load error
   int have_deposit, have_solve;

@@ -244,7 +244,8 @@ int ge_gmres(ge_ctx* c, double tol, int maxit, int m, int precond, ge_solve_repo
   double bnorm = std::sqrt(bn2);
   if (!(bnorm >= 0) || std::isinf(bnorm)) return ge_fail(c, GE_ERR_NONFINITE, "non-finite right-hand side");
   const double bref = bnorm > 0 ? bnorm : 1.0;
-  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), s(m + 1), y(m), hh(2 * HSTRIDE + 1);
+  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), s(m + 1), y(m);
+  double* hh = c->hhost;  // pinned: the per-iteration read-back is a direct copy
   int it = 0, restarts = 0, conv = 0;
   double rel = 0;
   while (true) {
@@ -298,7 +299,7 @@ int ge_gmres(ge_ctx* c, double tol, int maxit, int m, int precond, ge_solve_repo
       }
       hipLaunchKernelGGL(k_normalize, vgrid(n), dim3(KB), 0, c->stream, vn, w, hd + 128, n);
       GE_HIP(c, hipGetLastError());
-      GE_HIP(c, hipMemcpyAsync(hh.data(), hd, sizeof(double) * (2 * HSTRIDE + 1), hipMemcpyDeviceToHost, c->stream));
+      GE_HIP(c, hipMemcpyAsync(hh, hd, sizeof(double) * (2 * HSTRIDE + 1), hipMemcpyDeviceToHost, c->stream));
       GE_HIP(c, hipStreamSynchronize(c->stream));
       ++it;
       for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hh[i];
