@@ -237,15 +237,15 @@ int ge_gmres(ge_ctx* c, double tol, int maxit, int m, int precond, ge_solve_repo
   double* hd = c->hdev;  // [0,64): h1, [64,128): h2, [128]: |w|^2, [192,256): y
   if (precond == GE_PC_JACOBI && (rc = ge_launch_jacobi_setup(c))) return rc;
   // ||b||
+  double* hh = c->hhost;  // pinned mirror of hd: read-backs and the y upload are direct copies
   if ((rc = multidot(c, c->rhs, n, 1, c->rhs, n, hd + 128))) return rc;
-  double bn2;
-  GE_HIP(c, hipMemcpyAsync(&bn2, hd + 128, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  GE_HIP(c, hipMemcpyAsync(hh + 128, hd + 128, sizeof(double), hipMemcpyDeviceToHost, c->stream));
   GE_HIP(c, hipStreamSynchronize(c->stream));
-  double bnorm = std::sqrt(bn2);
+  double bnorm = std::sqrt(hh[128]);
   if (!(bnorm >= 0) || std::isinf(bnorm)) return ge_fail(c, GE_ERR_NONFINITE, "non-finite right-hand side");
   const double bref = bnorm > 0 ? bnorm : 1.0;
-  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), s(m + 1), y(m);
-  double* hh = c->hhost;  // pinned: the per-iteration read-back is a direct copy
+  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), s(m + 1);
+  double* y = hh + 192;  // host side of hd[192, 192 + m), m <= 64
   int it = 0, restarts = 0, conv = 0;
   double rel = 0;
   while (true) {
@@ -253,10 +253,9 @@ int ge_gmres(ge_ctx* c, double tol, int maxit, int m, int precond, ge_solve_repo
     if ((rc = ge_launch_apply_A(c, x, V))) return rc;
     hipLaunchKernelGGL(k_residual, vgrid(n), dim3(KB), 0, c->stream, V, c->rhs, n);
     if ((rc = multidot(c, V, n, 1, V, n, hd + 128))) return rc;
-    double b2;
-    GE_HIP(c, hipMemcpyAsync(&b2, hd + 128, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    GE_HIP(c, hipMemcpyAsync(hh + 128, hd + 128, sizeof(double), hipMemcpyDeviceToHost, c->stream));
     GE_HIP(c, hipStreamSynchronize(c->stream));
-    const double beta = std::sqrt(b2);
+    const double beta = std::sqrt(hh[128]);
     if (!std::isfinite(beta)) return ge_fail(c, GE_ERR_NONFINITE, "non-finite residual in GMRES");
     const double rel_prev = rel;
     rel = beta / bref;
@@ -351,7 +350,7 @@ int ge_gmres(ge_ctx* c, double tol, int maxit, int m, int precond, ge_solve_repo
       fallback = 1;
       continue;
     }
-    GE_HIP(c, hipMemcpyAsync(hd + 192, y.data(), sizeof(double) * k, hipMemcpyHostToDevice, c->stream));
+    GE_HIP(c, hipMemcpyAsync(hd + 192, y, sizeof(double) * k, hipMemcpyHostToDevice, c->stream));
     if (precond == GE_PC_NONE) {
       hipLaunchKernelGGL(k_multiaxpy, vgrid(n), dim3(KB), 0, c->stream, x, V, n, k, hd + 192, 1.0, n);
     } else if (precond == GE_PC_CNN) {
