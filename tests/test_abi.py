@@ -38,3 +38,32 @@ def test_binding_refuses_without_gpu(monkeypatch):
         pytest.skip("GPU present")
     with pytest.raises(RuntimeError):
         Simulation(1, (8, 1, 1), (0.5, 1, 1), theta=0.5, dt=0.5)
+
+
+def test_host_validation_refuses_before_any_device_call():
+    """ge_create checks its arguments on the host first: refused grids never
+    reach the device (so this runs without a GPU).  FP64 3D grids above
+    GE_FP64_3D_MAX_CELLS are refused."""
+    from paper_2506_11320_amd.glecsim import GEGrid, GEParams, load_library
+    L = load_library()
+    hdr = open(os.path.join(ROOT, "include", "glecsim.h")).read()
+    limit = int(re.search(r"#define GE_FP64_3D_MAX_CELLS (\d+)", hdr).group(1))
+    err_arg = int(re.search(r"GE_ERR_ARG\s*=\s*(-?\d+)", hdr).group(1))
+    fp64 = int(re.search(r"GE_FP64\s*=\s*(\d+)", hdr).group(1))
+
+    def create(dim, n, precision):
+        g = GEGrid()
+        g.dim = dim
+        for d in range(3):
+            g.n[d] = n[d]
+            g.dx[d] = 0.5
+        p = GEParams(0.5, 1.0, 0.5, 1, 1, 1.0, 1, 1.0, 1, 5, 0.5, precision, 0, 0, 0.8, 0.1, 0)
+        h = ctypes.c_void_p()
+        rc = L.ge_create(ctypes.byref(g), ctypes.byref(p), None, ctypes.byref(h))
+        return rc, h.value
+
+    assert create(4, (8, 8, 8), fp64) == (err_arg, None)
+    side = 2
+    while side ** 3 <= limit:
+        side += 1
+    assert create(3, (side, side, side), fp64) == (err_arg, None)
