@@ -196,13 +196,12 @@ int ge_step(ge_ctx* ctx, double tol, int maxit, int restart, int precond, ge_sol
  * J_g = (1/dV) sum_{s,p} q_s w_p (v_p - u(x_p)) W(x_p - x_g), with u the bulk
  * velocity after n_smooth_u filter passes, interpolated to the particle with
  * the same weights W; comoving frame off: the lab current
- * (1/dV) sum q w v W.  Then ns_j filter passes (Sec. 3.2).  Computed by the
- * deposit with the rotation alpha replaced by the identity (beta_s = 0):
- * J_lab - (1/dV) M0 u is then exactly the sum above, and Mtilde, hence the
- * E_M term, vanishes.  The mass matrices of that deposit are not those of the
- * implicit step, so ge_solve_fields needs a new ge_deposit afterwards
- * (GE_ERR_STATE otherwise).  J: device [3][N] FP64, may be NULL (the result
- * stays readable as GE_F_J_EFF).  Asynchronous. */
+ * (1/dV) sum q w v W.  Then ns_j filter passes (Sec. 3.2).  Two passes over
+ * the particles, no mass matrices: the moments (-> u, also left in GE_F_MASS,
+ * GE_F_MM and GE_F_U), then the current.  The moments and current of the
+ * implicit step are overwritten, so ge_solve_fields needs a new ge_deposit
+ * afterwards (GE_ERR_STATE otherwise).  J: device [3][N] FP64, may be NULL
+ * (the result stays readable as GE_F_J_EFF).  Asynchronous. */
 int ge_explicit_current(ge_ctx* ctx, double* J);
 
 /* Wait for the stream; returns GE_ERR_CFL if a push clamped a particle since

@@ -270,20 +270,13 @@ int ge_explicit_current(ge_ctx* c, double* J) {
   if (!c) return GE_ERR_ARG;
   if (c->nsp == 0) return ge_fail(c, GE_ERR_STATE, "no species");
   int rc;
-  if ((rc = ge_launch_node_avg(c))) return rc;
-  // the deposit with beta_s = 0 (alpha = I); the launch copies beta into the
-  // kernel arguments, so the species' own values are restored right after
-  double beta[GE_MAX_SPECIES];
-  for (int s = 0; s < c->nsp; ++s) {
-    beta[s] = c->sp[s].beta;
-    c->sp[s].beta = 0.0;
-  }
-  rc = ge_launch_deposit(c);
-  for (int s = 0; s < c->nsp; ++s) c->sp[s].beta = beta[s];
-  if (rc) return rc;
+  // moments -> smoothed bulk velocity -> current, then the ns_j passes
+  if ((rc = ge_launch_explicit_linear(c, 0))) return rc;
+  if ((rc = ge_launch_bulk_velocity(c))) return rc;
+  if ((rc = ge_launch_explicit_linear(c, c->P.comoving ? 1 : 2))) return rc;
+  if ((rc = ge_launch_smooth_current(c))) return rc;
   c->have_deposit = 0;
   c->have_solve = 0;
-  if ((rc = ge_launch_grid_pass(c))) return rc;
   if (J) GE_HIP(c, hipMemcpyAsync(J, c->Jeff, sizeof(double) * 3 * c->G.N, hipMemcpyDeviceToDevice, c->stream));
   return GE_OK;
 }

@@ -611,6 +611,28 @@ static void comoving_t(ge_ctx* c) {
     default: FN<float, 3>(c); break;                                \
   }
 
+// Bulk velocity u = mm / mass, then the filter passes: strides 1, 2, 1, 2, ...;
+// each pass sweeps x, then y, then z.
+int ge_launch_bulk_velocity(ge_ctx* c) {
+  const DGrid& G = c->G;
+  const int64_t N = G.N;
+  hipLaunchKernelGGL(k_bulk_u, grid1(N), dim3(256), 0, c->stream, N, c->mm, c->mass, c->u);
+  for (int k = 0; k < c->P.n_smooth_u; ++k)
+    for (int ax = 0; ax < G.dim; ++ax) {
+      hipLaunchKernelGGL(k_filter, grid1(N), dim3(256), 0, c->stream, G, c->u, c->utmp, ax, (k % 2 == 0) ? 1 : 2,
+                         c->P.phi_u);
+      std::swap(c->u, c->utmp);
+    }
+  GE_HIP(c, hipGetLastError());
+  return GE_OK;
+}
+
+int ge_launch_smooth_current(ge_ctx* c) {
+  smooth_current(c);
+  GE_HIP(c, hipGetLastError());
+  return GE_OK;
+}
+
 // Everything between the particle deposit and the linear solve.
 int ge_launch_grid_pass(ge_ctx* c) {
   const DGrid& G = c->G;
@@ -620,14 +642,7 @@ int ge_launch_grid_pass(ge_ctx* c) {
   GE_HIP(c, hipGetLastError());
   (void)hipEventRecord(c->ev[5], c->stream);
   (void)hipEventRecord(c->ev[6], c->stream);
-  hipLaunchKernelGGL(k_bulk_u, grid1(N), dim3(256), 0, c->stream, N, c->mm, c->mass, c->u);
-  // filter passes: strides 1, 2, 1, 2, ...; each pass sweeps x, then y, then z
-  for (int k = 0; k < c->P.n_smooth_u; ++k)
-    for (int ax = 0; ax < G.dim; ++ax) {
-      hipLaunchKernelGGL(k_filter, grid1(N), dim3(256), 0, c->stream, G, c->u, c->utmp, ax, (k % 2 == 0) ? 1 : 2,
-                         c->P.phi_u);
-      std::swap(c->u, c->utmp);
-    }
+  ge_launch_bulk_velocity(c);
   hipLaunchKernelGGL(k_motional, grid1(N), dim3(256), 0, c->stream, N, c->u, c->Bn, c->EM, c->anode, c->P.a_mode,
                      c->P.a_const);
   if (c->P.comoving) {
