@@ -29,6 +29,12 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "particle-steps/s (push+deposit); GMRES s/step plain vs NN-precond at 1e-8"
 
 
+# what each synthetic workload stands for
+KIND = {"c1": "1D3V shock tube", "c2": "2D3V uniform fast flow", "c3": "2D3V Harris-sheet reconnection",
+        "c4": "3D3V colliding-flow shock", "c5": "3D3V double-Harris reconnection with a 0.2c guide flow",
+        "ff1d": "1D3V uniform fast flow (solar wind)"}
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -268,9 +274,12 @@ def main():
         "vs_baseline": None,
         "dtype": "f32+f64" if wl.fp32 else "f64",
         "data": "synthetic",
-        "config": {"workload": f"{wl.name}: 3D3V double-Harris reconnection, {wl.n[0]}x{wl.n[1]}x{wl.n[2]} cells, "
-                               f"{wl.ppc} ppc/species, m_i/m_e={wl.m[1]:g}, guide flow {wl.u0[0]}c, "
-                               f"FP32 push/deposit, FP64 GMRES to {args.tol:g}, comoving current, limited LF",
+        "config": {"workload": f"{wl.name}: {KIND.get(args.workload, wl.name)}, "
+                               f"{'x'.join(str(v) for v in wl.n[:wl.dim])} cells, "
+                               f"{wl.ppc} ppc/species, m_i/m_e={wl.m[1]:g}, "
+                               f"{'FP32' if wl.fp32 else 'FP64'} push/deposit, FP64 GMRES to {args.tol:g}, "
+                               f"{'comoving' if wl.comoving else 'lab-frame'} current, "
+                               f"{'limited LF' if wl.lf_E or wl.lf_B else 'no LF'}",
                    "cells": wl.ncells, "particles": npart, "precond": args.precond, "ns_j": args.ns_j,
                    "dedner": bool(args.dedner)},
         "push_deposit_particle_steps_per_s": npart / pd_s,
