@@ -204,6 +204,21 @@ int ge_step(ge_ctx* ctx, double tol, int maxit, int restart, int precond, ge_sol
  * (the result stays readable as GE_F_J_EFF).  Asynchronous. */
 int ge_explicit_current(ge_ctx* ctx, double* J);
 
+/* One explicit PIC step that uses that current (the paper states the current
+ * for explicit codes but no explicit integrator; this is the leapfrog it
+ * writes for the 1D Yee scheme, Sec. 2.1, on this node/cell mesh).  The
+ * particle state is read as (x^n, v^{n-1/2}), the fields as E^n, B^n:
+ *   v^{n+1/2}: Boris push with E^n and the node-averaged B^n at x^n (the
+ *   mover of ge_push with E^n in place of E^{n+theta}); x^{n+1} = x^n +
+ *   dt v^{n+1/2}; re-binning;
+ *   J from ge_explicit_current at (x^{n+1}, v^{n+1/2});
+ *   B^{n+1/2} = B^n - (c dt/2) curl_NC E^n, E^{n+1} = E^n + c dt curl_CN
+ *   B^{n+1/2} - 4 pi dt J, B^{n+1} = B^{n+1/2} - (c dt/2) curl_NC E^{n+1}.
+ * theta, the LF terms and the cleaning are not used.  Stable for
+ * c dt < min dx / sqrt(dim).  Synchronises; returns GE_ERR_CFL like
+ * ge_sync if a particle moved a cell or more. */
+int ge_explicit_step(ge_ctx* ctx);
+
 /* Wait for the stream; returns GE_ERR_CFL if a push clamped a particle since
  * the last check, else GE_OK. */
 int ge_sync(ge_ctx* ctx);

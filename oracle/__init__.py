@@ -511,6 +511,32 @@ def explicit_current(G: Grid, species: List[Species], comoving: bool, n_smooth_u
     return smooth_current(G, J, n_smooth_j, phi_u) if n_smooth_j > 0 else J
 
 
+def explicit_step(G: Grid, species: List[Species], E, Bc, *, dt: float, c: float = 1.0, comoving: bool = True,
+                  n_smooth_u: int = 5, phi_u: float = 0.5, n_smooth_j: int = 0) -> Dict[str, object]:
+    """One explicit PIC step with the current of Sec. 3.1's explicit form (the
+    paper gives no explicit integrator; this is the leapfrog it writes for the
+    1D Yee scheme in Sec. 2.1, on the node/cell mesh with the multi-D curls of
+    the implicit path).  State: x^n, v^{n-1/2}, E^n at nodes, B^n at cells.
+      1. v^{n+1/2} from v^{n-1/2} with E^n and the node-averaged B^n at x^n
+         (push_species: its implicit-midpoint rotation is the Boris push),
+         x^{n+1} = x^n + dt v^{n+1/2};
+      2. J = explicit_current at (x^{n+1}, v^{n+1/2});
+      3. B^{n+1/2} = B^n - (c dt/2) curl_NC E^n,
+         E^{n+1} = E^n + c dt curl_CN B^{n+1/2} - 4 pi dt J,
+         B^{n+1} = B^{n+1/2} - (c dt/2) curl_NC E^{n+1}."""
+    Bn = node_avg(G, Bc)
+    moved = []
+    for sp in species:
+        xn, vn = push_species(G, beta_s(sp.q, sp.m, dt), dt, sp.x, sp.v, E, Bn)
+        moved.append(Species(sp.q, sp.m, xn, vn, sp.w))
+    J = explicit_current(G, moved, comoving, n_smooth_u, phi_u, n_smooth_j)
+    half = params(1.0, 0.5 * dt, c)
+    Bh = update_B(G, half, Bc, E)
+    En = rhs(G, params(1.0, dt, c), E, Bh, J)
+    Bnew = update_B(G, half, Bh, En)
+    return {"species": moved, "E": En, "B": Bnew, "J": J}
+
+
 def diffusion_speed(G: Grid, u, a_mode: int, c: float = 1.0) -> np.ndarray:
     """a at nodes (Sec. 2.2): c (a_mode 0) or the bulk speed |u| (a_mode 1)."""
     N = nnodes(G)

@@ -281,6 +281,29 @@ int ge_explicit_current(ge_ctx* c, double* J) {
   return GE_OK;
 }
 
+int ge_explicit_step(ge_ctx* c) {
+  if (!c) return GE_ERR_ARG;
+  if (c->nsp == 0) return ge_fail(c, GE_ERR_STATE, "no species");
+  int rc;
+  // corner fields of the push: E^n (through c->Eth) and the node average of B^n
+  GE_HIP(c, hipMemcpyAsync(c->Eth, c->E, sizeof(double) * 3 * c->G.N, hipMemcpyDeviceToDevice, c->stream));
+  if ((rc = ge_launch_node_avg(c))) return rc;
+  if ((rc = ge_launch_pack_node8(c, 0))) return rc;
+  for (int s = 0; s < c->nsp; ++s)
+    if ((rc = ge_launch_scan_counts(c, s))) return rc;
+  for (int s = 0; s < c->nsp; ++s)
+    if ((rc = ge_launch_push(c, s))) return rc;
+  // the current at (x^{n+1}, v^{n+1/2}), then the leapfrog
+  if ((rc = ge_launch_explicit_linear(c, 0))) return rc;
+  if ((rc = ge_launch_bulk_velocity(c))) return rc;
+  if ((rc = ge_launch_explicit_linear(c, c->P.comoving ? 1 : 2))) return rc;
+  if ((rc = ge_launch_smooth_current(c))) return rc;
+  if ((rc = ge_launch_explicit_fields(c))) return rc;
+  c->have_deposit = 0;
+  c->have_solve = 0;
+  return check_flags(c);
+}
+
 int ge_solve_fields(ge_ctx* c, double tol, int maxit, int restart, int precond, ge_solve_report* rep) {
   if (!c) return GE_ERR_ARG;
   if (!c->have_deposit) return ge_fail(c, GE_ERR_STATE, "ge_solve_fields before ge_deposit");

@@ -627,6 +627,26 @@ int ge_launch_bulk_velocity(ge_ctx* c) {
   return GE_OK;
 }
 
+// Leapfrog of the explicit step: B^{n+1/2} = B^n - (c dt/2) curl_NC E^n,
+// E^{n+1} = E^n + c dt curl_CN B^{n+1/2} - 4 pi dt J (J in c->Jeff),
+// B^{n+1} = B^{n+1/2} - (c dt/2) curl_NC E^{n+1}.  c->Eth and c->Bnew are
+// scratch here.
+int ge_launch_explicit_fields(ge_ctx* c) {
+  const int64_t N = c->G.N;
+  const double cdt = c->P.c * c->P.dt;
+  DISPATCH_DIM(c, k_curl_nc, grid1(N), dim3(256), 0, c->stream, c->G, c->E, c->ccell);
+  DISPATCH_DIM(c, k_update_B, grid1(N), dim3(256), 0, c->stream, c->G, c->B, c->ccell, nullptr, nullptr, 0.5 * cdt,
+               c->P.dt, c->Bnew);
+  DISPATCH_DIM(c, k_rhs, grid1(N), dim3(256), 0, c->stream, c->G, c->E, c->Bnew, c->Jeff, cdt,
+               4.0 * M_PI * c->P.dt, c->Eth);
+  std::swap(c->E, c->Eth);
+  DISPATCH_DIM(c, k_curl_nc, grid1(N), dim3(256), 0, c->stream, c->G, c->E, c->ccell);
+  DISPATCH_DIM(c, k_update_B, grid1(N), dim3(256), 0, c->stream, c->G, c->Bnew, c->ccell, nullptr, nullptr, 0.5 * cdt,
+               c->P.dt, c->B);
+  GE_HIP(c, hipGetLastError());
+  return GE_OK;
+}
+
 int ge_launch_smooth_current(ge_ctx* c) {
   smooth_current(c);
   GE_HIP(c, hipGetLastError());

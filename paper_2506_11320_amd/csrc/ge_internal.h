@@ -195,6 +195,7 @@ int ge_launch_grid_pass(ge_ctx* c);          // assemble .. rhs
 int ge_launch_bulk_velocity(ge_ctx* c);      // u from mm / mass, then the n_smooth_u filter passes
 int ge_launch_smooth_current(ge_ctx* c);     // ns_j filter passes on c->Jeff
 int ge_launch_explicit_linear(ge_ctx* c, int mode);  // explicit-PIC passes (ge_explicit.hip)
+int ge_launch_explicit_fields(ge_ctx* c);    // leapfrog E and B update with c->Jeff
 int ge_launch_node_avg(ge_ctx* c);
 int ge_launch_apply_A(ge_ctx* c, const double* x, double* y);
 int ge_launch_update(ge_ctx* c);

@@ -29,7 +29,7 @@ FIELDS = {
 EXPORTS = [
     "ge_create", "ge_destroy", "ge_last_error", "ge_add_species", "ge_set_fields", "ge_deposit", "ge_solve_fields",
     "ge_push", "ge_update_fields", "ge_step", "ge_sync", "ge_gather", "ge_set", "ge_half_stencil",
-    "ge_get_particles", "ge_apply_operator", "ge_diagnostics", "ge_timings", "ge_explicit_current",
+    "ge_get_particles", "ge_apply_operator", "ge_diagnostics", "ge_timings", "ge_explicit_current", "ge_explicit_step",
     "ge_cnn_init", "ge_cnn_size", "ge_cnn_weights", "ge_cnn_apply", "ge_cnn_harvest", "ge_cnn_add_pair",
     "ge_cnn_npairs", "ge_cnn_train", "ge_cnn_loss_grad",
 ]
@@ -109,6 +109,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.ge_get_particles.argtypes = [vp, ctypes.c_int, i64, vp, vp, vp, vp]
     L.ge_apply_operator.argtypes = [vp, vp, vp]
     L.ge_explicit_current.argtypes = [vp, vp]
+    L.ge_explicit_step.argtypes = [vp]
     L.ge_diagnostics.argtypes = [vp, ctypes.POINTER(GEDiag)]
     L.ge_timings.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
     L.ge_cnn_init.argtypes = [vp, ctypes.c_uint32, ctypes.c_int]
@@ -212,6 +213,10 @@ class Simulation:
 
     def push(self):
         self._check(self.L.ge_push(self.h))
+
+    def explicit_step(self):
+        """One explicit PIC step with the explicit-form current (see glecsim.h)."""
+        self._check(self.L.ge_explicit_step(self.h))
 
     def explicit_current(self) -> torch.Tensor:
         """Explicit-PIC current at the present particle state (see glecsim.h)."""
