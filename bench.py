@@ -166,6 +166,9 @@ def main():
     ap.add_argument("--dedner", action="store_true", help="divergence cleaning of B (Sec. 2.3)")
     ap.add_argument("--explicit-current", type=int, default=0, metavar="K",
                     help="also time K calls of the explicit-PIC current (Sec. 3.1) at the final particle state")
+    ap.add_argument("--explicit-steps", type=int, default=0, metavar="K",
+                    help="also time K explicit PIC steps (ge_explicit_step) on the same workload with dt = 0.25, "
+                         "which keeps c dt below dx / sqrt(3)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain device copy of 4 GiB (reference for the HBM byte counters) and exit")
     args = ap.parse_args()
@@ -261,6 +264,31 @@ def main():
         ev1.record(sim.stream)
         ev1.synchronize()
         expl = {"calls": args.explicit_current, "ms_per_call": round(ev0.elapsed_time(ev1) / args.explicit_current, 3)}
+    expl_step = None
+    if args.explicit_steps > 0:
+        sim.close()
+        sim = Simulation(wl.dim, wl.n, wl.dx, theta=wl.theta, dt=0.25, lf_E=False, lf_B=False, beta_lim=wl.beta_lim,
+                         a_mode=wl.a_mode, comoving=wl.comoving, n_smooth_u=wl.n_smooth_u, fp32=wl.fp32,
+                         ns_j=args.ns_j)
+        for s in range(wl.nsp):
+            p = synth.particles(wl, s, f32=wl.fp32)
+            t = {k: torch.from_numpy(v).cuda() for k, v in p.items()}
+            del p
+            sim.add_species(wl.q[s], wl.m[s], t["cell"], t["off"], t["v"], t["w"])
+            del t
+            torch.cuda.synchronize()
+        sim.set_fields(torch.from_numpy(E).cuda(), torch.from_numpy(B).cuda())
+        sim.explicit_step()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(sim.stream)
+        for _ in range(args.explicit_steps):
+            sim.explicit_step()
+        ev1.record(sim.stream)
+        ev1.synchronize()
+        ms = ev0.elapsed_time(ev1) / args.explicit_steps
+        expl_step = {"steps": args.explicit_steps, "dt": 0.25, "ms_per_step": round(ms, 3),
+                     "particle_steps_per_s": npart / (ms * 1e-3)}
+        log(f"explicit step: {ms:.3f} ms")
     out = {
         "metric": METRIC,
         "value": npart * args.steps / elapsed,
@@ -290,6 +318,7 @@ def main():
         "phase_ms": {k: round(v, 3) for k, v in phase.items()},
         "precond_compare": precond_cmp,
         "explicit_current": expl,
+        "explicit_step": expl_step,
         "roofline": roof,
     }
     sim.close()
