@@ -112,3 +112,23 @@ def test_particle_crossing_a_cell_is_reported():
     assert sim.particles(0)["cell"].numel() == parts[0]["cell"].size
     sim.sync()
     sim.close()
+
+
+@pytest.mark.parametrize("name,dim,n,ppc,base,fp32", CASES)
+def test_explicit_step_with_empty_cells_and_species(name, dim, n, ppc, base, fp32):
+    """The explicit step (two light particle passes, Boris push, leapfrog) on
+    ragged occupancy with an empty species, against the oracle."""
+    print(f"[gpu] explicit ragged {name}", flush=True)
+    wl = _wl(dim, n, ppc, base, fp32).replace(dt=0.2)
+    parts = _ragged(wl, fp32)
+    E, B = H.perturbed_fields(wl)
+    G, sp = H.oracle_species(wl, parts)
+    r = O.explicit_step(G, sp, E, B, dt=wl.dt, comoving=True, n_smooth_u=wl.n_smooth_u)
+    sim = H.make_sim(wl, parts, E, B)
+    sim.explicit_step()
+    tol = 1e-5 if fp32 else 1e-10
+    assert H.relerr(sim.gather("E").cpu().numpy(), r["E"]) < tol
+    assert H.relerr(sim.gather("B").cpu().numpy(), r["B"]) < tol
+    assert H.relerr(sim.gather("J_eff").cpu().numpy(), r["J"]) < tol
+    assert sim.particles(1)["cell"].numel() == 0
+    sim.close()
