@@ -1,6 +1,7 @@
 """Parity at the full size of the 3D reconnection workload (256x128x128 cells,
 64 particles per cell per species, FP32 particle path), in the launch
-configuration the benchmark times.
+configuration the benchmark times, and of the 3D colliding-flow shock
+(128x64x64 cells, 27 particles per cell) for the grid quantities.
 
 The FP64 oracle cannot run the whole grid in seconds, so it checks sampled
 outputs it can compute on its own:
@@ -33,10 +34,11 @@ pytestmark = [pytest.mark.gpu, pytest.mark.timeout(600)]
 PATCH = 24
 C = PATCH // 2
 NODES = [(7, 32, 5), (200, 64, 100), (131, 97, 64)]  # in a current sheet, between sheets, elsewhere
+NODES_C4 = [(64, 32, 32), (3, 60, 7), (100, 17, 50)]  # at the flows' meeting plane, near the wrap, elsewhere
 
 
-def _workload():
-    return synth.workloads()["c5"]
+def _workload(name="c5"):
+    return synth.workloads()[name]
 
 
 def _sim(wl, id_weights=False, keep=None):
@@ -131,14 +133,15 @@ def _probe_field(wl):
     return x
 
 
-def test_c5_grid_quantities_operator_and_solve_at_full_size():
-    wl = _workload()
-    print("[gpu] full-size C5 deposit/operator/solve", flush=True)
+@pytest.mark.parametrize("name,nodes", [("c5", NODES), ("c4", NODES_C4)])
+def test_grid_quantities_operator_and_solve_at_full_size(name, nodes):
+    wl = _workload(name)
+    print(f"[gpu] full-size {name} deposit/operator/solve", flush=True)
     E, B = synth.fields(wl)
     sim, _ = _sim(wl)
     sim.set_fields(torch.from_numpy(E).cuda(), torch.from_numpy(B).cuda())
     sim.deposit()
-    gidx = torch.tensor([n[0] + wl.n[0] * (n[1] + wl.n[1] * n[2]) for n in NODES], device="cuda")
+    gidx = torch.tensor([n[0] + wl.n[0] * (n[1] + wl.n[1] * n[2]) for n in nodes], device="cuda")
     got = {}
     for k in ["J_lab", "J_eff", "rho", "mm", "mass", "u", "EM", "Mt", "M0", "kappa_E", "rhs"]:
         g = sim.gather(k)
@@ -149,7 +152,7 @@ def test_c5_grid_quantities_operator_and_solve_at_full_size():
     got["Ax"] = Ax.index_select(1, gidx).cpu().numpy()
     del Ax
     torch.cuda.synchronize()
-    for q, node in enumerate(NODES):
+    for q, node in enumerate(nodes):
         print(f"  node {node}: oracle patch", flush=True)
         ref = _patch(wl, E, B, node)
         c = ref["cidx"]
