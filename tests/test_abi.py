@@ -67,3 +67,36 @@ def test_host_validation_refuses_before_any_device_call():
     while side ** 3 <= limit:
         side += 1
     assert create(3, (side, side, side), fp64) == (err_arg, None)
+
+
+@pytest.mark.parametrize("field,value", [("theta", 0.4), ("theta", 1.5), ("dt", 0.0), ("c", -1.0), ("precision", 7),
+                                         ("n_smooth_u", -1), ("beta_lim", -0.5), ("ns_j", -1), ("ch_frac", -0.1),
+                                         ("dedner_damp", -1.0), ("ns_e", -2)])
+def test_host_validation_of_each_parameter(field, value):
+    """Each out-of-range parameter is refused by ge_create before any device
+    call (so this runs without a GPU)."""
+    from paper_2506_11320_amd.glecsim import GEGrid, GEParams, load_library
+    L = load_library()
+    g = GEGrid()
+    g.dim = 1
+    g.n[0], g.n[1], g.n[2] = 8, 1, 1
+    g.dx[0] = g.dx[1] = g.dx[2] = 0.5
+    p = GEParams(0.5, 1.0, 0.5, 1, 1, 1.0, 1, 1.0, 1, 5, 0.5, 0, 0, 0, 0.8, 0.1, 0)
+    setattr(p, field, value)
+    h = ctypes.c_void_p()
+    assert L.ge_create(ctypes.byref(g), ctypes.byref(p), None, ctypes.byref(h)) == -1 and h.value is None
+
+
+@pytest.mark.parametrize("dim,n", [(1, (2, 1, 1)), (2, (8, 1, 1)), (2, (8, 8, 2)), (3, (8, 8, 2))])
+def test_host_validation_of_grid_shapes(dim, n):
+    """Active axes need at least 3 cells, inactive ones exactly 1."""
+    from paper_2506_11320_amd.glecsim import GEGrid, GEParams, load_library
+    L = load_library()
+    g = GEGrid()
+    g.dim = dim
+    for d in range(3):
+        g.n[d] = n[d]
+        g.dx[d] = 0.5
+    p = GEParams(0.5, 1.0, 0.5, 1, 1, 1.0, 1, 1.0, 1, 5, 0.5, 1, 0, 0, 0.8, 0.1, 0)
+    h = ctypes.c_void_p()
+    assert L.ge_create(ctypes.byref(g), ctypes.byref(p), None, ctypes.byref(h)) == -1 and h.value is None
