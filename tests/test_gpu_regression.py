@@ -178,3 +178,46 @@ def test_fast_flow_momentum_claim():
     print(f"  max |dP/P| over {steps} steps: CM=F ns_j=0 {d_lab:.3e}, CM=F ns_j=1 {d_lab_s:.3e}, "
           f"CM=T ns_j=1 {d_cm:.3e}", flush=True)
     assert d_cm < 0.2 * min(d_lab, d_lab_s)
+
+
+def _c2_history(comoving, steps=200):
+    """The 2D fast-flow workload (256x128 cells, 64 particles per cell per
+    species, bulk 0.2c) in FP32: field energy and total x momentum every 25
+    steps."""
+    from paper_2506_11320_amd import Simulation
+    wl = synth.workloads()["c2"].replace(fp32=True)
+    sim = Simulation(wl.dim, wl.n, wl.dx, theta=wl.theta, dt=wl.dt, lf_E=wl.lf_E, lf_B=wl.lf_B,
+                     beta_lim=wl.beta_lim, a_mode=wl.a_mode, comoving=comoving, n_smooth_u=wl.n_smooth_u, fp32=True)
+    for s in range(wl.nsp):
+        p = synth.particles(wl, s, f32=True)
+        t = {k: torch.from_numpy(np.ascontiguousarray(v)).cuda() for k, v in p.items()}
+        sim.add_species(wl.q[s], wl.m[s], t["cell"], t["off"], t["v"], t["w"])
+    E, B = synth.fields(wl)
+    sim.set_fields(torch.from_numpy(E).cuda(), torch.from_numpy(B).cuda())
+    d = sim.diagnostics()
+    P0, W0 = sum(p[0] for p in d["P"]), d["W_E"]
+    WE, dP = [], []
+    for k in range(steps):
+        assert sim.step(tol=1e-8, maxit=500, restart=30)["converged"]
+        if (k + 1) % 25 == 0:
+            d = sim.diagnostics()
+            WE.append(d["W_E"])
+            dP.append(abs(sum(p[0] for p in d["P"]) - P0) / abs(P0))
+    sim.close()
+    return W0, np.array(WE), np.array(dP)
+
+
+def test_fast_flow_2d_noise_at_full_size():
+    """The fast-flow noise test of the 2D configuration (Sec. 3.1 motivation,
+    Sec. 4.2 claim) at full size: with the lab-frame current the electric
+    field energy grows from the flow's motional field and the total momentum
+    drifts; with the comoving-frame current the field energy stays at its
+    initial value and the momentum drift is hundreds of times smaller."""
+    print("[gpu] 2D fast flow noise, full size", flush=True)
+    W0, WE_lab, dP_lab = _c2_history(False)
+    W1, WE_cm, dP_cm = _c2_history(True)
+    print(f"  W_E/W_E(0) max: lab {WE_lab.max() / W0:.3f}, comoving {WE_cm.max() / W1:.4f}; "
+          f"max |dP/P|: lab {dP_lab.max():.2e}, comoving {dP_cm.max():.2e}", flush=True)
+    assert WE_lab.max() > 1.5 * W0
+    assert np.abs(WE_cm / W1 - 1).max() < 0.01
+    assert dP_cm.max() < 0.01 * dP_lab.max()
