@@ -125,8 +125,15 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     return L
 
 
+def _require(ok: bool, msg: str) -> None:
+    """Argument checks that guard the device pointers handed to the library
+    (kept under python -O, unlike assert)."""
+    if not ok:
+        raise ValueError(msg)
+
+
 def _ptr(t: torch.Tensor) -> int:
-    assert t.is_cuda and t.is_contiguous(), "device tensors must be contiguous CUDA/HIP tensors"
+    _require(t.is_cuda and t.is_contiguous(), "device tensors must be contiguous CUDA/HIP tensors")
     return t.data_ptr()
 
 
@@ -190,15 +197,17 @@ class Simulation:
     def add_species(self, q: float, m: float, cell: torch.Tensor, off: torch.Tensor, v: torch.Tensor,
                     w: torch.Tensor):
         n = int(cell.numel())
-        assert cell.dtype == torch.int32 and off.dtype == self.fdtype and v.dtype == self.fdtype
-        assert off.shape == (3, n) and v.shape == (3, n) and w.shape == (n,)
+        _require(cell.dtype == torch.int32, "cell must be int32")
+        _require(off.dtype == v.dtype == w.dtype == self.fdtype, f"off, v and w must be {self.fdtype}")
+        _require(off.shape == (3, n) and v.shape == (3, n) and w.shape == (n,), "off, v: [3, n]; w: [n]")
         sp = GESpecies(q, m)
         self._check(self.L.ge_add_species(self.h, ctypes.byref(sp), n, _ptr(cell), _ptr(off), _ptr(v), _ptr(w)))
         self.nsp += 1
         self.counts.append(n)
 
     def set_fields(self, E: torch.Tensor, B: torch.Tensor):
-        assert E.dtype == torch.float64 and E.shape == (3, self.N) and B.shape == (3, self.N)
+        _require(E.dtype == torch.float64 and B.dtype == torch.float64, "E and B must be float64")
+        _require(E.shape == (3, self.N) and B.shape == (3, self.N), "E and B: [3, N]")
         self._check(self.L.ge_set_fields(self.h, _ptr(E), _ptr(B)))
 
     # -------------------------------------------------------------- step
@@ -259,7 +268,7 @@ class Simulation:
 
     def set(self, what: str, src: torch.Tensor):
         src = src.to(device=self.device, dtype=torch.float64).contiguous()
-        assert tuple(src.shape) == self.field_shape(what)
+        _require(tuple(src.shape) == self.field_shape(what), f"{what}: shape {self.field_shape(what)}")
         self._check(self.L.ge_set(self.h, FIELDS[what], _ptr(src)))
         self._keep = src  # keep alive until the stream has copied it
 
@@ -300,12 +309,12 @@ class Simulation:
     def cnn_set_weights(self, w) -> None:
         import numpy as np
         w = np.ascontiguousarray(w, dtype=np.float32)
-        assert w.shape == (self.cnn_size(),)
+        _require(w.shape == (self.cnn_size(),), "weights: one vector of cnn_size() values")
         self._check(self.L.ge_cnn_weights(self.h, 1, w.ctypes.data))
 
     def cnn_apply(self, r: torch.Tensor) -> torch.Tensor:
         r = r.to(device=self.device, dtype=torch.float64).contiguous()
-        assert tuple(r.shape) == (3, self.N)
+        _require(tuple(r.shape) == (3, self.N), "r: [3, N]")
         z = torch.empty_like(r)
         self._check(self.L.ge_cnn_apply(self.h, _ptr(r), _ptr(z)))
         return z
@@ -316,7 +325,7 @@ class Simulation:
     def cnn_add_pair(self, r: torch.Tensor, e: torch.Tensor):
         r = r.to(device=self.device, dtype=torch.float64).contiguous()
         e = e.to(device=self.device, dtype=torch.float64).contiguous()
-        assert tuple(r.shape) == (3, self.N) and tuple(e.shape) == (3, self.N)
+        _require(tuple(r.shape) == (3, self.N) and tuple(e.shape) == (3, self.N), "r and e: [3, N]")
         self._check(self.L.ge_cnn_add_pair(self.h, _ptr(r), _ptr(e)))
 
     def cnn_npairs(self) -> int:
@@ -336,7 +345,7 @@ class Simulation:
         tgt = tgt.to(device=self.device, dtype=torch.float32).contiguous()
         B, v6 = in_crops.shape[0], in_crops.shape[1]
         n = round(v6 ** (1.0 / 3.0)) - 6
-        assert (n + 6) ** 3 == v6 and tuple(tgt.shape) == (B, n ** 3, 3)
+        _require((n + 6) ** 3 == v6 and tuple(tgt.shape) == (B, n ** 3, 3), "in_crops [B, (n+6)^3, 3], tgt [B, n^3, 3]")
         g = torch.empty(self.cnn_size(), dtype=torch.float32, device=self.device)
         loss = ctypes.c_double()
         self._check(self.L.ge_cnn_loss_grad(self.h, B, n, _ptr(in_crops), _ptr(tgt), _ptr(g), ctypes.byref(loss)))

@@ -40,6 +40,15 @@ def test_binding_refuses_without_gpu(monkeypatch):
         Simulation(1, (8, 1, 1), (0.5, 1, 1), theta=0.5, dt=0.5)
 
 
+def test_binding_refuses_host_tensors():
+    """Pointers handed to the library must be device tensors; the check is a
+    ValueError (it stays under python -O)."""
+    import torch
+    from paper_2506_11320_amd.glecsim import _ptr
+    with pytest.raises(ValueError):
+        _ptr(torch.zeros(3, dtype=torch.float64))
+
+
 def test_host_validation_refuses_before_any_device_call():
     """ge_create checks its arguments on the host first: refused grids never
     reach the device (so this runs without a GPU).  FP64 3D grids above
