@@ -345,19 +345,22 @@ __global__ __launch_bounds__(64) void k_push(DGrid G, PushArgs<T> A) {
     wave_sync();
     const int m0 = dpp_scan<true, false>(mk[lane]);
     const int m1 = max(dpp_scan<true, false>(mk[64 + lane]), rl_i(m0, 63));
-    T f0[3], v0[3], w0 = 0, f1[3], v1[3], w1 = 0;
+    T f0[3], v0[3], w0, f1[3], v1[3], w1;
     const bool a0 = lane < total, a1 = 64 + lane < total;
     const int k0 = a0 ? m0 - 1 : 0, k1 = a1 ? m1 - 1 : 0;
     const int i0 = sst[k0] + lane - spr[k0], i1 = sst[k1] + 64 + lane - spr[k1];
+    // both records are loaded before either push, unconditionally (idle
+    // lanes read record 0, which every buffer holds, and drop it): a load
+    // under a branch would wait for the first push before the second load
+    load_particle<T, DIM>(A, a0 ? i0 : 0, f0, v0, w0);
+    load_particle<T, DIM>(A, a1 ? i1 : 0, f1, v1, w1);
+    // wait for both here (vmcnt(0); expcnt and lgkmcnt left at their
+    // maxima): the compiler then knows no load is pending on any path below
+    // and does not hold the second store for the first one's completion
+    __builtin_amdgcn_s_waitcnt(0xF70);
     int d0 = 31, d1 = 31;
-    if (a0) {
-      load_particle<T, DIM>(A, i0, f0, v0, w0);
-      d0 = push_one<T, DIM>(f0, v0, fc, A.beta, A.dtx, clamped);
-    }
-    if (a1) {
-      load_particle<T, DIM>(A, i1, f1, v1, w1);
-      d1 = push_one<T, DIM>(f1, v1, fc, A.beta, A.dtx, clamped);
-    }
+    if (a0) d0 = push_one<T, DIM>(f0, v0, fc, A.beta, A.dtx, clamped);
+    if (a1) d1 = push_one<T, DIM>(f1, v1, fc, A.beta, A.dtx, clamped);
     const DirStats q0 = dir_stats(a0, d0, lane), q1 = dir_stats(a1, d1, lane);
     cnt = q0.count_k + q1.count_k;
     dir_off = excl_scan(cnt);
