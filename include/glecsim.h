@@ -99,10 +99,6 @@ typedef struct {
   int ns_e;
 } ge_params;
 
-/* Largest FP64 3D grid (cells) ge_create accepts; FP32 3D and FP64 1D/2D
- * grids have no such limit. */
-#define GE_FP64_3D_MAX_CELLS 4096
-
 typedef struct { double q, m; } ge_species;   /* charge and mass per physical particle */
 
 typedef struct {

@@ -90,11 +90,6 @@ int ge_create(const ge_grid* grid, const ge_params* params, void* hip_stream, ge
   if (params->n_smooth_u < 0 || params->beta_lim < 0) return bad("n_smooth_u/beta_lim");
   if (params->ns_j < 0 || !(params->ch_frac >= 0) || !(params->dedner_damp >= 0)) return bad("ns_j/ch_frac/dedner_damp");
   if (params->ns_e < 0) return bad("ns_e");
-  // The FP64 3D particle path is validated on small grids only: a 64x32x32
-  // FP64 deposit faulted once with an illegal address whose cause is not
-  // found; until it is, larger FP64 3D grids are refused.
-  if (dim == 3 && params->precision == GE_FP64 && N > GE_FP64_3D_MAX_CELLS)
-    return bad("FP64 3D grids above " + std::to_string(GE_FP64_3D_MAX_CELLS) + " cells are not supported (use GE_FP32)");
   DGrid& G = c->G;
   G.dim = dim;
   G.N = N;

@@ -71,10 +71,37 @@ struct ExArgs {
   T* cells;         // [N][EX_NV] per-cell corner sums
 };
 
+// A particle record in registers: offset (3), w, v (3).  No load reaches past
+// the record (the last record of a buffer ends where the allocation may end):
+// FP32 reads one 4-vector and three values that the compiler merges into one
+// 12-byte load; FP64 reads the 4-vectors (x, y, z, w) and (w, vx, vy, vz), the
+// second ending at the record's last byte (three separate values there would
+// be merged into a wider load reading 8 bytes of the next record).
+template <typename T>
+struct ExRec {
+  T r[GE_REC];
+};
+template <typename T>
+using ex4 = T __attribute__((ext_vector_type(4), aligned(sizeof(T))));
+template <typename T>
+__device__ inline ExRec<T> load_rec(const T* __restrict__ p) {
+  ExRec<T> q;
+  const ex4<T> a = *reinterpret_cast<const ex4<T>*>(p);
+  q.r[0] = a[0]; q.r[1] = a[1]; q.r[2] = a[2]; q.r[3] = a[3];
+  if constexpr (sizeof(T) == 8) {
+    const ex4<T> b = *reinterpret_cast<const ex4<T>*>(p + 3);
+    q.r[4] = b[1]; q.r[5] = b[2]; q.r[6] = b[3];
+  } else {
+    q.r[4] = p[4]; q.r[5] = p[5]; q.r[6] = p[6];
+  }
+  return q;
+}
+
 // One particle's contribution to the lane's corner sums.
 template <typename T, int DIM, int MODE>
-__device__ inline void add_particle(const T* __restrict__ r, T qs, T ms, const T* s_u, T* acc) {
+__device__ inline void add_particle(const ExRec<T>& q, T qs, T ms, const T* s_u, T* acc) {
   constexpr int NC = Ex<DIM>::NC;
+  const T* r = q.r;
   const T f0 = r[0], f1 = DIM >= 2 ? r[1] : (T)0, f2 = DIM >= 3 ? r[2] : (T)0, w = r[3];
   const T v[3] = {r[4], r[5], r[6]};
   T W[NC];
@@ -141,9 +168,16 @@ __global__ __launch_bounds__(64) void k_cell_linear(DGrid G, ExArgs<T> A) {
     const ExSpecies<T>& Sa = A.sp[s0];
     const ExSpecies<T>& Sb = A.sp[s0 + 1 < A.nsp ? s0 + 1 : s0];
     const bool has_b = s0 + 1 < A.nsp;
+    // the pair's pointers and constants as wave-uniform values (a per-lane
+    // choice between the two structures would become a per-lane memory load)
+    const T* const reca = Sa.rec;
+    const T* const recb = Sb.rec;
+    const int32_t* const runa = Sa.runs;
+    const int32_t* const runb = Sb.runs;
+    const T qsa = Sa.qs, msa = Sa.ms, qsb = Sb.qs, msb = Sb.ms;
     int st = 0, cnt = 0;
     if (rl < ND && (hl == 0 || has_b)) {
-      const i2v rv = reinterpret_cast<const i2v*>(hl ? Sb.runs : Sa.runs)[c * ND + rl];
+      const i2v rv = reinterpret_cast<const i2v*>(hl ? runb : runa)[c * ND + rl];
       st = rv.x;
       cnt = rv.y;
     }
@@ -176,10 +210,16 @@ __global__ __launch_bounds__(64) void k_cell_linear(DGrid G, ExArgs<T> A) {
       const bool aa = ta < total, ab = tb < total;
       const int ka = aa ? m0 - 1 : 0, kb = ab ? m1 - 1 : 0;
       const bool sba = ka >= nseg0, sbb = kb >= nseg0;
-      const T* ra = (sba ? Sb.rec : Sa.rec) + GE_REC * ((int64_t)s_st[ka] + (ta - s_pre[ka]));
-      const T* rb = (sbb ? Sb.rec : Sa.rec) + GE_REC * ((int64_t)s_st[kb] + (tb - s_pre[kb]));
-      if (aa) add_particle<T, DIM, MODE>(ra, sba ? Sb.qs : Sa.qs, sba ? Sb.ms : Sa.ms, s_u, acc);
-      if (ab) add_particle<T, DIM, MODE>(rb, sbb ? Sb.qs : Sa.qs, sbb ? Sb.ms : Sa.ms, s_u, acc);
+      // both records are loaded unconditionally before either is used (idle
+      // lanes read record 0 of the first species, which every buffer holds):
+      // a load under a branch would wait for the first particle's sums
+      const int64_t ia = aa ? (int64_t)s_st[ka] + (ta - s_pre[ka]) : 0;
+      const int64_t ib = ab ? (int64_t)s_st[kb] + (tb - s_pre[kb]) : 0;
+      const ExRec<T> qa = load_rec((aa && sba ? recb : reca) + GE_REC * ia);
+      const ExRec<T> qb = load_rec((ab && sbb ? recb : reca) + GE_REC * ib);
+      __builtin_amdgcn_s_waitcnt(0xF70);  // vmcnt(0): both records are in
+      if (aa) add_particle<T, DIM, MODE>(qa, sba ? qsb : qsa, sba ? msb : msa, s_u, acc);
+      if (ab) add_particle<T, DIM, MODE>(qb, sbb ? qsb : qsa, sbb ? msb : msa, s_u, acc);
       wsync();  // s_mk is reset by the next round
     }
   }

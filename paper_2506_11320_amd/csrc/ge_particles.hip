@@ -269,20 +269,32 @@ __device__ inline DirStats dir_stats(bool act, int dir, int lane) {
 __device__ inline int excl_scan(int x) { return dpp_scan<false, false>(x) - x; }
 
 // Particle record i: GE_REC = 7 consecutive values, offset x, y, z, w, then
-// velocity x, y, z (28 bytes in FP32), read and written as one 4-vector and
-// three values that the compiler merges into one 3-wide access (a vec3 type
-// is avoided: its FP64 store writes a fourth, padding element over the next
-// record).  Consecutive records are contiguous, so a wave's records are read
-// and written as whole cache lines without padding.
+// velocity x, y, z (28 bytes in FP32, 56 in FP64).  Consecutive records are
+// contiguous, so a wave's records are read and written as whole cache lines
+// without padding.  No access may reach past the record: the last record of
+// a buffer ends where the allocation may end.
+//   FP32: read as one 4-vector and three values that the compiler merges into
+//   one 12-byte load.
+//   FP64: read as the 4-vectors (x, y, z, w) and (w, vx, vy, vz), the second
+//   ending at the record's last byte: three separate values at the end would
+//   be merged into a wider load that reads 8 bytes of the next record, past
+//   the buffer at its last record.
+// Written as one 4-vector and three values (a vec3 type is avoided: its FP64
+// store writes a fourth, padding element over the next record).
 template <typename T>
 using rec4 = T __attribute__((ext_vector_type(4), aligned(sizeof(T))));
 template <typename T, int DIM>
 __device__ inline void read_rec(const T* __restrict__ rec, int64_t i, T f[3], T v[3], T& w) {
-  const rec4<T> a = *reinterpret_cast<const rec4<T>*>(rec + GE_REC * i);
-  const T* b = rec + GE_REC * i + 4;
+  const T* p = rec + GE_REC * i;
+  const rec4<T> a = *reinterpret_cast<const rec4<T>*>(p);
 #pragma unroll
   for (int d = 0; d < 3; ++d) f[d] = d < DIM ? a[d] : (T)0;
-  v[0] = b[0]; v[1] = b[1]; v[2] = b[2];
+  if constexpr (sizeof(T) == 8) {
+    const rec4<T> b = *reinterpret_cast<const rec4<T>*>(p + 3);
+    v[0] = b[1]; v[1] = b[2]; v[2] = b[3];
+  } else {
+    v[0] = p[4]; v[1] = p[5]; v[2] = p[6];
+  }
   w = a[3];
 }
 template <typename T>

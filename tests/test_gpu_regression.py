@@ -180,20 +180,24 @@ def test_fast_flow_momentum_claim():
     assert d_cm < 0.2 * min(d_lab, d_lab_s)
 
 
-def _c2_history(comoving, steps=200):
-    """The 2D fast-flow workload (256x128 cells, 64 particles per cell per
-    species, bulk 0.2c) in FP32: field energy and total x momentum every 25
-    steps."""
+def _c2_sim(comoving, fp32):
     from paper_2506_11320_amd import Simulation
-    wl = synth.workloads()["c2"].replace(fp32=True)
+    wl = synth.workloads()["c2"].replace(fp32=fp32)
     sim = Simulation(wl.dim, wl.n, wl.dx, theta=wl.theta, dt=wl.dt, lf_E=wl.lf_E, lf_B=wl.lf_B,
-                     beta_lim=wl.beta_lim, a_mode=wl.a_mode, comoving=comoving, n_smooth_u=wl.n_smooth_u, fp32=True)
+                     beta_lim=wl.beta_lim, a_mode=wl.a_mode, comoving=comoving, n_smooth_u=wl.n_smooth_u, fp32=fp32)
     for s in range(wl.nsp):
-        p = synth.particles(wl, s, f32=True)
+        p = synth.particles(wl, s, f32=fp32)
         t = {k: torch.from_numpy(np.ascontiguousarray(v)).cuda() for k, v in p.items()}
         sim.add_species(wl.q[s], wl.m[s], t["cell"], t["off"], t["v"], t["w"])
     E, B = synth.fields(wl)
     sim.set_fields(torch.from_numpy(E).cuda(), torch.from_numpy(B).cuda())
+    return sim
+
+
+def _c2_history(comoving, steps=200, fp32=True):
+    """The 2D fast-flow workload (256x128 cells, 64 particles per cell per
+    species, bulk 0.2c): field energy and total x momentum every 25 steps."""
+    sim = _c2_sim(comoving, fp32)
     d = sim.diagnostics()
     P0, W0 = sum(p[0] for p in d["P"]), d["W_E"]
     WE, dP = [], []
@@ -217,6 +221,30 @@ def test_fast_flow_2d_noise_at_full_size():
     W0, WE_lab, dP_lab = _c2_history(False)
     W1, WE_cm, dP_cm = _c2_history(True)
     print(f"  W_E/W_E(0) max: lab {WE_lab.max() / W0:.3f}, comoving {WE_cm.max() / W1:.4f}; "
+          f"max |dP/P|: lab {dP_lab.max():.2e}, comoving {dP_cm.max():.2e}", flush=True)
+    assert WE_lab.max() > 1.5 * W0
+    assert np.abs(WE_cm / W1 - 1).max() < 0.01
+    assert dP_cm.max() < 0.01 * dP_lab.max()
+
+
+def test_fast_flow_2d_fp64_against_fp32():
+    """The same workload in FP64 (its species buffers are 112 MiB, a whole
+    number of 2 MiB pages): the FP64 and FP32 deposits of the first step
+    agree to the FP32 tolerance, and the FP64 run shows the same noise
+    behaviour over 200 steps."""
+    print("[gpu] 2D fast flow, FP64 against FP32", flush=True)
+    got = {}
+    for fp32 in (False, True):
+        sim = _c2_sim(True, fp32)
+        sim.deposit()
+        got[fp32] = {k: sim.gather(k).cpu().numpy() for k in ("Mt", "M0", "J_lab", "J_eff", "rho")}
+        sim.close()
+    for k in got[False]:
+        a, b = got[True][k], got[False][k]
+        assert np.linalg.norm(a - b) < 1e-5 * np.linalg.norm(b), k
+    W0, WE_lab, dP_lab = _c2_history(False, fp32=False)
+    W1, WE_cm, dP_cm = _c2_history(True, fp32=False)
+    print(f"  FP64: W_E/W_E(0) max: lab {WE_lab.max() / W0:.3f}, comoving {WE_cm.max() / W1:.4f}; "
           f"max |dP/P|: lab {dP_lab.max():.2e}, comoving {dP_cm.max():.2e}", flush=True)
     assert WE_lab.max() > 1.5 * W0
     assert np.abs(WE_cm / W1 - 1).max() < 0.01
