@@ -149,6 +149,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c5")
     ap.add_argument("--precond", default="none", choices=["none", "jacobi"])
+    ap.add_argument("--precision", default="workload", choices=["workload", "fp32", "fp64"],
+                    help="particle precision: the workload's own, or forced")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--compare-precond", action="store_true", help="also time a Jacobi-preconditioned solve")
@@ -190,6 +192,8 @@ def main():
         return
 
     wl = synth.workloads()[args.workload]
+    if args.precision != "workload":
+        wl = wl.replace(fp32=args.precision == "fp32")
     log(f"workload {wl.name}: cells {wl.n[:wl.dim]}, ppc {wl.ppc}, species {wl.nsp}")
     sim = Simulation(wl.dim, wl.n, wl.dx, theta=wl.theta, dt=wl.dt, lf_E=wl.lf_E, lf_B=wl.lf_B,
                      beta_lim=wl.beta_lim, a_mode=wl.a_mode, comoving=wl.comoving, n_smooth_u=wl.n_smooth_u,
@@ -237,11 +241,12 @@ def main():
     dom = "deposit" if tm[1] >= tm[0] else "push"
     dom_t = tm[1] if dom == "deposit" else tm[0]
     achieved = ab[dom] / dom_t / 1e9
-    roof = {"bound": "hbm", "kernel": "k_deposit<float,3>" if dom == "deposit" else "k_push<float,3> (x2 species)",
+    tname = f"{'float' if wl.fp32 else 'double'},{wl.dim}"
+    roof = {"bound": "hbm", "kernel": f"k_deposit<{tname}>" if dom == "deposit" else f"k_push<{tname}> (x2 species)",
             "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": measured_traffic("paper_2506_11320_amd/csrc/ge_particles.hip", "profiles/c5_deposit_traffic.json")
-            if (dom == "deposit" and args.workload == "c5") else None,
+            if (dom == "deposit" and args.workload == "c5" and wl.fp32) else None,
             "algorithmic_bytes_per_launch": ab[dom], "launch_ms": round(dom_t * 1e3, 4)}
     precond_cmp = None
     if args.compare_precond:
