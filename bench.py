@@ -325,6 +325,13 @@ def main():
         "explicit_current": expl,
         "explicit_step": expl_step,
         "roofline": roof,
+        # the other particle phase against the same peak: algorithmic bytes of
+        # both species' push over the phase's event-timed duration (the
+        # re-binning count and scan kernels included)
+        "push_roofline": {"bound": "hbm", "kernel": f"k_push<{tname}> (x{wl.nsp} species) + re-binning scans",
+                          "achieved": round(ab["push"] / tm[0] / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                          "frac": round(ab["push"] / tm[0] / 1e9 / HBM_PEAK_GBS, 4),
+                          "algorithmic_bytes": ab["push"], "phase_ms": round(tm[0] * 1e3, 4)},
     }
     sim.close()
     if not args.no_cpu_baseline:
