@@ -129,7 +129,9 @@ int ge_create(const ge_grid* grid, const ge_params* params, void* hip_stream, ge
 /* Free every library-owned buffer.  Accepts NULL. */
 void ge_destroy(ge_ctx* ctx);
 
-/* Message of the last failed call on ctx (never NULL). */
+/* Message of the last failed call on ctx (never NULL).  With ctx NULL: the
+ * reason the calling thread's last refused ge_create gave (ge_create returns
+ * no context to ask). */
 const char* ge_last_error(const ge_ctx* ctx);
 
 /* Add a species of n macro-particles (Sec. 3.1: macro-particles with charge

@@ -55,12 +55,18 @@ void accumulate_timings(ge_ctx* c, double solve_s) {
 
 extern "C" {
 
-const char* ge_last_error(const ge_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+// reason of the calling thread's last refused ge_create
+thread_local std::string g_create_err = "no refused ge_create";
+
+const char* ge_last_error(const ge_ctx* ctx) { return ctx ? ctx->err.c_str() : g_create_err.c_str(); }
 
 int ge_half_stencil(const ge_ctx* ctx) { return ctx ? ctx->nh : 0; }
 
 int ge_create(const ge_grid* grid, const ge_params* params, void* hip_stream, ge_ctx** out) {
-  if (!grid || !params || !out) return GE_ERR_ARG;
+  if (!grid || !params || !out) {
+    g_create_err = "ge_create: null grid, params or out";
+    return GE_ERR_ARG;
+  }
   *out = nullptr;
   ge_ctx* c = new ge_ctx();
   std::memset((void*)&c->G, 0, sizeof(c->G));
@@ -69,9 +75,10 @@ int ge_create(const ge_grid* grid, const ge_params* params, void* hip_stream, ge
   c->stream = (hipStream_t)hip_stream;
   const int dim = grid->dim;
   auto bad = [&](const std::string& m) {
-    // the caller gets no context on failure; report through stderr-free code
+    // the caller gets no context on failure: the reason is kept per thread
+    // for ge_last_error(NULL)
     delete c;
-    (void)m;
+    g_create_err = "ge_create: " + m;
     return GE_ERR_ARG;
   };
   if (dim < 1 || dim > 3) return bad("dim");
@@ -148,6 +155,7 @@ int ge_create(const ge_grid* grid, const ge_params* params, void* hip_stream, ge
   if (!rc) rc = dalloc(c, &c->partials, sizeof(double) * 16 * 512);  // 16 dots x 512 blocks
   if (!rc) rc = dalloc(c, &c->flags, sizeof(int) * 4);
   if (rc) {
+    g_create_err = "ge_create: " + c->err;
     ge_destroy(c);
     return rc;
   }
@@ -163,6 +171,7 @@ int ge_create(const ge_grid* grid, const ge_params* params, void* hip_stream, ge
   for (int k = 0; k < 8; ++k) c->tsum[k] = 0;
   c->tcnt = 0;
   if (hipGetLastError() != hipSuccess) {
+    g_create_err = "ge_create: a HIP call failed while clearing the fields";
     ge_destroy(c);
     return GE_ERR_HIP;
   }

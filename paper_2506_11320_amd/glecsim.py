@@ -171,7 +171,7 @@ class Simulation:
         rc = self.L.ge_create(ctypes.byref(g), ctypes.byref(p), ctypes.c_void_p(self.stream.cuda_stream),
                               ctypes.byref(h))
         if rc != GE_OK:
-            raise GlecsimError(rc, "ge_create failed (invalid grid/params or out of memory)")
+            raise GlecsimError(rc, self.L.ge_last_error(None).decode())
         self.h = h
         self.nsp = 0
         self.counts = []

@@ -71,6 +71,7 @@ def test_host_validation_refuses_before_any_device_call():
         return rc, h.value
 
     assert create(4, (8, 8, 8), fp64) == (err_arg, None)
+    assert L.ge_last_error(None).decode() == "ge_create: dim"
     assert create(3, (2048, 1024, 1024), fp64) == (err_arg, None)
 
 
