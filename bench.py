@@ -5,11 +5,21 @@ One step = the whole hot path on one batch of synthetic particles already
 resident in HBM: deposit (mass matrices, current, moments) -> grid pass
 (node assembly, smoothed bulk velocity, comoving current, limited LF
 coefficients, RHS) -> FP64 GMRES solve to 1e-8 -> field update -> implicit push
-with stable re-binning.  Prints one JSON line.
+with stable re-binning (and the stable re-sort of particles that moved more
+than one cell, when there are any).  Prints one JSON line.
 
 Workload (default): the 3D3V reconnection case at HBM scale (256x128x128
 cells, 64 macro-particles per cell per species, m_i/m_e = 100, double Harris
 sheet with a 0.2c guide flow), FP32 particle path, FP64 field solve.
+
+Legs after the timed steps, each from a fresh load of the same initial state
+(so that the driver's --steps does not change what they see):
+  nn_precond   learned preconditioner: harvest, train, then plain GMRES and
+               CNN-preconditioned FGMRES on the same systems;
+  cpu_baseline the FP64 oracle on a bounded sample of the workload, one core
+               and all cores (independent sub-boxes in parallel processes).
+The JSON line is printed at the end; the exit status is 0 only if every leg
+succeeded (a failed leg is named in "errors").
 """
 from __future__ import annotations
 
@@ -26,6 +36,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+BF16_PEAK_TFLOPS = 2500.0
 METRIC = "particle-steps/s (push+deposit); GMRES s/step plain vs NN-precond at 1e-8"
 
 
@@ -39,23 +50,29 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(wl, nsp, counts):
-    """Compulsory HBM bytes of one launch of the particle kernels (FP32, 3D):
-    deposit: particle state read once (28 B), the run table of each species
-    (27 x 8 B per cell), node-averaged B (12 B per node) and the per-cell sums
-    written once (558 x 4 B per cell with two species);
-    push (per species): particle state read and written once (2 x 28 B), run
-    table read and written (2 x 27 x 8 B per cell), segment offsets (4 B per
-    cell), E and B at nodes (24 B per node)."""
+def algorithmic_bytes(wl, nsp, npart):
+    """Algorithmic HBM bytes of the particle phases (the method's compulsory
+    traffic, not this library's staging), per launch:
+      deposit: each particle's state read once (offsets, weight, velocity:
+        (dim + 4) values), and per node the node-averaged B read (3 values)
+        and the grid outputs written once: the half-stencil mass matrices
+        Mtilde and M0 (2 x nh x 9 values in the particle precision), the
+        current (3), charge density per species (nsp), mass-weighted velocity
+        (3) and mass (1) in FP64;
+      push: each particle's state read and written once, and per node E^{n+theta}
+        and the node-averaged B read (6 values), per cell the segment start of
+        each species (4 B) -- the re-binning writes nothing beyond the
+        particle state it moves;
+      step: the two together, the push+deposit pass of one particle-step."""
     N = wl.ncells
-    nd = 3 ** wl.dim
-    nc = 2 ** wl.dim
     es = 4 if wl.fp32 else 8
-    per_p = (wl.dim + 3 + 1) * es
-    q_used = 18 * nd + nc * (7 + nsp)
-    dep = sum(counts) * per_p + N * (nsp * nd * 8 + 3 * es + q_used * es)
-    push = sum(c * 2 * per_p for c in counts) + nsp * N * (2 * nd * 8 + 4 + 6 * es)
-    return {"deposit": dep, "push": push}
+    nh = {1: 2, 2: 5, 3: 14}[wl.dim]
+    per_p = (wl.dim + 4) * es
+    node_dep = 3 * es + 2 * nh * 9 * es + (3 + nsp + 3 + 1) * 8
+    dep = npart * per_p + N * node_dep
+    push = npart * 2 * per_p + N * (6 * es + 4 * nsp)
+    return {"deposit": dep, "push": push, "step": dep + push,
+            "per_particle": per_p, "per_node_deposit": node_dep}
 
 
 def measured_traffic(kernel_file, record):
@@ -73,13 +90,25 @@ def measured_traffic(kernel_file, record):
     return float(rec["traffic_bytes"])
 
 
-def cpu_baseline(wl, box=24):
-    """The FP64 oracle, as it stands, timed on a bounded sample of the same
-    workload: one full step of a periodic box^3-cell sub-box built with the
-    same recipe (ppc, dx, dt, species)."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_sample(args):
+    """One full oracle step (deposit, comoving current, GMRES to 1e-8, B/E
+    update, push) of a periodic box^3 sub-box with the workload's recipe;
+    seed offset k makes each process's sub-box independent."""
+    wname, box, k = args
     import oracle as O
     import synth
-    sub = synth.small("cpu_sample", dim=3, n=(box, box, box), ppc=wl.ppc, base="c5")
+    wl = synth.workloads()[wname]
+    sub = synth.small("cpu_sample", dim=3, n=(box, box, box), ppc=wl.ppc, base=wname).replace(seed=wl.seed + 101 * k)
     G = O.grid(3, sub.n, sub.dx)
     E, B = synth.fields(sub)
     sp = []
@@ -91,54 +120,117 @@ def cpu_baseline(wl, box=24):
     t0 = time.perf_counter()
     O.step(G, sp, E, B, dt=sub.dt, theta=sub.theta, comoving=True, lf_E=True, lf_B=True, beta_lim=sub.beta_lim,
            a_mode=sub.a_mode, tol=1e-8, restart=30)
-    dt = time.perf_counter() - t0
-    return {"value": npart / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"1 full step (deposit, comoving current, GMRES to 1e-8, B/E update, push) of a "
-                      f"{box}^3-cell periodic sub-box with the same recipe ({npart} particles), "
-                      f"single-threaded FP64 C oracle, {dt:.1f} s"}
+    return npart, time.perf_counter() - t0
 
 
-def nn_compare(sim, args):
-    """Learned preconditioner, after the timed steps: harvest (residual,
-    correction) pairs from plain solves, train on the GPU, then solve each of
-    the next steps both ways from the same state (plain GMRES, then
-    CNN-preconditioned FGMRES, both to the same true residual) and push with
-    the second answer."""
+def cpu_baseline(wname, box, procs):
+    """The FP64 C oracle, as it stands, timed on bounded samples of the same
+    workload: one process (one core), then `procs` processes at once on
+    independent sub-boxes (all cores, aggregate rate)."""
+    import multiprocessing as mp
+    os.environ.setdefault("OMP_NUM_THREADS", "1")
+    n1, t1 = _oracle_sample((wname, box, 0))
+    ctx = mp.get_context("spawn")
+    t0 = time.perf_counter()
+    with ctx.Pool(procs) as pool:
+        res = pool.map(_oracle_sample, [(wname, box, k + 1) for k in range(procs)])
+    tall = time.perf_counter() - t0
+    nall = sum(r[0] for r in res)
+    return {"value": nall / tall, "unit": "particle-steps/s", "cores": procs, "kind": "oracle",
+            "sample": f"1 full FP64 oracle step (deposit, comoving current, GMRES to 1e-8, B/E update, push) of "
+                      f"a periodic {box}^3-cell sub-box with the workload's recipe ({n1} particles), one per "
+                      f"process, {procs} processes at once ({tall:.1f} s wall); single-threaded C oracle, gcc -O2",
+            "single_core": {"value": n1 / t1, "seconds": round(t1, 2), "particles": n1},
+            "nproc": os.cpu_count(), "cpu_model": cpu_model()}
+
+
+def make_sim(wl, args, Simulation, torch, synth):
+    sim = Simulation(wl.dim, wl.n, wl.dx, theta=wl.theta, dt=wl.dt, lf_E=wl.lf_E, lf_B=wl.lf_B,
+                     beta_lim=wl.beta_lim, a_mode=wl.a_mode, comoving=wl.comoving, n_smooth_u=wl.n_smooth_u,
+                     fp32=wl.fp32, ns_j=args.ns_j, dedner=args.dedner)
+    counts = []
+    for s in range(wl.nsp):
+        p = synth.particles(wl, s, f32=wl.fp32)
+        t = {k: torch.from_numpy(v).cuda() for k, v in p.items()}
+        del p
+        sim.add_species(wl.q[s], wl.m[s], t["cell"], t["off"], t["v"], t["w"])
+        counts.append(int(t["cell"].numel()))
+        del t
+        torch.cuda.synchronize()
+    E, B = synth.fields(wl)
+    sim.set_fields(torch.from_numpy(E).cuda(), torch.from_numpy(B).cuda())
+    torch.cuda.synchronize()
+    return sim, counts
+
+
+def cnn_flops_per_node():
+    """FLOPs of one application of the 3 -> 32 -> 32 -> 3 network of 3x3x3
+    convolutions per grid node (2 per multiply-add)."""
+    return 2 * 27 * (3 * 32 + 32 * 32 + 32 * 3)
+
+
+def nn_compare(wl, args, Simulation, torch, synth):
+    """Learned preconditioner from a fresh load of the initial state: harvest
+    (residual, correction) pairs from plain solves, train on the GPU, then
+    solve each of the next steps both ways from the same state (plain GMRES,
+    then CNN-preconditioned FGMRES, both to the same true residual) and push
+    with the second answer."""
     from paper_2506_11320_amd import GE_HARVEST_KRYLOV, GE_HARVEST_SOLUTION, GE_PC_CNN
-    sim.cnn_init(1, max_pairs=args.nn_pairs)
-    sim.cnn_harvest({"solution": GE_HARVEST_SOLUTION, "krylov": GE_HARVEST_KRYLOV,
-                     "both": GE_HARVEST_SOLUTION | GE_HARVEST_KRYLOV}[args.nn_data])
-    for k in range(args.nn_harvest):
-        r = sim.step(tol=args.tol, maxit=500, restart=30, precond=0)
-        log(f"harvest step {k}: {r['iterations']} iterations")
-    sim.cnn_harvest(0)
-    tr = sim.cnn_train(crop=args.nn_crop, batch=args.nn_batch, iters=args.nn_iters, lr=args.nn_lr, seed=7)
-    log(f"trained: {tr}")
-    res = {"plain": [], "nn": []}
-    for k in range(args.nn_eval):
-        sim.deposit()
-        rp = sim.solve(tol=args.tol, maxit=500, restart=30, precond=0)
-        rc = sim.solve(tol=args.tol, maxit=500, restart=30, precond=GE_PC_CNN)
-        if not (rp["converged"] and rc["converged"]):
-            log(f"eval step {k}: not converged (plain {rp['relres']:.2e}, nn {rc['relres']:.2e})")
-        res["plain"].append((rp["seconds"], rp["iterations"]))
-        res["nn"].append((rc["seconds"], rc["iterations"], rc["fallback"], rc["relres"]))
-        log(f"eval step {k}: plain {rp['iterations']} it {rp['seconds'] * 1e3:.2f} ms, "
-            f"nn {rc['iterations']} it {rc['seconds'] * 1e3:.2f} ms (relres {rc['relres']:.2e})")
-        sim.push()
-        sim.update_fields()
-    sim.sync()
+    sim, _ = make_sim(wl, args, Simulation, torch, synth)
+    try:
+        sim.cnn_init(1, max_pairs=args.nn_pairs)
+        sim.cnn_harvest({"solution": GE_HARVEST_SOLUTION, "krylov": GE_HARVEST_KRYLOV,
+                         "both": GE_HARVEST_SOLUTION | GE_HARVEST_KRYLOV}[args.nn_data])
+        for k in range(args.nn_harvest):
+            r = sim.step(tol=args.tol, maxit=500, restart=30, precond=0)
+            log(f"harvest step {k}: {r['iterations']} iterations")
+        sim.cnn_harvest(0)
+        tr = sim.cnn_train(crop=args.nn_crop, batch=args.nn_batch, iters=args.nn_iters, lr=args.nn_lr, seed=7)
+        log(f"trained: {tr}")
+        # one application of the network alone (event-timed), for its MFMA rate
+        r0 = torch.randn((3, sim.N), dtype=torch.float64, device=sim.device)
+        sim.cnn_apply(r0)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(sim.stream)
+        for _ in range(5):
+            sim.cnn_apply(r0)
+        ev1.record(sim.stream)
+        ev1.synchronize()
+        app_s = ev0.elapsed_time(ev1) / 5 * 1e-3
+        res = {"plain": [], "nn": []}
+        for k in range(args.nn_eval):
+            sim.deposit()
+            rp = sim.solve(tol=args.tol, maxit=500, restart=30, precond=0)
+            rc = sim.solve(tol=args.tol, maxit=500, restart=30, precond=GE_PC_CNN)
+            if not (rp["converged"] and rc["converged"]):
+                raise RuntimeError(f"eval step {k}: not converged (plain {rp['relres']:.2e}, nn {rc['relres']:.2e})")
+            res["plain"].append((rp["seconds"], rp["iterations"], rp["relres"]))
+            res["nn"].append((rc["seconds"], rc["iterations"], rc["fallback"], rc["relres"]))
+            log(f"eval step {k}: plain {rp['iterations']} it {rp['seconds'] * 1e3:.2f} ms, "
+                f"nn {rc['iterations']} it {rc['seconds'] * 1e3:.2f} ms (relres {rc['relres']:.2e})")
+            sim.push()
+            sim.update_fields()
+        sim.sync()
+    finally:
+        sim.close()
+    flops = cnn_flops_per_node() * wl.ncells
     return {
         "plain": {"seconds": float(np.mean([a[0] for a in res["plain"]])),
-                  "iterations": float(np.mean([a[1] for a in res["plain"]]))},
+                  "iterations": float(np.mean([a[1] for a in res["plain"]])),
+                  "max_relres": float(max(a[2] for a in res["plain"]))},
         "nn": {"seconds": float(np.mean([a[0] for a in res["nn"]])),
                "iterations": float(np.mean([a[1] for a in res["nn"]])),
                "fallbacks": int(sum(a[2] for a in res["nn"])),
                "max_relres": float(max(a[3] for a in res["nn"]))},
+        "speedup": float(np.mean([a[0] for a in res["plain"]]) / np.mean([a[0] for a in res["nn"]])),
+        "cnn_apply": {"ms": round(app_s * 1e3, 4), "flop": flops,
+                      "tflops": round(flops / app_s / 1e12, 1),
+                      "mfma_utilisation": round(flops / app_s / 1e12 / BF16_PEAK_TFLOPS, 4),
+                      "peak_tflops": BF16_PEAK_TFLOPS, "dtype": "bf16 operands, fp32 accumulation"},
         "train": {"pairs": tr["pairs"], "data": args.nn_data, "steps": tr["steps"], "crop": args.nn_crop,
                   "batch": args.nn_batch, "lr": args.nn_lr,
                   "loss_first": tr["loss_first"], "loss_last": tr["loss_last"], "seconds": tr["seconds"]},
-        "eval_steps": args.nn_eval,
+        "harvest_steps": args.nn_harvest, "eval_steps": args.nn_eval,
     }
 
 
@@ -153,6 +245,8 @@ def main():
                     help="particle precision: the workload's own, or forced")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-box", type=int, default=24, help="edge of the oracle's sub-box in cells")
+    ap.add_argument("--cpu-procs", type=int, default=0, help="oracle processes for the all-core rate (0: min(16, nproc))")
     ap.add_argument("--compare-precond", action="store_true", help="also time a Jacobi-preconditioned solve")
     ap.add_argument("--no-nn", action="store_true", help="skip the learned-preconditioner comparison")
     ap.add_argument("--nn-harvest", type=int, default=8, help="plain solves whose (residual, correction) pairs train")
@@ -195,29 +289,15 @@ def main():
     if args.precision != "workload":
         wl = wl.replace(fp32=args.precision == "fp32")
     log(f"workload {wl.name}: cells {wl.n[:wl.dim]}, ppc {wl.ppc}, species {wl.nsp}")
-    sim = Simulation(wl.dim, wl.n, wl.dx, theta=wl.theta, dt=wl.dt, lf_E=wl.lf_E, lf_B=wl.lf_B,
-                     beta_lim=wl.beta_lim, a_mode=wl.a_mode, comoving=wl.comoving, n_smooth_u=wl.n_smooth_u,
-                     fp32=wl.fp32, ns_j=args.ns_j, dedner=args.dedner)
-    counts = []
     t0 = time.perf_counter()
-    for s in range(wl.nsp):
-        p = synth.particles(wl, s, f32=wl.fp32)
-        t = {k: torch.from_numpy(v).cuda() for k, v in p.items()}
-        del p
-        sim.add_species(wl.q[s], wl.m[s], t["cell"], t["off"], t["v"], t["w"])
-        counts.append(int(t["cell"].numel()))
-        del t
-        torch.cuda.synchronize()
-        log(f"species {s} loaded ({counts[-1]} particles)")
-    E, B = synth.fields(wl)
-    sim.set_fields(torch.from_numpy(E).cuda(), torch.from_numpy(B).cuda())
-    torch.cuda.synchronize()
-    log(f"setup {time.perf_counter() - t0:.1f} s")
+    sim, counts = make_sim(wl, args, Simulation, torch, synth)
+    log(f"setup {time.perf_counter() - t0:.1f} s ({sum(counts)} particles)")
     pc = {"none": 0, "jacobi": 1}[args.precond]
     for k in range(args.warmup):
         r = sim.step(tol=args.tol, maxit=500, restart=30, precond=pc)
         log(f"warmup step {k}: {r['iterations']} GMRES iterations, relres {r['relres']:.2e}")
     sim.timings()  # reset the per-phase accumulators
+    sim.moves()
     iters = []
     solve_s = []
     torch.cuda.synchronize()
@@ -231,23 +311,26 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     tm = sim.timings()
-    log(f"timed {args.steps} steps in {elapsed:.3f} s")
+    moves = sim.moves()
+    diag = sim.diagnostics()
+    log(f"timed {args.steps} steps in {elapsed:.3f} s; moves {moves}")
     npart = sum(counts)
     ms_step = elapsed / args.steps * 1e3
     phase = {"push_rebin": tm[0] * 1e3, "deposit": tm[1] * 1e3, "assemble": tm[2] * 1e3, "grid_rest": tm[3] * 1e3,
              "update": tm[4] * 1e3, "solve": tm[5] * 1e3}
-    pd_s = tm[0] + tm[1]
-    ab = algorithmic_bytes(wl, wl.nsp, counts)
-    dom = "deposit" if tm[1] >= tm[0] else "push"
-    dom_t = tm[1] if dom == "deposit" else tm[0]
-    achieved = ab[dom] / dom_t / 1e9
+    pd_s = tm[0] + tm[1] + tm[2]
+    ab = algorithmic_bytes(wl, wl.nsp, npart)
     tname = f"{'float' if wl.fp32 else 'double'},{wl.dim}"
-    roof = {"bound": "hbm", "kernel": f"k_deposit<{tname}>" if dom == "deposit" else f"k_push<{tname}> (x2 species)",
+    achieved = ab["deposit"] / tm[1] / 1e9
+    roof = {"bound": "hbm", "kernel": f"k_deposit<{tname}>",
             "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": measured_traffic("paper_2506_11320_amd/csrc/ge_particles.hip", "profiles/c5_deposit_traffic.json")
-            if (dom == "deposit" and args.workload == "c5" and wl.fp32) else None,
-            "algorithmic_bytes_per_launch": ab[dom], "launch_ms": round(dom_t * 1e3, 4)}
+            if (args.workload == "c5" and wl.fp32) else None,
+            "algorithmic_bytes_per_launch": ab["deposit"], "launch_ms": round(tm[1] * 1e3, 4),
+            "algorithmic_bytes_per_unit": {"particle": ab["per_particle"], "node": ab["per_node_deposit"]}}
+    if roof["traffic"]:
+        roof["traffic_over_algorithmic"] = round(roof["traffic"] / ab["deposit"], 3)
     precond_cmp = None
     if args.compare_precond:
         pcs = {}
@@ -256,9 +339,6 @@ def main():
             rep = sim.solve(tol=args.tol, maxit=500, restart=30, precond=code)
             pcs[name] = {"seconds": rep["seconds"], "iterations": rep["iterations"]}
         precond_cmp = pcs
-    nn = None
-    if not args.no_nn and wl.dim == 3:
-        nn = nn_compare(sim, args)
     expl = None
     if args.explicit_current > 0:
         sim.explicit_current()
@@ -269,31 +349,9 @@ def main():
         ev1.record(sim.stream)
         ev1.synchronize()
         expl = {"calls": args.explicit_current, "ms_per_call": round(ev0.elapsed_time(ev1) / args.explicit_current, 3)}
-    expl_step = None
-    if args.explicit_steps > 0:
-        sim.close()
-        sim = Simulation(wl.dim, wl.n, wl.dx, theta=wl.theta, dt=0.25, lf_E=False, lf_B=False, beta_lim=wl.beta_lim,
-                         a_mode=wl.a_mode, comoving=wl.comoving, n_smooth_u=wl.n_smooth_u, fp32=wl.fp32,
-                         ns_j=args.ns_j)
-        for s in range(wl.nsp):
-            p = synth.particles(wl, s, f32=wl.fp32)
-            t = {k: torch.from_numpy(v).cuda() for k, v in p.items()}
-            del p
-            sim.add_species(wl.q[s], wl.m[s], t["cell"], t["off"], t["v"], t["w"])
-            del t
-            torch.cuda.synchronize()
-        sim.set_fields(torch.from_numpy(E).cuda(), torch.from_numpy(B).cuda())
-        sim.explicit_step()
-        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        ev0.record(sim.stream)
-        for _ in range(args.explicit_steps):
-            sim.explicit_step()
-        ev1.record(sim.stream)
-        ev1.synchronize()
-        ms = ev0.elapsed_time(ev1) / args.explicit_steps
-        expl_step = {"steps": args.explicit_steps, "dt": 0.25, "ms_per_step": round(ms, 3),
-                     "particle_steps_per_s": npart / (ms * 1e-3)}
-        log(f"explicit step: {ms:.3f} ms")
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
     out = {
         "metric": METRIC,
         "value": npart * args.steps / elapsed,
@@ -315,31 +373,81 @@ def main():
                                f"{'limited LF' if wl.lf_E or wl.lf_B else 'no LF'}",
                    "cells": wl.ncells, "particles": npart, "precond": args.precond, "ns_j": args.ns_j,
                    "dedner": bool(args.dedner)},
+        # the metric's first quantity: particle-steps per second of the
+        # particle phases alone (push with re-binning, deposit, node assembly)
         "push_deposit_particle_steps_per_s": npart / pd_s,
-        "gmres_s_per_step": {"plain" if pc == 0 else args.precond: float(np.mean(solve_s)),
-                             "nn": nn["nn"]["seconds"] if nn else None},
-        "nn_precond": nn,
+        "gmres_s_per_step": {"plain" if pc == 0 else args.precond: float(np.mean(solve_s)), "nn": None},
         "gmres_iterations": float(np.mean(iters)),
         "phase_ms": {k: round(v, 3) for k, v in phase.items()},
+        "moves": moves,
+        "energy_after": {"W_E": diag["W_E"], "W_B": diag["W_B"], "K": diag["K"]},
         "precond_compare": precond_cmp,
         "explicit_current": expl,
-        "explicit_step": expl_step,
         "roofline": roof,
-        # the other particle phase against the same peak: algorithmic bytes of
-        # both species' push over the phase's event-timed duration (the
-        # re-binning count and scan kernels included)
-        "push_roofline": {"bound": "hbm", "kernel": f"k_push<{tname}> (x{wl.nsp} species) + re-binning scans",
+        # the push phase and the whole particle pass against the same peak,
+        # with the algorithmic bytes of algorithmic_bytes()
+        "push_roofline": {"bound": "hbm", "kernel": f"k_push<{tname}> (x{wl.nsp} species) + segment scans",
                           "achieved": round(ab["push"] / tm[0] / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                           "frac": round(ab["push"] / tm[0] / 1e9 / HBM_PEAK_GBS, 4),
                           "algorithmic_bytes": ab["push"], "phase_ms": round(tm[0] * 1e3, 4)},
+        "particle_pass_roofline": {"bound": "hbm", "phases": "push + deposit + node assembly",
+                                   "achieved": round(ab["step"] / pd_s / 1e9, 1), "peak": HBM_PEAK_GBS,
+                                   "unit": "GB/s", "frac": round(ab["step"] / pd_s / 1e9 / HBM_PEAK_GBS, 4),
+                                   "algorithmic_bytes": ab["step"], "ms": round(pd_s * 1e3, 4)},
+        "nn_precond": None,
+        "explicit_step": None,
+        "cpu_baseline": None,
     }
-    sim.close()
+    errors = {}
+    if not args.no_nn and wl.dim == 3:
+        try:
+            nn = nn_compare(wl, args, Simulation, torch, synth)
+            out["nn_precond"] = nn
+            out["gmres_s_per_step"]["nn"] = nn["nn"]["seconds"]
+        except Exception as ex:  # recorded; the exit status reports it
+            errors["nn_precond"] = f"{type(ex).__name__}: {ex}"
+            log(f"nn leg failed: {errors['nn_precond']}")
+        torch.cuda.empty_cache()
+    if args.explicit_steps > 0:
+        try:
+            sim = Simulation(wl.dim, wl.n, wl.dx, theta=wl.theta, dt=0.25, lf_E=False, lf_B=False,
+                             beta_lim=wl.beta_lim, a_mode=wl.a_mode, comoving=wl.comoving,
+                             n_smooth_u=wl.n_smooth_u, fp32=wl.fp32, ns_j=args.ns_j)
+            for s in range(wl.nsp):
+                p = synth.particles(wl, s, f32=wl.fp32)
+                t = {k: torch.from_numpy(v).cuda() for k, v in p.items()}
+                del p
+                sim.add_species(wl.q[s], wl.m[s], t["cell"], t["off"], t["v"], t["w"])
+                del t
+                torch.cuda.synchronize()
+            E, B = synth.fields(wl)
+            sim.set_fields(torch.from_numpy(E).cuda(), torch.from_numpy(B).cuda())
+            sim.explicit_step()
+            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            ev0.record(sim.stream)
+            for _ in range(args.explicit_steps):
+                sim.explicit_step()
+            ev1.record(sim.stream)
+            ev1.synchronize()
+            ms = ev0.elapsed_time(ev1) / args.explicit_steps
+            sim.close()
+            out["explicit_step"] = {"steps": args.explicit_steps, "dt": 0.25, "ms_per_step": round(ms, 3),
+                                    "particle_steps_per_s": npart / (ms * 1e-3)}
+            log(f"explicit step: {ms:.3f} ms")
+        except Exception as ex:
+            errors["explicit_step"] = f"{type(ex).__name__}: {ex}"
     if not args.no_cpu_baseline:
-        log("timing the CPU oracle on a sample")
-        out["cpu_baseline"] = cpu_baseline(wl)
-    else:
-        out["cpu_baseline"] = None
+        log("timing the CPU oracle on samples")
+        try:
+            procs = args.cpu_procs or min(16, os.cpu_count() or 1)
+            out["cpu_baseline"] = cpu_baseline(args.workload if wl.dim == 3 else "c5", args.cpu_box, procs)
+        except Exception as ex:
+            errors["cpu_baseline"] = f"{type(ex).__name__}: {ex}"
+    if errors:
+        out["errors"] = errors
     print(json.dumps(out), flush=True)
+    if errors:
+        sys.exit(1)
 
 
 if __name__ == "__main__":

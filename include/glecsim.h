@@ -48,9 +48,11 @@ enum {
   GE_ERR_ARG = -1,        /* invalid argument or unsupported configuration */
   GE_ERR_OOM = -2,        /* device allocation failed */
   GE_ERR_HIP = -3,        /* a HIP runtime call failed */
-  GE_ERR_CFL = -4,        /* a particle moved one cell or more in a step
-                             (it was clamped to the neighbouring cell) */
-  GE_ERR_NONFINITE = -5,  /* NaN or Inf met in the solve */
+  GE_ERR_CFL = -4,        /* a particle would have moved more than n - 2 cells
+                             along an axis of n cells in one step (it was kept
+                             where it was; the message names the species) */
+  GE_ERR_NONFINITE = -5,  /* NaN or Inf met in the solve, or a non-finite
+                             particle velocity or position after a push */
   GE_ERR_STATE = -6,      /* call out of order (e.g. push before a solve) */
   GE_WARN_NOT_CONVERGED = 1 /* GMRES hit maxit; best iterate kept */
 };
@@ -178,8 +180,16 @@ int ge_solve_fields(ge_ctx* ctx, double tol, int maxit, int restart, int precond
 
 /* Implicit mover (Sec. 3.1) with E^{n+theta} from the last solve and the
  * node-averaged B^n of the last deposit, then the stable re-binning of every
- * species by cell.  Asynchronous; a CFL violation is reported by the next
- * synchronising call (GE_ERR_CFL). */
+ * species by cell.  A particle may move up to n - 2 cells along an axis of n
+ * cells (its new position relative to its old cell in [-(n - 2), n - 1) cells;
+ * further, the periodic wrap could bring it back next to its old cell):
+ * moves of at most one cell are re-binned inside the push; if any
+ * particle moved further, the next call that reads the particles (ge_deposit,
+ * ge_push, ge_get_particles, ge_diagnostics, ge_sync, ge_step's own end, ...)
+ * synchronises once and runs a stable re-sort of that species, so that the
+ * order is always the stable sort by cell of the previous order.
+ * Asynchronous; GE_ERR_CFL (a longer move: the particle is kept in place) and
+ * GE_ERR_NONFINITE are reported by that next call. */
 int ge_push(ge_ctx* ctx);
 
 /* B^{n+1} = B^n - c dt curl E^{n+theta} + dt D_B(B^n) and
@@ -217,9 +227,23 @@ int ge_explicit_current(ge_ctx* ctx, double* J);
  * ge_sync if a particle moved a cell or more. */
 int ge_explicit_step(ge_ctx* ctx);
 
-/* Wait for the stream; returns GE_ERR_CFL if a push clamped a particle since
- * the last check, else GE_OK. */
+/* Wait for the stream and settle the last push (see ge_push); returns
+ * GE_ERR_CFL or GE_ERR_NONFINITE if a push kept a particle in place since the
+ * last check, else GE_OK. */
 int ge_sync(ge_ctx* ctx);
+
+/* Particle moves since the last call (host struct), per species: particles
+ * that moved more than one cell along some axis in one push, and the largest
+ * move in cells (max over pushes and axes of |v_d| dt / dx_d); then the stable
+ * re-sorts those moves needed and the pushes counted.  Synchronises (settles
+ * the last push) and resets the counters. */
+typedef struct {
+  int64_t far_moves[4];
+  double max_move[4];
+  int resorts;
+  int pushes;
+} ge_move_report;
+int ge_moves(ge_ctx* ctx, ge_move_report* out);
 
 /* ------------------------------------------------------- inputs and outputs */
 
@@ -274,7 +298,9 @@ int ge_diagnostics(ge_ctx* ctx, ge_diag* out);
 
 /* Mean seconds per ge_step() since the last call, from HIP events recorded on
  * the context's stream around each kernel group; host array of 8:
- *   [0] push + re-binning kernels (all species)   [1] deposit kernel
+ *   [0] push + re-binning kernels (all species: corner-field packing,
+ *       segment scans, pushes; a re-sort of far movers is not included)
+ *                                                 [1] deposit kernel
  *   [2] node assembly kernel                      [3] rest of the grid pass
  *   [4] field update kernels                      [5] solve (host wall time)
  *   [6] 0                                         [7] number of steps averaged

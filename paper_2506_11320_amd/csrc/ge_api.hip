@@ -30,16 +30,53 @@ void dfree(P*& p) {
   p = nullptr;
 }
 
+// Read the flag block (synchronises): the errors raised since the last read,
+// and the statistics of a push that has not been settled yet.  Far movers of
+// that push are re-sorted here, before anything reads the particles again.
 int check_flags(ge_ctx* c) {
-  int h[4] = {0, 0, 0, 0};
+  int h[GE_FL_COUNT];
+  if (c->push_pending)
+    for (int s = 0; s < c->nsp; ++s) {
+      int rc = ge_launch_move_max(c, s);
+      if (rc) return rc;
+    }
   GE_HIP(c, hipMemcpyAsync(h, c->flags, sizeof(h), hipMemcpyDeviceToHost, c->stream));
   GE_HIP(c, hipStreamSynchronize(c->stream));
-  if (h[0] || h[1] || h[2]) GE_HIP(c, hipMemsetAsync(c->flags, 0, sizeof(int) * 4, c->stream));
-  if (h[1]) return ge_fail(c, GE_ERR_STATE, "internal: particle run bookkeeping mismatch in the push");
-  if (h[2]) return ge_fail(c, GE_ERR_ARG, "particles not sorted by cell or cell index out of range");
-  if (h[0]) return ge_fail(c, GE_ERR_CFL, "a particle moved one cell or more in one step (clamped)");
+  bool any = false;
+  for (int k = 0; k < GE_FL_COUNT; ++k) any = any || h[k] != 0;
+  if (any) GE_HIP(c, hipMemsetAsync(c->flags, 0, sizeof(h), c->stream));
+  std::string stuck;
+  if (c->push_pending) {
+    c->push_pending = 0;
+    c->moves.pushes += 1;
+    for (int s = 0; s < c->nsp; ++s) {
+      const int* st = h + GE_FL_SPECIES + 4 * s;
+      float mv;
+      std::memcpy(&mv, &st[1], sizeof(mv));
+      c->moves.far[s] += st[0];
+      if (mv > c->moves.maxmove[s]) c->moves.maxmove[s] = mv;
+      if (st[0] > 0) {
+        int rc = ge_launch_far_resort(c, s, st[0]);
+        if (rc) return rc;
+        c->moves.resorts += 1;
+      }
+      if (st[2] > 0)
+        stuck += " species " + std::to_string(s) + ": " + std::to_string(st[2]) + " particle(s), largest accepted move " +
+                 std::to_string(mv) + " cells;";
+    }
+  }
+  if (h[GE_FL_RUNS]) return ge_fail(c, GE_ERR_STATE, "internal: particle run bookkeeping mismatch in the push");
+  if (h[GE_FL_LOAD]) return ge_fail(c, GE_ERR_ARG, "particles not sorted by cell or cell index out of range");
+  if (h[GE_FL_NONFINITE])
+    return ge_fail(c, GE_ERR_NONFINITE, "a pushed particle had a non-finite velocity or position and was kept in place:" + stuck);
+  if (h[GE_FL_CFL])
+    return ge_fail(c, GE_ERR_CFL, "a particle would have moved more than n - 2 cells along an axis of n cells in one "
+                                  "step and was kept in place:" + stuck);
   return GE_OK;
 }
+
+// Settle a pending push (its far movers) before particles are read again.
+int settle(ge_ctx* c) { return c->push_pending ? check_flags(c) : GE_OK; }
 
 // add the elapsed time of the event pairs of the last step (stream idle)
 void accumulate_timings(ge_ctx* c, double solve_s) {
@@ -153,7 +190,7 @@ int ge_create(const ge_grid* grid, const ge_params* params, void* hip_stream, ge
     rc = ge_fail(c, GE_ERR_OOM, "pinned host buffer allocation failed");
   }
   if (!rc) rc = dalloc(c, &c->partials, sizeof(double) * 16 * 512);  // 16 dots x 512 blocks
-  if (!rc) rc = dalloc(c, &c->flags, sizeof(int) * 4);
+  if (!rc) rc = dalloc(c, &c->flags, sizeof(int) * GE_FL_COUNT);
   if (rc) {
     g_create_err = "ge_create: " + c->err;
     ge_destroy(c);
@@ -166,7 +203,7 @@ int ge_create(const ge_grid* grid, const ge_params* params, void* hip_stream, ge
   (void)hipMemsetAsync(c->kB, 0, sizeof(double) * 9 * N, s);
   (void)hipMemsetAsync(c->rho, 0, sizeof(double) * GE_MAX_SPECIES * N, s);
   (void)hipMemsetAsync(c->psi, 0, sizeof(double) * N, s);
-  (void)hipMemsetAsync(c->flags, 0, sizeof(int) * 4, s);
+  (void)hipMemsetAsync(c->flags, 0, sizeof(int) * GE_FL_COUNT, s);
   for (int k = 0; k < 10; ++k) (void)hipEventCreate(&c->ev[k]);
   for (int k = 0; k < 8; ++k) c->tsum[k] = 0;
   c->tcnt = 0;
@@ -194,11 +231,14 @@ void ge_destroy(ge_ctx* c) {
   dfree(c->seg_next);
   dfree(c->scan_blocks);
   dfree(c->flags);
-  for (int s = 0; s < c->nsp; ++s)
+  for (int s = 0; s < c->nsp; ++s) {
     for (int b = 0; b < 2; ++b) {
       dfree(c->sp[s].rec[b]);
       dfree(c->sp[s].runs[b]);
     }
+    dfree(c->sp[s].far);
+  }
+  ge_far_free(c);
   for (int k = 0; k < 10; ++k)
     if (c->ev[k]) (void)hipEventDestroy(c->ev[k]);
   ge_cnn_free(c);
@@ -227,11 +267,13 @@ int ge_add_species(ge_ctx* c, const ge_species* sp, int64_t n, const int32_t* ce
     rc = dalloc(c, &S.rec[b], es * GE_REC * (n > 0 ? n : 1));  // a valid record 0 even when empty
     if (!rc) rc = dalloc(c, &S.runs[b], sizeof(int32_t) * 2 * c->ND * c->G.N);
   }
+  if (!rc) rc = dalloc(c, &S.far, sizeof(int32_t) * 4 * c->G.N);
   c->nsp = s + 1;  // so that ge_destroy frees partial allocations
   if (rc) {
     for (int b = 0; b < 2; ++b) {
       dfree(S.rec[b]); dfree(S.runs[b]);
     }
+    dfree(S.far);
     c->nsp = s;
     return rc;
   }
@@ -242,6 +284,7 @@ int ge_add_species(ge_ctx* c, const ge_species* sp, int64_t n, const int32_t* ce
     for (int b = 0; b < 2; ++b) {
       dfree(S.rec[b]); dfree(S.runs[b]);
     }
+    dfree(S.far);
     c->nsp = s;
     return rc;
   }
@@ -259,7 +302,8 @@ int ge_set_fields(ge_ctx* c, const double* E, const double* B) {
 int ge_deposit(ge_ctx* c) {
   if (!c) return GE_ERR_ARG;
   if (c->nsp == 0) return ge_fail(c, GE_ERR_STATE, "no species");
-  int rc;
+  int rc = settle(c);
+  if (rc) return rc;
   if ((rc = ge_launch_node_avg(c))) return rc;
   (void)hipEventRecord(c->ev[2], c->stream);
   if ((rc = ge_launch_deposit(c))) return rc;
@@ -273,7 +317,8 @@ int ge_deposit(ge_ctx* c) {
 int ge_explicit_current(ge_ctx* c, double* J) {
   if (!c) return GE_ERR_ARG;
   if (c->nsp == 0) return ge_fail(c, GE_ERR_STATE, "no species");
-  int rc;
+  int rc = settle(c);
+  if (rc) return rc;
   // moments -> smoothed bulk velocity -> current, then the ns_j passes
   if ((rc = ge_launch_explicit_linear(c, 0))) return rc;
   if ((rc = ge_launch_bulk_velocity(c))) return rc;
@@ -288,7 +333,8 @@ int ge_explicit_current(ge_ctx* c, double* J) {
 int ge_explicit_step(ge_ctx* c) {
   if (!c) return GE_ERR_ARG;
   if (c->nsp == 0) return ge_fail(c, GE_ERR_STATE, "no species");
-  int rc;
+  int rc = settle(c);
+  if (rc) return rc;
   // corner fields of the push: E^n (through c->Eth) and the node average of B^n
   GE_HIP(c, hipMemcpyAsync(c->Eth, c->E, sizeof(double) * 3 * c->G.N, hipMemcpyDeviceToDevice, c->stream));
   if ((rc = ge_launch_node_avg(c))) return rc;
@@ -297,6 +343,9 @@ int ge_explicit_step(ge_ctx* c) {
     if ((rc = ge_launch_scan_counts(c, s))) return rc;
   for (int s = 0; s < c->nsp; ++s)
     if ((rc = ge_launch_push(c, s))) return rc;
+  // far movers are re-sorted before the current passes read the cells
+  c->push_pending = 1;
+  if ((rc = check_flags(c))) return rc;
   // the current at (x^{n+1}, v^{n+1/2}), then the leapfrog
   if ((rc = ge_launch_explicit_linear(c, 0))) return rc;
   if ((rc = ge_launch_bulk_velocity(c))) return rc;
@@ -347,14 +396,17 @@ int ge_solve_fields(ge_ctx* c, double tol, int maxit, int restart, int precond, 
 int ge_push(ge_ctx* c) {
   if (!c) return GE_ERR_ARG;
   if (!c->have_solve) return ge_fail(c, GE_ERR_STATE, "ge_push needs E^{n+theta} (solve or ge_set GE_F_ETH)");
-  int rc;
+  int rc = settle(c);
+  if (rc) return rc;
+  // timed phase [0]: packing of the corner fields, the segment scans and the pushes
+  (void)hipEventRecord(c->ev[0], c->stream);
   if ((rc = ge_launch_pack_node8(c, 0))) return rc;
   for (int s = 0; s < c->nsp; ++s)
     if ((rc = ge_launch_scan_counts(c, s))) return rc;
-  (void)hipEventRecord(c->ev[0], c->stream);
   for (int s = 0; s < c->nsp; ++s)
     if ((rc = ge_launch_push(c, s))) return rc;
   (void)hipEventRecord(c->ev[1], c->stream);
+  c->push_pending = 1;
   return GE_OK;
 }
 
@@ -440,6 +492,8 @@ int ge_set(ge_ctx* c, int what, const double* src) {
 int ge_get_particles(ge_ctx* c, int s, int64_t n, int32_t* cell, void* off, void* v, void* w) {
   if (!c || s < 0 || s >= c->nsp) return GE_ERR_ARG;
   if (n != c->sp[s].n) return ge_fail(c, GE_ERR_ARG, "particle count mismatch");
+  int rc = settle(c);
+  if (rc) return rc;
   if (n == 0) return GE_OK;  // an empty species: nothing to copy, the pointers may be null
   if (!cell || !off || !v || !w) return ge_fail(c, GE_ERR_ARG, "null output");
   return ge_launch_get_particles(c, s, cell, off, v, w);
@@ -455,7 +509,9 @@ int ge_diagnostics(ge_ctx* c, ge_diag* out) {
   std::memset(out, 0, sizeof(*out));
   out->nsp = c->nsp;
   double f[4];
-  int rc = ge_launch_field_diag(c, f);
+  int rc = settle(c);
+  if (rc) return rc;
+  rc = ge_launch_field_diag(c, f);
   if (rc) return rc;
   const double k8 = c->G.dV / (8.0 * M_PI);
   out->W_E = f[0] * k8;
@@ -468,6 +524,20 @@ int ge_diagnostics(ge_ctx* c, ge_diag* out) {
     for (int d = 0; d < 3; ++d) out->P[s][d] = c->sp[s].m * m4[1 + d];
   }
   return check_flags(c);
+}
+
+int ge_moves(ge_ctx* c, ge_move_report* out) {
+  if (!c || !out) return GE_ERR_ARG;
+  int rc = settle(c);
+  std::memset(out, 0, sizeof(*out));
+  for (int s = 0; s < c->nsp; ++s) {
+    out->far_moves[s] = c->moves.far[s];
+    out->max_move[s] = c->moves.maxmove[s];
+  }
+  out->resorts = c->moves.resorts;
+  out->pushes = c->moves.pushes;
+  std::memset(&c->moves, 0, sizeof(c->moves));
+  return rc;
 }
 
 int ge_timings(ge_ctx* c, double* out8) {

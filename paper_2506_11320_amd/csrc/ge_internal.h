@@ -131,12 +131,43 @@ struct HalfStencil<3> {
 // values per particle record: offset in the cell (3), weight, velocity (3)
 constexpr int GE_REC = 7;
 
+// Direction code of a particle that moved more than one cell along some axis
+// in one push (the 27 codes below it are the moves d in {-1,0,1}^3).
+constexpr int GE_DIR_FAR = 27;
+
 struct SpeciesBuf {
   double q, m, beta;     // beta = q dt / (2 m)
   int64_t n;
   void* rec[2];          // T[max(n,1)][GE_REC]: offset in the cell (3), w, velocity (3)
   int32_t* runs[2];      // [Ncell][ND][2]: (start, count) of the run entering cell c by move d
+  int32_t* far;          // [Ncell][4]: (start, count) of the far movers of home cell h (last push),
+                         // the largest move in the cell (float bits), 0
   int cur;
+};
+
+// Device flag block (int32): the errors, then per species the push statistics
+// that the host reads back after a push.
+enum {
+  GE_FL_CFL = 0,       // a particle moved the whole domain length or more (kept in place)
+  GE_FL_RUNS = 1,      // internal run bookkeeping mismatch
+  GE_FL_LOAD = 2,      // unsorted or out-of-range cell index at load
+  GE_FL_NONFINITE = 3, // a non-finite position after the push (kept in place)
+  GE_FL_SPECIES = 4,   // + 4 s: [0] far movers, [1] largest move in cells (float bits), [2] particles kept in place
+  GE_FL_COUNT = 4 + 4 * GE_MAX_SPECIES
+};
+
+// Host-side record of the moves since the last ge_moves() call.
+struct MoveStats {
+  int64_t far[GE_MAX_SPECIES];
+  double maxmove[GE_MAX_SPECIES];
+  int resorts, pushes;
+};
+
+// Scratch of the re-sort of far movers (allocated on first use).
+struct FarScratch {
+  int64_t cap;                  // entries of the far lists
+  int32_t *dest, *pos, *sorted; // [cap]: far list (destination, buffer position), positions sorted by destination
+  int32_t *pos_h, *cnt_in, *start_in, *fill, *newstart;  // [N] each
 };
 
 struct ge_ctx {
@@ -166,8 +197,11 @@ struct ge_ctx {
   double *V, *Zp, *kw, *kr, *kx, *hdev, *partials, *scal;
   double* hhost;  // pinned host copy of hdev (per-iteration read-backs of the solve)
   int64_t nred_blocks;
-  int* flags;            // [0] CFL clamp, [1] run overflow, [2] load error
+  int* flags;            // GE_FL_COUNT ints (see GE_FL_*)
   int have_deposit, have_solve;
+  int push_pending;      // a push ran whose statistics (and far movers) are not settled yet
+  MoveStats moves;
+  FarScratch fx;
   void* cnn;           // learned preconditioner state (ge_cnn.hip), lazily created
   double* Zb;          // flexible-GMRES basis of preconditioned vectors (lazily allocated)
   hipEvent_t ev[10];   // pairs: push, deposit, assemble, grid rest, update
@@ -187,6 +221,9 @@ int ge_fail(ge_ctx* c, int code, const std::string& msg);
 int ge_launch_load_species(ge_ctx* c, int s, const int32_t* cell, const void* off, const void* v, const void* w);
 int ge_launch_scan_counts(ge_ctx* c, int s);  // into seg_next + s*N
 int ge_launch_push(ge_ctx* c, int s);          // needs ge_launch_scan_counts(c, s) first
+int ge_launch_far_resort(ge_ctx* c, int s, int64_t nfar);  // stable re-sort after far moves (push of s done)
+int ge_launch_move_max(ge_ctx* c, int s);  // largest move of the last push into the flag block
+void ge_far_free(ge_ctx* c);
 int ge_launch_deposit(ge_ctx* c);
 int ge_launch_get_particles(ge_ctx* c, int s, int32_t* cell, void* off, void* v, void* w);
 int ge_launch_particle_moments(ge_ctx* c, int s, double* out4);  // K, P[3] (sync)

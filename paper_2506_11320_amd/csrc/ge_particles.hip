@@ -191,9 +191,19 @@ __device__ inline void gather_lds(const T W[8], const T* fc, T out[3]) {
 // v^{n+1} = 2 vbar - v^n, x^{n+3/2} = x^{n+1/2} + dt v^{n+1}.  alpha applied
 // as (t + beta t x B + beta^2 (t.B) B) / (1 + beta^2 |B|^2).  fc holds the
 // corner values of E^{n+theta} then of B^n.  Returns the direction code of the
-// cell move; clamps a move of one cell or more.
+// cell move (offsets renormalised to the new cell), or GE_DIR_FAR for a move
+// of more than one cell along some axis, with f then holding the new position
+// relative to the home cell (renormalised by the far re-sort).  Along an axis
+// of n cells a move is accepted while the new position relative to the home
+// cell stays in [-(n - 2), n - 1): beyond that the periodic wrap could land it
+// on a neighbour of its home cell, where it would share the destination of a
+// direction run and the stable order could no longer be rebuilt.  A refused
+// or non-finite move keeps the particle where it was and sets 'stuck' (1: too
+// far, 2: non-finite).  mv: running maximum of the accepted moves in cells
+// along any axis.
 template <typename T, int DIM>
-__device__ inline int push_one(T f[3], T v[3], const T* fc, T beta, const T dtx[3], int& clamped) {
+__device__ inline int push_one(T f[3], T v[3], const T* fc, T beta, const T dtx[3], const T lo[3], const T hi[3],
+                               int& stuck, T& mv) {
   constexpr int NC = Dm<DIM>::NC;
   T W[8];
   lin_weights<T, DIM>(f, W);
@@ -210,16 +220,33 @@ __device__ inline int push_one(T f[3], T v[3], const T* fc, T beta, const T dtx[
   v[0] = (T)2 * vb0 - v[0];
   v[1] = (T)2 * vb1 - v[1];
   v[2] = (T)2 * vb2 - v[2];
+  T sn[3];
+  bool far = false, keep = false;
+  T mloc = 0;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    const T m = v[d] * dtx[d];
+    sn[d] = f[d] + m;
+    if (!(sn[d] >= lo[d] && sn[d] < hi[d])) {  // also catches NaN and Inf
+      keep = true;
+      stuck |= (sn[d] - sn[d] == (T)0) ? 1 : 2;  // finite: too far; NaN or Inf: non-finite
+    }
+    const T am = fabs(m);
+    mloc = am > mloc ? am : mloc;
+    far = far || !(sn[d] >= (T)-1 && sn[d] < (T)2);
+  }
+  if (keep) return DIM == 3 ? 13 : (DIM == 2 ? 4 : 1);  // stays in its cell, offsets unchanged
+  mv = mloc > mv ? mloc : mv;
+  if (far) {
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) f[d] = sn[d];
+    return GE_DIR_FAR;
+  }
   int dir = 0, mul = 1;
 #pragma unroll
   for (int d = 0; d < DIM; ++d) {
-    T s = f[d] + v[d] * dtx[d];
-    if (!(s >= (T)-1 && s < (T)2)) {  // also catches NaN
-      clamped = 1;
-      s = (s != s) ? (T)0.5 : (s < (T)-1 ? (T)-1 : (T)1.5);
-    }
-    T e = floor(s);
-    T fn = s - e;
+    T e = floor(sn[d]);
+    T fn = sn[d] - e;
     if (fn >= (T)1) { fn = 0; e += (T)1; }
     f[d] = fn;
     dir += ((int)e + 1) * mul;
@@ -236,15 +263,18 @@ struct PushArgs {
   const int32_t *runs, *seg_next;
   int32_t* runs_o;
   const T* NF;   // node fields [N][8]: E^{n+theta}, node-averaged B^n
+  int32_t* far_o;  // [N][4]: far movers of each home cell (start, count), largest move (float bits), 0
   T beta;
   T dtx[3];
+  T lo[3], hi[3];  // accepted new positions relative to the home cell: [-(n - 2), n - 1) per axis
   int64_t n;
-  int* flags;
+  int* flags;      // error flags, then this species' statistics at flags + GE_FL_SPECIES + 4 s
+  int* stats;
 };
 
 // Direction statistics of one chunk from five bit-ballots of the direction
-// code (< 27): 'same' is the mask of active lanes sharing this lane's
-// direction; lane k < 27 receives the chunk's count of direction k.
+// code (<= GE_DIR_FAR): 'same' is the mask of active lanes sharing this lane's
+// direction; lane k <= GE_DIR_FAR receives the chunk's count of direction k.
 struct DirStats {
   uint64_t same;
   int count_k;
@@ -263,7 +293,7 @@ __device__ inline DirStats dir_stats(bool act, int dir, int lane) {
   }
   DirStats r;
   r.same = same;
-  r.count_k = lane < 27 ? __popcll(kk) : 0;
+  r.count_k = lane <= GE_DIR_FAR ? __popcll(kk) : 0;
   return r;
 }
 __device__ inline int excl_scan(int x) { return dpp_scan<false, false>(x) - x; }
@@ -342,7 +372,8 @@ __global__ __launch_bounds__(64) void k_push(DGrid G, PushArgs<T> A) {
   int* spr = s_pre;
   const int total = runs_setup<DIM>(G, c, A.runs, sst, spr, lane, nseg);
   const int64_t base = A.seg_next[c];
-  int cnt = 0, dir_off = 0, clamped = 0, bad = 0;
+  int cnt = 0, dir_off = 0, stuck = 0, bad = 0;
+  T mv = 0;
   if (total <= 128) {
     // particle t = lane and t = 64 + lane: run k from a max-scan of run-start
     // markers (k + 1 at position s_pre[k], 0 elsewhere)
@@ -371,8 +402,8 @@ __global__ __launch_bounds__(64) void k_push(DGrid G, PushArgs<T> A) {
     // and does not hold the second store for the first one's completion
     __builtin_amdgcn_s_waitcnt(0xF70);
     int d0 = 31, d1 = 31;
-    if (a0) d0 = push_one<T, DIM>(f0, v0, fc, A.beta, A.dtx, clamped);
-    if (a1) d1 = push_one<T, DIM>(f1, v1, fc, A.beta, A.dtx, clamped);
+    if (a0) d0 = push_one<T, DIM>(f0, v0, fc, A.beta, A.dtx, A.lo, A.hi, stuck, mv);
+    if (a1) d1 = push_one<T, DIM>(f1, v1, fc, A.beta, A.dtx, A.lo, A.hi, stuck, mv);
     const DirStats q0 = dir_stats(a0, d0, lane), q1 = dir_stats(a1, d1, lane);
     cnt = q0.count_k + q1.count_k;
     dir_off = excl_scan(cnt);
@@ -392,7 +423,7 @@ __global__ __launch_bounds__(64) void k_push(DGrid G, PushArgs<T> A) {
         int dir = 31;
         if (act) {
           load_particle<T, DIM>(A, run_index(t, sst, spr, nseg), f, v, w);
-          dir = push_one<T, DIM>(f, v, fc, A.beta, A.dtx, clamped);
+          dir = push_one<T, DIM>(f, v, fc, A.beta, A.dtx, A.lo, A.hi, stuck, mv);
         }
         const DirStats q = dir_stats(act, dir, lane);
         if (pass == 0) {
@@ -409,7 +440,7 @@ __global__ __launch_bounds__(64) void k_push(DGrid G, PushArgs<T> A) {
       }
       if (pass == 0) dir_off = excl_scan(cnt);
     }
-    if (lane < ND && running != cnt) bad = 1;
+    if (lane <= GE_DIR_FAR && running != cnt) bad = 1;
   }
   if (lane < ND) {
     // run (c, lane) is recorded at its destination cell
@@ -418,8 +449,41 @@ __global__ __launch_bounds__(64) void k_push(DGrid G, PushArgs<T> A) {
     const int64_t dst = flat3(G, cx + lane % 3 - 1, DIM >= 2 ? cy + (lane / 3) % 3 - 1 : cy, DIM >= 3 ? cz + lane / 9 - 1 : cz);
     reinterpret_cast<i2*>(A.runs_o)[dst * ND + lane] = i2{(int)(base + dir_off), cnt};
   }
-  if (clamped) atomicOr(&A.flags[0], 1);
-  if (bad) atomicOr(&A.flags[1], 1);
+  // the far movers close the home segment; their run is kept at the home
+  // cell, with the cell's largest move (reduced over the cells afterwards:
+  // one atomic per wave on a single address would serialise the push)
+  const int mvb = dpp_scan<true, false>(__float_as_int((float)mv));  // non-negative floats order as integers
+  const int mvmax = __builtin_amdgcn_readlane(mvb, 63);
+  if (lane == GE_DIR_FAR) {
+    typedef int i4 __attribute__((ext_vector_type(4)));
+    reinterpret_cast<i4*>(A.far_o)[c] = i4{(int)(base + dir_off), cnt, mvmax, 0};
+    if (cnt > 0) atomicAdd(&A.stats[0], cnt);  // rare: far movers only
+  }
+  // refusals are rare too: one atomic per quantity from lane 0
+  const uint64_t sflags = __ballot((stuck & 1) != 0), nflags = __ballot((stuck & 2) != 0);
+  if (lane == 0 && (sflags | nflags)) {
+    atomicAdd(&A.stats[2], __popcll(sflags | nflags));
+    if (sflags) atomicOr(&A.flags[GE_FL_CFL], 1);
+    if (nflags) atomicOr(&A.flags[GE_FL_NONFINITE], 1);
+  }
+  if (bad) atomicOr(&A.flags[GE_FL_RUNS], 1);
+}
+
+// Largest move of a push over the cells (the per-cell maxima the push left
+// with the far runs), into the species' statistics: a block maximum, then
+// one atomic per block.
+__global__ __launch_bounds__(256) void k_move_max(int64_t N, const int32_t* __restrict__ far, int* __restrict__ out) {
+  __shared__ int sh[256];
+  int m = 0;
+  for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < N; c += (int64_t)gridDim.x * blockDim.x)
+    m = max(m, far[4 * c + 2]);
+  sh[threadIdx.x] = m;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sh[threadIdx.x] = max(sh[threadIdx.x], sh[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && sh[0] > 0) atomicMax(out, sh[0]);
 }
 
 // ------------------------------------------------------------------ scan
@@ -925,8 +989,8 @@ __global__ void k_load_bounds(DGrid G, const int32_t* __restrict__ cell, int64_t
   int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (p >= n) return;
   int32_t c = cell[p];
-  if (c < 0 || c >= G.N) { atomicOr(&flags[2], 1); return; }
-  if (p > 0 && cell[p - 1] > c) atomicOr(&flags[2], 1);
+  if (c < 0 || c >= G.N) { atomicOr(&flags[GE_FL_LOAD], 1); return; }
+  if (p > 0 && cell[p - 1] > c) atomicOr(&flags[GE_FL_LOAD], 1);
   if (p == 0 || cell[p - 1] != c) r[c * stride] = (int32_t)p;
   if (p == n - 1 || cell[p + 1] != c) r[c * stride + 1] = (int32_t)(p + 1);
 }
@@ -994,6 +1058,155 @@ __global__ __launch_bounds__(256) void k_particle_moments(const T* __restrict__ 
   if (threadIdx.x < 4) part[threadIdx.x * gridDim.x + blockIdx.x] = sh[threadIdx.x][0];
 }
 
+// ------------------------------------------------------------------ far movers
+// A particle that moved more than one cell along some axis has no run of its
+// own: the push leaves it at the end of its home segment (the far run of the
+// home cell, far[h]) with its position relative to the home cell.  The
+// re-sort below then rebuilds the canonical layout -- every cell's particles
+// contiguous, in the order of a stable sort by cell of the previous order --
+// as one run per cell: the buffer order after the push is (home cell,
+// direction group, previous order), and a destination cell's contributions
+// (its 27 direction runs and its far movers) are ordered by buffer position.
+
+__global__ void k_far_counts(int64_t N, const int32_t* __restrict__ far, int32_t* __restrict__ cnt) {
+  const int64_t h = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (h < N) cnt[h] = far[4 * h + 1];
+}
+
+// One wavefront per home cell: the far movers' destinations (wrapped on the
+// periodic axes), their list entries in buffer order, the per-destination
+// counts (integer atomics), and the offsets renormalised in place to the
+// destination cell with the arithmetic of the mover.
+template <typename T, int DIM>
+__global__ __launch_bounds__(64) void k_far_list(DGrid G, T* __restrict__ rec, const int32_t* __restrict__ far,
+                                                 const int32_t* __restrict__ pos_h, int32_t* __restrict__ ldest,
+                                                 int32_t* __restrict__ lpos, int32_t* __restrict__ cnt_in) {
+  const int64_t h = blockIdx.x;
+  if (h >= G.N) return;
+  const int start = far[4 * h], cnt = far[4 * h + 1];
+  if (cnt == 0) return;
+  int hc[3];
+  unflat3(G, h, hc[0], hc[1], hc[2]);
+  for (int t = threadIdx.x; t < cnt; t += 64) {
+    const int64_t i = (int64_t)start + t;
+    T f[3], v[3], w;
+    read_rec<T, DIM>(rec, i, f, v, w);
+    int dc[3] = {hc[0], hc[1], hc[2]};
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      T e = floor(f[d]);
+      T fn = f[d] - e;
+      if (fn >= (T)1) { fn = 0; e += (T)1; }
+      f[d] = fn;
+      const int64_t n = G.n[d];
+      dc[d] = (int)((((int64_t)hc[d] + (int64_t)e) % n + n) % n);
+    }
+    write_rec<T>(rec, i, f, v, w);
+    const int64_t dst = (int64_t)dc[0] + (int64_t)G.n[0] * ((int64_t)dc[1] + (int64_t)G.n[1] * dc[2]);
+    const int64_t j = (int64_t)pos_h[h] + t;
+    ldest[j] = (int32_t)dst;
+    lpos[j] = (int32_t)i;
+    atomicAdd(&cnt_in[dst], 1);
+  }
+}
+
+// Stable bucketing of the far list by destination, by one wavefront walking
+// the list in order (chunks of 64): lanes with equal destinations rank among
+// themselves by lane, and the first of them takes the group's slots from the
+// destination's fill counter.  Only this wavefront touches the counters, in
+// program order, so the result is deterministic.  nbits: bits of a cell index.
+__global__ __launch_bounds__(64) void k_far_bucket(int64_t F, int nbits, const int32_t* __restrict__ ldest,
+                                                   const int32_t* __restrict__ lpos,
+                                                   const int32_t* __restrict__ start_in, int32_t* __restrict__ fill,
+                                                   int32_t* __restrict__ sorted) {
+  const int lane = threadIdx.x;
+  const uint64_t lt = lanemask_lt(lane);
+  for (int64_t j0 = 0; j0 < F; j0 += 64) {
+    const int64_t j = j0 + lane;
+    const bool act = j < F;
+    const int d = act ? ldest[j] : -1;
+    uint64_t peers = __ballot(act);
+    for (int b = 0; b < nbits; ++b) {
+      const uint64_t m = __ballot(act && ((d >> b) & 1));
+      peers &= ((d >> b) & 1) ? m : ~m;
+    }
+    int base = 0;
+    const int leader = act ? __ffsll((unsigned long long)peers) - 1 : 0;
+    if (act && leader == lane) base = atomicAdd(&fill[d], __popcll(peers));
+    base = __shfl(base, leader, 64);
+    if (act) sorted[start_in[d] + base + __popcll(peers & lt)] = lpos[j];
+  }
+}
+
+// Particles of cell c after the re-sort: its direction runs plus its far
+// movers (scan -> new segment starts).
+template <int DIM>
+__global__ __launch_bounds__(256) void k_far_newcount(DGrid G, const int32_t* __restrict__ runs,
+                                                      const int32_t* __restrict__ cnt_in, int32_t* __restrict__ out) {
+  const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (c >= G.N) return;
+  int s = cnt_in[c];
+  for (int j = 0; j < Dm<DIM>::ND; ++j) s += runs[2 * (c * Dm<DIM>::ND + j) + 1];
+  out[c] = s;
+}
+
+// number of entries of the ascending list a[0..n) below x
+__device__ inline int count_below(const int32_t* a, int n, int x) {
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (a[mid] < x) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+// One wavefront per destination cell: merge its direction runs and its far
+// movers by buffer position into one contiguous segment of the other buffer;
+// the cell's run table then holds the single run "no move".
+template <typename T, int DIM>
+__global__ __launch_bounds__(64) void k_far_merge(DGrid G, const T* __restrict__ rec, const int32_t* __restrict__ runs,
+                                                  const int32_t* __restrict__ sorted,
+                                                  const int32_t* __restrict__ cnt_in,
+                                                  const int32_t* __restrict__ start_in,
+                                                  const int32_t* __restrict__ newstart, T* __restrict__ rec_o,
+                                                  int32_t* __restrict__ runs_o) {
+  constexpr int ND = Dm<DIM>::ND;
+  __shared__ int s_start[32], s_pre[32];
+  const int lane = threadIdx.x;
+  const int64_t c = blockIdx.x;
+  if (c >= G.N) return;
+  int nseg;
+  const int total = runs_setup<DIM>(G, c, runs, s_start, s_pre, lane, nseg);
+  const int nf = cnt_in[c];
+  const int32_t* fl = sorted + start_in[c];  // ascending buffer positions
+  const int64_t o = newstart[c];
+  for (int t = lane; t < total; t += 64) {
+    int k = 0;
+    for (int i = 1; i < nseg; ++i)
+      if (s_pre[i] <= t) k = i;
+    const int src = s_start[k] + (t - s_pre[k]);
+    const int nb = nf > 0 ? count_below(fl, nf, s_start[k]) : 0;
+    T f[3], v[3], w;
+    read_rec<T, DIM>(rec, src, f, v, w);
+    write_rec<T>(rec_o, o + t + nb, f, v, w);
+  }
+  for (int j = lane; j < nf; j += 64) {
+    const int p = fl[j];
+    int nn = 0;
+    for (int k = 0; k < nseg; ++k) {
+      const int ck = (k + 1 < nseg ? s_pre[k + 1] : total) - s_pre[k];
+      if (s_start[k] < p) nn += ck;
+    }
+    T f[3], v[3], w;
+    read_rec<T, DIM>(rec, p, f, v, w);
+    write_rec<T>(rec_o, o + j + nn, f, v, w);
+  }
+  if (lane < ND) {
+    const bool centre = lane == (ND - 1) / 2;
+    reinterpret_cast<i2*>(runs_o)[c * ND + lane] = centre ? i2{(int)o, total + nf} : i2{0, 0};
+  }
+}
+
 }  // namespace
 
 // ===================================================================== host
@@ -1033,10 +1246,16 @@ static void launch_push_t(ge_ctx* c, int s) {
   A.runs = S.runs[cur]; A.seg_next = c->seg_next + (int64_t)s * c->G.N;
   A.runs_o = S.runs[nxt];
   A.NF = (const T*)c->node8;
+  A.far_o = S.far;
   A.beta = (T)S.beta;
-  for (int d = 0; d < 3; ++d) A.dtx[d] = (T)(c->P.dt * c->G.idx[d]);
+  for (int d = 0; d < 3; ++d) {
+    A.dtx[d] = (T)(c->P.dt * c->G.idx[d]);
+    A.lo[d] = (T)(2 - c->G.n[d]);
+    A.hi[d] = (T)(c->G.n[d] - 1);
+  }
   A.n = S.n;
   A.flags = c->flags;
+  A.stats = c->flags + GE_FL_SPECIES + 4 * s;
   hipLaunchKernelGGL((k_push<T, DIM>), dim3((unsigned)c->G.N), dim3(64), 0, c->stream, c->G, A);
 }
 
@@ -1053,6 +1272,98 @@ int ge_launch_push(ge_ctx* c, int s) {
   }
   GE_HIP(c, hipGetLastError());
   c->sp[s].cur = 1 - c->sp[s].cur;
+  return GE_OK;
+}
+
+
+// ------------------------------------------------------------------ far re-sort (host)
+template <typename P>
+static int far_alloc(ge_ctx* c, P** p, size_t bytes) {
+  hipError_t e = hipMalloc((void**)p, bytes ? bytes : 8);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    return ge_fail(c, GE_ERR_OOM, "hipMalloc of the far-mover scratch failed: " + std::string(hipGetErrorString(e)));
+  }
+  return GE_OK;
+}
+
+void ge_far_free(ge_ctx* c) {
+  FarScratch& X = c->fx;
+  int32_t** all[] = {&X.dest, &X.pos, &X.sorted, &X.pos_h, &X.cnt_in, &X.start_in, &X.fill, &X.newstart};
+  for (auto p : all) {
+    if (*p) (void)hipFree(*p);
+    *p = nullptr;
+  }
+  X.cap = 0;
+}
+
+template <typename T, int DIM>
+static void far_kernels_t(ge_ctx* c, SpeciesBuf& S, int64_t F) {
+  FarScratch& X = c->fx;
+  const int64_t N = c->G.N;
+  const int cur = S.cur;
+  hipLaunchKernelGGL((k_far_list<T, DIM>), dim3((unsigned)N), dim3(64), 0, c->stream, c->G, (T*)S.rec[cur], S.far,
+                     X.pos_h, X.dest, X.pos, X.cnt_in);
+  scan_into(c, X.cnt_in, X.start_in);
+  int nbits = 1;
+  while (((int64_t)1 << nbits) < N) ++nbits;
+  hipLaunchKernelGGL(k_far_bucket, dim3(1), dim3(64), 0, c->stream, F, nbits, X.dest, X.pos, X.start_in, X.fill,
+                     X.sorted);
+  hipLaunchKernelGGL((k_far_newcount<DIM>), dim3((N + 255) / 256), dim3(256), 0, c->stream, c->G, S.runs[cur],
+                     X.cnt_in, X.newstart);
+  scan_into(c, X.newstart, X.newstart);
+  hipLaunchKernelGGL((k_far_merge<T, DIM>), dim3((unsigned)N), dim3(64), 0, c->stream, c->G, (const T*)S.rec[cur],
+                     S.runs[cur], X.sorted, X.cnt_in, X.start_in, X.newstart, (T*)S.rec[1 - cur], S.runs[1 - cur]);
+}
+
+// Largest move of the last push of species s into the flag block.
+int ge_launch_move_max(ge_ctx* c, int s) {
+  hipLaunchKernelGGL(k_move_max, dim3(256), dim3(256), 0, c->stream, c->G.N, c->sp[s].far,
+                     c->flags + GE_FL_SPECIES + 4 * s + 1);
+  GE_HIP(c, hipGetLastError());
+  return GE_OK;
+}
+
+// Stable re-sort of species s after a push that left F > 0 far movers.
+int ge_launch_far_resort(ge_ctx* c, int s, int64_t F) {
+  FarScratch& X = c->fx;
+  SpeciesBuf& S = c->sp[s];
+  const int64_t N = c->G.N;
+  int rc = GE_OK;
+  if (!X.pos_h) {
+    int32_t** per_cell[] = {&X.pos_h, &X.cnt_in, &X.start_in, &X.fill, &X.newstart};
+    for (auto p : per_cell)
+      if (!rc) rc = far_alloc(c, p, sizeof(int32_t) * N);
+    if (rc) { ge_far_free(c); return rc; }
+  }
+  if (X.cap < F) {
+    int32_t** lists[] = {&X.dest, &X.pos, &X.sorted};
+    for (auto p : lists) {
+      if (*p) (void)hipFree(*p);
+      *p = nullptr;
+    }
+    X.cap = 0;
+    for (auto p : lists)
+      if (!rc) rc = far_alloc(c, p, sizeof(int32_t) * F);
+    if (rc) { ge_far_free(c); return rc; }
+    X.cap = F;
+  }
+  GE_HIP(c, hipMemsetAsync(X.cnt_in, 0, sizeof(int32_t) * N, c->stream));
+  GE_HIP(c, hipMemsetAsync(X.fill, 0, sizeof(int32_t) * N, c->stream));
+  hipLaunchKernelGGL(k_far_counts, dim3((N + 255) / 256), dim3(256), 0, c->stream, N, S.far, X.pos_h);
+  scan_into(c, X.pos_h, X.pos_h);
+  const bool f32 = c->P.precision == GE_FP32;
+  switch (c->G.dim * 2 + (f32 ? 1 : 0)) {
+    case 2: far_kernels_t<double, 1>(c, S, F); break;
+    case 3: far_kernels_t<float, 1>(c, S, F); break;
+    case 4: far_kernels_t<double, 2>(c, S, F); break;
+    case 5: far_kernels_t<float, 2>(c, S, F); break;
+    case 6: far_kernels_t<double, 3>(c, S, F); break;
+    default: far_kernels_t<float, 3>(c, S, F); break;
+  }
+  GE_HIP(c, hipGetLastError());
+  S.cur = 1 - S.cur;
   return GE_OK;
 }
 

@@ -30,6 +30,7 @@ EXPORTS = [
     "ge_create", "ge_destroy", "ge_last_error", "ge_add_species", "ge_set_fields", "ge_deposit", "ge_solve_fields",
     "ge_push", "ge_update_fields", "ge_step", "ge_sync", "ge_gather", "ge_set", "ge_half_stencil",
     "ge_get_particles", "ge_apply_operator", "ge_diagnostics", "ge_timings", "ge_explicit_current", "ge_explicit_step",
+    "ge_moves",
     "ge_cnn_init", "ge_cnn_size", "ge_cnn_weights", "ge_cnn_apply", "ge_cnn_harvest", "ge_cnn_add_pair",
     "ge_cnn_npairs", "ge_cnn_train", "ge_cnn_loss_grad",
 ]
@@ -74,6 +75,11 @@ class GEDiag(ctypes.Structure):
                 ("P", (ctypes.c_double * 3) * 4), ("gauss", ctypes.c_double), ("nsp", ctypes.c_int)]
 
 
+class GEMoveReport(ctypes.Structure):
+    _fields_ = [("far_moves", ctypes.c_int64 * 4), ("max_move", ctypes.c_double * 4), ("resorts", ctypes.c_int),
+                ("pushes", ctypes.c_int)]
+
+
 class GlecsimError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"glecsim error {code}: {msg}")
@@ -112,6 +118,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.ge_explicit_step.argtypes = [vp]
     L.ge_diagnostics.argtypes = [vp, ctypes.POINTER(GEDiag)]
     L.ge_timings.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+    L.ge_moves.argtypes = [vp, ctypes.POINTER(GEMoveReport)]
     L.ge_cnn_init.argtypes = [vp, ctypes.c_uint32, ctypes.c_int]
     L.ge_cnn_size.argtypes = []
     L.ge_cnn_weights.argtypes = [vp, ctypes.c_int, vp]
@@ -350,6 +357,14 @@ class Simulation:
         loss = ctypes.c_double()
         self._check(self.L.ge_cnn_loss_grad(self.h, B, n, _ptr(in_crops), _ptr(tgt), _ptr(g), ctypes.byref(loss)))
         return loss.value, g
+
+    def moves(self) -> Dict:
+        """Particle moves since the last call (see ge_moves)."""
+        r = GEMoveReport()
+        self._check(self.L.ge_moves(self.h, ctypes.byref(r)))
+        return {"far_moves": [int(r.far_moves[s]) for s in range(self.nsp)],
+                "max_move": [float(r.max_move[s]) for s in range(self.nsp)],
+                "resorts": int(r.resorts), "pushes": int(r.pushes)}
 
     def timings(self):
         out = (ctypes.c_double * 8)()

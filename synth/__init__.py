@@ -252,5 +252,8 @@ def small(name: str, dim: int = 3, n=(6, 5, 4), ppc: int = 7, fp32: bool = False
     if out.profile == PROF_HARRIS2 and dim < 2:
         out = out.replace(profile=PROF_UNIFORM)
     if out.profile == PROF_HARRIS2:
-        out = out.replace(lam=max(1.0, nn[1] * dx[1] / 8.0))
+        # a narrower box needs a narrower sheet; the drifts that carry the
+        # sheet current scale as 1/lambda (u_i - u_e = B0/lambda)
+        lam = max(1.0, nn[1] * dx[1] / 8.0)
+        out = out.replace(lam=lam, dsheet=tuple(u * wl.lam / lam for u in wl.dsheet))
     return out.replace(**kw)

@@ -80,8 +80,10 @@ static void domain_len(const synth_cfg* c, double L[3]) {
   for (int d = 0; d < 3; ++d) L[d] = (d < c->dim) ? c->n[d] * c->dx[d] : 1.0;
 }
 
-/* Harris double sheet at y = Ly/4 (current along -z for the ions' drift sign
- * dsheet) and y = 3Ly/4 (opposite current). */
+/* Harris double sheet at y = Ly/4 and y = 3Ly/4.  Across sheet 1 B_x rises
+ * (B_x ~ Bh tanh((y - y1)/lambda)), so (curl B)_z = -dB_x/dy < 0 there and the
+ * current that Ampere's law asks for, sum_s q_s n u_s = (c/4 pi) curl B, points
+ * along -z; sheet 2 carries the opposite current. */
 static void harris_parts(const synth_cfg* c, double y, double* n1, double* n2, double* nbk) {
   double L[3]; domain_len(c, L);
   double y1 = 0.25 * L[1], y2 = 0.75 * L[1];
@@ -109,8 +111,10 @@ static void drift(const synth_cfg* c, int s, const double x[3], double pick, dou
   } else if (c->profile == PROF_HARRIS2) {
     double n1, n2, nb; harris_parts(c, x[1], &n1, &n2, &nb);
     double nt = n1 + n2 + nb;
-    if (pick * nt < n1) u[2] += c->dsheet[s];
-    else if (pick * nt < n1 + n2) u[2] -= c->dsheet[s];
+    /* dsheet[s] is the drift of species s along +z that carries a current
+     * along +z (ions positive, electrons negative); sheet 1 takes it reversed */
+    if (pick * nt < n1) u[2] -= c->dsheet[s];
+    else if (pick * nt < n1 + n2) u[2] += c->dsheet[s];
   }
 }
 
