@@ -296,6 +296,19 @@ int ge_apply_operator(ge_ctx* ctx, const double* x, double* y);
 /* FP64 energies, momenta and Gauss residual (host struct).  Synchronises. */
 int ge_diagnostics(ge_ctx* ctx, ge_diag* out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid it): ge_diagnostics
+ * without any allocation.  Same results as ge_diagnostics, bit for bit (same
+ * kernels, same summation order); its reduction partials live in a static
+ * device array of 4 x 256 + 4 doubles per GPU, which every reduction fits
+ * (they always run on 256 blocks).  It allocates nothing, reads back through
+ * the pinned host buffer of the context, and synchronises.  Every call on a
+ * GPU shares that GPU's array: calls that overlap on one GPU (other threads,
+ * other contexts) race.  Errors: GE_ERR_STATE if a push is not settled yet
+ * (call ge_sync first: settling may re-sort far movers, which allocates on
+ * first use) or if the context has no scratch address for its device. */
+int ge_diagnostics_noalloc(ge_ctx* ctx, ge_diag* out);
+
 /* Mean seconds per ge_step() since the last call, from HIP events recorded on
  * the context's stream around each kernel group; host array of 8:
  *   [0] push + re-binning kernels (all species: corner-field packing,

@@ -11,7 +11,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libglecsim.so")
-SOURCES = ["ge_api.hip", "ge_particles.hip", "ge_grid.hip", "ge_krylov.hip", "ge_cnn.hip", "ge_explicit.hip"]
+SOURCES = ["ge_api.hip", "ge_particles.hip", "ge_grid.hip", "ge_krylov.hip", "ge_cnn.hip", "ge_explicit.hip",
+           "ge_noalloc.hip"]
 ARCH = os.environ.get("GLECSIM_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -191,6 +191,7 @@ int ge_create(const ge_grid* grid, const ge_params* params, void* hip_stream, ge
   }
   if (!rc) rc = dalloc(c, &c->partials, sizeof(double) * 16 * 512);  // 16 dots x 512 blocks
   if (!rc) rc = dalloc(c, &c->flags, sizeof(int) * GE_FL_COUNT);
+  if (!rc) rc = ge_noalloc_setup(c);
   if (rc) {
     g_create_err = "ge_create: " + c->err;
     ge_destroy(c);

@@ -803,10 +803,18 @@ int ge_launch_sub(ge_ctx* c, const double* a, const double* b, double* out, int6
   return GE_OK;
 }
 
-int ge_launch_field_diag(ge_ctx* c, double* out) {
-  const int nbk = 256;
-  DISPATCH_DIM(c, k_field_diag, dim3(nbk), dim3(256), 0, c->stream, c->G, c->E, c->B, c->rho, c->nsp, c->partials);
+// k_field_diag into part[4][GE_DIAG_BLOCKS] (block partials of |E|^2, |B|^2 and
+// the two Gauss-residual sums)
+int ge_launch_field_diag_part(ge_ctx* c, double* part) {
+  DISPATCH_DIM(c, k_field_diag, dim3(GE_DIAG_BLOCKS), dim3(256), 0, c->stream, c->G, c->E, c->B, c->rho, c->nsp, part);
   GE_HIP(c, hipGetLastError());
+  return GE_OK;
+}
+
+int ge_launch_field_diag(ge_ctx* c, double* out) {
+  const int nbk = GE_DIAG_BLOCKS;
+  int rc = ge_launch_field_diag_part(c, c->partials);
+  if (rc) return rc;
   double h[4 * 256];
   GE_HIP(c, hipMemcpyAsync(h, c->partials, sizeof(double) * 4 * nbk, hipMemcpyDeviceToHost, c->stream));
   GE_HIP(c, hipStreamSynchronize(c->stream));

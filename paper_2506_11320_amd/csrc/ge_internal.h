@@ -200,6 +200,7 @@ struct ge_ctx {
   int* flags;            // GE_FL_COUNT ints (see GE_FL_*)
   int have_deposit, have_solve;
   int push_pending;      // a push ran whose statistics (and far movers) are not settled yet
+  int device;            // HIP device the context was created on
   MoveStats moves;
   FarScratch fx;
   void* cnn;           // learned preconditioner state (ge_cnn.hip), lazily created
@@ -240,7 +241,12 @@ int ge_launch_widen_M(ge_ctx* c, const void* M, double* dst);
 int ge_launch_pack_node8(ge_ctx* c, int half);  // half 0: E^{n+theta} from Eth, 1: B from Bn
 int ge_launch_jacobi_setup(ge_ctx* c);
 int ge_launch_jacobi_apply(ge_ctx* c, const double* x, double* y);
+// blocks of the FP64 diagnostic reductions (each writes 4 partial sums)
+constexpr int GE_DIAG_BLOCKS = 256;
 int ge_launch_field_diag(ge_ctx* c, double* out);  // W_E, W_B, gauss (sync)
+int ge_launch_field_diag_part(ge_ctx* c, double* part);             // partials only, asynchronous
+int ge_launch_particle_moments_part(ge_ctx* c, int s, double* part);  // partials only, asynchronous
+int ge_noalloc_setup(ge_ctx* c);  // per-device address of the static diagnostics scratch
 int ge_launch_sub(ge_ctx* c, const double* a, const double* b, double* out, int64_t n);  // out = a - b
 
 int ge_gmres(ge_ctx* c, double tol, int maxit, int restart, int precond, ge_solve_report* rep);

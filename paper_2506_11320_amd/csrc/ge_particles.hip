@@ -1454,18 +1454,25 @@ int ge_launch_get_particles(ge_ctx* c, int s, int32_t* cell, void* off, void* v,
   return GE_OK;
 }
 
-int ge_launch_particle_moments(ge_ctx* c, int s, double* out4) {
+// k_particle_moments of species s into part[4][GE_DIAG_BLOCKS]
+int ge_launch_particle_moments_part(ge_ctx* c, int s, double* part) {
   SpeciesBuf& S = c->sp[s];
-  const int nbk = 256;
-  double* part = c->partials;  // needs 4 * nbk
   if (c->P.precision == GE_FP32)
-    hipLaunchKernelGGL(k_particle_moments<float>, dim3(nbk), dim3(256), 0, c->stream, (const float*)S.rec[S.cur], S.n,
-                       part);
+    hipLaunchKernelGGL(k_particle_moments<float>, dim3(GE_DIAG_BLOCKS), dim3(256), 0, c->stream,
+                       (const float*)S.rec[S.cur], S.n, part);
   else
-    hipLaunchKernelGGL(k_particle_moments<double>, dim3(nbk), dim3(256), 0, c->stream, (const double*)S.rec[S.cur], S.n,
-                       part);
+    hipLaunchKernelGGL(k_particle_moments<double>, dim3(GE_DIAG_BLOCKS), dim3(256), 0, c->stream,
+                       (const double*)S.rec[S.cur], S.n, part);
   GE_HIP(c, hipGetLastError());
-  double h[4 * 256];
+  return GE_OK;
+}
+
+int ge_launch_particle_moments(ge_ctx* c, int s, double* out4) {
+  const int nbk = GE_DIAG_BLOCKS;
+  double* part = c->partials;  // needs 4 * nbk
+  int rc = ge_launch_particle_moments_part(c, s, part);
+  if (rc) return rc;
+  double h[4 * GE_DIAG_BLOCKS];
   GE_HIP(c, hipMemcpyAsync(h, part, sizeof(double) * 4 * nbk, hipMemcpyDeviceToHost, c->stream));
   GE_HIP(c, hipStreamSynchronize(c->stream));
   for (int k = 0; k < 4; ++k) {

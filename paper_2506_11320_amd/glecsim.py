@@ -30,7 +30,7 @@ EXPORTS = [
     "ge_create", "ge_destroy", "ge_last_error", "ge_add_species", "ge_set_fields", "ge_deposit", "ge_solve_fields",
     "ge_push", "ge_update_fields", "ge_step", "ge_sync", "ge_gather", "ge_set", "ge_half_stencil",
     "ge_get_particles", "ge_apply_operator", "ge_diagnostics", "ge_timings", "ge_explicit_current", "ge_explicit_step",
-    "ge_moves",
+    "ge_moves", "ge_diagnostics_noalloc",
     "ge_cnn_init", "ge_cnn_size", "ge_cnn_weights", "ge_cnn_apply", "ge_cnn_harvest", "ge_cnn_add_pair",
     "ge_cnn_npairs", "ge_cnn_train", "ge_cnn_loss_grad",
 ]
@@ -119,6 +119,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.ge_diagnostics.argtypes = [vp, ctypes.POINTER(GEDiag)]
     L.ge_timings.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
     L.ge_moves.argtypes = [vp, ctypes.POINTER(GEMoveReport)]
+    L.ge_diagnostics_noalloc.argtypes = [vp, ctypes.POINTER(GEDiag)]
     L.ge_cnn_init.argtypes = [vp, ctypes.c_uint32, ctypes.c_int]
     L.ge_cnn_size.argtypes = []
     L.ge_cnn_weights.argtypes = [vp, ctypes.c_int, vp]
@@ -294,9 +295,12 @@ class Simulation:
         self._check(self.L.ge_apply_operator(self.h, _ptr(x), _ptr(y)))
         return y
 
-    def diagnostics(self) -> Dict:
+    def diagnostics(self, noalloc: bool = False) -> Dict:
+        """FP64 energies, momenta and Gauss residual (ge_diagnostics, or its
+        allocation-free variant ge_diagnostics_noalloc)."""
         dg = GEDiag()
-        self._check(self.L.ge_diagnostics(self.h, ctypes.byref(dg)))
+        fn = self.L.ge_diagnostics_noalloc if noalloc else self.L.ge_diagnostics
+        self._check(fn(self.h, ctypes.byref(dg)))
         return {"W_E": dg.W_E, "W_B": dg.W_B, "K": [dg.K[s] for s in range(self.nsp)],
                 "P": [[dg.P[s][d] for d in range(3)] for s in range(self.nsp)], "gauss": dg.gauss}
 
