@@ -60,6 +60,7 @@ enum {
 enum { GE_FP64 = 0, GE_FP32 = 1 };           /* particle and mass-matrix precision */
 enum { GE_A_LIGHT = 0, GE_A_BULK = 1 };      /* diffusion speed a: c, or |u| */
 enum { GE_PC_NONE = 0, GE_PC_JACOBI = 1, GE_PC_CNN = 2 };  /* GMRES preconditioner */
+enum { GE_LAG_EN = 0, GE_PICARD1 = 1 };      /* E limiter: lagged to E^n, or one Picard step */
 
 typedef struct ge_ctx ge_ctx;
 
@@ -99,6 +100,12 @@ typedef struct {
    * its update, strides 1, 2, 1, ..., weight phi_u, each pass sweeping x, y,
    * z.  0 = off (the method itself uses the LF diffusion instead). */
   int ns_e;
+  /* The E limiter's smoothness ratio r_E uses the unknown E^{n+theta}
+   * (Sec. 2.2), which makes the implicit system nonlinear.  GE_LAG_EN takes
+   * r_E from E^n (one linear solve per step); GE_PICARD1 then takes one Picard
+   * step: the LF coefficients from that first E^{n+theta}, and the system
+   * solved again starting from it (twice the solve work). */
+  int limiter_lag;
 } ge_params;
 
 typedef struct { double q, m; } ge_species;   /* charge and mass per physical particle */
@@ -198,6 +205,30 @@ int ge_update_fields(ge_ctx* ctx);
 
 /* One full step: deposit, solve, push, update.  Synchronises. */
 int ge_step(ge_ctx* ctx, double tol, int maxit, int restart, int precond, ge_solve_report* report);
+
+/* Steps completed on this context (field updates of ge_update_fields /
+ * ge_step and explicit steps), restored by ge_restore. */
+int64_t ge_step_count(const ge_ctx* ctx);
+
+/* Macro-particles of species s (-1 if there is no such species). */
+int64_t ge_species_count(const ge_ctx* ctx, int s);
+
+/* Checkpoint of the state between steps to the file at path (host string):
+ * grid and parameters, the step count, E^n, B^n, the cleaning scalar psi,
+ * every species (charge, mass and its particles in cell order) and, if the
+ * learned preconditioner exists, its master weights, Adam moments and step
+ * (not its pair store).  Settles the last push first; synchronises.  Errors:
+ * GE_ERR_STATE between a deposit and its field update, GE_ERR_ARG if the file
+ * cannot be written. */
+int ge_checkpoint(ge_ctx* ctx, const char* path);
+
+/* Restore a checkpoint into a context created with the same grid and
+ * parameters and with no species yet.  Continuing from the restored state
+ * gives the same bits as continuing the run that wrote it (the particle
+ * order is the cell order of the run).  Synchronises.  Errors: GE_ERR_ARG for
+ * a missing, truncated or corrupt file (checksum) or a grid/parameter
+ * mismatch, GE_ERR_STATE if the context already has species. */
+int ge_restore(ge_ctx* ctx, const char* path);
 
 /* Current of an explicit PIC step at the particles' present positions and
  * velocities (Sec. 3.1, its explicit form).  Comoving frame on:

@@ -74,6 +74,7 @@ def lib():
         L.or_curl_nc.argtypes = [G, _p, _p]
         L.or_curl_cn.argtypes = [G, _p, _p]
         L.or_div_nc.argtypes = [G, _p, _p]
+        L.or_gauss_sums.argtypes = [G, _p, _p, _p]
         L.or_diffusion.argtypes = [G, _p, _p, _p]
         L.or_apply_A.argtypes = [G, P, _p, _p, _p, _p]
         L.or_rhs.argtypes = [G, P, _p, _p, _p, _p]
@@ -314,6 +315,17 @@ def div_nc(G: Grid, E) -> np.ndarray:
     return _unary(lib().or_div_nc, G, E, (nnodes(G),))
 
 
+def gauss_residual(G: Grid, E, rho_s) -> float:
+    """||div_NC E - 4 pi rho_c|| / ||4 pi rho_c|| with rho_c the cell mean of
+    the node charge density summed over species (the absolute norm if there is
+    no charge); see or_gauss_sums."""
+    rho = _f64(np.sum(np.asarray(rho_s, np.float64).reshape(-1, nnodes(G)), axis=0))
+    E = _f64(E)
+    out = np.zeros(2)
+    lib().or_gauss_sums(ctypes.byref(G), _ptr(E), _ptr(rho), _ptr(out))
+    return float(math.sqrt(out[0] / out[1])) if out[1] > 0 else float(math.sqrt(out[0]))
+
+
 def diffusion(G: Grid, kappa, F) -> np.ndarray:
     kappa, F = _f64(kappa), _f64(F)
     out = np.empty_like(F)
@@ -545,39 +557,55 @@ def diffusion_speed(G: Grid, u, a_mode: int, c: float = 1.0) -> np.ndarray:
     return np.sqrt((np.asarray(u) ** 2).sum(axis=0))
 
 
-def diagnostics(G: Grid, species: List[Species], E, Bc) -> Dict[str, object]:
+def diagnostics(G: Grid, species: List[Species], E, Bc, rho_s=None) -> Dict[str, object]:
     """Energies and momenta in FP64: W_E = sum |E|^2 dV / 8pi over nodes,
-    W_B over cells, K_s = sum 1/2 m_s w |v|^2, P_s = sum m_s w v."""
+    W_B over cells, K_s = sum 1/2 m_s w |v|^2, P_s = sum m_s w v; with the
+    node charge densities rho_s (per species) also the Gauss residual."""
     dV = cellvol(G)
     WE = float((np.asarray(E) ** 2).sum() * dV / (8 * math.pi))
     WB = float((np.asarray(Bc) ** 2).sum() * dV / (8 * math.pi))
     K = [float(0.5 * sp.m * (sp.w[:, None] * sp.v ** 2).sum()) for sp in species]
     P = [(sp.m * (sp.w[:, None] * sp.v).sum(axis=0)) for sp in species]
-    return {"W_E": WE, "W_B": WB, "K": K, "P": P}
+    out = {"W_E": WE, "W_B": WB, "K": K, "P": P}
+    if rho_s is not None:
+        out["gauss"] = gauss_residual(G, E, rho_s)
+    return out
 
 
 def step(G: Grid, species: List[Species], E, Bc, *, dt: float, theta: float, c: float = 1.0,
          comoving: bool = False, lf_E: bool = False, lf_B: bool = False, beta_lim: float = 1.0,
          a_mode: int = 1, n_smooth_u: int = 5, tol: float = 1e-12, restart: int = 30,
          solve: str = "gmres", n_smooth_j: int = 0, dedner: bool = False, ch_frac: float = 0.8,
-         dedner_damp: float = 0.1, psi=None, n_smooth_e: int = 0) -> Dict[str, object]:
+         dedner_damp: float = 0.1, psi=None, n_smooth_e: int = 0, limiter_lag: str = "en") -> Dict[str, object]:
     """One full GL-ECSIM step without the Gauss's-law correction:
     deposit -> implicit E solve -> B and E update -> particle push.
     With dedner, the cleaning scalar psi (cells, zero if None) is advanced
     from B^n first and B^{n+1} gets -dt grad psi^{n+1} (Sec. 2.3).
     n_smooth_e > 0 smooths E^{n+1} with that many filter passes (Sec. 2.4,
-    strides 1, 2, 1, ...), the alternative to the LF diffusion of Sec. 4.1."""
+    strides 1, 2, 1, ...), the alternative to the LF diffusion of Sec. 4.1.
+    The E limiter's smoothness ratio is taken from the unknown E^{n+theta} in
+    Sec. 2.2, which makes the system nonlinear.  limiter_lag "en" takes it
+    from E^n (one linear solve); "picard1" then takes one Picard step: the
+    limiter from that first E^{n+theta}, and the system solved again from it."""
     P = params(theta, dt, c)
     dep = deposit(G, species, dt, Bc, comoving, n_smooth_u, n_smooth_j=n_smooth_j)
     a_node = diffusion_speed(G, dep["u"], a_mode, c)
     kE = kappa_E(G, E, a_node, beta_lim) if lf_E else None
     kB = kappa_B(G, Bc, a_node, beta_lim) if lf_B else None
     b = rhs(G, P, E, Bc, dep["J_eff"])
-    if solve == "dense":
-        Eth = dense_solve(dense_A(G, P, dep["Mt"], kE), b.ravel()).reshape(E.shape)
-        its, rel = 0, 0.0
-    else:
-        Eth, its, rel = gmres(G, P, dep["Mt"], kE, b, E, tol=tol, maxit=5000, restart=restart)
+    if limiter_lag not in ("en", "picard1"):
+        raise ValueError(f"limiter_lag {limiter_lag!r}")
+
+    def _solve(kE_, x0):
+        if solve == "dense":
+            return dense_solve(dense_A(G, P, dep["Mt"], kE_), b.ravel()).reshape(E.shape), 0, 0.0
+        return gmres(G, P, dep["Mt"], kE_, b, x0, tol=tol, maxit=5000, restart=restart)
+
+    Eth, its, rel = _solve(kE, E)
+    if limiter_lag == "picard1" and lf_E:
+        kE = kappa_E(G, Eth, a_node, beta_lim)
+        Eth, its2, rel = _solve(kE, Eth)
+        its += its2
     Bnew = update_B(G, P, Bc, Eth, kB)
     psi_new = None
     if dedner:

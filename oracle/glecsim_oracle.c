@@ -18,10 +18,11 @@
  * passages that are silent or garbled are marked READING.
  *
  * Parity unpinned (no closed form, printed value or invariant fixes them;
- * the GPU path implements the same reading): the node averaging of B used to
- * interpolate B to the particles (or_node_avg), the multi-dimensional form of
+ * the GPU path implements the same reading): the multi-dimensional form of
  * the LF coefficients and their diffusion speed (or_kappa_E / or_kappa_B
- * beyond 1D), and the lag of the E limiter to E^n.
+ * beyond 1D), and which lag of the E limiter the paper's code uses.  The node
+ * average of B (or_node_avg) is pinned by its exactness on linear fields;
+ * where B is interpolated to the particles stays a reading.
  */
 #include <math.h>
 #include <stdint.h>
@@ -404,6 +405,34 @@ void or_curl_cn(const or_grid* G, const double* B, double* out) {
 void or_div_nc(const or_grid* G, const double* E, double* out) {
   int64_t N = nnodes(G);
   for (int64_t c = 0; c < N; ++c) out[c] = dnc(G, &E[0], c, 0) + dnc(G, &E[N], c, 1) + dnc(G, &E[2 * N], c, 2);
+}
+
+/* Gauss's law residual.  Sec. 2.1 writes Maxwell's equations; Gauss's law
+ * div E = 4 pi rho is the constraint the GL correction named in Sec. 1 restores
+ * (the correction itself is not described there).  READING: the residual is
+ * taken at cell centres, where div_NC lives, against the cell mean of the
+ * node charge density (rho_node summed over species, mean over the cell's
+ * 2^dim nodes):
+ *   out[0] = sum_c (div_NC E - 4 pi rho_c)^2,   out[1] = sum_c (4 pi rho_c)^2,
+ * so that the relative residual is sqrt(out[0] / out[1]). */
+void or_gauss_sums(const or_grid* G, const double* E, const double* rho_node, double out[2]) {
+  int64_t N = nnodes(G);
+  int nc = 1 << G->dim;
+  double* div = (double*)malloc(sizeof(double) * N);
+  or_div_nc(G, E, div);
+  out[0] = out[1] = 0.0;
+  for (int64_t c = 0; c < N; ++c) {
+    double rc = 0.0;
+    for (int a = 0; a < nc; ++a) {
+      int o[3] = {0, 0, 0};
+      for (int e = 0; e < G->dim; ++e) o[e] = (a >> e) & 1;
+      rc += rho_node[shifted(G, c, o)];
+    }
+    double r4 = 4.0 * M_PI * rc / nc;
+    out[0] += (div[c] - r4) * (div[c] - r4);
+    out[1] += r4 * r4;
+  }
+  free(div);
 }
 
 /* Diffusion operator D applied to a field F (node or cell, same stencil):

@@ -26,6 +26,7 @@ void or_kappa_B(const or_grid* G, const double* B, const double* a_node, double 
 void or_curl_nc(const or_grid* G, const double* E, double* out);
 void or_curl_cn(const or_grid* G, const double* B, double* out);
 void or_div_nc(const or_grid* G, const double* E, double* out);
+void or_gauss_sums(const or_grid* G, const double* E, const double* rho_node, double out[2]);
 void or_diffusion(const or_grid* G, const double* kappa, const double* F, double* out);
 void or_apply_A(const or_grid* G, const or_params* P, const double* Mtilde, const double* kappaE, const double* x,
                 double* y);

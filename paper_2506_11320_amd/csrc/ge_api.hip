@@ -1,7 +1,9 @@
 // C ABI of the gfx950 GL-ECSIM library: context, buffers and step sequencing.
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "ge_internal.h"
 
@@ -88,6 +90,94 @@ void accumulate_timings(ge_ctx* c, double solve_s) {
   c->tcnt += 1;
 }
 
+// ------------------------------------------------------------ checkpoint file
+// Little-endian binary: magic, version, then the sections in the order of
+// ge_checkpoint; a 64-bit FNV-1a checksum of every byte before it closes the
+// file.
+const char GE_CKPT_MAGIC[8] = {'G', 'E', 'C', 'K', 'P', 'T', '0', '1'};
+constexpr uint32_t GE_CKPT_VERSION = 1;
+
+struct CkptWriter {
+  FILE* f = nullptr;
+  uint64_t h = 1469598103934665603ull;
+  bool ok = true;
+  void put(const void* p, size_t n) {
+    const unsigned char* b = (const unsigned char*)p;
+    for (size_t i = 0; i < n; ++i) h = (h ^ b[i]) * 1099511628211ull;
+    if (ok && n && fwrite(p, 1, n, f) != n) ok = false;
+  }
+  template <typename T>
+  void val(const T& v) { put(&v, sizeof(T)); }
+};
+struct CkptReader {
+  FILE* f = nullptr;
+  uint64_t h = 1469598103934665603ull;
+  bool ok = true;
+  void get(void* p, size_t n) {
+    if (!ok) return;
+    if (n && fread(p, 1, n, f) != n) { ok = false; return; }
+    const unsigned char* b = (const unsigned char*)p;
+    for (size_t i = 0; i < n; ++i) h = (h ^ b[i]) * 1099511628211ull;
+  }
+  template <typename T>
+  T val() { T v{}; get(&v, sizeof(T)); return v; }
+};
+
+// Device staging of one species' particles as four arrays (cell int32[n],
+// off T[3n], v T[3n], w T[n]), each starting on a 256-byte boundary; the
+// checkpoint file holds the same arrays back to back.
+struct PartStage {
+  size_t seg[4], at[4], bytes;
+};
+PartStage part_stage(int64_t n, size_t es) {
+  PartStage P;
+  P.seg[0] = 4 * (size_t)n;
+  P.seg[1] = 3 * es * (size_t)n;
+  P.seg[2] = 3 * es * (size_t)n;
+  P.seg[3] = es * (size_t)n;
+  size_t o = 0;
+  for (int k = 0; k < 4; ++k) {
+    P.at[k] = o;
+    o += (P.seg[k] + 255) / 256 * 256;
+  }
+  P.bytes = o ? o : 256;
+  return P;
+}
+
+// the grid and parameters written field by field (no struct padding)
+void put_config(CkptWriter& W, const ge_grid& g, const ge_params& P) {
+  W.val(g.dim);
+  for (int d = 0; d < 3; ++d) W.val(g.n[d]);
+  for (int d = 0; d < 3; ++d) W.val(g.dx[d]);
+  W.val(P.theta); W.val(P.c); W.val(P.dt); W.val(P.lf_E); W.val(P.lf_B); W.val(P.beta_lim); W.val(P.a_mode);
+  W.val(P.a_const); W.val(P.comoving); W.val(P.n_smooth_u); W.val(P.phi_u); W.val(P.precision); W.val(P.ns_j);
+  W.val(P.dedner); W.val(P.ch_frac); W.val(P.dedner_damp); W.val(P.ns_e); W.val(P.limiter_lag);
+}
+bool same_config(CkptReader& R, const ge_grid& g, const ge_params& P) {
+  bool same = R.val<int>() == g.dim;
+  for (int d = 0; d < 3; ++d) same = (R.val<int>() == g.n[d]) && same;
+  for (int d = 0; d < 3; ++d) same = (R.val<double>() == g.dx[d]) && same;
+  same = (R.val<double>() == P.theta) && same;
+  same = (R.val<double>() == P.c) && same;
+  same = (R.val<double>() == P.dt) && same;
+  same = (R.val<int>() == P.lf_E) && same;
+  same = (R.val<int>() == P.lf_B) && same;
+  same = (R.val<double>() == P.beta_lim) && same;
+  same = (R.val<int>() == P.a_mode) && same;
+  same = (R.val<double>() == P.a_const) && same;
+  same = (R.val<int>() == P.comoving) && same;
+  same = (R.val<int>() == P.n_smooth_u) && same;
+  same = (R.val<double>() == P.phi_u) && same;
+  same = (R.val<int>() == P.precision) && same;
+  same = (R.val<int>() == P.ns_j) && same;
+  same = (R.val<int>() == P.dedner) && same;
+  same = (R.val<double>() == P.ch_frac) && same;
+  same = (R.val<double>() == P.dedner_damp) && same;
+  same = (R.val<int>() == P.ns_e) && same;
+  same = (R.val<int>() == P.limiter_lag) && same;
+  return same;
+}
+
 }  // namespace
 
 extern "C" {
@@ -134,6 +224,7 @@ int ge_create(const ge_grid* grid, const ge_params* params, void* hip_stream, ge
   if (params->n_smooth_u < 0 || params->beta_lim < 0) return bad("n_smooth_u/beta_lim");
   if (params->ns_j < 0 || !(params->ch_frac >= 0) || !(params->dedner_damp >= 0)) return bad("ns_j/ch_frac/dedner_damp");
   if (params->ns_e < 0) return bad("ns_e");
+  if (params->limiter_lag != GE_LAG_EN && params->limiter_lag != GE_PICARD1) return bad("limiter_lag");
   DGrid& G = c->G;
   G.dim = dim;
   G.N = N;
@@ -355,6 +446,7 @@ int ge_explicit_step(ge_ctx* c) {
   if ((rc = ge_launch_explicit_fields(c))) return rc;
   c->have_deposit = 0;
   c->have_solve = 0;
+  c->steps += 1;
   return check_flags(c);
 }
 
@@ -366,6 +458,20 @@ int ge_solve_fields(ge_ctx* c, double tol, int maxit, int restart, int precond, 
   ge_solve_report r;
   std::memset(&r, 0, sizeof(r));
   int rc = ge_gmres(c, tol, maxit, restart, precond, &r);
+  if (rc >= 0 && c->P.limiter_lag == GE_PICARD1 && c->P.lf_E) {
+    // one Picard step of the limiter: coefficients from the first E^{n+theta},
+    // then the system again, starting from that solution
+    ge_solve_report r2;
+    std::memset(&r2, 0, sizeof(r2));
+    int kr = ge_launch_kappa_E(c, c->Eth);
+    if (kr) return kr;
+    rc = ge_gmres(c, tol, maxit, restart, precond, &r2);
+    r2.iterations += r.iterations;
+    r2.restarts += r.restarts;
+    r2.seconds += r.seconds;
+    r2.fallback |= r.fallback;
+    r = r2;
+  }
   if (rep) *rep = r;
   if (rc < 0) return rc;
   c->have_solve = 1;
@@ -418,6 +524,7 @@ int ge_update_fields(ge_ctx* c) {
   if (rc) return rc;
   c->have_solve = 0;
   c->have_deposit = 0;
+  c->steps += 1;
   return GE_OK;
 }
 
@@ -525,6 +632,192 @@ int ge_diagnostics(ge_ctx* c, ge_diag* out) {
     for (int d = 0; d < 3; ++d) out->P[s][d] = c->sp[s].m * m4[1 + d];
   }
   return check_flags(c);
+}
+
+int64_t ge_step_count(const ge_ctx* c) { return c ? c->steps : -1; }
+
+int64_t ge_species_count(const ge_ctx* c, int s) { return (c && s >= 0 && s < c->nsp) ? c->sp[s].n : -1; }
+
+int ge_checkpoint(ge_ctx* c, const char* path) {
+  if (!c || !path) return GE_ERR_ARG;
+  if (c->have_deposit || c->have_solve)
+    return ge_fail(c, GE_ERR_STATE, "ge_checkpoint between a deposit and its field update");
+  int rc = settle(c);
+  if (rc) return rc;
+  const int64_t N = c->G.N;
+  const size_t es = c->P.precision == GE_FP32 ? 4 : 8;
+  CkptWriter W;
+  W.f = std::fopen(path, "wb");
+  if (!W.f) return ge_fail(c, GE_ERR_ARG, std::string("cannot open ") + path + " for writing");
+  W.put(GE_CKPT_MAGIC, 8);
+  W.val(GE_CKPT_VERSION);
+  put_config(W, c->grid, c->P);
+  W.val(c->steps);
+  W.val(c->nsp);
+  for (int s = 0; s < c->nsp; ++s) {
+    W.val(c->sp[s].q);
+    W.val(c->sp[s].m);
+    W.val(c->sp[s].n);
+  }
+  // fields
+  std::vector<double> hf(3 * N);
+  const double* fsrc[3] = {c->E, c->B, c->psi};
+  const int64_t fcnt[3] = {3 * N, 3 * N, N};
+  for (int k = 0; k < 3 && !rc; ++k) {
+    if (hipMemcpyAsync(hf.data(), fsrc[k], sizeof(double) * fcnt[k], hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess)
+      rc = ge_fail(c, GE_ERR_HIP, "checkpoint: field read-back failed");
+    else
+      W.put(hf.data(), sizeof(double) * fcnt[k]);
+  }
+  // particles in cell order, one species at a time (device staging, then host)
+  for (int s = 0; s < c->nsp && !rc; ++s) {
+    const int64_t n = c->sp[s].n;
+    if (n == 0) continue;
+    char* dbuf = nullptr;
+    const PartStage PS = part_stage(n, es);
+    if (hipMalloc((void**)&dbuf, PS.bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      rc = ge_fail(c, GE_ERR_OOM, "checkpoint: particle staging allocation failed");
+      break;
+    }
+    rc = ge_launch_get_particles(c, s, (int32_t*)(dbuf + PS.at[0]), dbuf + PS.at[1], dbuf + PS.at[2],
+                                 dbuf + PS.at[3]);
+    std::vector<char> hb(PS.seg[0] + PS.seg[1] + PS.seg[2] + PS.seg[3]);
+    size_t o = 0;
+    for (int k = 0; k < 4 && !rc; ++k) {
+      if (hipMemcpyAsync(hb.data() + o, dbuf + PS.at[k], PS.seg[k], hipMemcpyDeviceToHost, c->stream) != hipSuccess)
+        rc = ge_fail(c, GE_ERR_HIP, "checkpoint: particle read-back failed");
+      o += PS.seg[k];
+    }
+    if (!rc && hipStreamSynchronize(c->stream) != hipSuccess)
+      rc = ge_fail(c, GE_ERR_HIP, "checkpoint: particle read-back failed");
+    (void)hipFree(dbuf);
+    if (!rc) W.put(hb.data(), hb.size());
+  }
+  // learned preconditioner
+  int has_cnn = c->cnn ? 1 : 0;
+  std::vector<float> cw, cm, cv;
+  int ct = 0, ccap = 0;
+  if (!rc && has_cnn && ge_cnn_export(c, cw, cm, cv, ct, ccap) != GE_OK) has_cnn = 0;
+  if (!rc) {
+    W.val(has_cnn);
+    if (has_cnn) {
+      const int nw = (int)cw.size();
+      W.val(nw);
+      W.put(cw.data(), sizeof(float) * nw);
+      W.put(cm.data(), sizeof(float) * nw);
+      W.put(cv.data(), sizeof(float) * nw);
+      W.val(ct);
+      W.val(ccap);
+    }
+    const uint64_t sum = W.h;
+    W.val(sum);
+  }
+  const bool ok = W.ok;
+  if (std::fclose(W.f) != 0 && !rc) return ge_fail(c, GE_ERR_ARG, std::string("cannot write ") + path);
+  if (!rc && !ok) return ge_fail(c, GE_ERR_ARG, std::string("cannot write ") + path);
+  return rc;
+}
+
+int ge_restore(ge_ctx* c, const char* path) {
+  if (!c || !path) return GE_ERR_ARG;
+  if (c->nsp != 0) return ge_fail(c, GE_ERR_STATE, "ge_restore needs a context without species");
+  CkptReader R;
+  R.f = std::fopen(path, "rb");
+  if (!R.f) return ge_fail(c, GE_ERR_ARG, std::string("cannot open ") + path);
+  long fsize = -1;
+  if (std::fseek(R.f, 0, SEEK_END) == 0) fsize = std::ftell(R.f);
+  std::rewind(R.f);
+  auto fail = [&](int code, const std::string& m) {
+    std::fclose(R.f);
+    return ge_fail(c, code, "ge_restore: " + m);
+  };
+  char magic[8];
+  R.get(magic, 8);
+  if (!R.ok || std::memcmp(magic, GE_CKPT_MAGIC, 8) != 0) return fail(GE_ERR_ARG, "not a checkpoint file");
+  if (R.val<uint32_t>() != GE_CKPT_VERSION) return fail(GE_ERR_ARG, "unknown checkpoint version");
+  if (!same_config(R, c->grid, c->P)) return fail(GE_ERR_ARG, "grid or parameters differ from the checkpoint's");
+  const int64_t steps = R.val<int64_t>();
+  const int nsp = R.val<int>();
+  if (!R.ok || nsp < 0 || nsp > GE_MAX_SPECIES) return fail(GE_ERR_ARG, "truncated or corrupt header");
+  double q[GE_MAX_SPECIES], m[GE_MAX_SPECIES];
+  int64_t n[GE_MAX_SPECIES];
+  for (int s = 0; s < nsp; ++s) {
+    q[s] = R.val<double>();
+    m[s] = R.val<double>();
+    n[s] = R.val<int64_t>();
+    if (!R.ok || n[s] < 0 || n[s] >= ((int64_t)1 << 31)) return fail(GE_ERR_ARG, "truncated or corrupt header");
+  }
+  const int64_t N = c->G.N;
+  const size_t es = c->P.precision == GE_FP32 ? 4 : 8;
+  {
+    // the declared sizes must fit in the file before anything is allocated
+    uint64_t need = sizeof(double) * 7 * (uint64_t)N;
+    for (int s = 0; s < nsp; ++s) need += (uint64_t)n[s] * (4 + 7 * es);
+    if (fsize < 0 || need > (uint64_t)fsize) return fail(GE_ERR_ARG, "truncated file");
+  }
+  std::vector<double> E(3 * N), B(3 * N), psi(N);
+  R.get(E.data(), sizeof(double) * 3 * N);
+  R.get(B.data(), sizeof(double) * 3 * N);
+  R.get(psi.data(), sizeof(double) * N);
+  std::vector<std::vector<char>> parts(nsp);
+  for (int s = 0; s < nsp && R.ok; ++s) {
+    parts[s].resize((size_t)n[s] * (4 + 7 * es));
+    R.get(parts[s].data(), parts[s].size());
+  }
+  const int has_cnn = R.val<int>();
+  std::vector<float> cw, cm, cv;
+  int ct = 0, ccap = 0;
+  if (R.ok && has_cnn) {
+    const int nw = R.val<int>();
+    if (!R.ok || nw != ge_cnn_size()) return fail(GE_ERR_ARG, "network size differs");
+    cw.resize(nw); cm.resize(nw); cv.resize(nw);
+    R.get(cw.data(), sizeof(float) * nw);
+    R.get(cm.data(), sizeof(float) * nw);
+    R.get(cv.data(), sizeof(float) * nw);
+    ct = R.val<int>();
+    ccap = R.val<int>();
+  }
+  const uint64_t want = R.h;
+  const uint64_t sum = R.val<uint64_t>();
+  if (!R.ok) return fail(GE_ERR_ARG, "truncated file");
+  if (sum != want) return fail(GE_ERR_ARG, "checksum mismatch (corrupt file)");
+  std::fclose(R.f);
+  // species through the loading path (cell order is kept: the file holds them sorted)
+  for (int s = 0; s < nsp; ++s) {
+    char* dbuf = nullptr;
+    const PartStage PS = part_stage(n[s], es);
+    if (hipMalloc((void**)&dbuf, PS.bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      return ge_fail(c, GE_ERR_OOM, "ge_restore: particle staging allocation failed");
+    }
+    int rc = GE_OK;
+    size_t o = 0;
+    for (int k = 0; k < 4 && !rc; ++k) {
+      if (PS.seg[k] &&
+          hipMemcpyAsync(dbuf + PS.at[k], parts[s].data() + o, PS.seg[k], hipMemcpyHostToDevice, c->stream) != hipSuccess)
+        rc = ge_fail(c, GE_ERR_HIP, "ge_restore: particle upload failed");
+      o += PS.seg[k];
+    }
+    if (!rc && hipStreamSynchronize(c->stream) != hipSuccess) rc = ge_fail(c, GE_ERR_HIP, "ge_restore: particle upload failed");
+    ge_species sp{q[s], m[s]};
+    if (!rc)
+      rc = ge_add_species(c, &sp, n[s], (const int32_t*)(dbuf + PS.at[0]), dbuf + PS.at[1], dbuf + PS.at[2],
+                          dbuf + PS.at[3]);
+    (void)hipFree(dbuf);
+    if (rc) return rc;
+  }
+  GE_HIP(c, hipMemcpyAsync(c->E, E.data(), sizeof(double) * 3 * N, hipMemcpyHostToDevice, c->stream));
+  GE_HIP(c, hipMemcpyAsync(c->B, B.data(), sizeof(double) * 3 * N, hipMemcpyHostToDevice, c->stream));
+  GE_HIP(c, hipMemcpyAsync(c->psi, psi.data(), sizeof(double) * N, hipMemcpyHostToDevice, c->stream));
+  GE_HIP(c, hipStreamSynchronize(c->stream));
+  if (has_cnn) {
+    int rc = ge_cnn_import(c, cw.data(), cm.data(), cv.data(), ct, ccap);
+    if (rc) return rc;
+  }
+  c->steps = steps;
+  return GE_OK;
 }
 
 int ge_moves(ge_ctx* c, ge_move_report* out) {

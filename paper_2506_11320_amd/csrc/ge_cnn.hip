@@ -509,6 +509,7 @@ struct ge_cnn_state {
   int ready;
 };
 
+extern "C" int ge_cnn_init(ge_ctx* c, uint32_t seed, int max_pairs);
 static const int64_t CNN_OFF[4] = {0, 27 * 3 * 32, 27 * 3 * 32 + 27 * 32 * 32, 27 * 3 * 32 + 27 * 32 * 32 + 27 * 32 * 3};
 #define CNN_NW (27 * 3 * 32 + 27 * 32 * 32 + 27 * 32 * 3)
 
@@ -755,6 +756,36 @@ static int train_step_grad(ge_ctx* c, double* loss) {
 }
 
 int ge_cnn_harvesting(const ge_ctx* c) { return (c && c->cnn) ? ((ge_cnn_state*)c->cnn)->harvest : 0; }
+
+// Master weights, Adam moments and step of the network (checkpoints).
+int ge_cnn_export(ge_ctx* c, std::vector<float>& w, std::vector<float>& m, std::vector<float>& v, int& t,
+                  int& cap) {
+  ge_cnn_state* s = cnn(c);
+  if (!s || !s->ready) return ge_fail(c, GE_ERR_STATE, "no learned preconditioner");
+  w.resize(CNN_NW);
+  m.resize(CNN_NW);
+  v.resize(CNN_NW);
+  GE_HIP(c, hipMemcpyAsync(w.data(), s->w, sizeof(float) * CNN_NW, hipMemcpyDeviceToHost, c->stream));
+  GE_HIP(c, hipMemcpyAsync(m.data(), s->m, sizeof(float) * CNN_NW, hipMemcpyDeviceToHost, c->stream));
+  GE_HIP(c, hipMemcpyAsync(v.data(), s->v, sizeof(float) * CNN_NW, hipMemcpyDeviceToHost, c->stream));
+  GE_HIP(c, hipStreamSynchronize(c->stream));
+  t = s->adam_t;
+  cap = s->cap_pairs;
+  return GE_OK;
+}
+
+int ge_cnn_import(ge_ctx* c, const float* w, const float* m, const float* v, int t, int cap) {
+  int rc = ge_cnn_init(c, 0, cap);
+  if (rc) return rc;
+  ge_cnn_state* s = cnn(c);
+  GE_HIP(c, hipMemcpyAsync(s->w, w, sizeof(float) * CNN_NW, hipMemcpyHostToDevice, c->stream));
+  GE_HIP(c, hipMemcpyAsync(s->m, m, sizeof(float) * CNN_NW, hipMemcpyHostToDevice, c->stream));
+  GE_HIP(c, hipMemcpyAsync(s->v, v, sizeof(float) * CNN_NW, hipMemcpyHostToDevice, c->stream));
+  s->adam_t = t;
+  rc = pack_weights(c);
+  GE_HIP(c, hipStreamSynchronize(c->stream));  // the host arrays may go out of scope
+  return rc;
+}
 
 // ----------------------------------------------------------------- C ABI
 extern "C" {

@@ -654,6 +654,14 @@ int ge_launch_smooth_current(ge_ctx* c) {
 }
 
 // Everything between the particle deposit and the linear solve.
+// LF coefficients of the E operator from the field E (E^n in the grid pass,
+// the first E^{n+theta} for the Picard step of the limiter)
+int ge_launch_kappa_E(ge_ctx* c, const double* E) {
+  DISPATCH_DIM(c, k_kappa_E, grid1(c->G.N), dim3(256), 0, c->stream, c->G, E, c->anode, c->P.beta_lim, c->kE);
+  GE_HIP(c, hipGetLastError());
+  return GE_OK;
+}
+
 int ge_launch_grid_pass(ge_ctx* c) {
   const DGrid& G = c->G;
   const int64_t N = G.N;

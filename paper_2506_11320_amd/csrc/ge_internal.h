@@ -201,6 +201,7 @@ struct ge_ctx {
   int have_deposit, have_solve;
   int push_pending;      // a push ran whose statistics (and far movers) are not settled yet
   int device;            // HIP device the context was created on
+  int64_t steps;         // completed steps (field updates)
   MoveStats moves;
   FarScratch fx;
   void* cnn;           // learned preconditioner state (ge_cnn.hip), lazily created
@@ -236,6 +237,7 @@ int ge_launch_explicit_linear(ge_ctx* c, int mode);  // explicit-PIC passes (ge_
 int ge_launch_explicit_fields(ge_ctx* c);    // leapfrog E and B update with c->Jeff
 int ge_launch_node_avg(ge_ctx* c);
 int ge_launch_apply_A(ge_ctx* c, const double* x, double* y);
+int ge_launch_kappa_E(ge_ctx* c, const double* E);  // E limiter coefficients from E
 int ge_launch_update(ge_ctx* c);
 int ge_launch_widen_M(ge_ctx* c, const void* M, double* dst);
 int ge_launch_pack_node8(ge_ctx* c, int half);  // half 0: E^{n+theta} from Eth, 1: B from Bn
@@ -254,3 +256,6 @@ int ge_cnn_apply_grid(ge_ctx* c, const double* v, double* z, double scale);  // 
 void ge_cnn_free(ge_ctx* c);
 extern "C" int ge_cnn_add_pair(ge_ctx* c, const double* r, const double* e);
 int ge_cnn_harvesting(const ge_ctx* c);
+#include <vector>
+int ge_cnn_export(ge_ctx* c, std::vector<float>& w, std::vector<float>& m, std::vector<float>& v, int& t, int& cap);
+int ge_cnn_import(ge_ctx* c, const float* w, const float* m, const float* v, int t, int cap);

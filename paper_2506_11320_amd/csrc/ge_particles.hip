@@ -801,9 +801,14 @@ __global__ __launch_bounds__(64) void k_deposit(DGrid G, DepArgs<T> A) {
     for (int s = 0; s < A.nsp; ++s) {
       const DepSpecies<T>& S = A.sp[s];
       const int total = L.total[s];
-      v4 acc[NRB];
+      // the MFMA sums each chunk of up to 64 particles from zero; the chunk
+      // sums of a species are added with a compensated (Neumaier) sum, so
+      // that many chunks (hundreds of particles per cell) do not accumulate
+      // FP32 rounding in the matrix core
+      v4 acc[NRB], cmp[NRB];
 #pragma unroll
-      for (int rb = 0; rb < NRB; ++rb) acc[rb] = v4{0, 0, 0, 0};
+      for (int rb = 0; rb < NRB; ++rb) acc[rb] = cmp[rb] = v4{0, 0, 0, 0};
+      int nchunk = 0;
       // one chunk of up to 64 particles: operands to LDS, then the MFMA sweep
       auto chunk = [&](const PState<T>& q, int t0) {
         // lanes past the count take a zero weight (all B columns vanish) at
@@ -887,6 +892,9 @@ __global__ __launch_bounds__(64) void k_deposit(DGrid G, DepArgs<T> A) {
             a[1][i] = NRB == 2 ? rows[rofsA1] : (T)0;
           }
         };
+        v4 cacc[NRB];
+#pragma unroll
+        for (int rb = 0; rb < NRB; ++rb) cacc[rb] = v4{0, 0, 0, 0};
         rd(0, ca, cb);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -898,8 +906,8 @@ __global__ __launch_bounds__(64) void k_deposit(DGrid G, DepArgs<T> A) {
           __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
-            acc[0] = M::op(ca[0][i], cb[i], acc[0]);
-            if (NRB == 2) acc[NRB - 1] = M::op(ca[1][i], cb[i], acc[NRB - 1]);
+            cacc[0] = M::op(ca[0][i], cb[i], cacc[0]);
+            if (NRB == 2) cacc[NRB - 1] = M::op(ca[1][i], cb[i], cacc[NRB - 1]);
           }
           __builtin_amdgcn_sched_barrier(0);
           if (g < 3) {
@@ -912,6 +920,20 @@ __global__ __launch_bounds__(64) void k_deposit(DGrid G, DepArgs<T> A) {
           }
         }
         wave_sync();
+        if (nchunk == 0) {
+#pragma unroll
+          for (int rb = 0; rb < NRB; ++rb) acc[rb] = cacc[rb];
+        } else {
+#pragma unroll
+          for (int rb = 0; rb < NRB; ++rb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const T a = acc[rb][i], x = cacc[rb][i], t = a + x;
+              cmp[rb][i] += fabs(a) >= fabs(x) ? (a - t) + x : (x - t) + a;
+              acc[rb][i] = t;
+            }
+        }
+        ++nchunk;
       };
       // particles 0..127 of species 0 and 1 come from the prefetched registers
       // (selected with compile-time indices: a dynamic index would send the
@@ -932,7 +954,7 @@ __global__ __launch_bounds__(64) void k_deposit(DGrid G, DepArgs<T> A) {
       for (int rb = 0; rb < NRB; ++rb)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          const T val = acc[rb][i];
+          const T val = acc[rb][i] + cmp[rb][i];
           aMt[rb][i] += bq * val;
           aM0[rb][i] += qs * val;
           aLin[rb][i] += ls * val;

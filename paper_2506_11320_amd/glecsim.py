@@ -21,6 +21,7 @@ GE_WARN_NOT_CONVERGED = 1
 GE_FP64, GE_FP32 = 0, 1
 GE_A_LIGHT, GE_A_BULK = 0, 1
 GE_PC_NONE, GE_PC_JACOBI, GE_PC_CNN = 0, 1, 2
+GE_LAG_EN, GE_PICARD1 = 0, 1
 GE_HARVEST_SOLUTION, GE_HARVEST_KRYLOV = 1, 2
 FIELDS = {
     "E": 0, "B": 1, "Eth": 2, "Bn": 3, "J_lab": 4, "J_eff": 5, "rho": 6, "mm": 7, "mass": 8, "u": 9,
@@ -30,7 +31,7 @@ EXPORTS = [
     "ge_create", "ge_destroy", "ge_last_error", "ge_add_species", "ge_set_fields", "ge_deposit", "ge_solve_fields",
     "ge_push", "ge_update_fields", "ge_step", "ge_sync", "ge_gather", "ge_set", "ge_half_stencil",
     "ge_get_particles", "ge_apply_operator", "ge_diagnostics", "ge_timings", "ge_explicit_current", "ge_explicit_step",
-    "ge_moves", "ge_diagnostics_noalloc",
+    "ge_moves", "ge_diagnostics_noalloc", "ge_step_count", "ge_species_count", "ge_checkpoint", "ge_restore",
     "ge_cnn_init", "ge_cnn_size", "ge_cnn_weights", "ge_cnn_apply", "ge_cnn_harvest", "ge_cnn_add_pair",
     "ge_cnn_npairs", "ge_cnn_train", "ge_cnn_loss_grad",
 ]
@@ -46,7 +47,7 @@ class GEParams(ctypes.Structure):
                 ("a_mode", ctypes.c_int), ("a_const", ctypes.c_double), ("comoving", ctypes.c_int),
                 ("n_smooth_u", ctypes.c_int), ("phi_u", ctypes.c_double), ("precision", ctypes.c_int),
                 ("ns_j", ctypes.c_int), ("dedner", ctypes.c_int), ("ch_frac", ctypes.c_double),
-                ("dedner_damp", ctypes.c_double), ("ns_e", ctypes.c_int)]
+                ("dedner_damp", ctypes.c_double), ("ns_e", ctypes.c_int), ("limiter_lag", ctypes.c_int)]
 
 
 class GESpecies(ctypes.Structure):
@@ -120,6 +121,12 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.ge_timings.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
     L.ge_moves.argtypes = [vp, ctypes.POINTER(GEMoveReport)]
     L.ge_diagnostics_noalloc.argtypes = [vp, ctypes.POINTER(GEDiag)]
+    L.ge_step_count.argtypes = [vp]
+    L.ge_step_count.restype = ctypes.c_int64
+    L.ge_species_count.argtypes = [vp, ctypes.c_int]
+    L.ge_species_count.restype = ctypes.c_int64
+    L.ge_checkpoint.argtypes = [vp, ctypes.c_char_p]
+    L.ge_restore.argtypes = [vp, ctypes.c_char_p]
     L.ge_cnn_init.argtypes = [vp, ctypes.c_uint32, ctypes.c_int]
     L.ge_cnn_size.argtypes = []
     L.ge_cnn_weights.argtypes = [vp, ctypes.c_int, vp]
@@ -152,7 +159,8 @@ class Simulation:
                  lf_B: bool = True, beta_lim: float = 1.0, a_mode: int = GE_A_BULK, a_const: float = 1.0,
                  comoving: bool = True, n_smooth_u: int = 5, phi_u: float = 0.5, fp32: bool = False,
                  ns_j: int = 0, dedner: bool = False, ch_frac: float = 0.8, dedner_damp: float = 0.1,
-                 ns_e: int = 0, device: str = "cuda:0", stream: Optional[torch.cuda.Stream] = None):
+                 ns_e: int = 0, limiter_lag: int = GE_LAG_EN, device: str = "cuda:0",
+                 stream: Optional[torch.cuda.Stream] = None):
         if not torch.cuda.is_available():
             raise RuntimeError("glecsim needs a GPU (no CPU fallback)")
         self.L = load_library()
@@ -171,7 +179,7 @@ class Simulation:
             g.dx[d] = float(dx[d]) if d < dim else 1.0
         p = GEParams(theta, c, dt, int(lf_E), int(lf_B), beta_lim, a_mode, a_const, int(comoving), n_smooth_u,
                      phi_u, GE_FP32 if fp32 else GE_FP64, int(ns_j), int(dedner), ch_frac, dedner_damp,
-                     int(ns_e))
+                     int(ns_e), int(limiter_lag))
         self.params = p
         with torch.cuda.device(self.device):
             self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
@@ -252,6 +260,24 @@ class Simulation:
 
     def sync(self):
         self._check(self.L.ge_sync(self.h))
+
+    def step_count(self) -> int:
+        return int(self.L.ge_step_count(self.h))
+
+    def checkpoint(self, path: str):
+        self._check(self.L.ge_checkpoint(self.h, os.fsencode(path)))
+
+    def restore(self, path: str):
+        """Restore a checkpoint into this (species-less) context; the species
+        counts come from the file."""
+        self._check(self.L.ge_restore(self.h, os.fsencode(path)))
+        d = GEDiag()
+        self._check(self.L.ge_diagnostics(self.h, ctypes.byref(d)))
+        self.nsp = d.nsp
+        self.counts = [self._species_count(s) for s in range(self.nsp)]
+
+    def _species_count(self, s: int) -> int:
+        return int(self.L.ge_species_count(self.h, s))
 
     # -------------------------------------------------------------- data
     def half_stencil(self) -> int:

@@ -87,3 +87,13 @@ def oracle_grid_pass(wl, G, sp, E, B, comoving=None, beta_lim=None, a_mode=None,
     dep["J_s"] = Js
     dep["J_scale"] = sum(np.linalg.norm(j) for j in Js)
     return dep
+
+
+def make_bare_sim(wl, **over):
+    """A context with the workload's grid and parameters and no species (for
+    ge_restore)."""
+    from paper_2506_11320_amd import Simulation
+    kw = dict(theta=wl.theta, dt=wl.dt, lf_E=wl.lf_E, lf_B=wl.lf_B, beta_lim=wl.beta_lim, a_mode=wl.a_mode,
+              a_const=1.0, comoving=wl.comoving, n_smooth_u=wl.n_smooth_u, fp32=wl.fp32)
+    kw.update(over)
+    return Simulation(wl.dim, wl.n, wl.dx, **kw)

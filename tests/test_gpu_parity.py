@@ -25,6 +25,9 @@ CASES = [
     ("3d_fp32", 3, (5, 3, 3), 70, "c5", True),
     # more than 128 particles per cell: the two-pass push and 3-chunk deposit
     ("3d_fp32_dense", 3, (4, 3, 3), 150, "c5", True),
+    # the paper's baseline particle count (Table 1: 1600 per cell per species),
+    # 25 chunks per species and cell in FP32
+    ("2d_fp32_1600ppc", 2, (4, 3, 1), 1600, "c3", True),
 ]
 
 
@@ -52,6 +55,11 @@ def test_deposit_and_grid_pass(name, dim, n, ppc, base, fp32):
     g = {k: sim.gather(k).cpu().numpy() for k in ["Bn", "J_lab", "J_eff", "rho", "mm", "mass", "u", "EM", "Mt",
                                                   "M0", "kappa_E", "kappa_B", "rhs"]}
     tol = _tol(fp32)
+    errs = {"J_lab": H.relerr(g["J_lab"], ref["J_lab"], ref["J_scale"]),
+            "Mt": H.relerr(g["Mt"], H.half_from_full(ref["Mt"], dim)),
+            "M0": H.relerr(g["M0"], H.half_from_full(ref["M0"], dim)),
+            "J_eff": H.relerr(g["J_eff"], ref["J_eff"], ref["J_scale"])}
+    print("  errors " + " ".join(f"{k} {v:.2e}" for k, v in errs.items()), flush=True)
     assert H.relerr(g["Bn"], ref["Bn"]) < 1e-14
     assert H.relerr(g["J_lab"], ref["J_lab"], ref["J_scale"]) < tol
     assert H.relerr(g["Mt"], H.half_from_full(ref["Mt"], dim)) < tol
@@ -259,4 +267,31 @@ def test_full_step_matches_oracle_c1():
         d = (xg - xo[order, 0] + 0.5 * L) % L - 0.5 * L
         assert np.abs(d).max() < 1e-12
         assert np.abs(got["v"].T - r["species"][s].v[order]).max() < 1e-12
+    sim.close()
+
+
+@pytest.mark.parametrize("name,dim,n,ppc,base,fp32", CASES)
+def test_diagnostics_match_oracle(name, dim, n, ppc, base, fp32):
+    """The FP64 reductions of ge_diagnostics against the oracle on the same
+    state: W_E, W_B (fields), K_s and P_s (particles, the FP32 path's records
+    widened exactly), and the Gauss residual with the charge density of the
+    deposit (1e-10 in FP64, 1e-5 with the FP32 deposit)."""
+    print(f"[gpu] diagnostics parity {name}", flush=True)
+    wl = _wl(dim, n, ppc, base, fp32)
+    parts = H.species_arrays(wl, fp32)
+    E, B = H.perturbed_fields(wl)
+    G, sp = H.oracle_species(wl, parts)
+    dep = O.deposit(G, sp, wl.dt, B, wl.comoving, wl.n_smooth_u)
+    ref = O.diagnostics(G, sp, E, B, rho_s=dep["rho_s"])
+    sim = H.make_sim(wl, parts, E, B)
+    sim.deposit()
+    got = sim.diagnostics()
+    assert abs(got["W_E"] - ref["W_E"]) <= 1e-12 * ref["W_E"]
+    assert abs(got["W_B"] - ref["W_B"]) <= 1e-12 * ref["W_B"]
+    for s in range(wl.nsp):
+        assert abs(got["K"][s] - ref["K"][s]) <= 1e-12 * ref["K"][s]
+        pscale = sp[s].m * np.sum(sp[s].w * np.linalg.norm(sp[s].v, axis=1))
+        assert np.abs(np.array(got["P"][s]) - ref["P"][s]).max() <= 1e-12 * pscale
+    assert ref["gauss"] > 0
+    assert abs(got["gauss"] - ref["gauss"]) <= (1e-5 if fp32 else 1e-10) * ref["gauss"]
     sim.close()

@@ -498,3 +498,86 @@ def test_half_offset_enumeration():
     for o in O.half_offsets(3):
         assert tuple(-c for c in o) not in seen or o == (0, 0, 0)
         seen.add(o)
+
+
+@pytest.mark.parametrize("dim", [1, 2, 3])
+def test_node_average_is_exact_on_linear_fields(dim):
+    """The node average of a cell-centred field (the B interpolated to the
+    particles) reproduces a linear field exactly at the node: the 2^dim cells
+    around node g have centres x_g +- dx/2 per axis.  Nodes whose cells wrap
+    around the periodic boundary are left out.  A wrong cell offset (cells
+    g..g+1 instead of g-1..g) would give the field at x_g + dx: the check
+    tells the two apart."""
+    n = (7, 6, 5)[:dim] + (1,) * (3 - dim)
+    dx = (0.5, 0.4, 0.3)[:dim] + (1.0,) * (3 - dim)
+    G = O.grid(dim, n, dx)
+    N = O.nnodes(G)
+    idx = np.stack(np.unravel_index(np.arange(N), n[::-1])[::-1])  # (i, j, k) per linear index
+    xc = (idx + 0.5) * np.array(dx)[:, None]
+    xn = idx * np.array(dx)[:, None]
+    coef = np.array([[0.3, 1.7, -0.6, 0.25], [-1.1, 0.4, 2.2, -0.9], [0.05, -2.0, 0.7, 1.3]])
+
+    def lin(x):
+        return np.stack([c[0] + sum(c[1 + d] * x[d] for d in range(dim)) for c in coef])
+
+    Bn = O.node_avg(G, lin(xc))
+    inner = np.all(idx[:dim] >= 1, axis=0)
+    assert inner.sum() > 0
+    np.testing.assert_allclose(Bn[:, inner], lin(xn)[:, inner], rtol=0, atol=1e-13)
+    shifted = lin(xn + np.array(dx)[:, None] * (np.arange(3) < dim)[:, None])
+    assert np.abs(Bn[:, inner] - shifted[:, inner]).max() > 0.1
+    # a uniform field stays uniform
+    U = np.array([0.2, -0.7, 1.9])[:, None] * np.ones((3, N))
+    np.testing.assert_allclose(O.node_avg(G, U), U, rtol=1e-15, atol=0)
+
+
+@pytest.mark.parametrize("species_split", [1, 2])
+def test_gauss_residual_vanishes_for_a_discrete_poisson_mode(species_split):
+    """Closed form of the discrete Gauss residual: for E_x = A sin(kx x)
+    cos(ky y) at the nodes, div_NC E at the cell centre is
+    (2A/dx) sin(kx dx/2) cos(kx x_c) cos(ky y_c) cos(ky dy/2) (face means), and
+    the cell mean of the node charge rho = R cos(kx x) cos(ky y) is
+    R cos(kx x_c) cos(kx dx/2) cos(ky y_c) cos(ky dy/2); so with
+    R = A tan(kx dx/2) / (2 pi dx) the residual is zero to rounding, while
+    the continuum amplitude R = A kx / (4 pi) leaves a residual of the size of
+    the discretisation error.  The charge may be split over species."""
+    n, dx = (8, 6, 5), (0.5, 0.4, 0.3)
+    G = O.grid(3, n, dx)
+    N = O.nnodes(G)
+    idx = np.stack(np.unravel_index(np.arange(N), n[::-1])[::-1])
+    x, y = idx[0] * dx[0], idx[1] * dx[1]
+    kx, ky = 2 * math.pi * 2 / (n[0] * dx[0]), 2 * math.pi / (n[1] * dx[1])
+    A = 0.37
+    E = np.zeros((3, N))
+    E[0] = A * np.sin(kx * x) * np.cos(ky * y)
+    R = A * math.tan(0.5 * kx * dx[0]) / (2 * math.pi * dx[0])
+    rho = R * np.cos(kx * x) * np.cos(ky * y)
+    rho_s = [rho / species_split] * species_split
+    assert O.gauss_residual(G, E, rho_s) < 1e-13
+    rho_c = (A * kx / (4 * math.pi)) * np.cos(kx * x) * np.cos(ky * y)
+    r_cont = O.gauss_residual(G, E, [rho_c])
+    assert 1e-3 < r_cont < 0.5
+    # and the residual is relative to the charge, not to E
+    assert abs(O.gauss_residual(G, 10 * E, [10 * rho]) - O.gauss_residual(G, E, [rho])) < 1e-13
+
+
+def test_picard_limiter_step():
+    """The one-step Picard option of the E limiter (Sec. 2.2: the ratio uses
+    the unknown E^{n+theta}): its E^{n+theta} solves the system whose limiter
+    is taken from the lagged solution; with beta = 0 the limiter is the
+    constant phi = 0, so the option changes nothing; and with the limiter
+    active it changes the answer."""
+    wl, G, E, Bc, sp = _tiny_plasma(3, (4, 3, 3), 6)
+    E = E + 0.05 * np.random.default_rng(3).standard_normal(E.shape)
+    kw = dict(dt=wl.dt, theta=0.5, comoving=True, lf_E=True, lf_B=True, a_mode=0, solve="dense")
+    lag = O.step(G, sp, E, Bc, beta_lim=1.5, **kw)
+    pic = O.step(G, sp, E, Bc, beta_lim=1.5, limiter_lag="picard1", **kw)
+    kE1 = O.kappa_E(G, lag["Eth"], pic["a_node"], 1.5)
+    np.testing.assert_array_equal(pic["kE"], kE1)
+    P = O.params(0.5, wl.dt)
+    res = O.apply_A(G, P, pic["dep"]["Mt"], kE1, pic["Eth"]) - pic["b"]
+    assert np.linalg.norm(res) <= 1e-12 * np.linalg.norm(pic["b"])
+    assert np.abs(pic["Eth"] - lag["Eth"]).max() > 1e-8 * np.abs(lag["Eth"]).max()
+    lag0 = O.step(G, sp, E, Bc, beta_lim=0.0, **kw)
+    pic0 = O.step(G, sp, E, Bc, beta_lim=0.0, limiter_lag="picard1", **kw)
+    np.testing.assert_allclose(pic0["Eth"], lag0["Eth"], rtol=0, atol=1e-13 * np.abs(lag0["Eth"]).max())
