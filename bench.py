@@ -42,7 +42,7 @@ METRIC = "particle-steps/s (push+deposit); GMRES s/step plain vs NN-precond at 1
 
 # what each synthetic workload stands for
 KIND = {"c1": "1D3V shock tube", "c2": "2D3V uniform fast flow", "c3": "2D3V Harris-sheet reconnection",
-        "c4": "3D3V colliding-flow shock", "c5": "3D3V double-Harris reconnection with a 0.2c guide flow",
+        "c4": "3D3V shock: flow at -0.15c onto a reflecting wall, inflow at x = L", "c4p": "3D3V colliding-flow shock (periodic)", "c5": "3D3V double-Harris reconnection with a 0.2c guide flow",
         "ff1d": "1D3V uniform fast flow (solar wind)"}
 
 

@@ -18,8 +18,9 @@
  *             by cell with a stable integer sort
  *
  * Mesh: E at nodes, B at cell centres (Sec. 2.1); node (i,j,k) at
- * (i dx, j dy, k dz), cell (i,j,k) centred at ((i+1/2) dx, ...).  Every
- * active axis is periodic and needs at least 3 cells.  Grid arrays are
+ * (i dx, j dy, k dz), cell (i,j,k) centred at ((i+1/2) dx, ...).  Active
+ * axes are periodic (x may instead end in walls or an inflow plane, see
+ * ge_grid) and need at least 3 cells.  Grid arrays are
  * component-major [ncomp][N], linear index i + nx*(j + ny*k), N = cells =
  * nodes.  Units are the normalised Gaussian units of the paper (c, 4 pi).
  *
@@ -61,6 +62,7 @@ enum { GE_FP64 = 0, GE_FP32 = 1 };           /* particle and mass-matrix precisi
 enum { GE_A_LIGHT = 0, GE_A_BULK = 1 };      /* diffusion speed a: c, or |u| */
 enum { GE_PC_NONE = 0, GE_PC_JACOBI = 1, GE_PC_CNN = 2 };  /* GMRES preconditioner */
 enum { GE_LAG_EN = 0, GE_PICARD1 = 1 };      /* E limiter: lagged to E^n, or one Picard step */
+enum { GE_BC_PERIODIC = 0, GE_BC_WALL = 1, GE_BC_INFLOW = 2 };  /* boundary kinds (ge_grid) */
 
 typedef struct ge_ctx ge_ctx;
 
@@ -68,6 +70,21 @@ typedef struct {
   int dim;        /* 1, 2 or 3 active axes (x, then y, then z) */
   int n[3];       /* cells per axis; n[d] >= 3 for active d, 1 otherwise */
   double dx[3];   /* spacing per active axis */
+  /* Boundary kinds of the low and high end of each axis.  Every axis is
+   * GE_BC_PERIODIC except, optionally, x: bc_lo[0] = GE_BC_WALL (a conducting,
+   * specularly reflecting wall at x = 0) with bc_hi[0] = GE_BC_WALL or
+   * GE_BC_INFLOW (x = L: E held at its value, upstream B in the ghost cell,
+   * particles leave through it; new ones come through ge_inject).  The paper
+   * runs its shocks as flows against a boundary (Sec. 4.3, 4.4) but prints no
+   * boundary discretisation; the readings: a wall is the mirror plane of the
+   * domain (tangential E and normal B odd, normal E and tangential B even),
+   * the tangential E on a wall and all of E on an inflow plane are held, no
+   * LF flux crosses a boundary (phi = 0 on the face next to a wall), the
+   * filter mirrors (normal component odd), and no image charge is deposited.
+   * A walled grid stores n[0] + 1 points along x: nodes 0..n[0], the cells
+   * 0..n[0]-1 and a ghost cell n[0] (the inflow's upstream B), so every array
+   * below has N = (n[0] + 1) n[1] n[2] entries per component. */
+  int bc_lo[3], bc_hi[3];
 } ge_grid;
 
 typedef struct {
@@ -156,6 +173,16 @@ const char* ge_last_error(const ge_ctx* ctx);
  * Errors: GE_ERR_ARG if unsorted, out of range or too many species. */
 int ge_add_species(ge_ctx* ctx, const ge_species* sp, int64_t n, const int32_t* cell, const void* off,
                    const void* v, const void* w);
+
+/* Add m particles to species s (new particles entering through an inflow
+ * plane, Sec. 4.3-4.4's driven shocks), with the layout of ge_add_species:
+ * cell[m] int32 (a cell of the domain, not the ghost), off[3][m], v[3][m],
+ * w[m] (device, read during the call).  They join the species at the next
+ * synchronising call (with the particles of the last push): in their cell
+ * they follow the particles already there, in the given order.  Call between
+ * steps (not between a deposit and its field update).  The library grows its
+ * particle buffers as needed. */
+int ge_inject(ge_ctx* ctx, int s, int64_t m, const int32_t* cell, const void* off, const void* v, const void* w);
 
 /* Copy initial fields: E at nodes, B at cell centres; device double [3][N]. */
 int ge_set_fields(ge_ctx* ctx, const double* E_nodes, const double* B_cells);
@@ -273,6 +300,8 @@ typedef struct {
   double max_move[4];
   int resorts;
   int pushes;
+  int64_t gone[4];       /* particles that left through an inflow plane */
+  int64_t injected[4];   /* particles added by ge_inject */
 } ge_move_report;
 int ge_moves(ge_ctx* ctx, ge_move_report* out);
 

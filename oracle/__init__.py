@@ -28,8 +28,14 @@ _i64 = ctypes.c_int64
 _p = ctypes.c_void_p
 
 
+BC_PERIODIC, BC_WALL, BC_INFLOW = 0, 1, 2
+
+
 class Grid(ctypes.Structure):
-    _fields_ = [("dim", ctypes.c_int), ("n", ctypes.c_int * 3), ("dx", ctypes.c_double * 3)]
+    # bc_lo, bc_hi: the x axis's boundaries (see glecsim_oracle.h); a walled
+    # grid stores n[0] = nx + 1 points along x (ghost cell nx)
+    _fields_ = [("dim", ctypes.c_int), ("n", ctypes.c_int * 3), ("dx", ctypes.c_double * 3),
+                ("bc_lo", ctypes.c_int), ("bc_hi", ctypes.c_int)]
 
 
 class Params(ctypes.Structure):
@@ -80,7 +86,7 @@ def lib():
         L.or_rhs.argtypes = [G, P, _p, _p, _p, _p]
         L.or_update_B.argtypes = [G, P, _p, _p, _p, _p]
         L.or_update_E.argtypes = [_i64, _d, _p, _p, _p]
-        L.or_push_species.argtypes = [G, _d, _d, _i64, _p, _p, _p, _p, _p, _p]
+        L.or_push_species.argtypes = [G, _d, _d, _i64, _p, _p, _p, _p, _p, _p, _p]
         L.or_gmres.restype = ctypes.c_int
         L.or_gmres.argtypes = [G, P, _p, _p, _p, _p, _d, ctypes.c_int, ctypes.c_int, _p]
         L.or_dense_A.argtypes = [G, P, _p, _p, _p]
@@ -102,13 +108,32 @@ def _f64(a) -> np.ndarray:
     return np.ascontiguousarray(a, dtype=np.float64)
 
 
-def grid(dim: int, n, dx) -> Grid:
+def grid(dim: int, n, dx, bc=(BC_PERIODIC, BC_PERIODIC)) -> Grid:
+    """n: cells per axis; with walls on x (bc = (BC_WALL, BC_WALL or
+    BC_INFLOW)) n[0] counts the physical cells and the grid stores n[0] + 1
+    points along x."""
     g = Grid()
     g.dim = dim
     for d in range(3):
         g.n[d] = int(n[d]) if d < dim else 1
         g.dx[d] = float(dx[d]) if d < dim else 1.0
+    g.bc_lo, g.bc_hi = int(bc[0]), int(bc[1])
+    if g.bc_lo != BC_PERIODIC:
+        g.n[0] += 1
     return g
+
+
+def walled(G: Grid) -> bool:
+    return G.bc_lo != BC_PERIODIC
+
+
+def physical_cells(G: Grid) -> np.ndarray:
+    """Mask of the physical cells of the storage grid (all but the ghost
+    cell column of a walled grid)."""
+    N = nnodes(G)
+    if not walled(G):
+        return np.ones(N, bool)
+    return (np.arange(N) % G.n[0]) < G.n[0] - 1
 
 
 def params(theta: float, dt: float, c: float = 1.0) -> Params:
@@ -364,12 +389,19 @@ def update_E(theta: float, En, Eth) -> np.ndarray:
     return out
 
 
-def push_species(G: Grid, beta: float, dt: float, x, v, Eth, Bn):
-    """Implicit mover (Sec. 3.1): returns (x^{n+3/2}, v^{n+1})."""
-    x, v, Eth, Bn = _f64(x), _f64(v), _f64(Eth), _f64(Bn)
-    xn, vn = np.empty_like(x), np.empty_like(v)
-    lib().or_push_species(ctypes.byref(G), beta, dt, x.shape[0], _ptr(x), _ptr(v), _ptr(Eth), _ptr(Bn),
-                          _ptr(xn), _ptr(vn))
+def push_species(G: Grid, beta: float, dt: float, x, v, Eth, Bn, with_keep: bool = False):
+    """Implicit mover (Sec. 3.1).  Returns (x_new, v_new), and with
+    with_keep the mask of particles that stay in the domain (a walled grid
+    with an inflow plane loses the particles that cross it)."""
+    x, v = _f64(x), _f64(v)
+    n = x.shape[0]
+    xn = np.empty_like(x)
+    vn = np.empty_like(v)
+    keep = np.ones(n, np.int32)
+    lib().or_push_species(ctypes.byref(G), beta, dt, n, _ptr(x), _ptr(v), _ptr(_f64(Eth)), _ptr(_f64(Bn)),
+                          _ptr(xn), _ptr(vn), keep.ctypes.data)
+    if with_keep:
+        return xn, vn, keep.astype(bool)
     return xn, vn
 
 
@@ -557,13 +589,25 @@ def diffusion_speed(G: Grid, u, a_mode: int, c: float = 1.0) -> np.ndarray:
     return np.sqrt((np.asarray(u) ** 2).sum(axis=0))
 
 
+def node_weights(G: Grid) -> np.ndarray:
+    """Control-volume weights of the nodes: 1, and 1/2 on the boundary node
+    planes of a walled grid (the trapezoid rule of the mirror-doubled domain)."""
+    N = nnodes(G)
+    w = np.ones(N)
+    if walled(G):
+        i = np.arange(N) % G.n[0]
+        w[(i == 0) | (i == G.n[0] - 1)] = 0.5
+    return w
+
+
 def diagnostics(G: Grid, species: List[Species], E, Bc, rho_s=None) -> Dict[str, object]:
-    """Energies and momenta in FP64: W_E = sum |E|^2 dV / 8pi over nodes,
-    W_B over cells, K_s = sum 1/2 m_s w |v|^2, P_s = sum m_s w v; with the
+    """Energies and momenta in FP64: W_E = sum |E|^2 dV / 8pi over nodes
+    (half weight on the boundary planes of a walled grid), W_B over the
+    physical cells, K_s = sum 1/2 m_s w |v|^2, P_s = sum m_s w v; with the
     node charge densities rho_s (per species) also the Gauss residual."""
     dV = cellvol(G)
-    WE = float((np.asarray(E) ** 2).sum() * dV / (8 * math.pi))
-    WB = float((np.asarray(Bc) ** 2).sum() * dV / (8 * math.pi))
+    WE = float((node_weights(G) * (np.asarray(E) ** 2).sum(axis=0)).sum() * dV / (8 * math.pi))
+    WB = float((np.asarray(Bc)[:, physical_cells(G)] ** 2).sum() * dV / (8 * math.pi))
     K = [float(0.5 * sp.m * (sp.w[:, None] * sp.v ** 2).sum()) for sp in species]
     P = [(sp.m * (sp.w[:, None] * sp.v).sum(axis=0)) for sp in species]
     out = {"W_E": WE, "W_B": WB, "K": K, "P": P}
@@ -576,7 +620,8 @@ def step(G: Grid, species: List[Species], E, Bc, *, dt: float, theta: float, c: 
          comoving: bool = False, lf_E: bool = False, lf_B: bool = False, beta_lim: float = 1.0,
          a_mode: int = 1, n_smooth_u: int = 5, tol: float = 1e-12, restart: int = 30,
          solve: str = "gmres", n_smooth_j: int = 0, dedner: bool = False, ch_frac: float = 0.8,
-         dedner_damp: float = 0.1, psi=None, n_smooth_e: int = 0, limiter_lag: str = "en") -> Dict[str, object]:
+         dedner_damp: float = 0.1, psi=None, n_smooth_e: int = 0, limiter_lag: str = "en",
+         inject=None) -> Dict[str, object]:
     """One full GL-ECSIM step without the Gauss's-law correction:
     deposit -> implicit E solve -> B and E update -> particle push.
     With dedner, the cleaning scalar psi (cells, zero if None) is advanced
@@ -586,7 +631,10 @@ def step(G: Grid, species: List[Species], E, Bc, *, dt: float, theta: float, c: 
     The E limiter's smoothness ratio is taken from the unknown E^{n+theta} in
     Sec. 2.2, which makes the system nonlinear.  limiter_lag "en" takes it
     from E^n (one linear solve); "picard1" then takes one Picard step: the
-    limiter from that first E^{n+theta}, and the system solved again from it."""
+    limiter from that first E^{n+theta}, and the system solved again from it.
+    On a walled grid particles reflect on walls and leave through an inflow
+    plane; inject (one (x, v, w) triple or None per species) appends
+    particles after the push."""
     P = params(theta, dt, c)
     dep = deposit(G, species, dt, Bc, comoving, n_smooth_u, n_smooth_j=n_smooth_j)
     a_node = diffusion_speed(G, dep["u"], a_mode, c)
@@ -615,9 +663,16 @@ def step(G: Grid, species: List[Species], E, Bc, *, dt: float, theta: float, c: 
     Enew = update_E(theta, E, Eth)
     if n_smooth_e:
         Enew = smooth(G, Enew, n_smooth_e)
-    new_species = []
-    for sp in species:
-        xn, vn = push_species(G, beta_s(sp.q, sp.m, dt), dt, sp.x, sp.v, Eth, dep["Bn"])
-        new_species.append(Species(sp.q, sp.m, xn, vn, sp.w))
+    new_species, kept = [], []
+    for k, sp in enumerate(species):
+        xn, vn, keep = push_species(G, beta_s(sp.q, sp.m, dt), dt, sp.x, sp.v, Eth, dep["Bn"], with_keep=True)
+        x2, v2, w2 = xn[keep], vn[keep], sp.w[keep]
+        if inject is not None and inject[k] is not None:
+            xi, vi, wi = inject[k]
+            x2 = np.concatenate([x2, _f64(xi).reshape(-1, 3)])
+            v2 = np.concatenate([v2, _f64(vi).reshape(-1, 3)])
+            w2 = np.concatenate([w2, _f64(wi).reshape(-1)])
+        new_species.append(Species(sp.q, sp.m, x2, v2, w2))
+        kept.append(keep)
     return {"dep": dep, "kE": kE, "kB": kB, "b": b, "Eth": Eth, "E": Enew, "B": Bnew,
-            "species": new_species, "iters": its, "relres": rel, "a_node": a_node, "psi": psi_new}
+            "species": new_species, "kept": kept, "iters": its, "relres": rel, "a_node": a_node, "psi": psi_new}

@@ -64,6 +64,58 @@ static int64_t shifted(const or_grid* G, int64_t g, const int o[3]) {
 int64_t or_nnodes(const or_grid* G) { return nnodes(G); }
 
 /* ---------------------------------------------------------------------- */
+/* Walled x axis (READING: the paper's shock runs are driven flows against a
+ * boundary, Sec. 4.3-4.4, whose discretisation it does not print).  A
+ * conducting wall is the mirror of the domain: under x -> -x the tangential
+ * E and the normal B are odd (they vanish on the wall) and the normal E and
+ * the tangential B are even.  At the inflow plane E is held at its upstream
+ * value and the ghost cell beyond it holds the upstream B.
+ * Storage: n[0] = nx + 1 points along x (nodes 0..nx; cells 0..nx-1 and the
+ * ghost cell nx). */
+enum { OR_PERIODIC = 0, OR_WALL = 1, OR_INFLOW = 2 };
+static int walled(const or_grid* G) { return G->bc_lo != OR_PERIODIC; }
+static int nxp(const or_grid* G) { return G->n[0] - 1; } /* physical cells along x when walled */
+/* cell (i, j, k), i possibly beyond the walls: value of component comp of a
+ * cell field; odd: the component changes sign under the mirror */
+static double cell_val(const or_grid* G, const double* F, int comp, int i, int j, int k, int odd) {
+  int64_t N = nnodes(G);
+  double sg = 1.0;
+  if (walled(G)) {
+    int nx = nxp(G);
+    if (i < 0) { i = -1 - i; sg = odd ? -1.0 : 1.0; }
+    else if (i >= nx && G->bc_hi == OR_WALL) { i = 2 * nx - 1 - i; sg = odd ? -1.0 : 1.0; }
+  }
+  int ic[3] = {i, j, k};
+  return sg * F[comp * N + flat(G, ic)];
+}
+/* node (i, j, k) of a node field with the wall mirror (i in [-nx, 2 nx]) */
+static double node_val(const or_grid* G, const double* F, int comp, int i, int j, int k, int odd) {
+  int64_t N = nnodes(G);
+  double sg = 1.0;
+  if (walled(G)) {
+    int nx = nxp(G);
+    if (i < 0) { i = -i; sg = odd ? -1.0 : 1.0; }
+    else if (i > nx) { i = 2 * nx - i; sg = odd ? -1.0 : 1.0; }
+  }
+  int ic[3] = {i, j, k};
+  return sg * F[comp * N + flat(G, ic)];
+}
+/* parity of vector components under the x mirror: B-like (pseudo-vector:
+ * normal odd) and E-like / velocity-like (normal even, tangential odd for E;
+ * the velocity's normal component is odd) */
+static int odd_B(int comp) { return comp == 0; }
+static int odd_u(int comp) { return comp == 0; }
+/* E^{n+theta} components held at a node: the tangential components on a wall,
+ * all three on the inflow plane */
+static int dirichlet(const or_grid* G, int i, int comp) {
+  if (!walled(G)) return 0;
+  int nx = nxp(G);
+  if (i == 0) return comp != 0;
+  if (i == nx) return G->bc_hi == OR_INFLOW ? 1 : comp != 0;
+  return 0;
+}
+
+/* ---------------------------------------------------------------------- */
 /* Shape function (linear, cloud-in-cell).  READING: the paper does not name
  * the shape order; the workloads use linear shapes.
  * W(x_p - x_g) = prod_d max(0, 1 - |x_p,d - x_g,d| / dx_d), the distance taken
@@ -125,16 +177,18 @@ static void matvec3(const double A[9], const double x[3], double y[3]) {
 void or_node_avg(const or_grid* G, const double* Bc, double* Bn) {
   int64_t N = nnodes(G);
   int nc = 1 << G->dim;
-  for (int64_t g = 0; g < N; ++g)
+  for (int64_t g = 0; g < N; ++g) {
+    int ic[3]; unflat(G, g, ic);
     for (int comp = 0; comp < 3; ++comp) {
       double s = 0.0;
       for (int a = 0; a < nc; ++a) {
         int o[3] = {0, 0, 0};
         for (int d = 0; d < G->dim; ++d) o[d] = -((a >> d) & 1);
-        s += Bc[comp * N + shifted(G, g, o)];
+        s += cell_val(G, Bc, comp, ic[0] + o[0], ic[1] + o[1], ic[2] + o[2], odd_B(comp));
       }
       Bn[comp * N + g] = s / nc;
     }
+  }
 }
 
 static void gather(const or_grid* G, const double* F, const int64_t nodes[8], const double W[8], int nc,
@@ -213,7 +267,19 @@ void or_filter_axis(const or_grid* G, double* f, int ncomp, double phi, int stri
     for (int64_t g = 0; g < N; ++g) {
       int om[3] = {0, 0, 0}, op[3] = {0, 0, 0};
       om[axis] = -stride; op[axis] = stride;
-      tmp[g] = phi * f[c * N + g] + 0.5 * (1.0 - phi) * (f[c * N + shifted(G, g, om)] + f[c * N + shifted(G, g, op)]);
+      double lo, hi;
+      if (axis == 0 && walled(G)) {
+        /* READING: mirror at the walls (a 3-component field is a velocity or
+           a current: its normal component is odd) */
+        int ic[3]; unflat(G, g, ic);
+        int odd = ncomp == 3 && odd_u(c);
+        lo = node_val(G, f, c, ic[0] - stride, ic[1], ic[2], odd);
+        hi = node_val(G, f, c, ic[0] + stride, ic[1], ic[2], odd);
+      } else {
+        lo = f[c * N + shifted(G, g, om)];
+        hi = f[c * N + shifted(G, g, op)];
+      }
+      tmp[g] = phi * f[c * N + g] + 0.5 * (1.0 - phi) * (lo + hi);
     }
     memcpy(&f[c * N], tmp, sizeof(double) * N);
   }
@@ -312,6 +378,13 @@ void or_kappa_E(const or_grid* G, const double* E, const double* a_node, double 
         int64_t gm = shifted(G, g, om), gp = shifted(G, g, op);
         double phi = or_limiter(E[m * N + g] - E[m * N + gm], E[m * N + gp] - E[m * N + g], beta);
         double a = 0.5 * (a_node[g] + a_node[gp]);
+        if (d == 0 && walled(G)) {
+          /* READING: no flux through the boundary planes; at the face next to
+             the lower wall the ratio would need a value beyond it: phi = 0 */
+          int ic[3]; unflat(G, g, ic);
+          if (ic[0] == nxp(G)) { kappa[(d * 3 + m) * N + g] = 0.0; continue; }
+          if (ic[0] == 0) phi = 0.0;
+        }
         kappa[(d * 3 + m) * N + g] = 0.5 * (1.0 - phi) * a;
       }
   }
@@ -345,8 +418,15 @@ void or_kappa_B(const or_grid* G, const double* B, const double* a_node, double 
       (void)k;
       double a = asum / nf;
       int64_t cm = shifted(G, c, om), cp = shifted(G, c, op);
+      int ic[3]; unflat(G, c, ic);
       for (int m = 0; m < 3; ++m) {
         double phi = or_limiter(B[m * N + c] - B[m * N + cm], B[m * N + cp] - B[m * N + c], beta);
+        if (walled(G)) {
+          /* READING: no flux through the boundary faces and none on the ghost
+             cells; next to the lower wall the ratio is not defined: phi = 0 */
+          if (ic[0] >= nxp(G) - (d == 0)) { kappa[(d * 3 + m) * N + c] = 0.0; continue; }
+          if (d == 0 && ic[0] == 0) phi = 0.0;
+        }
         kappa[(d * 3 + m) * N + c] = 0.5 * (1.0 - phi) * a;
       }
     }
@@ -391,11 +471,35 @@ void or_curl_nc(const or_grid* G, const double* E, double* out) {
     out[c] = dnc(G, &E[2 * N], c, 1) - dnc(G, &E[N], c, 2);
     out[N + c] = dnc(G, &E[0], c, 2) - dnc(G, &E[2 * N], c, 0);
     out[2 * N + c] = dnc(G, &E[N], c, 0) - dnc(G, &E[0], c, 1);
+    if (walled(G)) {
+      int ic[3]; unflat(G, c, ic);
+      if (ic[0] == nxp(G)) out[c] = out[N + c] = out[2 * N + c] = 0.0;  /* the ghost cell */
+    }
   }
+}
+/* cell -> node derivative of component comp along d with the wall mirror */
+static double dcn_w(const or_grid* G, const double* B, int comp, int64_t g, int d) {
+  if (d >= G->dim) return 0.0;
+  int nc = 1 << G->dim;
+  int ic[3]; unflat(G, g, ic);
+  double up = 0.0, lo = 0.0;
+  for (int a = 0; a < nc; ++a) {
+    int o[3] = {0, 0, 0};
+    for (int e = 0; e < G->dim; ++e) o[e] = -((a >> e) & 1);
+    double val = cell_val(G, B, comp, ic[0] + o[0], ic[1] + o[1], ic[2] + o[2], odd_B(comp));
+    if ((a >> d) & 1) lo += val; else up += val;
+  }
+  return (up - lo) / (nc / 2) / G->dx[d];
 }
 void or_curl_cn(const or_grid* G, const double* B, double* out) {
   int64_t N = nnodes(G);
   for (int64_t g = 0; g < N; ++g) {
+    if (walled(G)) {
+      out[g] = dcn_w(G, B, 2, g, 1) - dcn_w(G, B, 1, g, 2);
+      out[N + g] = dcn_w(G, B, 0, g, 2) - dcn_w(G, B, 2, g, 0);
+      out[2 * N + g] = dcn_w(G, B, 1, g, 0) - dcn_w(G, B, 0, g, 1);
+      continue;
+    }
     out[g] = dcn(G, &B[2 * N], g, 1) - dcn(G, &B[N], g, 2);
     out[N + g] = dcn(G, &B[0], g, 2) - dcn(G, &B[2 * N], g, 0);
     out[2 * N + g] = dcn(G, &B[N], g, 0) - dcn(G, &B[0], g, 1);
@@ -422,6 +526,10 @@ void or_gauss_sums(const or_grid* G, const double* E, const double* rho_node, do
   or_div_nc(G, E, div);
   out[0] = out[1] = 0.0;
   for (int64_t c = 0; c < N; ++c) {
+    if (walled(G)) {
+      int ic[3]; unflat(G, c, ic);
+      if (ic[0] == nxp(G)) continue;  /* the ghost cell */
+    }
     double rc = 0.0;
     for (int a = 0; a < nc; ++a) {
       int o[3] = {0, 0, 0};
@@ -483,6 +591,12 @@ void or_apply_A(const or_grid* G, const or_params* P, const double* Mtilde, cons
     or_diffusion(G, kappaE, x, t);
     for (int64_t i = 0; i < 3 * N; ++i) y[i] -= P->theta * P->dt * t[i];
   }
+  if (walled(G))
+    for (int64_t g = 0; g < N; ++g) {
+      int ic[3]; unflat(G, g, ic);
+      for (int m = 0; m < 3; ++m)
+        if (dirichlet(G, ic[0], m)) y[m * N + g] = x[m * N + g];  /* held components: identity rows */
+    }
   free(cc);
   free(t);
 }
@@ -496,6 +610,12 @@ void or_rhs(const or_grid* G, const or_params* P, const double* En, const double
   or_curl_cn(G, Bc, t);
   for (int64_t i = 0; i < 3 * N; ++i)
     b[i] = En[i] + P->c * P->theta * P->dt * t[i] - 4.0 * M_PI * P->theta * P->dt * Jeff[i];
+  if (walled(G))
+    for (int64_t g = 0; g < N; ++g) {
+      int ic[3]; unflat(G, g, ic);
+      for (int m = 0; m < 3; ++m)
+        if (dirichlet(G, ic[0], m)) b[m * N + g] = En[m * N + g];  /* E^{n+theta} = E^n there */
+    }
   free(t);
 }
 
@@ -513,6 +633,12 @@ void or_update_B(const or_grid* G, const or_params* P, const double* Bc, const d
     or_diffusion(G, kappaB, Bc, t);
     for (int64_t i = 0; i < 3 * N; ++i) Bnew[i] += P->dt * t[i];
   }
+  if (walled(G))
+    for (int64_t c = 0; c < N; ++c) {
+      int ic[3]; unflat(G, c, ic);
+      if (ic[0] == nxp(G))
+        for (int m = 0; m < 3; ++m) Bnew[m * N + c] = Bc[m * N + c];  /* the ghost cell keeps its value */
+    }
   free(t);
 }
 
@@ -528,8 +654,9 @@ void or_update_E(int64_t n3, double theta, const double* En, const double* Eth, 
  *   v^{n+1} = 2 vbar - v^n,  x^{n+3/2} = x^{n+1/2} + dt v^{n+1}  (periodic).
  * alpha_p uses B at x^{n+1/2}, the same as in the deposit. */
 void or_push_species(const or_grid* G, double beta_s, double dt, int64_t np, const double* x, const double* v,
-                     const double* Eth, const double* Bn, double* xnew, double* vnew) {
+                     const double* Eth, const double* Bn, double* xnew, double* vnew, int* keep) {
   for (int64_t p = 0; p < np; ++p) {
+    if (keep) keep[p] = 1;
     int64_t nodes[8]; double W[8];
     int nc = or_shape(G, &x[3 * p], nodes, W);
     double Ep[3], Bp[3];
@@ -541,7 +668,23 @@ void or_push_species(const or_grid* G, double beta_s, double dt, int64_t np, con
     for (int d = 0; d < 3; ++d) {
       vnew[3 * p + d] = 2.0 * vb[d] - v[3 * p + d];
       double xn = x[3 * p + d];
-      if (d < G->dim) {
+      if (d == 0 && walled(G)) {
+        /* READING: specular reflection on a wall (x -> -x, v_x -> -v_x about
+           the wall plane); a particle crossing the inflow plane leaves */
+        double L = nxp(G) * G->dx[0];
+        xn += dt * vnew[3 * p];
+        if (xn < 0.0) {
+          xn = -xn;
+          vnew[3 * p] = -vnew[3 * p];
+        } else if (xn >= L) {
+          if (G->bc_hi == OR_WALL) {
+            xn = 2.0 * L - xn;
+            vnew[3 * p] = -vnew[3 * p];
+          } else if (keep) {
+            keep[p] = 0;
+          }
+        }
+      } else if (d < G->dim) {
         double L = G->n[d] * G->dx[d];
         xn += dt * vnew[3 * p + d];
         xn = fmod(xn, L);

@@ -4,7 +4,11 @@
 #define GLECSIM_ORACLE_H
 #include <stdint.h>
 
-typedef struct { int dim; int n[3]; double dx[3]; } or_grid;
+/* bc_lo, bc_hi: boundaries of the x axis, 0 periodic (both), or bc_lo = 1 (a
+ * conducting, reflecting wall at x = 0) with bc_hi = 1 (wall) or 2 (inflow) at
+ * x = L.  Walled grids store n[0] = nx + 1 points along x: nodes 0..nx, the
+ * physical cells 0..nx-1 and one ghost cell nx (the inflow's upstream B). */
+typedef struct { int dim; int n[3]; double dx[3]; int bc_lo, bc_hi; } or_grid;
 typedef struct { double theta, c, dt; } or_params;
 
 int64_t or_nnodes(const or_grid* G);
@@ -35,7 +39,7 @@ void or_update_B(const or_grid* G, const or_params* P, const double* Bc, const d
                  double* Bnew);
 void or_update_E(int64_t n3, double theta, const double* En, const double* Eth, double* Enew);
 void or_push_species(const or_grid* G, double beta_s, double dt, int64_t np, const double* x, const double* v,
-                     const double* Eth, const double* Bn, double* xnew, double* vnew);
+                     const double* Eth, const double* Bn, double* xnew, double* vnew, int* keep);
 int or_gmres(const or_grid* G, const or_params* P, const double* Mtilde, const double* kappaE, const double* b,
              double* x, double tol, int maxit, int restart, double* relres_out);
 void or_dense_A(const or_grid* G, const or_params* P, const double* Mtilde, const double* kappaE, double* Ad);

@@ -48,18 +48,34 @@ int check_flags(ge_ctx* c) {
   for (int k = 0; k < GE_FL_COUNT; ++k) any = any || h[k] != 0;
   if (any) GE_HIP(c, hipMemsetAsync(c->flags, 0, sizeof(h), c->stream));
   std::string stuck;
-  if (c->push_pending) {
+  if (h[GE_FL_LOAD] && c->inject_pending) {
+    // an injected particle named a cell outside the domain (or a ghost
+    // cell): the pending injections are dropped before any re-sort indexes
+    // with them
+    for (int s = 0; s < c->nsp; ++s) c->sp[s].inj_n = 0;
+  }
+  if (c->push_pending || c->inject_pending) {
+    const bool pushed = c->push_pending;
     c->push_pending = 0;
-    c->moves.pushes += 1;
+    c->inject_pending = 0;
+    if (pushed) c->moves.pushes += 1;
     for (int s = 0; s < c->nsp; ++s) {
-      const int* st = h + GE_FL_SPECIES + 4 * s;
+      SpeciesBuf& S = c->sp[s];
+      int zero[4] = {0, 0, 0, 0};
+      const int* st = pushed ? h + GE_FL_SPECIES + 4 * s : zero;
       float mv;
       std::memcpy(&mv, &st[1], sizeof(mv));
       c->moves.far[s] += st[0];
+      c->moves.gone[s] += st[3];
+      c->moves.injected[s] += S.inj_n;
       if (mv > c->moves.maxmove[s]) c->moves.maxmove[s] = mv;
-      if (st[0] > 0) {
+      if (st[0] > 0 || st[3] > 0 || S.inj_n > 0) {
+        // far movers, losses or injected particles: rebuild the cell order
+        const int64_t n_new = S.nbuf - st[3] + S.inj_n;
         int rc = ge_launch_far_resort(c, s, st[0]);
         if (rc) return rc;
+        S.n = S.nbuf = n_new;
+        S.inj_n = 0;
         c->moves.resorts += 1;
       }
       if (st[2] > 0)
@@ -68,7 +84,8 @@ int check_flags(ge_ctx* c) {
     }
   }
   if (h[GE_FL_RUNS]) return ge_fail(c, GE_ERR_STATE, "internal: particle run bookkeeping mismatch in the push");
-  if (h[GE_FL_LOAD]) return ge_fail(c, GE_ERR_ARG, "particles not sorted by cell or cell index out of range");
+  if (h[GE_FL_LOAD])
+    return ge_fail(c, GE_ERR_ARG, "particles not sorted by cell or cell index out of range (pending injections dropped)");
   if (h[GE_FL_NONFINITE])
     return ge_fail(c, GE_ERR_NONFINITE, "a pushed particle had a non-finite velocity or position and was kept in place:" + stuck);
   if (h[GE_FL_CFL])
@@ -78,7 +95,7 @@ int check_flags(ge_ctx* c) {
 }
 
 // Settle a pending push (its far movers) before particles are read again.
-int settle(ge_ctx* c) { return c->push_pending ? check_flags(c) : GE_OK; }
+int settle(ge_ctx* c) { return (c->push_pending || c->inject_pending) ? check_flags(c) : GE_OK; }
 
 // add the elapsed time of the event pairs of the last step (stream idle)
 void accumulate_timings(ge_ctx* c, double solve_s) {
@@ -209,11 +226,20 @@ int ge_create(const ge_grid* grid, const ge_params* params, void* hip_stream, ge
     return GE_ERR_ARG;
   };
   if (dim < 1 || dim > 3) return bad("dim");
+  for (int d = 0; d < 3; ++d) {
+    const bool xs = d == 0 && grid->bc_lo[0] == GE_BC_WALL &&
+                    (grid->bc_hi[0] == GE_BC_WALL || grid->bc_hi[0] == GE_BC_INFLOW);
+    if (!xs && (grid->bc_lo[d] != GE_BC_PERIODIC || grid->bc_hi[d] != GE_BC_PERIODIC))
+      return bad("boundaries: every axis periodic, or x with a wall at x = 0 and a wall or an inflow plane at x = L");
+  }
+  const bool wall = grid->bc_lo[0] == GE_BC_WALL;
+  if (wall && (params->dedner || params->ns_e))
+    return bad("divergence cleaning and E smoothing need periodic axes");
   int64_t N = 1;
   for (int d = 0; d < 3; ++d) {
     if (d < dim) {
       if (grid->n[d] < 3 || !(grid->dx[d] > 0)) return bad("n/dx");
-      N *= grid->n[d];
+      N *= grid->n[d] + (d == 0 && wall ? 1 : 0);
     } else if (grid->n[d] != 1) {
       return bad("inactive axes need n = 1");
     }
@@ -235,6 +261,10 @@ int ge_create(const ge_grid* grid, const ge_params* params, void* hip_stream, ge
     G.idx[d] = 1.0 / G.dx[d];
     if (d < dim) G.dV *= G.dx[d];
   }
+  G.bcl = grid->bc_lo[0];
+  G.bch = wall ? grid->bc_hi[0] : GE_BC_PERIODIC;
+  G.nxp = grid->n[0];
+  if (wall) G.n[0] += 1;  // the ghost cell column
   grid_div_magic(G);
   G.colsh = visit_colsh(G);
   c->nsp = 0;
@@ -329,6 +359,7 @@ void ge_destroy(ge_ctx* c) {
       dfree(c->sp[s].runs[b]);
     }
     dfree(c->sp[s].far);
+    dfree(c->sp[s].inj_cell);
   }
   ge_far_free(c);
   for (int k = 0; k < 10; ++k)
@@ -353,6 +384,8 @@ int ge_add_species(ge_ctx* c, const ge_species* sp, int64_t n, const int32_t* ce
   S.m = sp->m;
   S.beta = sp->q * c->P.dt / (2.0 * sp->m);
   S.n = n;
+  S.nbuf = n;
+  S.cap = n > 0 ? n : 1;
   const size_t es = c->P.precision == GE_FP32 ? 4 : 8;
   int rc = GE_OK;
   for (int b = 0; b < 2 && !rc; ++b) {
@@ -369,6 +402,7 @@ int ge_add_species(ge_ctx* c, const ge_species* sp, int64_t n, const int32_t* ce
     c->nsp = s;
     return rc;
   }
+  GE_HIP(c, hipMemsetAsync(S.far, 0, sizeof(int32_t) * 4 * c->G.N, c->stream));
   rc = ge_launch_load_species(c, s, cell, off, v, w);
   if (rc) return rc;
   rc = check_flags(c);
@@ -409,6 +443,7 @@ int ge_deposit(ge_ctx* c) {
 int ge_explicit_current(ge_ctx* c, double* J) {
   if (!c) return GE_ERR_ARG;
   if (c->nsp == 0) return ge_fail(c, GE_ERR_STATE, "no species");
+  if (walled(c->G)) return ge_fail(c, GE_ERR_ARG, "the explicit-PIC path needs periodic axes");
   int rc = settle(c);
   if (rc) return rc;
   // moments -> smoothed bulk velocity -> current, then the ns_j passes
@@ -425,6 +460,7 @@ int ge_explicit_current(ge_ctx* c, double* J) {
 int ge_explicit_step(ge_ctx* c) {
   if (!c) return GE_ERR_ARG;
   if (c->nsp == 0) return ge_fail(c, GE_ERR_STATE, "no species");
+  if (walled(c->G)) return ge_fail(c, GE_ERR_ARG, "the explicit-PIC path needs periodic axes");
   int rc = settle(c);
   if (rc) return rc;
   // corner fields of the push: E^n (through c->Eth) and the node average of B^n
@@ -634,6 +670,21 @@ int ge_diagnostics(ge_ctx* c, ge_diag* out) {
   return check_flags(c);
 }
 
+int ge_inject(ge_ctx* c, int s, int64_t m, const int32_t* cell, const void* off, const void* v, const void* w) {
+  if (!c || s < 0 || s >= c->nsp) return GE_ERR_ARG;
+  if (m < 0) return ge_fail(c, GE_ERR_ARG, "negative particle count");
+  if (m == 0) return GE_OK;
+  if (!cell || !off || !v || !w) return ge_fail(c, GE_ERR_ARG, "null particle array");
+  if (c->have_deposit || c->have_solve)
+    return ge_fail(c, GE_ERR_STATE, "ge_inject between a deposit and its field update");
+  SpeciesBuf& S = c->sp[s];
+  if (S.nbuf + S.inj_n + m >= ((int64_t)1 << 31)) return ge_fail(c, GE_ERR_ARG, "species would exceed 2^31 particles");
+  int rc = ge_launch_inject_pack(c, s, m, cell, off, v, w);
+  if (rc) return rc;
+  c->inject_pending = 1;
+  return GE_OK;
+}
+
 int64_t ge_step_count(const ge_ctx* c) { return c ? c->steps : -1; }
 
 int64_t ge_species_count(const ge_ctx* c, int s) { return (c && s >= 0 && s < c->nsp) ? c->sp[s].n : -1; }
@@ -827,6 +878,8 @@ int ge_moves(ge_ctx* c, ge_move_report* out) {
   for (int s = 0; s < c->nsp; ++s) {
     out->far_moves[s] = c->moves.far[s];
     out->max_move[s] = c->moves.maxmove[s];
+    out->gone[s] = c->moves.gone[s];
+    out->injected[s] = c->moves.injected[s];
   }
   out->resorts = c->moves.resorts;
   out->pushes = c->moves.pushes;

@@ -20,10 +20,30 @@ struct Gd {
 __device__ inline int ax_bit(int a, int d) { return (a >> d) & 1; }
 
 // ----------------------------------------------------------------- node average of B
+// value of component q of a cell field at cell (i, j, k), i possibly beyond
+// a wall (mirror: odd components change sign)
+__device__ inline double cellv(const DGrid& G, const double* __restrict__ F, int q, int i, int j, int k, bool odd) {
+  double sg;
+  const int im = cell_mirror(G, i, sg, odd);
+  return sg * F[q * G.N + flat3(G, im, j, k)];
+}
+
 template <int DIM>
 __global__ void k_node_avg(DGrid G, const double* __restrict__ B, double* __restrict__ Bn) {
   int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (g >= G.N) return;
+  if (walled(G)) {
+    int gx, gy, gz;
+    unflat3(G, g, gx, gy, gz);
+    for (int q = 0; q < 3; ++q) {
+      double s = 0;
+      for (int a = 0; a < Gd<DIM>::NC; ++a)
+        s += cellv(G, B, q, gx - ax_bit(a, 0), gy - (DIM >= 2 ? ax_bit(a, 1) : 0), gz - (DIM >= 3 ? ax_bit(a, 2) : 0),
+                   q == 0);
+      Bn[q * G.N + g] = s / Gd<DIM>::NC;
+    }
+    return;
+  }
   for (int q = 0; q < 3; ++q) {
     double s = 0;
     for (int a = 0; a < Gd<DIM>::NC; ++a)
@@ -132,14 +152,27 @@ __global__ void k_bulk_u(int64_t N, const double* __restrict__ mm, const double*
 
 // One pass of the digital filter (Sec. 2.4) along 'axis' with stride d:
 // v* = phi v + (1 - phi)/2 (v_{-d} + v_{+d}).
+// Along a walled x axis the neighbours mirror about the wall planes; the
+// field is a velocity or a current, whose normal (x) component is odd.
 __global__ void k_filter(DGrid G, const double* __restrict__ src, double* __restrict__ dst, int axis, int d, double phi) {
   int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (g >= G.N) return;
+  const double half = 0.5 * (1.0 - phi);
+  if (axis == 0 && walled(G)) {
+    int gx, gy, gz;
+    unflat3(G, g, gx, gy, gz);
+    for (int q = 0; q < 3; ++q) {
+      double sm, sp;
+      const int im = node_mirror(G, gx - d, sm, q == 0), ip = node_mirror(G, gx + d, sp, q == 0);
+      dst[q * G.N + g] = phi * src[q * G.N + g] +
+                         half * (sm * src[q * G.N + flat3(G, im, gy, gz)] + sp * src[q * G.N + flat3(G, ip, gy, gz)]);
+    }
+    return;
+  }
   int o[3] = {0, 0, 0};
   o[axis] = d;
   int64_t gp = nbr3(G, g, o[0], o[1], o[2]);
   int64_t gm = nbr3(G, g, -o[0], -o[1], -o[2]);
-  const double half = 0.5 * (1.0 - phi);
   for (int q = 0; q < 3; ++q) dst[q * G.N + g] = phi * src[q * G.N + g] + half * (src[q * G.N + gm] + src[q * G.N + gp]);
 }
 
@@ -251,8 +284,16 @@ __global__ void k_kappa_E(DGrid G, const double* __restrict__ E, const double* _
     o[d] = 1;
     int64_t gp = nbr3(G, g, o[0], o[1], o[2]), gm = nbr3(G, g, -o[0], -o[1], -o[2]);
     double a = 0.5 * (anode[g] + anode[gp]);
+    // walled x: no flux through the boundary planes; phi = 0 next to the lower wall
+    int bx = -1;
+    if (d == 0 && walled(G)) {
+      int gy, gz;
+      unflat3(G, g, bx, gy, gz);
+      if (bx == G.nxp) a = 0.0;
+    }
     for (int m = 0; m < 3; ++m) {
       double phi = mc_limiter(E[m * N + g] - E[m * N + gm], E[m * N + gp] - E[m * N + g], beta);
+      if (bx == 0) phi = 0.0;
       kE[(d * 3 + m) * N + g] = 0.5 * (1.0 - phi) * a;
     }
   }
@@ -284,8 +325,17 @@ __global__ void k_kappa_B(DGrid G, const double* __restrict__ B, const double* _
     int o[3] = {0, 0, 0};
     o[d] = 1;
     int64_t cp = nbr3(G, c, o[0], o[1], o[2]), cm = nbr3(G, c, -o[0], -o[1], -o[2]);
+    // walled x: no flux through the boundary faces nor on the ghost cells;
+    // phi = 0 on the face next to the lower wall
+    int bx = -1;
+    if (walled(G)) {
+      int cy, cz;
+      unflat3(G, c, bx, cy, cz);
+      if (bx >= G.nxp - (d == 0)) a = 0.0;
+    }
     for (int m = 0; m < 3; ++m) {
       double phi = mc_limiter(B[m * N + c] - B[m * N + cm], B[m * N + cp] - B[m * N + c], beta);
+      if (d == 0 && bx == 0) phi = 0.0;
       kB[(d * 3 + m) * N + c] = 0.5 * (1.0 - phi) * a;
     }
   }
@@ -317,6 +367,11 @@ __global__ void k_curl_nc(DGrid G, const double* __restrict__ E, double* __restr
   C[c] = D[1][2] - D[2][1];
   C[N + c] = D[2][0] - D[0][2];
   C[2 * N + c] = D[0][1] - D[1][0];
+  if (walled(G)) {
+    int cx, cy, cz;
+    unflat3(G, c, cx, cy, cz);
+    if (cx == G.nxp) C[c] = C[N + c] = C[2 * N + c] = 0.0;  // the ghost cell
+  }
 }
 
 template <int DIM>
@@ -324,9 +379,21 @@ __device__ inline void curl_cn_at(const DGrid& G, const double* __restrict__ B, 
   const int64_t N = G.N;
   constexpr int NC = Gd<DIM>::NC;
   double up[3][3] = {{0}}, lo[3][3] = {{0}};
+  int gx = 0, gy = 0, gz = 0;
+  const bool w = walled(G);
+  if (w) unflat3(G, g, gx, gy, gz);
   for (int a = 0; a < NC; ++a) {
-    int64_t cc = nbr3(G, g, -ax_bit(a, 0), DIM >= 2 ? -ax_bit(a, 1) : 0, DIM >= 3 ? -ax_bit(a, 2) : 0);
-    double b0 = B[cc], b1 = B[N + cc], b2 = B[2 * N + cc];
+    double b0, b1, b2;
+    if (w) {
+      // cells beyond a wall are the mirror images (B_x odd, B_y, B_z even)
+      const int ci = gx - ax_bit(a, 0), cj = gy - (DIM >= 2 ? ax_bit(a, 1) : 0), ck = gz - (DIM >= 3 ? ax_bit(a, 2) : 0);
+      b0 = cellv(G, B, 0, ci, cj, ck, true);
+      b1 = cellv(G, B, 1, ci, cj, ck, false);
+      b2 = cellv(G, B, 2, ci, cj, ck, false);
+    } else {
+      int64_t cc = nbr3(G, g, -ax_bit(a, 0), DIM >= 2 ? -ax_bit(a, 1) : 0, DIM >= 3 ? -ax_bit(a, 2) : 0);
+      b0 = B[cc]; b1 = B[N + cc]; b2 = B[2 * N + cc];
+    }
     for (int d = 0; d < DIM; ++d) {
       if (ax_bit(a, d)) { lo[d][0] += b0; lo[d][1] += b1; lo[d][2] += b2; }
       else { up[d][0] += b0; up[d][1] += b1; up[d][2] += b2; }
@@ -365,7 +432,61 @@ __global__ void k_rhs(DGrid G, const double* __restrict__ E, const double* __res
   if (g >= G.N) return;
   double cb[3];
   curl_cn_at<DIM>(G, B, g, cb);
-  for (int q = 0; q < 3; ++q) b[q * G.N + g] = E[q * G.N + g] + ctd * cb[q] - ftd * J[q * G.N + g];
+  int gx = -1, gy, gz;
+  if (walled(G)) unflat3(G, g, gx, gy, gz);
+  for (int q = 0; q < 3; ++q)
+    b[q * G.N + g] = (gx >= 0 && held(G, gx, q)) ? E[q * G.N + g]  // E^{n+theta} = E^n on held components
+                                                  : E[q * G.N + g] + ctd * cb[q] - ftd * J[q * G.N + g];
+}
+
+// curl_NC of a node field at physical cell (i, j, k)
+template <int DIM>
+__device__ inline void curl_nc_cell(const DGrid& G, const double* __restrict__ E, int i, int j, int k, double C[3]) {
+  constexpr int NC = Gd<DIM>::NC;
+  const int64_t N = G.N;
+  double up[3][3] = {{0}}, lo[3][3] = {{0}};
+  for (int a = 0; a < NC; ++a) {
+    const int64_t g = flat3(G, i + ax_bit(a, 0), j + (DIM >= 2 ? ax_bit(a, 1) : 0), k + (DIM >= 3 ? ax_bit(a, 2) : 0));
+    const double e[3] = {E[g], E[N + g], E[2 * N + g]};
+    for (int d = 0; d < DIM; ++d)
+      for (int q = 0; q < 3; ++q) (ax_bit(a, d) ? up : lo)[d][q] += e[q];
+  }
+  double D[3][3] = {{0}};
+  const double inv = 2.0 / NC;
+  for (int d = 0; d < DIM; ++d)
+    for (int q = 0; q < 3; ++q) D[d][q] = (up[d][q] - lo[d][q]) * inv * G.idx[d];
+  C[0] = D[1][2] - D[2][1];
+  C[1] = D[2][0] - D[0][2];
+  C[2] = D[0][1] - D[1][0];
+}
+
+// curl_CN (curl_NC x) at a node of a boundary plane of a walled grid: the
+// cells beyond a wall are the mirror images of curl_NC x (a pseudo-vector:
+// x component odd); the ghost cell of an inflow plane carries zero
+template <int DIM>
+__device__ inline void curlcurl_wall(const DGrid& G, const double* __restrict__ x, int gx, int gy, int gz,
+                                     double out[3]) {
+  constexpr int NC = Gd<DIM>::NC;
+  double up[3][3] = {{0}}, lo[3][3] = {{0}};
+  for (int a = 0; a < NC; ++a) {
+    const int ci = gx - ax_bit(a, 0), cj = gy - (DIM >= 2 ? ax_bit(a, 1) : 0), ck = gz - (DIM >= 3 ? ax_bit(a, 2) : 0);
+    double sg;
+    const int cm = cell_mirror(G, ci, sg, true);
+    double C[3] = {0, 0, 0};
+    if (cm < G.nxp) {
+      curl_nc_cell<DIM>(G, x, cm, cj, ck, C);
+      C[0] *= sg;
+    }
+    for (int d = 0; d < DIM; ++d)
+      for (int q = 0; q < 3; ++q) (ax_bit(a, d) ? lo : up)[d][q] += C[q];
+  }
+  double D[3][3] = {{0}};
+  const double inv = 2.0 / NC;
+  for (int d = 0; d < DIM; ++d)
+    for (int q = 0; q < 3; ++q) D[d][q] = (up[d][q] - lo[d][q]) * inv * G.idx[d];
+  out[0] = D[1][2] - D[2][1];
+  out[1] = D[2][0] - D[0][2];
+  out[2] = D[0][1] - D[1][0];
 }
 
 // A x = x + (c theta dt)^2 curl_CN curl_NC x + (4 pi theta dt / dV) Mtilde x
@@ -389,6 +510,13 @@ __global__ __launch_bounds__(256) void k_apply_A(DGrid G, const double* __restri
   const int64_t g = visit_order(G, (unsigned)t, gx, gy, gz);
   double acc[3] = {x[g], x[N + g], x[2 * N + g]};
   const double x0[3] = {acc[0], acc[1], acc[2]};
+  const bool bplane = walled(G) && (gx == 0 || gx == G.nxp);
+  if (bplane) {
+    // a boundary node plane: curl_CN (curl_NC x) with the mirror cells
+    double cc[3];
+    curlcurl_wall<DIM>(G, x, gx, gy, gz, cc);
+    for (int m = 0; m < 3; ++m) acc[m] += k2 * cc[m];
+  }
   // curl-curl stencil
   constexpr int RY = DIM >= 2 ? 1 : 0, RZ = DIM >= 3 ? 1 : 0;
 #pragma unroll
@@ -402,7 +530,7 @@ __global__ __launch_bounds__(256) void k_apply_A(DGrid G, const double* __restri
         const double xv[3] = {x[h], x[N + h], x[2 * N + h]};
 #pragma unroll
         for (int m = 0; m < 3; ++m)
-          acc[m] += k2 * (K.k[oi][3 * m] * xv[0] + K.k[oi][3 * m + 1] * xv[1] + K.k[oi][3 * m + 2] * xv[2]);
+          acc[m] += bplane ? 0.0 : k2 * (K.k[oi][3 * m] * xv[0] + K.k[oi][3 * m + 1] * xv[1] + K.k[oi][3 * m + 2] * xv[2]);
       }
   if (Mt) {
     double mx[3];
@@ -422,6 +550,9 @@ __global__ __launch_bounds__(256) void k_apply_A(DGrid G, const double* __restri
       }
     }
   }
+  if (bplane)
+    for (int m = 0; m < 3; ++m)
+      if (held(G, gx, m)) acc[m] = x0[m];  // held components: identity rows
 #pragma unroll
   for (int m = 0; m < 3; ++m) y[m * N + g] = acc[m];
 }
@@ -433,6 +564,14 @@ __global__ void k_update_B(DGrid G, const double* __restrict__ B, const double* 
                            double* __restrict__ Bnew) {
   int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (c >= G.N) return;
+  if (walled(G)) {
+    int cx, cy, cz;
+    unflat3(G, c, cx, cy, cz);
+    if (cx == G.nxp) {  // the ghost cell keeps its (upstream) value
+      for (int q = 0; q < 3; ++q) Bnew[q * G.N + c] = B[q * G.N + c];
+      return;
+    }
+  }
   for (int q = 0; q < 3; ++q) {
     double v = B[q * G.N + c] - cdt * C[q * G.N + c];
     if (kB) v += dt * diffusion_at<DIM>(G, kB, B, c, q);
@@ -475,6 +614,12 @@ __global__ void k_jacobi_setup(DGrid G, const T* __restrict__ Mt, const double* 
       }
     A[4 * m] += 1.0 + k2 * cc + tdt * dd;
   }
+  if (walled(G)) {
+    int gx, gy, gz;
+    unflat3(G, g, gx, gy, gz);
+    if (gx == 0 || gx == G.nxp)  // boundary planes: the identity block (a preconditioner need not be exact)
+      for (int e = 0; e < 9; ++e) A[e] = (e % 4 == 0) ? 1.0 : 0.0;
+  }
   double det = A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6]) + A[2] * (A[3] * A[7] - A[4] * A[6]);
   double id = det != 0.0 ? 1.0 / det : 0.0;
   double I[9];
@@ -514,8 +659,19 @@ __global__ __launch_bounds__(256) void k_field_diag(DGrid G, const double* __res
   const int64_t N = G.N;
   double a[4] = {0, 0, 0, 0};
   for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < N; c += (int64_t)gridDim.x * blockDim.x) {
+    // walled x: half weight of the boundary node planes, ghost cells left out
+    double wn = 1.0;
+    if (walled(G)) {
+      int cx, cy, cz;
+      unflat3(G, c, cx, cy, cz);
+      if (cx == 0 || cx == G.nxp) wn = 0.5;
+      if (cx == G.nxp) {
+        for (int q = 0; q < 3; ++q) a[0] += wn * E[q * N + c] * E[q * N + c];
+        continue;
+      }
+    }
     for (int q = 0; q < 3; ++q) {
-      a[0] += E[q * N + c] * E[q * N + c];
+      a[0] += wn * E[q * N + c] * E[q * N + c];
       a[1] += B[q * N + c] * B[q * N + c];
     }
     double up[3] = {0, 0, 0}, lo[3] = {0, 0, 0}, rc = 0;

@@ -24,7 +24,38 @@ struct DGrid {
   int ds[2];
   // visiting order of the stencil kernels (visit_order); < 0: storage order
   int colsh;
+  // x boundaries: bcl = GE_BC_PERIODIC (both periodic) or GE_BC_WALL, with
+  // bch = GE_BC_WALL or GE_BC_INFLOW; a walled grid stores n[0] = nxp + 1
+  // points along x (nodes 0..nxp, cells 0..nxp-1 and the ghost cell nxp)
+  int bcl, bch, nxp;
 };
+
+// Walled x axis: the wall is the mirror plane of the domain (tangential E and
+// normal B odd, normal E and tangential B even); the inflow plane holds E at
+// its upstream value and its ghost cell the upstream B.
+__host__ __device__ inline bool walled(const DGrid& G) { return G.bcl != GE_BC_PERIODIC; }
+// storage x index of cell i (i = -1 or nxp beyond a wall) and the sign of an
+// odd component there
+__device__ inline int cell_mirror(const DGrid& G, int i, double& sg, bool odd) {
+  sg = 1.0;
+  if (i < 0) { sg = odd ? -1.0 : 1.0; return -1 - i; }
+  if (i >= G.nxp && G.bch == GE_BC_WALL) { sg = odd ? -1.0 : 1.0; return 2 * G.nxp - 1 - i; }
+  return i;
+}
+// storage x index of node i mirrored about the wall planes (i in [-nxp, 2 nxp])
+__device__ inline int node_mirror(const DGrid& G, int i, double& sg, bool odd) {
+  sg = 1.0;
+  if (i < 0) { sg = odd ? -1.0 : 1.0; return -i; }
+  if (i > G.nxp) { sg = odd ? -1.0 : 1.0; return 2 * G.nxp - i; }
+  return i;
+}
+// E^{n+theta} components held at node plane i: tangential ones on a wall,
+// all three on the inflow plane
+__device__ inline bool held(const DGrid& G, int i, int comp) {
+  if (i == 0) return comp != 0;
+  if (i == G.nxp) return G.bch == GE_BC_INFLOW ? true : comp != 0;
+  return false;
+}
 
 // Multiplier m = ceil(2^(31+s) / n), s = ceil(log2 n): for x < 2^31 the error
 // of x m / 2^(31+s) against x / n is below 2^-s <= 1/n, so the floor is exact
@@ -134,6 +165,8 @@ constexpr int GE_REC = 7;
 // Direction code of a particle that moved more than one cell along some axis
 // in one push (the 27 codes below it are the moves d in {-1,0,1}^3).
 constexpr int GE_DIR_FAR = 27;
+// Direction code of a particle that left through an inflow plane.
+constexpr int GE_DIR_GONE = 28;
 
 struct SpeciesBuf {
   double q, m, beta;     // beta = q dt / (2 m)
@@ -141,8 +174,12 @@ struct SpeciesBuf {
   void* rec[2];          // T[max(n,1)][GE_REC]: offset in the cell (3), w, velocity (3)
   int32_t* runs[2];      // [Ncell][ND][2]: (start, count) of the run entering cell c by move d
   int32_t* far;          // [Ncell][4]: (start, count) of the far movers of home cell h (last push),
-                         // the largest move in the cell (float bits), 0
+                         // the largest move in the cell (float bits), particles gone through an inflow plane
   int cur;
+  int64_t nbuf;          // records held by rec[cur] (n, or the count before a push's losses are compacted)
+  int64_t cap;           // records each of rec[0], rec[1] can hold
+  int32_t* inj_cell;     // cells of the injected particles waiting for the next re-sort [inj_cap]
+  int64_t inj_n, inj_cap;
 };
 
 // Device flag block (int32): the errors, then per species the push statistics
@@ -152,13 +189,14 @@ enum {
   GE_FL_RUNS = 1,      // internal run bookkeeping mismatch
   GE_FL_LOAD = 2,      // unsorted or out-of-range cell index at load
   GE_FL_NONFINITE = 3, // a non-finite position after the push (kept in place)
-  GE_FL_SPECIES = 4,   // + 4 s: [0] far movers, [1] largest move in cells (float bits), [2] particles kept in place
+  GE_FL_SPECIES = 4,   // + 4 s: [0] far movers, [1] largest move in cells (float bits), [2] particles kept
+                       // in place, [3] particles gone through an inflow plane
   GE_FL_COUNT = 4 + 4 * GE_MAX_SPECIES
 };
 
 // Host-side record of the moves since the last ge_moves() call.
 struct MoveStats {
-  int64_t far[GE_MAX_SPECIES];
+  int64_t far[GE_MAX_SPECIES], gone[GE_MAX_SPECIES], injected[GE_MAX_SPECIES];
   double maxmove[GE_MAX_SPECIES];
   int resorts, pushes;
 };
@@ -200,6 +238,7 @@ struct ge_ctx {
   int* flags;            // GE_FL_COUNT ints (see GE_FL_*)
   int have_deposit, have_solve;
   int push_pending;      // a push ran whose statistics (and far movers) are not settled yet
+  int inject_pending;    // injected particles wait for their re-sort
   int device;            // HIP device the context was created on
   int64_t steps;         // completed steps (field updates)
   MoveStats moves;
@@ -223,7 +262,11 @@ int ge_fail(ge_ctx* c, int code, const std::string& msg);
 int ge_launch_load_species(ge_ctx* c, int s, const int32_t* cell, const void* off, const void* v, const void* w);
 int ge_launch_scan_counts(ge_ctx* c, int s);  // into seg_next + s*N
 int ge_launch_push(ge_ctx* c, int s);          // needs ge_launch_scan_counts(c, s) first
-int ge_launch_far_resort(ge_ctx* c, int s, int64_t nfar);  // stable re-sort after far moves (push of s done)
+// stable re-sort of species s: nfar far movers of the last push, its gone
+// particles dropped, the pending injected particles merged in
+int ge_launch_far_resort(ge_ctx* c, int s, int64_t nfar);
+int ge_launch_inject_pack(ge_ctx* c, int s, int64_t m, const int32_t* cell, const void* off, const void* v,
+                          const void* w);  // records at rec[cur][nbuf + inj_n ..], cells into inj_cell
 int ge_launch_move_max(ge_ctx* c, int s);  // largest move of the last push into the flag block
 void ge_far_free(ge_ctx* c);
 int ge_launch_deposit(ge_ctx* c);

@@ -13,6 +13,7 @@
 // stable sort by present cell gives, so the re-binning is an integer,
 // deterministic, bit-exact stable sort that moves each particle once, inside
 // the push.
+#include <algorithm>
 #include <cstring>
 
 #include "ge_internal.h"
@@ -203,7 +204,7 @@ __device__ inline void gather_lds(const T W[8], const T* fc, T out[3]) {
 // along any axis.
 template <typename T, int DIM>
 __device__ inline int push_one(T f[3], T v[3], const T* fc, T beta, const T dtx[3], const T lo[3], const T hi[3],
-                               int& stuck, T& mv) {
+                               int& stuck, T& mv, const DGrid& G, int hx) {
   constexpr int NC = Dm<DIM>::NC;
   T W[8];
   lin_weights<T, DIM>(f, W);
@@ -227,7 +228,30 @@ __device__ inline int push_one(T f[3], T v[3], const T* fc, T beta, const T dtx[
   for (int d = 0; d < DIM; ++d) {
     const T m = v[d] * dtx[d];
     sn[d] = f[d] + m;
-    if (!(sn[d] >= lo[d] && sn[d] < hi[d])) {  // also catches NaN and Inf
+    T lo_d = lo[d], hi_d = hi[d];
+    if (d == 0 && walled(G)) {
+      // walled x: specular reflection on a wall (about x = 0: hx + s -> -(hx + s);
+      // about x = L: -> 2 nxp - (hx + s)), or leaving through an inflow plane;
+      // positions relative to the home cell, so no large numbers cancel
+      if (sn[0] < (T)(-hx)) {
+        sn[0] = (T)(-2 * hx) - sn[0];
+        v[0] = -v[0];
+      } else if (sn[0] >= (T)(G.nxp - hx)) {
+        if (G.bch == GE_BC_INFLOW) {
+          if (sn[0] - sn[0] == (T)0) {
+            const T am = fabs(m);
+            mv = am > mv ? am : mv;
+            return GE_DIR_GONE;
+          }
+        } else {
+          sn[0] = (T)(2 * (G.nxp - hx)) - sn[0];
+          v[0] = -v[0];
+        }
+      }
+      lo_d = (T)(-hx);
+      hi_d = (T)(G.nxp - hx);
+    }
+    if (!(sn[d] >= lo_d && sn[d] < hi_d)) {  // also catches NaN and Inf
       keep = true;
       stuck |= (sn[d] - sn[d] == (T)0) ? 1 : 2;  // finite: too far; NaN or Inf: non-finite
     }
@@ -293,7 +317,7 @@ __device__ inline DirStats dir_stats(bool act, int dir, int lane) {
   }
   DirStats r;
   r.same = same;
-  r.count_k = lane <= GE_DIR_FAR ? __popcll(kk) : 0;
+  r.count_k = lane <= GE_DIR_GONE ? __popcll(kk) : 0;
   return r;
 }
 __device__ inline int excl_scan(int x) { return dpp_scan<false, false>(x) - x; }
@@ -371,6 +395,8 @@ __global__ __launch_bounds__(64) void k_push(DGrid G, PushArgs<T> A) {
   int* sst = s_start;
   int* spr = s_pre;
   const int total = runs_setup<DIM>(G, c, A.runs, sst, spr, lane, nseg);
+  int hx, hy, hz;
+  unflat3(G, c, hx, hy, hz);
   const int64_t base = A.seg_next[c];
   int cnt = 0, dir_off = 0, stuck = 0, bad = 0;
   T mv = 0;
@@ -402,8 +428,8 @@ __global__ __launch_bounds__(64) void k_push(DGrid G, PushArgs<T> A) {
     // and does not hold the second store for the first one's completion
     __builtin_amdgcn_s_waitcnt(0xF70);
     int d0 = 31, d1 = 31;
-    if (a0) d0 = push_one<T, DIM>(f0, v0, fc, A.beta, A.dtx, A.lo, A.hi, stuck, mv);
-    if (a1) d1 = push_one<T, DIM>(f1, v1, fc, A.beta, A.dtx, A.lo, A.hi, stuck, mv);
+    if (a0) d0 = push_one<T, DIM>(f0, v0, fc, A.beta, A.dtx, A.lo, A.hi, stuck, mv, G, hx);
+    if (a1) d1 = push_one<T, DIM>(f1, v1, fc, A.beta, A.dtx, A.lo, A.hi, stuck, mv, G, hx);
     const DirStats q0 = dir_stats(a0, d0, lane), q1 = dir_stats(a1, d1, lane);
     cnt = q0.count_k + q1.count_k;
     dir_off = excl_scan(cnt);
@@ -423,7 +449,7 @@ __global__ __launch_bounds__(64) void k_push(DGrid G, PushArgs<T> A) {
         int dir = 31;
         if (act) {
           load_particle<T, DIM>(A, run_index(t, sst, spr, nseg), f, v, w);
-          dir = push_one<T, DIM>(f, v, fc, A.beta, A.dtx, A.lo, A.hi, stuck, mv);
+          dir = push_one<T, DIM>(f, v, fc, A.beta, A.dtx, A.lo, A.hi, stuck, mv, G, hx);
         }
         const DirStats q = dir_stats(act, dir, lane);
         if (pass == 0) {
@@ -440,7 +466,7 @@ __global__ __launch_bounds__(64) void k_push(DGrid G, PushArgs<T> A) {
       }
       if (pass == 0) dir_off = excl_scan(cnt);
     }
-    if (lane <= GE_DIR_FAR && running != cnt) bad = 1;
+    if (lane <= GE_DIR_GONE && running != cnt) bad = 1;
   }
   if (lane < ND) {
     // run (c, lane) is recorded at its destination cell
@@ -454,10 +480,12 @@ __global__ __launch_bounds__(64) void k_push(DGrid G, PushArgs<T> A) {
   // one atomic per wave on a single address would serialise the push)
   const int mvb = dpp_scan<true, false>(__float_as_int((float)mv));  // non-negative floats order as integers
   const int mvmax = __builtin_amdgcn_readlane(mvb, 63);
+  const int ngone = __builtin_amdgcn_readlane(cnt, GE_DIR_GONE);  // the segment's last group: dropped later
   if (lane == GE_DIR_FAR) {
     typedef int i4 __attribute__((ext_vector_type(4)));
-    reinterpret_cast<i4*>(A.far_o)[c] = i4{(int)(base + dir_off), cnt, mvmax, 0};
+    reinterpret_cast<i4*>(A.far_o)[c] = i4{(int)(base + dir_off), cnt, mvmax, ngone};
     if (cnt > 0) atomicAdd(&A.stats[0], cnt);  // rare: far movers only
+    if (ngone > 0) atomicAdd(&A.stats[3], ngone);  // boundary cells of an inflow plane only
   }
   // refusals are rare too: one atomic per quantity from lane 0
   const uint64_t sflags = __ballot((stuck & 1) != 0), nflags = __ballot((stuck & 2) != 0);
@@ -1132,6 +1160,28 @@ __global__ __launch_bounds__(64) void k_far_list(DGrid G, T* __restrict__ rec, c
   }
 }
 
+// Injected particles as far-list entries after the nfar far movers: their
+// cells, buffer positions base + j, and the per-destination counts.
+__global__ void k_inj_list(int64_t m, const int32_t* __restrict__ cell, int64_t base, int64_t nfar,
+                           int32_t* __restrict__ ldest, int32_t* __restrict__ lpos, int32_t* __restrict__ cnt_in) {
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j >= m) return;
+  const int32_t c = cell[j];
+  ldest[nfar + j] = c;
+  lpos[nfar + j] = (int32_t)(base + j);
+  atomicAdd(&cnt_in[c], 1);
+}
+
+// Cells of injected particles: in range and not a ghost cell (flag otherwise).
+__global__ void k_inj_check(DGrid G, int64_t m, const int32_t* __restrict__ cell, int* __restrict__ flags) {
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j >= m) return;
+  const int32_t c = cell[j];
+  bool ok = c >= 0 && c < G.N;
+  if (ok && walled(G)) ok = (c % G.n[0]) < G.nxp;
+  if (!ok) atomicOr(&flags[GE_FL_LOAD], 1);
+}
+
 // Stable bucketing of the far list by destination, by one wavefront walking
 // the list in order (chunks of 64): lanes with equal destinations rank among
 // themselves by lane, and the first of them takes the group's slots from the
@@ -1325,6 +1375,8 @@ static void far_kernels_t(ge_ctx* c, SpeciesBuf& S, int64_t F) {
   FarScratch& X = c->fx;
   const int64_t N = c->G.N;
   const int cur = S.cur;
+  // (the far runs of a species that has not been pushed since its last
+  // re-sort are zero: the re-sort clears them)
   hipLaunchKernelGGL((k_far_list<T, DIM>), dim3((unsigned)N), dim3(64), 0, c->stream, c->G, (T*)S.rec[cur], S.far,
                      X.pos_h, X.dest, X.pos, X.cnt_in);
   scan_into(c, X.cnt_in, X.start_in);
@@ -1347,11 +1399,13 @@ int ge_launch_move_max(ge_ctx* c, int s) {
   return GE_OK;
 }
 
-// Stable re-sort of species s after a push that left F > 0 far movers.
-int ge_launch_far_resort(ge_ctx* c, int s, int64_t F) {
+// Stable re-sort of species s: the far movers of the last push (nfar), its
+// gone particles dropped, the pending injected particles merged in.
+int ge_launch_far_resort(ge_ctx* c, int s, int64_t nfar) {
   FarScratch& X = c->fx;
   SpeciesBuf& S = c->sp[s];
   const int64_t N = c->G.N;
+  const int64_t F = nfar + S.inj_n;
   int rc = GE_OK;
   if (!X.pos_h) {
     int32_t** per_cell[] = {&X.pos_h, &X.cnt_in, &X.start_in, &X.fill, &X.newstart};
@@ -1359,22 +1413,26 @@ int ge_launch_far_resort(ge_ctx* c, int s, int64_t F) {
       if (!rc) rc = far_alloc(c, p, sizeof(int32_t) * N);
     if (rc) { ge_far_free(c); return rc; }
   }
-  if (X.cap < F) {
+  if (X.cap < F || F == 0) {
     int32_t** lists[] = {&X.dest, &X.pos, &X.sorted};
     for (auto p : lists) {
       if (*p) (void)hipFree(*p);
       *p = nullptr;
     }
     X.cap = 0;
+    const int64_t cap = F > 0 ? F : 1;
     for (auto p : lists)
-      if (!rc) rc = far_alloc(c, p, sizeof(int32_t) * F);
+      if (!rc) rc = far_alloc(c, p, sizeof(int32_t) * cap);
     if (rc) { ge_far_free(c); return rc; }
-    X.cap = F;
+    X.cap = cap;
   }
   GE_HIP(c, hipMemsetAsync(X.cnt_in, 0, sizeof(int32_t) * N, c->stream));
   GE_HIP(c, hipMemsetAsync(X.fill, 0, sizeof(int32_t) * N, c->stream));
   hipLaunchKernelGGL(k_far_counts, dim3((N + 255) / 256), dim3(256), 0, c->stream, N, S.far, X.pos_h);
   scan_into(c, X.pos_h, X.pos_h);
+  if (S.inj_n > 0)
+    hipLaunchKernelGGL(k_inj_list, dim3((S.inj_n + 255) / 256), dim3(256), 0, c->stream, S.inj_n, S.inj_cell, S.nbuf,
+                       nfar, X.dest, X.pos, X.cnt_in);
   const bool f32 = c->P.precision == GE_FP32;
   switch (c->G.dim * 2 + (f32 ? 1 : 0)) {
     case 2: far_kernels_t<double, 1>(c, S, F); break;
@@ -1385,7 +1443,61 @@ int ge_launch_far_resort(ge_ctx* c, int s, int64_t F) {
     default: far_kernels_t<float, 3>(c, S, F); break;
   }
   GE_HIP(c, hipGetLastError());
+  // the far runs are consumed: a later re-sort without a push (injection
+  // only) must not see them again
+  GE_HIP(c, hipMemsetAsync(S.far, 0, sizeof(int32_t) * 4 * N, c->stream));
   S.cur = 1 - S.cur;
+  return GE_OK;
+}
+
+// Injected particles: records appended to rec[cur] after the held ones (the
+// buffers grow when needed), cells kept for the next re-sort.
+int ge_launch_inject_pack(ge_ctx* c, int s, int64_t m, const int32_t* cell, const void* off, const void* v,
+                          const void* w) {
+  SpeciesBuf& S = c->sp[s];
+  const size_t es = c->P.precision == GE_FP32 ? 4 : 8;
+  const int64_t at = S.nbuf + S.inj_n, need = at + m;
+  if (need > S.cap) {
+    const int64_t cap = std::max(need, S.cap + S.cap / 2);
+    void* nb[2] = {nullptr, nullptr};
+    for (int b = 0; b < 2; ++b) {
+      if (hipMalloc(&nb[b], es * GE_REC * cap) != hipSuccess) {
+        (void)hipGetLastError();
+        if (nb[0]) (void)hipFree(nb[0]);
+        return ge_fail(c, GE_ERR_OOM, "particle buffer growth failed");
+      }
+    }
+    GE_HIP(c, hipMemcpyAsync(nb[S.cur], S.rec[S.cur], es * GE_REC * at, hipMemcpyDeviceToDevice, c->stream));
+    GE_HIP(c, hipStreamSynchronize(c->stream));
+    for (int b = 0; b < 2; ++b) {
+      (void)hipFree(S.rec[b]);
+      S.rec[b] = nb[b];
+    }
+    S.cap = cap;
+  }
+  if (S.inj_n + m > S.inj_cap) {
+    const int64_t cap = std::max(S.inj_n + m, 2 * S.inj_cap);
+    int32_t* nc = nullptr;
+    if (hipMalloc((void**)&nc, sizeof(int32_t) * cap) != hipSuccess) {
+      (void)hipGetLastError();
+      return ge_fail(c, GE_ERR_OOM, "injection list allocation failed");
+    }
+    if (S.inj_n) GE_HIP(c, hipMemcpyAsync(nc, S.inj_cell, sizeof(int32_t) * S.inj_n, hipMemcpyDeviceToDevice, c->stream));
+    GE_HIP(c, hipStreamSynchronize(c->stream));
+    if (S.inj_cell) (void)hipFree(S.inj_cell);
+    S.inj_cell = nc;
+    S.inj_cap = cap;
+  }
+  hipLaunchKernelGGL(k_inj_check, dim3((m + 255) / 256), dim3(256), 0, c->stream, c->G, m, cell, c->flags);
+  GE_HIP(c, hipMemcpyAsync(S.inj_cell + S.inj_n, cell, sizeof(int32_t) * m, hipMemcpyDeviceToDevice, c->stream));
+  if (es == 4)
+    hipLaunchKernelGGL(k_pack_particles<float>, dim3((m + 255) / 256), dim3(256), 0, c->stream, m, (const float*)off,
+                       (const float*)v, (const float*)w, (float*)S.rec[S.cur] + GE_REC * at);
+  else
+    hipLaunchKernelGGL(k_pack_particles<double>, dim3((m + 255) / 256), dim3(256), 0, c->stream, m, (const double*)off,
+                       (const double*)v, (const double*)w, (double*)S.rec[S.cur] + GE_REC * at);
+  GE_HIP(c, hipGetLastError());
+  S.inj_n += m;
   return GE_OK;
 }
 

@@ -32,13 +32,18 @@ EXPORTS = [
     "ge_push", "ge_update_fields", "ge_step", "ge_sync", "ge_gather", "ge_set", "ge_half_stencil",
     "ge_get_particles", "ge_apply_operator", "ge_diagnostics", "ge_timings", "ge_explicit_current", "ge_explicit_step",
     "ge_moves", "ge_diagnostics_noalloc", "ge_step_count", "ge_species_count", "ge_checkpoint", "ge_restore",
+    "ge_inject",
     "ge_cnn_init", "ge_cnn_size", "ge_cnn_weights", "ge_cnn_apply", "ge_cnn_harvest", "ge_cnn_add_pair",
     "ge_cnn_npairs", "ge_cnn_train", "ge_cnn_loss_grad",
 ]
 
 
+GE_BC_PERIODIC, GE_BC_WALL, GE_BC_INFLOW = 0, 1, 2
+
+
 class GEGrid(ctypes.Structure):
-    _fields_ = [("dim", ctypes.c_int), ("n", ctypes.c_int * 3), ("dx", ctypes.c_double * 3)]
+    _fields_ = [("dim", ctypes.c_int), ("n", ctypes.c_int * 3), ("dx", ctypes.c_double * 3),
+                ("bc_lo", ctypes.c_int * 3), ("bc_hi", ctypes.c_int * 3)]
 
 
 class GEParams(ctypes.Structure):
@@ -78,7 +83,7 @@ class GEDiag(ctypes.Structure):
 
 class GEMoveReport(ctypes.Structure):
     _fields_ = [("far_moves", ctypes.c_int64 * 4), ("max_move", ctypes.c_double * 4), ("resorts", ctypes.c_int),
-                ("pushes", ctypes.c_int)]
+                ("pushes", ctypes.c_int), ("gone", ctypes.c_int64 * 4), ("injected", ctypes.c_int64 * 4)]
 
 
 class GlecsimError(RuntimeError):
@@ -123,6 +128,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.ge_diagnostics_noalloc.argtypes = [vp, ctypes.POINTER(GEDiag)]
     L.ge_step_count.argtypes = [vp]
     L.ge_step_count.restype = ctypes.c_int64
+    L.ge_inject.argtypes = [vp, ctypes.c_int, i64, vp, vp, vp, vp]
     L.ge_species_count.argtypes = [vp, ctypes.c_int]
     L.ge_species_count.restype = ctypes.c_int64
     L.ge_checkpoint.argtypes = [vp, ctypes.c_char_p]
@@ -159,17 +165,20 @@ class Simulation:
                  lf_B: bool = True, beta_lim: float = 1.0, a_mode: int = GE_A_BULK, a_const: float = 1.0,
                  comoving: bool = True, n_smooth_u: int = 5, phi_u: float = 0.5, fp32: bool = False,
                  ns_j: int = 0, dedner: bool = False, ch_frac: float = 0.8, dedner_damp: float = 0.1,
-                 ns_e: int = 0, limiter_lag: int = GE_LAG_EN, device: str = "cuda:0",
-                 stream: Optional[torch.cuda.Stream] = None):
+                 ns_e: int = 0, limiter_lag: int = GE_LAG_EN, bc=(GE_BC_PERIODIC, GE_BC_PERIODIC),
+                 device: str = "cuda:0", stream: Optional[torch.cuda.Stream] = None):
+        """bc: the x axis's (low, high) boundary kinds; with a wall the grid
+        stores n[0] + 1 points along x (see ge_grid)."""
         if not torch.cuda.is_available():
             raise RuntimeError("glecsim needs a GPU (no CPU fallback)")
         self.L = load_library()
         self.device = torch.device(device)
         self.dim = dim
         self.n = tuple(int(n[d]) if d < dim else 1 for d in range(3))
+        self.bc = (int(bc[0]), int(bc[1]))
         self.N = 1
         for d in range(dim):
-            self.N *= self.n[d]
+            self.N *= self.n[d] + (1 if d == 0 and self.bc[0] != GE_BC_PERIODIC else 0)
         self.fp32 = fp32
         self.fdtype = torch.float32 if fp32 else torch.float64
         g = GEGrid()
@@ -177,6 +186,7 @@ class Simulation:
         for d in range(3):
             g.n[d] = self.n[d]
             g.dx[d] = float(dx[d]) if d < dim else 1.0
+        g.bc_lo[0], g.bc_hi[0] = self.bc
         p = GEParams(theta, c, dt, int(lf_E), int(lf_B), beta_lim, a_mode, a_const, int(comoving), n_smooth_u,
                      phi_u, GE_FP32 if fp32 else GE_FP64, int(ns_j), int(dedner), ch_frac, dedner_damp,
                      int(ns_e), int(limiter_lag))
@@ -306,8 +316,24 @@ class Simulation:
         self._check(self.L.ge_set(self.h, FIELDS[what], _ptr(src)))
         self._keep = src  # keep alive until the stream has copied it
 
+    def inject(self, s: int, cell: torch.Tensor, off: torch.Tensor, v: torch.Tensor, w: torch.Tensor):
+        """Particles entering species s (see ge_inject)."""
+        n = int(cell.numel())
+        _require(cell.dtype == torch.int32, "cell must be int32")
+        _require(off.dtype == v.dtype == w.dtype == self.fdtype, f"off, v and w must be {self.fdtype}")
+        _require(off.shape == (3, n) and v.shape == (3, n) and w.shape == (n,), "off, v: [3, n]; w: [n]")
+        if n == 0:
+            return
+        self._check(self.L.ge_inject(self.h, s, n, _ptr(cell), _ptr(off), _ptr(v), _ptr(w)))
+        self._keep = (cell, off, v, w)  # alive until the stream has packed them
+
+    def count(self, s: int) -> int:
+        """Live particles of species s (settles the last push)."""
+        self.sync()
+        return int(self.L.ge_species_count(self.h, s))
+
     def particles(self, s: int) -> Dict[str, torch.Tensor]:
-        n = self.counts[s]
+        n = self.count(s)
         cell = torch.empty(n, dtype=torch.int32, device=self.device)
         off = torch.empty((3, n), dtype=self.fdtype, device=self.device)
         v = torch.empty((3, n), dtype=self.fdtype, device=self.device)
@@ -394,7 +420,9 @@ class Simulation:
         self._check(self.L.ge_moves(self.h, ctypes.byref(r)))
         return {"far_moves": [int(r.far_moves[s]) for s in range(self.nsp)],
                 "max_move": [float(r.max_move[s]) for s in range(self.nsp)],
-                "resorts": int(r.resorts), "pushes": int(r.pushes)}
+                "resorts": int(r.resorts), "pushes": int(r.pushes),
+                "gone": [int(r.gone[s]) for s in range(self.nsp)],
+                "injected": [int(r.injected[s]) for s in range(self.nsp)]}
 
     def timings(self):
         out = (ctypes.c_double * 8)()

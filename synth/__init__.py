@@ -37,6 +37,7 @@ class _Cfg(ctypes.Structure):
         ("n0", ctypes.c_double), ("u0", ctypes.c_double * 3), ("ushock", ctypes.c_double),
         ("B0", ctypes.c_double * 3), ("lambda_", ctypes.c_double), ("nb", ctypes.c_double),
         ("Bh", ctypes.c_double), ("psi", ctypes.c_double), ("dsheet", ctypes.c_double * 4),
+        ("ghost_x", ctypes.c_int), ("dt_inj", ctypes.c_double),
     ]
 
 
@@ -64,6 +65,9 @@ def lib():
                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                       ctypes.c_int]
         L.synth_fields.argtypes = [ctypes.POINTER(_Cfg), ctypes.c_void_p, ctypes.c_void_p]
+        L.synth_inflow.restype = ctypes.c_int64
+        L.synth_inflow.argtypes = [ctypes.POINTER(_Cfg), ctypes.c_int, ctypes.c_int64, ctypes.c_int64,
+                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
         L.synth_cfg_size.restype = ctypes.c_int
         assert L.synth_cfg_size() == ctypes.sizeof(_Cfg), "synth_cfg layout mismatch"
         _lib = L
@@ -112,6 +116,9 @@ class Workload:
     comoving: bool = True
     n_smooth_u: int = 5
     fp32: bool = False
+    # x boundaries (0 periodic, 1 wall, 2 inflow): (1, 1) or (1, 2) put a wall
+    # at x = 0; the grid then stores n[0] + 1 points along x (a ghost cell)
+    bc: tuple = (0, 0)
     note: str = ""
 
     @property
@@ -119,17 +126,33 @@ class Workload:
         return len(self.q)
 
     @property
+    def walled(self) -> bool:
+        return self.bc[0] != 0
+
+    @property
+    def nstore(self) -> tuple:
+        """Points per axis of the storage grid (a ghost cell column along x
+        when walled)."""
+        return (self.n[0] + (1 if self.walled else 0),) + tuple(self.n[1:])
+
+    @property
     def ncells(self) -> int:
+        """Grid points of the storage grid (= nodes = cells with their ghosts)."""
+        return int(np.prod(self.nstore[: self.dim]))
+
+    @property
+    def nphys(self) -> int:
+        """Physical cells (the ones that hold particles)."""
         return int(np.prod(self.n[: self.dim]))
 
     def nparticles(self) -> int:
-        return self.ncells * self.ppc * self.nsp
+        return self.nphys * self.ppc * self.nsp
 
     def cfg(self) -> _Cfg:
         c = _Cfg()
         c.dim = self.dim
         for d in range(3):
-            c.n[d] = int(self.n[d]) if d < self.dim else 1
+            c.n[d] = int(self.nstore[d]) if d < self.dim else 1
             c.dx[d] = float(self.dx[d]) if d < self.dim else 1.0
         c.ppc, c.nsp = self.ppc, self.nsp
         for s in range(self.nsp):
@@ -140,6 +163,7 @@ class Workload:
         for d in range(3):
             c.u0[d], c.B0[d] = self.u0[d], self.B0[d]
         c.ushock, c.lambda_, c.nb, c.Bh, c.psi = self.ushock, self.lam, self.nb, self.Bh, self.psi
+        c.ghost_x, c.dt_inj = int(self.walled), self.dt
         return c
 
     def replace(self, **kw) -> "Workload":
@@ -154,7 +178,11 @@ def particles(wl: Workload, s: int, cell_begin: int = 0, cell_end: Optional[int]
     'v' ([3, n]) and 'w' ([n]) in float64 (or float32 if f32)."""
     if cell_end is None:
         cell_end = wl.ncells
-    n = (cell_end - cell_begin) * wl.ppc
+
+    def ghosts_before(a):  # ghost cells (last x index of a walled grid) among [0, a)
+        return a // wl.nstore[0] if wl.walled else 0
+
+    n = (cell_end - cell_begin - (ghosts_before(cell_end) - ghosts_before(cell_begin))) * wl.ppc
     dt = np.float32 if f32 else np.float64
     cell = np.empty(n, np.int32)
     off = np.empty((3, n), dt)
@@ -175,6 +203,24 @@ def fields(wl: Workload):
     c = wl.cfg()
     lib().synth_fields(ctypes.byref(c), E.ctypes.data, B.ctypes.data)
     return E, B
+
+
+def inflow(wl: Workload, s: int, step: int, f32: bool = False) -> Dict[str, np.ndarray]:
+    """Particles of species s entering through the inflow plane of a walled
+    workload during step `step` (see synth_inflow in gen.c): same layout as
+    particles()."""
+    c = wl.cfg()
+    need = lib().synth_inflow(ctypes.byref(c), s, step, 0, None, None, None, None, int(f32))
+    dt = np.float32 if f32 else np.float64
+    cell = np.empty(need, np.int32)
+    off = np.empty((3, need), dt)
+    v = np.empty((3, need), dt)
+    w = np.empty(need, dt)
+    if need:
+        got = lib().synth_inflow(ctypes.byref(c), s, step, need, cell.ctypes.data, off.ctypes.data, v.ctypes.data,
+                                 w.ctypes.data, int(f32))
+        assert got == need
+    return {"cell": cell, "off": off, "v": v, "w": w}
 
 
 def _harris(name, dim, n, mi, ppc, guide, steps, fp32):
@@ -213,14 +259,20 @@ def workloads() -> Dict[str, Workload]:
         fp32=False)
     # C3: 2D3V Harris sheet reconnection (double sheet, periodic).
     W["c3"] = _harris("c3_harris_2d", 2, (512, 256, 1), 25.0, 100, 0.0, 500, True)
-    # C4: 3D3V collisionless shock (periodic, mirror-symmetric colliding flows).
+    # C4: 3D3V collisionless shock: plasma flowing at -0.15c toward a
+    # reflecting, conducting wall at x = 0, fed through an inflow plane at
+    # x = L (fields held at the upstream values, injection per step).
     th = math.radians(30.0)
     W["c4"] = Workload(
         name="c4_shock_3d", dim=3, n=(128, 64, 64), dx=(0.5, 0.5, 0.5), ppc=27,
         q=(-1.0, 1.0), m=(1.0, 25.0), vth=(0.05, 0.01), paired=False, seed=4,
-        profile=PROF_SHOCK_TUBE, ushock=0.15, B0=(0.15 * math.cos(th), 0.15 * math.sin(th), 0.0),
+        profile=PROF_UNIFORM, u0=(-0.15, 0.0, 0.0), B0=(0.15 * math.cos(th), 0.15 * math.sin(th), 0.0),
         dt=0.5, theta=0.5, steps=200, lf_E=True, lf_B=True, beta_lim=1.0, a_mode=1,
-        comoving=True, fp32=True)
+        comoving=True, fp32=True, bc=(1, 2))
+    # the same shock as two colliding flows in a periodic box (the mirror image
+    # of the wall; no inflow)
+    W["c4p"] = W["c4"].replace(name="c4p_colliding_flows_3d", profile=PROF_SHOCK_TUBE, u0=(0.0, 0.0, 0.0),
+                               ushock=0.15, bc=(0, 0))
     # C5: 3D3V reconnection at HBM scale with a guide flow.
     W["c5"] = _harris("c5_harris_3d", 3, (256, 128, 128), 100.0, 64, 0.2, 50, True)
     # Sec. 4.2 uniform fast flow (solar wind at 1 AU) in code units c = 1,
@@ -248,7 +300,7 @@ def small(name: str, dim: int = 3, n=(6, 5, 4), ppc: int = 7, fp32: bool = False
     wl = workloads()[base]
     nn = tuple(n[:dim]) + (1,) * (3 - dim)
     dx = tuple(wl.dx[:dim]) + (1.0,) * (3 - dim) if wl.dim >= dim else (0.5,) * dim + (1.0,) * (3 - dim)
-    out = wl.replace(name=name, dim=dim, n=nn, dx=dx, ppc=ppc, fp32=fp32)
+    out = wl.replace(name=name, dim=dim, n=nn, dx=dx, ppc=ppc, fp32=fp32, bc=(0, 0))
     if out.profile == PROF_HARRIS2 and dim < 2:
         out = out.replace(profile=PROF_UNIFORM)
     if out.profile == PROF_HARRIS2:

@@ -74,6 +74,8 @@ typedef struct {
   double Bh;          /* Harris asymptotic field */
   double psi;         /* perturbation amplitude (flux units) */
   double dsheet[4];   /* per-species drift speed along z inside sheet 1 */
+  int ghost_x;        /* 1: x ends in walls; the last x cell (index n[0]-1) is a ghost cell */
+  double dt_inj;      /* time step of the inflow injection (synth_inflow) */
 } synth_cfg;
 
 static void domain_len(const synth_cfg* c, double L[3]) {
@@ -141,17 +143,24 @@ int64_t synth_ncells(const synth_cfg* c) {
  * If f32 != 0 the float outputs are written as float, else double.
  * Returns the number of particles written.
  */
+/* ghost cells (x index n[0]-1 of a walled grid) among the linear cells [0, a) */
+static int64_t ghosts_before(const synth_cfg* c, int64_t a) {
+  return c->ghost_x ? a / c->n[0] : 0;
+}
+
 int64_t synth_particles(const synth_cfg* c, int s, int64_t cb, int64_t ce, int32_t* cell,
                         void* off, void* v, void* w, int f32) {
-  int64_t count = (ce - cb) * (int64_t)c->ppc;
+  int64_t count = (ce - cb - (ghosts_before(c, ce) - ghosts_before(c, cb))) * (int64_t)c->ppc;
   double dV = 1.0;
   for (int d = 0; d < c->dim; ++d) dV *= c->dx[d];
   #pragma omp parallel for schedule(static)
   for (int64_t cc = cb; cc < ce; ++cc) {
     int64_t ic[3] = {0, 0, 0}, rem = cc;
     for (int d = 0; d < c->dim; ++d) { ic[d] = rem % c->n[d]; rem /= c->n[d]; }
+    if (c->ghost_x && ic[0] == c->n[0] - 1) continue;  /* no particles in a ghost cell */
+    const int64_t slot = cc - cb - (ghosts_before(c, cc) - ghosts_before(c, cb));
     for (int k = 0; k < c->ppc; ++k) {
-      int64_t p = (cc - cb) * c->ppc + k;
+      int64_t p = slot * c->ppc + k;
       uint32_t key[2] = {c->seed, 0x9A1Eu};
       uint32_t ca[4] = {(uint32_t)cc, (uint32_t)k, c->paired ? 0u : (uint32_t)(s + 1), 0x50u};
       uint32_t cv[4] = {(uint32_t)cc, (uint32_t)k, (uint32_t)(s + 1), 0x56u};
@@ -225,7 +234,71 @@ void synth_fields(const synth_cfg* c, double* E, double* B) {
     E[0 * N + g] = -(u[1] * Bn[2] - u[2] * Bn[1]);
     E[1 * N + g] = -(u[2] * Bn[0] - u[0] * Bn[2]);
     E[2 * N + g] = -(u[0] * Bn[1] - u[1] * Bn[0]);
+    if (c->ghost_x && ic[0] == 0) E[1 * N + g] = E[2 * N + g] = 0.0;  /* the wall: no tangential E */
   }
+}
+
+/*
+ * Particles of species s entering through the inflow plane x = L during
+ * step `step` (0-based) of a walled grid: a slab of thickness |u_x| dt_inj
+ * at the upper end of the last physical cell column, ppc |u_x| dt_inj / dx
+ * particles per column and step on average, the count of step k being
+ * floor((k+1) r) - floor(k r) so that the flux is exact over the run.  Drifting
+ * Maxwellian velocities as in the bulk; keyed by (seed, 0x1F10), counted by
+ * (cell, k, species, step).  Writes up to max particles (cell-major); returns
+ * the number written (or the number needed if max is smaller).
+ */
+int64_t synth_inflow(const synth_cfg* c, int s, int64_t step, int64_t max, int32_t* cell, void* off, void* v,
+                     void* w, int f32) {
+  if (!c->ghost_x) return 0;
+  const int nx = c->n[0] - 1;  /* physical cells along x */
+  const double r = c->ppc * fabs(c->u0[0]) * c->dt_inj / c->dx[0];
+  const int per = (int)(floor((step + 1) * r) - floor(step * r));
+  const int64_t ncol = (int64_t)c->n[1] * c->n[2];
+  const int64_t count = ncol * per;
+  if (count > max) return count;
+  double dV = 1.0;
+  for (int d = 0; d < c->dim; ++d) dV *= c->dx[d];
+  const double slab = fabs(c->u0[0]) * c->dt_inj / c->dx[0];
+  for (int64_t col = 0; col < ncol; ++col) {
+    const int64_t cc = (nx - 1) + (int64_t)c->n[0] * col;
+    int64_t ic[3] = {nx - 1, col % c->n[1], col / c->n[1]};
+    for (int k = 0; k < per; ++k) {
+      const int64_t p = col * per + k;
+      uint32_t key[2] = {c->seed, 0x1F10u};
+      uint32_t ca[4] = {(uint32_t)cc, (uint32_t)k, (uint32_t)(s + 1), (uint32_t)(0x50000u + step)};
+      uint32_t cv[4] = {(uint32_t)cc, (uint32_t)k, (uint32_t)(s + 1), (uint32_t)(0x560000u + step)};
+      uint32_t ra[4], rv[4];
+      synth_philox4x32_10(ca, key, ra);
+      synth_philox4x32_10(cv, key, rv);
+      double f[3] = {0, 0, 0}, x[3] = {0, 0, 0};
+      for (int d = 0; d < c->dim; ++d) f[d] = u01_24(ra[d]);
+      f[0] = 1.0 - slab * f[0];  /* in the slab next to x = L */
+      if (f[0] >= 1.0) f[0] = 0.99999994039535522;
+      for (int d = 0; d < c->dim; ++d) x[d] = ((double)ic[d] + f[d]) * c->dx[d];
+      double u[3]; drift(c, s, x, u01(ra[3]), u);
+      double nn[4]; normals4(rv, nn);
+      double r2 = nn[0] * nn[0] + nn[1] * nn[1] + nn[2] * nn[2];
+      if (r2 > RCLIP * RCLIP) {
+        double sc = RCLIP / sqrt(r2);
+        nn[0] *= sc; nn[1] *= sc; nn[2] *= sc;
+      }
+      double vv[3];
+      for (int d = 0; d < 3; ++d) vv[d] = u[d] + c->vth[s] * nn[d];
+      double ww = synth_density(c, x) * dV / c->ppc;
+      cell[p] = (int32_t)cc;
+      if (f32) {
+        float* fo = (float*)off; float* fv = (float*)v; float* fw = (float*)w;
+        for (int d = 0; d < 3; ++d) { fo[d * count + p] = (float)f[d]; fv[d * count + p] = (float)vv[d]; }
+        fw[p] = (float)ww;
+      } else {
+        double* fo = (double*)off; double* fv = (double*)v; double* fw = (double*)w;
+        for (int d = 0; d < 3; ++d) { fo[d * count + p] = f[d]; fv[d * count + p] = vv[d]; }
+        fw[p] = ww;
+      }
+    }
+  }
+  return count;
 }
 
 int synth_cfg_size(void) { return (int)sizeof(synth_cfg); }

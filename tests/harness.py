@@ -41,7 +41,7 @@ def species_arrays(wl, f32: bool):
 
 
 def oracle_species(wl, parts):
-    G = O.grid(wl.dim, wl.n, wl.dx)
+    G = O.grid(wl.dim, wl.n, wl.dx, bc=wl.bc)
     out = []
     for s, p in enumerate(parts):
         x = O.global_positions(G, p["cell"], p["off"].astype(np.float64))
@@ -52,7 +52,7 @@ def oracle_species(wl, parts):
 def make_sim(wl, parts, E, B, **over):
     from paper_2506_11320_amd import Simulation
     kw = dict(theta=wl.theta, dt=wl.dt, lf_E=wl.lf_E, lf_B=wl.lf_B, beta_lim=wl.beta_lim, a_mode=wl.a_mode,
-              a_const=1.0, comoving=wl.comoving, n_smooth_u=wl.n_smooth_u, fp32=wl.fp32)
+              a_const=1.0, comoving=wl.comoving, n_smooth_u=wl.n_smooth_u, fp32=wl.fp32, bc=wl.bc)
     kw.update(over)
     sim = Simulation(wl.dim, wl.n, wl.dx, **kw)
     dev = sim.device
@@ -94,6 +94,6 @@ def make_bare_sim(wl, **over):
     ge_restore)."""
     from paper_2506_11320_amd import Simulation
     kw = dict(theta=wl.theta, dt=wl.dt, lf_E=wl.lf_E, lf_B=wl.lf_B, beta_lim=wl.beta_lim, a_mode=wl.a_mode,
-              a_const=1.0, comoving=wl.comoving, n_smooth_u=wl.n_smooth_u, fp32=wl.fp32)
+              a_const=1.0, comoving=wl.comoving, n_smooth_u=wl.n_smooth_u, fp32=wl.fp32, bc=wl.bc)
     kw.update(over)
     return Simulation(wl.dim, wl.n, wl.dx, **kw)

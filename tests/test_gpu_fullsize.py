@@ -133,7 +133,7 @@ def _probe_field(wl):
     return x
 
 
-@pytest.mark.parametrize("name,nodes", [("c5", NODES), ("c4", NODES_C4)])
+@pytest.mark.parametrize("name,nodes", [("c5", NODES), ("c4p", NODES_C4)])
 def test_grid_quantities_operator_and_solve_at_full_size(name, nodes):
     wl = _workload(name)
     print(f"[gpu] full-size {name} deposit/operator/solve", flush=True)

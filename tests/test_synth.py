@@ -49,3 +49,42 @@ def test_maxwellian_moments():
     assert abs(v[0].mean() - 0.2) < 3 * 0.02 / np.sqrt(v.shape[1]) * 3
     assert abs(v[1].std() / 0.02 - 1) < 0.02
     assert np.linalg.norm(v - np.array(wl.u0)[:, None], axis=0).max() <= 4.5 * 0.02 + 1e-12
+
+
+def test_walled_loading_skips_the_ghost_cells():
+    """A walled workload stores a ghost cell column along x: no particles in
+    it, the same per-range regeneration, and no tangential E on the wall."""
+    wl = synth.workloads()["c4"].replace(n=(6, 4, 3), ppc=3)
+    assert wl.nstore == (7, 4, 3) and wl.ncells == 84 and wl.nphys == 72
+    full = synth.particles(wl, 0)
+    assert full["cell"].size == wl.nphys * wl.ppc
+    assert np.all(full["cell"] % 7 != 6)
+    assert np.all(np.diff(full["cell"]) >= 0)
+    part = synth.particles(wl, 0, 5, 20)  # a range across two ghost cells (6 and 13)
+    sel = (full["cell"] >= 5) & (full["cell"] < 20)
+    assert part["cell"].size == sel.sum() == (15 - 2) * wl.ppc
+    assert np.array_equal(part["cell"], full["cell"][sel]) and np.array_equal(part["v"], full["v"][:, sel])
+    E, B = synth.fields(wl)
+    i = np.arange(wl.ncells) % 7
+    assert np.all(E[1:, i == 0] == 0) and np.any(E[2, i == 3] != 0)
+    np.testing.assert_allclose(B[:, i == 6], np.array(wl.B0)[:, None] * np.ones((1, 12)))
+
+
+def test_inflow_injection_flux():
+    """The particles entering through x = L: in the last physical cell
+    column, inside the slab |u_x| dt next to the plane, and on average
+    ppc |u_x| dt / dx per column and step (the flux n |u_x| dt A)."""
+    wl = synth.workloads()["c4"].replace(n=(6, 4, 3), ppc=27)
+    r = wl.ppc * abs(wl.u0[0]) * wl.dt / wl.dx[0]
+    tot = 0
+    K = 40
+    for k in range(K):
+        p = synth.inflow(wl, 1, k)
+        tot += p["cell"].size
+        if p["cell"].size:
+            assert np.all(p["cell"] % 7 == 5)
+            assert np.all(p["off"][0] >= 1 - abs(wl.u0[0]) * wl.dt / wl.dx[0]) and np.all(p["off"][0] < 1)
+        assert np.array_equal(synth.inflow(wl, 1, k)["v"], p["v"])  # regenerable per step
+    ncol = 4 * 3
+    assert tot == ncol * int(np.floor(K * r))
+    assert abs(tot / (K * ncol) - r) < 1.0 / K
