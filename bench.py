@@ -147,7 +147,7 @@ def cpu_baseline(wname, box, procs):
 def make_sim(wl, args, Simulation, torch, synth):
     sim = Simulation(wl.dim, wl.n, wl.dx, theta=wl.theta, dt=wl.dt, lf_E=wl.lf_E, lf_B=wl.lf_B,
                      beta_lim=wl.beta_lim, a_mode=wl.a_mode, comoving=wl.comoving, n_smooth_u=wl.n_smooth_u,
-                     fp32=wl.fp32, ns_j=args.ns_j, dedner=args.dedner)
+                     fp32=wl.fp32, ns_j=args.ns_j, dedner=args.dedner, bc=wl.bc)
     counts = []
     for s in range(wl.nsp):
         p = synth.particles(wl, s, f32=wl.fp32)
@@ -177,12 +177,22 @@ def nn_compare(wl, args, Simulation, torch, synth):
     with the second answer."""
     from paper_2506_11320_amd import GE_HARVEST_KRYLOV, GE_HARVEST_SOLUTION, GE_PC_CNN
     sim, _ = make_sim(wl, args, Simulation, torch, synth)
+    k_inj = [0]
+
+    def inject():
+        if wl.walled and wl.bc[1] == 2:
+            for s in range(wl.nsp):
+                p = {kk: torch.from_numpy(v).cuda() for kk, v in synth.inflow(wl, s, k_inj[0], f32=wl.fp32).items()}
+                sim.inject(s, p["cell"], p["off"], p["v"], p["w"])
+            k_inj[0] += 1
+
     try:
         sim.cnn_init(1, max_pairs=args.nn_pairs)
         sim.cnn_harvest({"solution": GE_HARVEST_SOLUTION, "krylov": GE_HARVEST_KRYLOV,
                          "both": GE_HARVEST_SOLUTION | GE_HARVEST_KRYLOV}[args.nn_data])
         for k in range(args.nn_harvest):
             r = sim.step(tol=args.tol, maxit=500, restart=30, precond=0)
+            inject()
             log(f"harvest step {k}: {r['iterations']} iterations")
         sim.cnn_harvest(0)
         tr = sim.cnn_train(crop=args.nn_crop, batch=args.nn_batch, iters=args.nn_iters, lr=args.nn_lr, seed=7)
@@ -210,6 +220,7 @@ def nn_compare(wl, args, Simulation, torch, synth):
                 f"nn {rc['iterations']} it {rc['seconds'] * 1e3:.2f} ms (relres {rc['relres']:.2e})")
             sim.push()
             sim.update_fields()
+            inject()
         sim.sync()
     finally:
         sim.close()
@@ -293,8 +304,22 @@ def main():
     sim, counts = make_sim(wl, args, Simulation, torch, synth)
     log(f"setup {time.perf_counter() - t0:.1f} s ({sum(counts)} particles)")
     pc = {"none": 0, "jacobi": 1}[args.precond]
+    # an inflow plane: the particles entering in each step, generated and
+    # uploaded before the timed region, injected after each step
+    inflow = []
+    if wl.walled and wl.bc[1] == 2:
+        for k in range(args.warmup + args.steps):
+            inflow.append([{kk: torch.from_numpy(v).cuda() for kk, v in synth.inflow(wl, s, k, f32=wl.fp32).items()}
+                           for s in range(wl.nsp)])
+        torch.cuda.synchronize()
+
+    def inject(k):
+        for s, p in enumerate(inflow[k] if inflow else []):
+            sim.inject(s, p["cell"], p["off"], p["v"], p["w"])
+
     for k in range(args.warmup):
         r = sim.step(tol=args.tol, maxit=500, restart=30, precond=pc)
+        inject(k)
         log(f"warmup step {k}: {r['iterations']} GMRES iterations, relres {r['relres']:.2e}")
     sim.timings()  # reset the per-phase accumulators
     sim.moves()
@@ -304,17 +329,19 @@ def main():
     t0 = time.perf_counter()
     for k in range(args.steps):
         r = sim.step(tol=args.tol, maxit=500, restart=30, precond=pc)
+        inject(args.warmup + k)
         iters.append(r["iterations"])
         solve_s.append(r["seconds"])
         if not r["converged"]:
             log(f"step {k}: GMRES did not converge (relres {r['relres']:.2e})")
+    sim.sync()  # the last injection joins the species
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     tm = sim.timings()
     moves = sim.moves()
     diag = sim.diagnostics()
     log(f"timed {args.steps} steps in {elapsed:.3f} s; moves {moves}")
-    npart = sum(counts)
+    npart = sum(counts) if not inflow else sum(sim.count(s) for s in range(wl.nsp))
     ms_step = elapsed / args.steps * 1e3
     phase = {"push_rebin": tm[0] * 1e3, "deposit": tm[1] * 1e3, "assemble": tm[2] * 1e3, "grid_rest": tm[3] * 1e3,
              "update": tm[4] * 1e3, "solve": tm[5] * 1e3}
@@ -371,7 +398,9 @@ def main():
                                f"{'FP32' if wl.fp32 else 'FP64'} push/deposit, FP64 GMRES to {args.tol:g}, "
                                f"{'comoving' if wl.comoving else 'lab-frame'} current, "
                                f"{'limited LF' if wl.lf_E or wl.lf_B else 'no LF'}",
-                   "cells": wl.ncells, "particles": npart, "precond": args.precond, "ns_j": args.ns_j,
+                   "cells": wl.nphys, "particles": npart, "precond": args.precond, "ns_j": args.ns_j,
+                   "x_boundaries": {0: "periodic", 1: "wall", 2: "inflow"}[wl.bc[0]] + "/" +
+                                   {0: "periodic", 1: "wall", 2: "inflow"}[wl.bc[1]],
                    "dedner": bool(args.dedner)},
         # the metric's first quantity: particle-steps per second of the
         # particle phases alone (push with re-binning, deposit, node assembly)
