@@ -600,8 +600,9 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_final(const int32_t* __rest
 // W_a W_b of the cell is one of these rows, and every linear weight W_a is a
 // sum of them, so S = A B holds the whole cell's contribution to the mass
 // matrices, current and moments.  Each lane computes one particle's operands
-// and writes them to an LDS row laid out for the MFMA reads (one 8-byte read
-// of the two A rows and one 4-byte read of B per 4-particle step).  Each
+// and writes them to an LDS row laid out for the MFMA reads: the per-axis
+// weight factors, whose products give the A rows as the operands are read,
+// and the B columns.  Each
 // species' S is scaled (beta_s q_s, q_s, m_s) into per-wave LDS accumulators
 // and the cell's sums are written once at the end.
 template <typename T>
@@ -639,12 +640,20 @@ template <typename T, int DIM>
 struct DepCfg {
   static constexpr int NR = Dm<DIM>::ND;
   static constexpr int NRB = Dm<DIM>::NRB;
-  // staged row of a particle: its NR A values (quadratic rows), then the 16 B
-  // columns, padded to a multiple of 4.  ST / 4 is odd (3D: 11, 2D: 7, 1D: 5),
-  // so the 16 lanes of a 16-byte write phase hit 16 different bank groups.
-  static constexpr int AW = NR;
-  static constexpr int ST = (NR + 16 + 3) / 4 * 4;
-  static constexpr int NACC = NR * (7 + GE_MAX_SPECIES);  // linear sums only (quadratic ones stay in registers)
+  // staged row of a particle: the quadratic weight factors of x (3 values)
+  // and the products of those of the other axes (NB = 3^(DIM-1) values), whose
+  // products are the NR A values (row r = factor r % 3 times product r / 3,
+  // formed when the MFMA operands are read); then the 16 B columns, padded to
+  // a multiple of 4 with ST / 4 odd (3D and 2D: 7, 1D: 5), so that the 16
+  // lanes of a 16-byte write phase hit 16 different bank groups.
+  static constexpr int NB = DIM == 3 ? 9 : (DIM == 2 ? 3 : 1);
+  static constexpr int AW = 3 + NB;
+  static constexpr int ST0 = (AW + 16 + 3) / 4 * 4;
+  static constexpr int ST = (ST0 / 4) % 2 ? ST0 : ST0 + 4;
+  // linear sums only (quadratic ones stay in registers): [NR][LW], the 7
+  // species-summed columns then the charge of each species (odd stride)
+  static constexpr int LW = 7 + GE_MAX_SPECIES;
+  static constexpr int NACC = NR * LW;
 };
 
 // Run table of one cell for two species at once: lanes 0..26 hold the runs
@@ -766,8 +775,10 @@ __device__ inline void load_p(const DepSpecies<T>& S, int i, PState<T>& P) {
 // registers).  The corner fields and the run table are loaded first; the run
 // table gives the particle indices, whose loads are then all in flight
 // together before the first chunk is staged.
+// In FP32 the registers fit four waves per SIMD, which the staging memory
+// also allows; latency hiding sets this kernel's speed.
 template <typename T, int DIM>
-__global__ __launch_bounds__(64) void k_deposit(DGrid G, DepArgs<T> A) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1))) void k_deposit(DGrid G, DepArgs<T> A) {
   using M = Mfma<T>;
   typedef typename M::v4 v4;
   using C = DepCfg<T, DIM>;
@@ -776,13 +787,17 @@ __global__ __launch_bounds__(64) void k_deposit(DGrid G, DepArgs<T> A) {
   const int lane = threadIdx.x;
   const int64_t c = __builtin_amdgcn_readfirstlane((int)xcd_block(blockIdx.x, gridDim.x));
   if (c >= G.N) return;
-  T* acc_lin = L.acc;             // [NR][7]: q alpha v (3), m v (3), m w
-  T* acc_rho = acc_lin + 7 * NR;  // [NR][GE_MAX_SPECIES]
+  constexpr int LW = C::LW;
+  T* lin = L.acc;  // [NR][LW]: q alpha v (3), m v (3), m w, then q_s w of each species
   const int col = lane & 15;
-  // MFMA operand reads of a step: row 4 stp + lane/16, A row col (and 16 +
-  // col), B column col.  A rows past NR read other values of the row: their
-  // products land in accumulator rows that are never used.
-  const int rofsA0 = (lane >> 4) * ST + col, rofsA1 = rofsA0 + 16, rofsB = (lane >> 4) * ST + AW + col;
+  // MFMA operand reads of a step: row 4 stp + lane/16; A row col (and 16 +
+  // col) as the product of its two staged factors, B column col.  A rows past
+  // NR read other (finite) values of the row: their products land in
+  // accumulator rows that are never used.
+  const int rrow = (lane >> 4) * ST, r1 = 16 + col;
+  const int rofsXa0 = rrow + col % 3, rofsXb0 = rrow + 3 + col / 3;
+  const int rofsXa1 = rrow + r1 % 3, rofsXb1 = rrow + 3 + r1 / 3;
+  const int rofsB = rrow + AW + col;
 
   // B at the corners: FP32 in scalar registers (wave-uniform loads); FP64 (twice
   // the registers) one corner per lane (lanes past the corners reload corner 0)
@@ -820,12 +835,13 @@ __global__ __launch_bounds__(64) void k_deposit(DGrid G, DepArgs<T> A) {
   }
   wave_sync();
   {
-    // Mtilde and M0 rows (B columns 0..8) and the linear sums (columns 9..15)
-    // accumulate over species in registers; the charge density of each
-    // species goes to LDS as it is completed
-    v4 aMt[NRB], aM0[NRB], aLin[NRB];
+    // Mtilde rows (B columns 0..8; the linear sums, columns 9..15, in the
+    // same registers of the other lanes) and M0 rows accumulate over species
+    // in registers; the charge density of each species goes to LDS as it is
+    // completed
+    v4 aX[NRB], aM0[NRB];
 #pragma unroll
-    for (int rb = 0; rb < NRB; ++rb) aMt[rb] = aM0[rb] = aLin[rb] = v4{0, 0, 0, 0};
+    for (int rb = 0; rb < NRB; ++rb) aX[rb] = aM0[rb] = v4{0, 0, 0, 0};
     for (int s = 0; s < A.nsp; ++s) {
       const DepSpecies<T>& S = A.sp[s];
       const int total = L.total[s];
@@ -843,7 +859,7 @@ __global__ __launch_bounds__(64) void k_deposit(DGrid G, DepArgs<T> A) {
         // the corner-0 position with zero velocity, so every staged value is
         // finite and the MFMA adds exact zeros for them
         const bool ok = t0 + lane < total;
-        T vals[ST];  // A rows 0..NR-1, then the 16 B columns
+        T vals[ST];  // the A factors, then the 16 B columns
         {
           T f[3], v[3];
 #pragma unroll
@@ -889,13 +905,12 @@ __global__ __launch_bounds__(64) void k_deposit(DGrid G, DepArgs<T> A) {
               X[d][0] = 1; X[d][1] = 0; X[d][2] = 0;
             }
           }
-          T YZ[9];
 #pragma unroll
-          for (int k = 0; k < 9; ++k) YZ[k] = X[1][k % 3] * X[2][k / 3];
+          for (int k = 0; k < 3; ++k) vals[k] = X[0][k];
 #pragma unroll
-          for (int r = 0; r < NR; ++r) vals[r] = X[0][r % 3] * YZ[r / 3];
+          for (int k = 0; k < C::NB; ++k) vals[3 + k] = X[1][k % 3] * X[2][k / 3];
 #pragma unroll
-          for (int k = NR + 16; k < ST; ++k) vals[k] = 0;
+          for (int k = AW + 16; k < ST; ++k) vals[k] = 0;
         }
         {
           typedef T t4 __attribute__((ext_vector_type(4)));
@@ -916,8 +931,8 @@ __global__ __launch_bounds__(64) void k_deposit(DGrid G, DepArgs<T> A) {
           for (int i = 0; i < 4; ++i) {
             const T* rows = L.stage + (16 * g + 4 * i) * ST;
             b[i] = rows[rofsB];
-            a[0][i] = rows[rofsA0];
-            a[1][i] = NRB == 2 ? rows[rofsA1] : (T)0;
+            a[0][i] = rows[rofsXa0] * rows[rofsXb0];
+            a[1][i] = NRB == 2 ? rows[rofsXa1] * rows[rofsXb1] : (T)0;
           }
         };
         v4 cacc[NRB];
@@ -951,6 +966,11 @@ __global__ __launch_bounds__(64) void k_deposit(DGrid G, DepArgs<T> A) {
         if (nchunk == 0) {
 #pragma unroll
           for (int rb = 0; rb < NRB; ++rb) acc[rb] = cacc[rb];
+        } else if (total <= 128) {
+          // the second and last chunk: the compensated sum of two terms
+          // rounds to the plain sum, so add directly (same bits)
+#pragma unroll
+          for (int rb = 0; rb < NRB; ++rb) acc[rb] += cacc[rb];
         } else {
 #pragma unroll
           for (int rb = 0; rb < NRB; ++rb)
@@ -977,17 +997,16 @@ __global__ __launch_bounds__(64) void k_deposit(DGrid G, DepArgs<T> A) {
       }
       // scale this species' sums into the cell accumulators (each (row, col)
       // belongs to one lane)
-      const T qs = S.q, ms = S.m, bq = S.beta * S.q, ls = col < 12 ? qs : ms;
+      const T qs = S.q, ms = S.m, bq = S.beta * S.q, sx = col < 9 ? bq : (col < 12 ? qs : ms);
 #pragma unroll
       for (int rb = 0; rb < NRB; ++rb)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const T val = acc[rb][i] + cmp[rb][i];
-          aMt[rb][i] += bq * val;
+          aX[rb][i] += sx * val;
           aM0[rb][i] += qs * val;
-          aLin[rb][i] += ls * val;
           const int r = 16 * rb + M::row(lane, i);
-          if (col == 15 && r < NR) acc_rho[r * GE_MAX_SPECIES + s] = qs * val;
+          if (col == 15 && r < NR) lin[r * LW + 7 + s] = qs * val;
         }
     }
     // linear sums to LDS for the corner sums (rows < NR, columns 9..15)
@@ -996,7 +1015,7 @@ __global__ __launch_bounds__(64) void k_deposit(DGrid G, DepArgs<T> A) {
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int r = 16 * rb + M::row(lane, i);
-        if (r < NR && col >= 9) acc_lin[r * 7 + col - 9] = aLin[rb][i];
+        if (r < NR && col >= 9) lin[r * LW + col - 9] = aX[rb][i];
       }
     wave_sync();
     // write the cell: quadratic rows of Mtilde and M0, then corner sums of the
@@ -1009,7 +1028,7 @@ __global__ __launch_bounds__(64) void k_deposit(DGrid G, DepArgs<T> A) {
         for (int i = 0; i < 4; ++i) {
           const int r = 16 * rb + M::row(lane, i);
           if (r < NR) {
-            Qc[cq_off(r * 9 + col)] = aMt[rb][i];
+            Qc[cq_off(r * 9 + col)] = aX[rb][i];
             Qc[cq_off(9 * NR + r * 9 + col)] = aM0[rb][i];
           }
         }
@@ -1023,7 +1042,7 @@ __global__ __launch_bounds__(64) void k_deposit(DGrid G, DepArgs<T> A) {
         int r = (a & 1) + (b & 1);
         if (DIM >= 2) r += 3 * (((a >> 1) & 1) + ((b >> 1) & 1));
         if (DIM >= 3) r += 9 * (((a >> 2) & 1) + ((b >> 2) & 1));
-        sum += k < 7 ? acc_lin[r * 7 + k] : acc_rho[r * GE_MAX_SPECIES + (k - 7)];
+        sum += lin[r * LW + k];
       }
       Qc[cq_off(18 * NR + k * NC + a)] = sum;
     }
