@@ -494,85 +494,60 @@ __device__ inline void curlcurl_wall(const DGrid& G, const double* __restrict__ 
 // curl_CN curl_NC is a constant 3^DIM-point stencil (a sum of tensor products
 // of 1D differences and averages), precomputed on the host into K:
 // K.k[o][3 m + j] multiplies x_j at offset o for output component m.
-// curl_CN (curl_NC x) at an interior node (Sec. 2.1 discretisation), as
-// partial sums per grid factor: for output component m and each derivative
-// axis d != m, the second difference of x_m along d (weights -2 at the node,
-// 1 at the two neighbours) times the transverse averages along the remaining
-// axes (1/2 at the node's index, 1/4 at either neighbour) enters with
-// -1/dx_d^2; the central differences of x_d along d and m (weights o_d o_m /
-// 4) times the transverse average along the third axis enter with
-// 1/(dx_d dx_m).  Every stencil weight is a compile-time constant.
-template <int DIM>
-__device__ inline void curlcurl_node(const DGrid& G, const double* __restrict__ x, int gx, int gy, int gz,
-                                     double out[3]) {
-  const int64_t N = G.N;
-  constexpr int RY = DIM >= 2 ? 1 : 0, RZ = DIM >= 3 ? 1 : 0;
-  double sd[3][3], so[3][3];  // [m][d]: second differences of x_m, mixed differences of x_d
-#pragma unroll
-  for (int m = 0; m < 3; ++m)
-#pragma unroll
-    for (int d = 0; d < 3; ++d) sd[m][d] = so[m][d] = 0.0;
-#pragma unroll
-  for (int oz = -RZ; oz <= RZ; ++oz)
-#pragma unroll
-    for (int oy = -RY; oy <= RY; ++oy)
-#pragma unroll
-      for (int ox = -1; ox <= 1; ++ox) {
-        const int o[3] = {ox, oy, oz};
-        const int64_t h = flat3(G, gx + ox, gy + oy, gz + oz);
-        const double xv[3] = {x[h], x[N + h], x[2 * N + h]};
-#pragma unroll
-        for (int m = 0; m < 3; ++m)
-#pragma unroll
-          for (int d = 0; d < DIM; ++d) {
-            if (d == m) continue;
-            double wdg = o[d] == 0 ? -2.0 : 1.0, wof = 0.25 * o[d] * (m < DIM ? o[m] : 0);
-#pragma unroll
-            for (int e = 0; e < DIM; ++e) {
-              const double tw = o[e] == 0 ? 0.5 : 0.25;
-              if (e != d) wdg *= tw;
-              if (e != d && e != m) wof *= tw;
-            }
-            sd[m][d] += wdg * xv[m];
-            if (wof != 0.0) so[m][d] += wof * xv[d];
-          }
-      }
-#pragma unroll
-  for (int m = 0; m < 3; ++m) {
-    double v = 0.0;
-#pragma unroll
-    for (int d = 0; d < DIM; ++d) {
-      if (d == m) continue;
-      v -= G.idx[d] * G.idx[d] * sd[m][d];
-      if (m < DIM) v += G.idx[d] * G.idx[m] * so[m][d];
-    }
-    out[m] = v;
-  }
-}
+// curl_CN (curl_NC x) at an interior node as a 27-point stencil of 3x3
+// blocks (Sec. 2.1 discretisation), built on the host (curl_curl_stencil)
+struct CurlCurl {
+  double k[27][9];
+};
 
-template <typename T, int DIM>
+// A x at every node (BP false), then, on a walled x axis, again at the node
+// planes of the walls and of the inflow plane (BP true: a second launch over
+// those two planes, which overwrites what the first wrote there).  Keeping
+// the mirror-cell curl-curl out of the first launch, and that launch free of
+// an early exit, keeps it at 65 registers per thread (it had taken 386).
+template <typename T, int DIM, bool BP>
 __global__ __launch_bounds__(256) void k_apply_A(DGrid G, const double* __restrict__ x, const T* __restrict__ Mt,
-                                                 const double* __restrict__ kE, double k2, double mcoef,
+                                                 const double* __restrict__ kE, CurlCurl K, double k2, double mcoef,
                                                  double tdt, double* __restrict__ y) {
-  using HS = HalfStencil<DIM>;
   const int64_t t = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-  if (t >= G.N) return;
   const int64_t N = G.N;
   int gx, gy, gz;
-  const int64_t g = visit_order(G, (unsigned)t, gx, gy, gz);
+  int64_t g;
+  if (BP) {
+    const int64_t plane = (int64_t)G.n[1] * G.n[2];
+    if (t >= 2 * plane) return;
+    const int64_t r = t < plane ? t : t - plane;
+    gx = t < plane ? 0 : G.nxp;
+    gy = (int)(r % G.n[1]);
+    gz = (int)(r / G.n[1]);
+    g = flat3(G, gx, gy, gz);
+  } else {
+    if (t >= N) return;
+    g = visit_order(G, (unsigned)t, gx, gy, gz);
+  }
   double acc[3] = {x[g], x[N + g], x[2 * N + g]};
   const double x0[3] = {acc[0], acc[1], acc[2]};
-  const bool bplane = walled(G) && (gx == 0 || gx == G.nxp);
-  if (bplane) {
-    // a boundary node plane: curl_CN (curl_NC x) with the mirror cells
+  if (BP) {
+    // curl_CN (curl_NC x) with the mirror cells
     double cc[3];
     curlcurl_wall<DIM>(G, x, gx, gy, gz, cc);
-    for (int m = 0; m < 3; ++m) acc[m] += k2 * cc[m];
-  } else {
-    double cc[3];
-    curlcurl_node<DIM>(G, x, gx, gy, gz, cc);
 #pragma unroll
     for (int m = 0; m < 3; ++m) acc[m] += k2 * cc[m];
+  } else {
+    constexpr int RY = DIM >= 2 ? 1 : 0, RZ = DIM >= 3 ? 1 : 0;
+#pragma unroll
+    for (int oz = -RZ; oz <= RZ; ++oz)
+#pragma unroll
+      for (int oy = -RY; oy <= RY; ++oy)
+#pragma unroll
+        for (int ox = -1; ox <= 1; ++ox) {
+          const int oi = (ox + 1) + 3 * (oy + 1) + 9 * (oz + 1);
+          const int64_t h = flat3(G, gx + ox, gy + oy, gz + oz);
+          const double xv[3] = {x[h], x[N + h], x[2 * N + h]};
+#pragma unroll
+          for (int m = 0; m < 3; ++m)
+            acc[m] += k2 * (K.k[oi][3 * m] * xv[0] + K.k[oi][3 * m + 1] * xv[1] + K.k[oi][3 * m + 2] * xv[2]);
+        }
   }
   if (Mt) {
     double mx[3];
@@ -592,7 +567,7 @@ __global__ __launch_bounds__(256) void k_apply_A(DGrid G, const double* __restri
       }
     }
   }
-  if (bplane)
+  if (BP)
     for (int m = 0; m < 3; ++m)
       if (held(G, gx, m)) acc[m] = x0[m];  // held components: identity rows
 #pragma unroll
@@ -891,13 +866,46 @@ int ge_launch_grid_pass(ge_ctx* c) {
 // along a == b the second difference [1,-2,1]/dx^2; along a != b the centred
 // difference [-1,0,1]/(2 dx) on both axes a and b; the average [1,2,1]/4
 // along every other active axis.
+static CurlCurl curl_curl_stencil(const DGrid& G) {
+  CurlCurl K;
+  std::memset(&K, 0, sizeof(K));
+  const int dim = G.dim;
+  auto s1 = [&](int axis, int a, int b, int o) -> double {  // 1D factor of D_CN,a D_NC,b along axis
+    if (axis >= dim) return o == 0 ? 1.0 : 0.0;
+    const double ih = G.idx[axis];
+    if (axis == a && axis == b) return (o == 0 ? -2.0 : 1.0) * ih * ih;
+    if (axis == a || axis == b) return o == 0 ? 0.0 : 0.5 * o * ih;
+    return o == 0 ? 0.5 : 0.25;
+  };
+  auto prod = [&](int a, int b, int ox, int oy, int oz) {
+    return s1(0, a, b, ox) * s1(1, a, b, oy) * s1(2, a, b, oz);
+  };
+  for (int oz = -1; oz <= 1; ++oz)
+    for (int oy = -1; oy <= 1; ++oy)
+      for (int ox = -1; ox <= 1; ++ox) {
+        const int oi = (ox + 1) + 3 * (oy + 1) + 9 * (oz + 1);
+        for (int m = 0; m < 3; ++m)
+          for (int d = 0; d < dim; ++d) {
+            if (d == m) continue;
+            K.k[oi][3 * m + m] -= prod(d, d, ox, oy, oz);
+            if (m < dim) K.k[oi][3 * m + d] += prod(d, m, ox, oy, oz);
+          }
+      }
+  return K;
+}
+
 template <typename T, int DIM>
 static void apply_t(ge_ctx* c, const double* x, double* y) {
   const double ctd = c->P.c * c->P.theta * c->P.dt;
   const double mcoef = 4.0 * M_PI * c->P.theta * c->P.dt / c->G.dV;
-  hipLaunchKernelGGL((k_apply_A<T, DIM>), grid1(c->G.N), dim3(256), 0, c->stream, c->G, x,
-                     c->have_deposit ? (const T*)c->Mt : nullptr, c->P.lf_E ? c->kE : nullptr,
+  const T* Mt = c->have_deposit ? (const T*)c->Mt : nullptr;
+  const double* kE = c->P.lf_E ? c->kE : nullptr;
+  const CurlCurl K = curl_curl_stencil(c->G);
+  hipLaunchKernelGGL((k_apply_A<T, DIM, false>), grid1(c->G.N), dim3(256), 0, c->stream, c->G, x, Mt, kE, K,
                      ctd * ctd, mcoef, c->P.theta * c->P.dt, y);
+  if (walled(c->G))
+    hipLaunchKernelGGL((k_apply_A<T, DIM, true>), grid1(2 * (int64_t)c->G.n[1] * c->G.n[2]), dim3(256), 0, c->stream,
+                       c->G, x, Mt, kE, K, ctd * ctd, mcoef, c->P.theta * c->P.dt, y);
 }
 int ge_launch_apply_A(ge_ctx* c, const double* x, double* y) {
   switch (c->G.dim * 2 + (c->P.precision == GE_FP32 ? 1 : 0)) {
