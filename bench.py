@@ -163,6 +163,39 @@ def make_sim(wl, args, Simulation, torch, synth):
     return sim, counts
 
 
+def per_step_metrics(sim, wl, args, pc, synth, torch):
+    """Per-step record of an untimed continuation of the run (one JSON object
+    per line): each step is followed by a synchronising read of its phase
+    times, diagnostics and move report, so it is kept out of the timed steps."""
+    k0 = args.warmup + args.steps
+    sim.timings()
+    sim.moves()
+    with open(args.metrics_jsonl, "w") as f:
+        for k in range(args.metrics_steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = sim.step(tol=args.tol, maxit=500, restart=30, precond=pc)
+            if wl.walled and wl.bc[1] == 2:
+                for s in range(wl.nsp):
+                    p = {kk: torch.from_numpy(v).cuda() for kk, v in synth.inflow(wl, s, k0 + k, f32=wl.fp32).items()}
+                    sim.inject(s, p["cell"], p["off"], p["v"], p["w"])
+            sim.sync()
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            tm = sim.timings()
+            d = sim.diagnostics()
+            rec = {"step": k0 + k, "workload": wl.name, "wall_ms": round(wall * 1e3, 3),
+                   "phase_ms": {"push_rebin": tm[0] * 1e3, "deposit": tm[1] * 1e3, "assemble": tm[2] * 1e3,
+                                "grid_rest": tm[3] * 1e3, "update": tm[4] * 1e3, "solve": tm[5] * 1e3},
+                   "gmres": {"iterations": r["iterations"], "relres": r["relres"], "converged": r["converged"]},
+                   "W_E": d["W_E"], "W_B": d["W_B"], "K": d["K"], "P": d["P"], "gauss": d["gauss"],
+                   "particles": [sim.count(s) for s in range(wl.nsp)], "moves": sim.moves()}
+            f.write(json.dumps(rec) + "\n")
+            f.flush()
+            log(f"metrics step {k0 + k}: {r['iterations']} GMRES iterations, W_E {d['W_E']:.4e}, "
+                f"gauss {d['gauss']:.3e}")
+
+
 def cnn_flops_per_node():
     """FLOPs of one application of the 3 -> 32 -> 32 -> 3 network of 3x3x3
     convolutions per grid node (2 per multiply-add)."""
@@ -276,6 +309,11 @@ def main():
     ap.add_argument("--explicit-steps", type=int, default=0, metavar="K",
                     help="also time K explicit PIC steps (ge_explicit_step) on the same workload with dt = 0.25, "
                          "which keeps c dt below dx / sqrt(3)")
+    ap.add_argument("--metrics-jsonl", default="", metavar="PATH",
+                    help="after the timed steps, run --metrics-steps more steps (untimed) and write one JSON line "
+                         "per step to PATH: phase times, GMRES iterations and residual, FP64 energies, momenta, "
+                         "Gauss residual, moves")
+    ap.add_argument("--metrics-steps", type=int, default=10)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain device copy of 4 GiB (reference for the HBM byte counters) and exit")
     args = ap.parse_args()
@@ -358,6 +396,8 @@ def main():
             "algorithmic_bytes_per_unit": {"particle": ab["per_particle"], "node": ab["per_node_deposit"]}}
     if roof["traffic"]:
         roof["traffic_over_algorithmic"] = round(roof["traffic"] / ab["deposit"], 3)
+    if args.metrics_jsonl:
+        per_step_metrics(sim, wl, args, pc, synth, torch)
     precond_cmp = None
     if args.compare_precond:
         pcs = {}

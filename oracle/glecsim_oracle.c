@@ -9,10 +9,11 @@
  * library.
  *
  * Mesh (Sec. 2.1): E on nodes, B at cell centres.  Node (i,j,k) sits at
- * (i dx, j dy, k dz); cell (i,j,k) has its centre at ((i+1/2) dx, ...).  All
- * active axes are periodic.  Fields are stored component-major, [3][N], with
- * linear index i + nx*(j + ny*k); with periodic axes there are as many nodes
- * as cells.
+ * (i dx, j dy, k dz); cell (i,j,k) has its centre at ((i+1/2) dx, ...).  The
+ * active axes are periodic, except an x axis closed by walls (see "Walled x
+ * axis" below).  Fields are stored component-major, [3][N], with linear index
+ * i + nx*(j + ny*k); nodes and cells share the index space (as many nodes as
+ * cells; a walled x axis stores one more point).
  *
  * Each function names the passage of the paper it follows.  Readings of
  * passages that are silent or garbled are marked READING.

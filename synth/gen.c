@@ -14,8 +14,8 @@
  * particles can be regenerated alone, in any order and on any thread.
  * Normal deviates: the Box-Muller transform; the thermal velocity vector is
  * truncated at |n| <= RCLIP (its length, so that gyration cannot rotate a
- * clipped tail into a faster component) so that no particle starts faster
- * than the time step allows.
+ * clipped tail into a faster component), which keeps every electron of the
+ * workloads well below the speed of light of this non-relativistic mover.
  */
 #include <math.h>
 #include <stdint.h>

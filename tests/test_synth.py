@@ -1,5 +1,6 @@
 """The seeded input generator: Philox4x32-10 known answers and the loading
 recipe's invariants (it holds no arithmetic of the PIC method)."""
+import os
 import numpy as np
 import pytest
 
@@ -88,3 +89,14 @@ def test_inflow_injection_flux():
     ncol = 4 * 3
     assert tot == ncol * int(np.floor(K * r))
     assert abs(tot / (K * ncol) - r) < 1.0 / K
+
+
+def test_committed_configs_match_the_workloads():
+    """configs/<name>.json (written by synth/write_configs.py) records exactly
+    what synth.workloads() defines, for every workload."""
+    from synth.write_configs import OUT, render
+    names = sorted(synth.workloads())
+    assert sorted(f[:-5] for f in os.listdir(OUT) if f.endswith(".json")) == names
+    for name, wl in synth.workloads().items():
+        with open(os.path.join(OUT, f"{name}.json")) as f:
+            assert f.read() == render(wl), name
