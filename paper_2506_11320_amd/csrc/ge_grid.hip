@@ -215,6 +215,26 @@ __device__ inline void apply_half(const DGrid& G, const T* __restrict__ M, const
   }
 }
 
+// Row 0 (the x component) of apply_half alone, summed in the same order.
+template <typename T, int DIM>
+__device__ inline double half_row0(const DGrid& G, const T* __restrict__ M, const double* __restrict__ x, int64_t g,
+                                   int gx, int gy, int gz) {
+  using HS = HalfStencil<DIM>;
+  const int64_t N = G.N;
+  double y0 = 0.0;
+#pragma unroll
+  for (int h = 0; h < HS::NH; ++h) {
+    const int64_t gp = flat3(G, gx + HS::o[h][0], gy + HS::o[h][1], gz + HS::o[h][2]);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) y0 += (double)M[(int64_t)(h * 9 + j) * N + g] * x[j * N + gp];
+    if (h == 0) continue;
+    const int64_t gm = flat3(G, gx - HS::o[h][0], gy - HS::o[h][1], gz - HS::o[h][2]);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) y0 += (double)M[(int64_t)(h * 9 + j) * N + gm] * x[j * N + gm];
+  }
+  return y0;
+}
+
 // J_eff = J_lab - (1/dV)(M0 u + Mtilde E_M)  (Sec. 3.1, comoving frame).
 // PART 0: both terms, Jout = Jin - (1/dV)(M0 u + Mtilde E_M); PART 1: the
 // comoving-frame current J_C = Jin - (1/dV) M0 u; PART 2: the E_M term alone,
@@ -528,11 +548,31 @@ __global__ __launch_bounds__(256) void k_apply_A(DGrid G, const double* __restri
   double acc[3] = {x[g], x[N + g], x[2 * N + g]};
   const double x0[3] = {acc[0], acc[1], acc[2]};
   if (BP) {
-    // curl_CN (curl_NC x) with the mirror cells
+    // held components are identity rows: all three on the inflow plane, the
+    // tangential ones on a wall, whose normal (x) row is computed here with
+    // the mirror cells (the plane's nodes lie n_x apart in memory, so every
+    // load of this launch touches its own cache line: load only that row)
+#pragma unroll
+    for (int m = 1; m < 3; ++m) y[m * N + g] = x0[m];
+    if (held(G, gx, 0)) {
+      y[g] = x0[0];
+      return;
+    }
     double cc[3];
     curlcurl_wall<DIM>(G, x, gx, gy, gz, cc);
+    double a0 = x0[0] + k2 * cc[0];
+    if (Mt) a0 += mcoef * half_row0<T, DIM>(G, Mt, x, g, gx, gy, gz);
+    if (kE) {
 #pragma unroll
-    for (int m = 0; m < 3; ++m) acc[m] += k2 * cc[m];
+      for (int d = 0; d < DIM; ++d) {
+        const int64_t gp = flat3(G, gx + (d == 0), gy + (d == 1), gz + (d == 2));
+        const int64_t gm = flat3(G, gx - (d == 0), gy - (d == 1), gz - (d == 2));
+        const double kp = kE[(d * 3) * N + g], km = kE[(d * 3) * N + gm];
+        a0 -= tdt * G.idx[d] * (kp * (x[gp] - x0[0]) - km * (x0[0] - x[gm]));
+      }
+    }
+    y[g] = a0;
+    return;
   } else {
     constexpr int RY = DIM >= 2 ? 1 : 0, RZ = DIM >= 3 ? 1 : 0;
 #pragma unroll
@@ -567,9 +607,6 @@ __global__ __launch_bounds__(256) void k_apply_A(DGrid G, const double* __restri
       }
     }
   }
-  if (BP)
-    for (int m = 0; m < 3; ++m)
-      if (held(G, gx, m)) acc[m] = x0[m];  // held components: identity rows
 #pragma unroll
   for (int m = 0; m < 3; ++m) y[m * N + g] = acc[m];
 }

@@ -1201,32 +1201,54 @@ __global__ void k_inj_check(DGrid G, int64_t m, const int32_t* __restrict__ cell
   if (!ok) atomicOr(&flags[GE_FL_LOAD], 1);
 }
 
-// Stable bucketing of the far list by destination, by one wavefront walking
-// the list in order (chunks of 64): lanes with equal destinations rank among
-// themselves by lane, and the first of them takes the group's slots from the
-// destination's fill counter.  Only this wavefront touches the counters, in
-// program order, so the result is deterministic.  nbits: bits of a cell index.
-__global__ __launch_bounds__(64) void k_far_bucket(int64_t F, int nbits, const int32_t* __restrict__ ldest,
-                                                   const int32_t* __restrict__ lpos,
-                                                   const int32_t* __restrict__ start_in, int32_t* __restrict__ fill,
-                                                   int32_t* __restrict__ sorted) {
-  const int lane = threadIdx.x;
-  const uint64_t lt = lanemask_lt(lane);
-  for (int64_t j0 = 0; j0 < F; j0 += 64) {
-    const int64_t j = j0 + lane;
-    const bool act = j < F;
-    const int d = act ? ldest[j] : -1;
-    uint64_t peers = __ballot(act);
-    for (int b = 0; b < nbits; ++b) {
-      const uint64_t m = __ballot(act && ((d >> b) & 1));
-      peers &= ((d >> b) & 1) ? m : ~m;
-    }
-    int base = 0;
-    const int leader = act ? __ffsll((unsigned long long)peers) - 1 : 0;
-    if (act && leader == lane) base = atomicAdd(&fill[d], __popcll(peers));
-    base = __shfl(base, leader, 64);
-    if (act) sorted[start_in[d] + base + __popcll(peers & lt)] = lpos[j];
+// Bucket of every list entry (far movers in home-cell order, then the
+// injected particles in their order): its list index j into the entries of
+// its destination, in any slot order (integer atomics).
+__global__ void k_far_scatter(int64_t F, const int32_t* __restrict__ ldest, const int32_t* __restrict__ start_in,
+                              int32_t* __restrict__ fill, int32_t* __restrict__ sorted) {
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j >= F) return;
+  const int32_t d = ldest[j];
+  const int32_t k = atomicAdd(&fill[d], 1);
+  sorted[start_in[d] + k] = (int32_t)j;
+}
+
+// One thread per destination: its entries put back in list order (the list
+// order is the stable order), then replaced by the particles' buffer
+// positions.  Insertion sort for the few entries a cell gets in practice,
+// heap sort (O(n log n)) for large buckets.
+__device__ inline void sift_down(int32_t* a, int i, int n) {
+  for (;;) {
+    int m = i, l = 2 * i + 1, r = l + 1;
+    if (l < n && a[l] > a[m]) m = l;
+    if (r < n && a[r] > a[m]) m = r;
+    if (m == i) return;
+    const int32_t t = a[i]; a[i] = a[m]; a[m] = t;
+    i = m;
   }
+}
+__global__ void k_far_order(int64_t N, const int32_t* __restrict__ cnt_in, const int32_t* __restrict__ start_in,
+                            const int32_t* __restrict__ lpos, int32_t* __restrict__ sorted) {
+  const int64_t d = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (d >= N) return;
+  const int n = cnt_in[d];
+  if (n == 0) return;
+  int32_t* b = sorted + start_in[d];
+  if (n <= 32) {
+    for (int i = 1; i < n; ++i) {
+      const int32_t v = b[i];
+      int k = i - 1;
+      while (k >= 0 && b[k] > v) { b[k + 1] = b[k]; --k; }
+      b[k + 1] = v;
+    }
+  } else {
+    for (int i = n / 2 - 1; i >= 0; --i) sift_down(b, i, n);
+    for (int e = n - 1; e > 0; --e) {
+      const int32_t t = b[0]; b[0] = b[e]; b[e] = t;
+      sift_down(b, 0, e);
+    }
+  }
+  for (int i = 0; i < n; ++i) b[i] = lpos[b[i]];
 }
 
 // Particles of cell c after the re-sort: its direction runs plus its far
@@ -1390,19 +1412,22 @@ void ge_far_free(ge_ctx* c) {
 }
 
 template <typename T, int DIM>
-static void far_kernels_t(ge_ctx* c, SpeciesBuf& S, int64_t F) {
+static void far_kernels_t(ge_ctx* c, SpeciesBuf& S, int64_t F, int64_t nfar) {
   FarScratch& X = c->fx;
   const int64_t N = c->G.N;
   const int cur = S.cur;
   // (the far runs of a species that has not been pushed since its last
-  // re-sort are zero: the re-sort clears them)
-  hipLaunchKernelGGL((k_far_list<T, DIM>), dim3((unsigned)N), dim3(64), 0, c->stream, c->G, (T*)S.rec[cur], S.far,
-                     X.pos_h, X.dest, X.pos, X.cnt_in);
+  // re-sort are zero: the re-sort clears them; with no far mover at all, as
+  // when only injected particles join, there is nothing to list)
+  if (nfar > 0)
+    hipLaunchKernelGGL((k_far_list<T, DIM>), dim3((unsigned)N), dim3(64), 0, c->stream, c->G, (T*)S.rec[cur], S.far,
+                       X.pos_h, X.dest, X.pos, X.cnt_in);
   scan_into(c, X.cnt_in, X.start_in);
-  int nbits = 1;
-  while (((int64_t)1 << nbits) < N) ++nbits;
-  hipLaunchKernelGGL(k_far_bucket, dim3(1), dim3(64), 0, c->stream, F, nbits, X.dest, X.pos, X.start_in, X.fill,
-                     X.sorted);
+  if (F > 0)
+    hipLaunchKernelGGL(k_far_scatter, dim3((unsigned)((F + 255) / 256)), dim3(256), 0, c->stream, F, X.dest,
+                       X.start_in, X.fill, X.sorted);
+  hipLaunchKernelGGL(k_far_order, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, c->stream, N, X.cnt_in, X.start_in,
+                     X.pos, X.sorted);
   hipLaunchKernelGGL((k_far_newcount<DIM>), dim3((N + 255) / 256), dim3(256), 0, c->stream, c->G, S.runs[cur],
                      X.cnt_in, X.newstart);
   scan_into(c, X.newstart, X.newstart);
@@ -1447,19 +1472,21 @@ int ge_launch_far_resort(ge_ctx* c, int s, int64_t nfar) {
   }
   GE_HIP(c, hipMemsetAsync(X.cnt_in, 0, sizeof(int32_t) * N, c->stream));
   GE_HIP(c, hipMemsetAsync(X.fill, 0, sizeof(int32_t) * N, c->stream));
-  hipLaunchKernelGGL(k_far_counts, dim3((N + 255) / 256), dim3(256), 0, c->stream, N, S.far, X.pos_h);
-  scan_into(c, X.pos_h, X.pos_h);
+  if (nfar > 0) {  // each home cell's first entry in the far list
+    hipLaunchKernelGGL(k_far_counts, dim3((N + 255) / 256), dim3(256), 0, c->stream, N, S.far, X.pos_h);
+    scan_into(c, X.pos_h, X.pos_h);
+  }
   if (S.inj_n > 0)
     hipLaunchKernelGGL(k_inj_list, dim3((S.inj_n + 255) / 256), dim3(256), 0, c->stream, S.inj_n, S.inj_cell, S.nbuf,
                        nfar, X.dest, X.pos, X.cnt_in);
   const bool f32 = c->P.precision == GE_FP32;
   switch (c->G.dim * 2 + (f32 ? 1 : 0)) {
-    case 2: far_kernels_t<double, 1>(c, S, F); break;
-    case 3: far_kernels_t<float, 1>(c, S, F); break;
-    case 4: far_kernels_t<double, 2>(c, S, F); break;
-    case 5: far_kernels_t<float, 2>(c, S, F); break;
-    case 6: far_kernels_t<double, 3>(c, S, F); break;
-    default: far_kernels_t<float, 3>(c, S, F); break;
+    case 2: far_kernels_t<double, 1>(c, S, F, nfar); break;
+    case 3: far_kernels_t<float, 1>(c, S, F, nfar); break;
+    case 4: far_kernels_t<double, 2>(c, S, F, nfar); break;
+    case 5: far_kernels_t<float, 2>(c, S, F, nfar); break;
+    case 6: far_kernels_t<double, 3>(c, S, F, nfar); break;
+    default: far_kernels_t<float, 3>(c, S, F, nfar); break;
   }
   GE_HIP(c, hipGetLastError());
   // the far runs are consumed: a later re-sort without a push (injection
