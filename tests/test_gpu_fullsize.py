@@ -1,7 +1,8 @@
 """Parity at the full size of the 3D reconnection workload (256x128x128 cells,
 64 particles per cell per species, FP32 particle path), in the launch
-configuration the benchmark times, and of the 3D colliding-flow shock
-(128x64x64 cells, 27 particles per cell) for the grid quantities.
+configuration the benchmark times, and of the 3D shock (128x64x64 cells, 27
+particles per cell; against a wall with an inflow plane, and its periodic
+colliding-flow variant) for the grid quantities.
 
 The FP64 oracle cannot run the whole grid in seconds, so it checks sampled
 outputs it can compute on its own:
@@ -48,7 +49,7 @@ def _sim(wl, id_weights=False, keep=None):
     from paper_2506_11320_amd import Simulation
     sim = Simulation(wl.dim, wl.n, wl.dx, theta=wl.theta, dt=wl.dt, lf_E=wl.lf_E, lf_B=wl.lf_B,
                      beta_lim=wl.beta_lim, a_mode=wl.a_mode, comoving=wl.comoving, n_smooth_u=wl.n_smooth_u,
-                     fp32=wl.fp32)
+                     fp32=wl.fp32, bc=wl.bc)
     kept = {}
     for s in range(wl.nsp):
         p = synth.particles(wl, s, f32=wl.fp32)
@@ -236,4 +237,119 @@ def test_c5_push_and_rebinning_at_full_size():
         ev = np.abs(gv.T - vo).max() / np.abs(vo).max()
         print(f"  species {s}: position err {ex:.1e} cells, velocity err {ev:.1e}", flush=True)
         assert ex < 2e-6 and ev < 1e-5
+    sim.close()
+
+
+# walled shock: a node on the wall plane, one near the wall, one in the interior
+NODES_C4W = [(0, 40, 9), (3, 5, 60), (64, 32, 32)]
+PX = 24  # x extent of the walled patch (walls at both of its ends)
+
+
+def _patch_walled(wl, E, B, node):
+    """Oracle state of a patch of the walled grid around node: y and z as in
+    _patch (periodic, PATCH wide, centred); along x either cells [0, PX) with
+    walls at both ends (nodes within 12 of the wall: the patch's far wall is
+    beyond the 9-node reach of every quantity at the node), or a periodic
+    PATCH-wide window centred on the node (interior nodes, whose reach never
+    meets a wall)."""
+    nxs, ny, nz = wl.nstore
+    near = node[0] <= 12
+    a = np.arange(PATCH)
+    fy, fz = [(node[d] - C + a) % wl.n[d] for d in (1, 2)]
+    if near:
+        xs = np.arange(PX + 1)  # storage x of the patch: nodes 0..PX, cells 0..PX-1, ghost PX
+        Gp = O.grid(3, (PX, PATCH, PATCH), wl.dx, bc=(O.BC_WALL, O.BC_WALL))
+        cidx = node[0] + (PX + 1) * (C + PATCH * C)
+        pwl = wl.replace(n=(PX, PATCH, PATCH), bc=(O.BC_WALL, O.BC_WALL))
+        cell_x = np.arange(PX)
+    else:
+        xs = (node[0] - C + a)
+        Gp = O.grid(3, (PATCH, PATCH, PATCH), wl.dx)
+        cidx = C + PATCH * (C + PATCH * C)
+        pwl = wl.replace(n=(PATCH, PATCH, PATCH), bc=(0, 0))
+        cell_x = xs
+    nxp = xs.size
+    full = (xs[None, None, :] + nxs * (fy[None, :, None] + ny * fz[:, None, None])).ravel()
+    Ep, Bp = E[:, full], B[:, full]
+    sp = []
+    for s in range(wl.nsp):
+        cells, offs, vs, ws = [], [], [], []
+        for kz in range(PATCH):
+            for ky in range(PATCH):
+                row = nxs * (fy[ky] + ny * fz[kz])
+                p = synth.particles(wl, s, row + int(cell_x[0]), row + int(cell_x[-1]) + 1, f32=wl.fp32)
+                px = p["cell"] - row - int(cell_x[0])
+                cells.append(px + nxp * (ky + PATCH * kz))
+                offs.append(p["off"])
+                vs.append(p["v"])
+                ws.append(p["w"])
+        cell = np.concatenate(cells)
+        x = O.global_positions(Gp, cell, np.concatenate(offs, axis=1).astype(np.float64))
+        sp.append(O.Species(wl.q[s], wl.m[s], x, np.concatenate(vs, axis=1).astype(np.float64).T,
+                            np.concatenate(ws).astype(np.float64)))
+    ref = H.oracle_grid_pass(pwl, Gp, sp, Ep, Bp)
+    ref["J_scale_node"] = sum(np.linalg.norm(j[:, cidx]) for j in ref["J_s"])
+    ref["cidx"], ref["G"], ref["full"] = cidx, Gp, full
+    return ref
+
+
+def test_walled_shock_grid_quantities_and_operator_at_full_size():
+    wl = _workload("c4")
+    assert wl.walled
+    print("[gpu] full-size walled c4 deposit/operator/solve", flush=True)
+    E, B = synth.fields(wl)
+    sim, _ = _sim(wl)
+    sim.set_fields(torch.from_numpy(E).cuda(), torch.from_numpy(B).cuda())
+    sim.deposit()
+    nxs, ny, nz = wl.nstore
+    gidx = torch.tensor([n[0] + nxs * (n[1] + ny * n[2]) for n in NODES_C4W], device="cuda")
+    got = {}
+    for k in ["J_lab", "J_eff", "rho", "mm", "mass", "u", "EM", "Mt", "M0", "kappa_E", "rhs"]:
+        g = sim.gather(k)
+        got[k] = g.index_select(g.dim() - 1, gidx).cpu().numpy()
+        del g
+    # a smooth probe field on the storage grid for the operator
+    i = np.arange(nxs)[None, None, :]
+    j = np.arange(ny)[None, :, None]
+    k = np.arange(nz)[:, None, None]
+    ph = 2 * math.pi * (3 * i / nxs + 2 * j / ny + k / nz)
+    xprobe = E.copy()
+    xprobe[0] += 0.01 * np.sin(ph).ravel()
+    xprobe[1] += 0.02 * np.cos(ph + 0.3).ravel()
+    xprobe[2] += 0.015 * np.sin(2 * ph + 1.0).ravel()
+    Ax = sim.apply_operator(torch.from_numpy(xprobe).cuda())
+    got["Ax"] = Ax.index_select(1, gidx).cpu().numpy()
+    del Ax
+    torch.cuda.synchronize()
+    for q, node in enumerate(NODES_C4W):
+        print(f"  node {node}: oracle patch", flush=True)
+        ref = _patch_walled(wl, E, B, node)
+        c = ref["cidx"]
+        un = np.linalg.norm(ref["u"][:, c])
+        errs = {
+            "J_lab": _rel(got["J_lab"][:, q], ref["J_lab"][:, c], ref["J_scale_node"]),
+            "Mt": _rel(got["Mt"][:, :, q], H.half_from_full(ref["Mt"], 3)[:, :, c]),
+            "M0": _rel(got["M0"][:, :, q], H.half_from_full(ref["M0"], 3)[:, :, c]),
+            "mass": _rel(got["mass"][q], ref["mass"][c]),
+            "mm": _rel(got["mm"][:, q], ref["mm"][:, c]),
+            "u": _rel(got["u"][:, q], ref["u"][:, c]),
+            "EM": _rel(got["EM"][:, q], ref["EM"][:, c], un * np.linalg.norm(ref["Bn"][:, c])),
+            "J_eff": _rel(got["J_eff"][:, q], ref["J_eff"][:, c], ref["J_scale_node"]),
+            "kappa_E": _rel(got["kappa_E"][:, :, q], ref["kE"][:, :, c], 0.5 * un),
+            "rhs": _rel(got["rhs"][:, q], ref["rhs"][:, c]),
+        }
+        for s in range(wl.nsp):
+            errs[f"rho{s}"] = _rel(got["rho"][s, q], ref["rho_s"][s][c])
+        Ax_ref = O.apply_A(ref["G"], ref["P"], ref["Mt"], ref["kE"], xprobe[:, ref["full"]])
+        errs["Ax"] = _rel(got["Ax"][:, q], Ax_ref[:, c])
+        print("   " + ", ".join(f"{k} {v:.1e}" for k, v in errs.items()), flush=True)
+        for k, v in errs.items():
+            assert v < 1e-5, (node, k, v)
+    rep = sim.solve(tol=1e-8, maxit=500, restart=30)
+    assert rep["converged"] and rep["relres"] <= 1e-8
+    b = sim.gather("rhs")
+    r = b - sim.apply_operator(sim.gather("Eth"))
+    rel = (torch.linalg.vector_norm(r) / torch.linalg.vector_norm(b)).item()
+    print(f"  solve: {rep['iterations']} iterations, true relres {rel:.2e}", flush=True)
+    assert rel <= 1.01e-8
     sim.close()
