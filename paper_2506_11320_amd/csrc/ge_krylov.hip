@@ -146,6 +146,11 @@ __global__ void k_normalize(double* __restrict__ v, const double* __restrict__ w
   const double inv = 1.0 / sqrt(*nrm2);
   for (int64_t k = blockIdx.x * (int64_t)KB + threadIdx.x; k < n; k += (int64_t)gridDim.x * KB) v[k] = w[k] * inv;
 }
+// v = v / sqrt(*nrm2), in place
+__global__ void k_normalize_inplace(double* __restrict__ v, const double* __restrict__ nrm2, int64_t n) {
+  const double inv = 1.0 / sqrt(*nrm2);
+  for (int64_t k = blockIdx.x * (int64_t)KB + threadIdx.x; k < n; k += (int64_t)gridDim.x * KB) v[k] = v[k] * inv;
+}
 // r = b - r
 __global__ void k_residual(double* __restrict__ r, const double* __restrict__ b, int64_t n) {
   for (int64_t k = blockIdx.x * (int64_t)KB + threadIdx.x; k < n; k += (int64_t)gridDim.x * KB) r[k] = b[k] - r[k];
@@ -267,7 +272,7 @@ int ge_gmres(ge_ctx* c, double tol, int maxit, int m, int precond, ge_solve_repo
       precond = GE_PC_NONE;
       fallback = 1;
     }
-    hipLaunchKernelGGL(k_normalize, vgrid(n), dim3(KB), 0, c->stream, V, V, hd + 128, n);
+    hipLaunchKernelGGL(k_normalize_inplace, vgrid(n), dim3(KB), 0, c->stream, V, hd + 128, n);
     std::fill(s.begin(), s.end(), 0.0);
     s[0] = beta;
     int k = 0;
