@@ -430,7 +430,10 @@ __global__ __launch_bounds__(64) void k_push(DGrid G, PushArgs<T> A) {
     int d0 = 31, d1 = 31;
     if (a0) d0 = push_one<T, DIM>(f0, v0, fc, A.beta, A.dtx, A.lo, A.hi, stuck, mv, G, hx);
     if (a1) d1 = push_one<T, DIM>(f1, v1, fc, A.beta, A.dtx, A.lo, A.hi, stuck, mv, G, hx);
-    const DirStats q0 = dir_stats(a0, d0, lane), q1 = dir_stats(a1, d1, lane);
+    const DirStats q0 = dir_stats(a0, d0, lane);
+    // the second slot is empty in every lane of a cell of at most 64
+    // particles (a wave-uniform test): its statistics are zero then
+    const DirStats q1 = total > 64 ? dir_stats(a1, d1, lane) : DirStats{0, 0};
     cnt = q0.count_k + q1.count_k;
     dir_off = excl_scan(cnt);
     const int b0 = __shfl(dir_off, d0 & 31, 64);
