@@ -181,3 +181,46 @@ def test_whole_domain_move_and_nonfinite_velocity_are_refused():
         sim.step(tol=1e-10, maxit=500, restart=30)
     assert ei.value.code == -4
     sim.close()
+
+
+def test_injection_order_in_crowded_cells():
+    """Injected particles join their cells after the particles already there,
+    in the given order, also when one cell receives more than 32 of them
+    (the re-sort orders a destination's entries by heap sort beyond 32)."""
+    print("[gpu] re-sort: crowded injection", flush=True)
+    wl = _wl(3, (6, 5, 4), 10, "c5", False)
+    parts = H.species_arrays(wl, False)
+    for p in parts:
+        p["w"] = (np.arange(p["w"].size) + 1).astype(np.float64)
+    E, B = H.perturbed_fields(wl)
+    sim = H.make_sim(wl, parts, E, B)
+    rng = np.random.default_rng(3)
+    # 100 particles for cell 37, 7 for cell 5, interleaved in a shuffled order
+    cells = np.array([37] * 100 + [5] * 7, np.int32)
+    rng.shuffle(cells)
+    m = cells.size
+    off = rng.random((3, m))
+    v = 0.01 * rng.standard_normal((3, m))
+    w = 1e6 + np.arange(m, dtype=np.float64)  # injection index rides in the weight
+    t = {k: torch.from_numpy(np.ascontiguousarray(a)).cuda() for k, a in
+         {"cell": cells, "off": off, "v": v, "w": w}.items()}
+    sim.inject(0, t["cell"], t["off"], t["v"], t["w"])
+    sim.sync()
+    got = {k: a.cpu().numpy() for k, a in sim.particles(0).items()}
+    n0 = parts[0]["w"].size
+    assert got["cell"].size == n0 + m
+    assert np.all(np.diff(got["cell"]) >= 0)
+    for c in (5, 37):
+        ws = got["w"][got["cell"] == c]
+        old = ws[ws < 1e6]
+        new = ws[ws >= 1e6] - 1e6
+        assert ws.size == (parts[0]["cell"] == c).sum() + (cells == c).sum()
+        # the cell's own particles first, in their order, then the injected ones in the given order
+        assert np.array_equal(ws[:old.size], old) and np.all(np.diff(old) > 0)
+        assert np.array_equal(new.astype(np.int64), np.nonzero(cells == c)[0])
+        sel = np.nonzero(cells == c)[0]
+        assert np.array_equal(got["off"][:, got["cell"] == c][:, old.size:], off[:, sel])
+    # the other cells are untouched
+    keep = (got["cell"] != 5) & (got["cell"] != 37)
+    assert np.array_equal(got["w"][keep], parts[0]["w"][(parts[0]["cell"] != 5) & (parts[0]["cell"] != 37)])
+    sim.close()
