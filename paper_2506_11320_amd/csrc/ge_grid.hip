@@ -215,26 +215,6 @@ __device__ inline void apply_half(const DGrid& G, const T* __restrict__ M, const
   }
 }
 
-// Row 0 (the x component) of apply_half alone, summed in the same order.
-template <typename T, int DIM>
-__device__ inline double half_row0(const DGrid& G, const T* __restrict__ M, const double* __restrict__ x, int64_t g,
-                                   int gx, int gy, int gz) {
-  using HS = HalfStencil<DIM>;
-  const int64_t N = G.N;
-  double y0 = 0.0;
-#pragma unroll
-  for (int h = 0; h < HS::NH; ++h) {
-    const int64_t gp = flat3(G, gx + HS::o[h][0], gy + HS::o[h][1], gz + HS::o[h][2]);
-#pragma unroll
-    for (int j = 0; j < 3; ++j) y0 += (double)M[(int64_t)(h * 9 + j) * N + g] * x[j * N + gp];
-    if (h == 0) continue;
-    const int64_t gm = flat3(G, gx - HS::o[h][0], gy - HS::o[h][1], gz - HS::o[h][2]);
-#pragma unroll
-    for (int j = 0; j < 3; ++j) y0 += (double)M[(int64_t)(h * 9 + j) * N + gm] * x[j * N + gm];
-  }
-  return y0;
-}
-
 // J_eff = J_lab - (1/dV)(M0 u + Mtilde E_M)  (Sec. 3.1, comoving frame).
 // PART 0: both terms, Jout = Jin - (1/dV)(M0 u + Mtilde E_M); PART 1: the
 // comoving-frame current J_C = Jin - (1/dV) M0 u; PART 2: the E_M term alone,
@@ -480,35 +460,6 @@ __device__ inline void curl_nc_cell(const DGrid& G, const double* __restrict__ E
   C[2] = D[0][1] - D[1][0];
 }
 
-// curl_CN (curl_NC x) at a node of a boundary plane of a walled grid: the
-// cells beyond a wall are the mirror images of curl_NC x (a pseudo-vector:
-// x component odd); the ghost cell of an inflow plane carries zero
-template <int DIM>
-__device__ inline void curlcurl_wall(const DGrid& G, const double* __restrict__ x, int gx, int gy, int gz,
-                                     double out[3]) {
-  constexpr int NC = Gd<DIM>::NC;
-  double up[3][3] = {{0}}, lo[3][3] = {{0}};
-  for (int a = 0; a < NC; ++a) {
-    const int ci = gx - ax_bit(a, 0), cj = gy - (DIM >= 2 ? ax_bit(a, 1) : 0), ck = gz - (DIM >= 3 ? ax_bit(a, 2) : 0);
-    double sg;
-    const int cm = cell_mirror(G, ci, sg, true);
-    double C[3] = {0, 0, 0};
-    if (cm < G.nxp) {
-      curl_nc_cell<DIM>(G, x, cm, cj, ck, C);
-      C[0] *= sg;
-    }
-    for (int d = 0; d < DIM; ++d)
-      for (int q = 0; q < 3; ++q) (ax_bit(a, d) ? lo : up)[d][q] += C[q];
-  }
-  double D[3][3] = {{0}};
-  const double inv = 2.0 / NC;
-  for (int d = 0; d < DIM; ++d)
-    for (int q = 0; q < 3; ++q) D[d][q] = (up[d][q] - lo[d][q]) * inv * G.idx[d];
-  out[0] = D[1][2] - D[2][1];
-  out[1] = D[2][0] - D[0][2];
-  out[2] = D[0][1] - D[1][0];
-}
-
 // A x = x + (c theta dt)^2 curl_CN curl_NC x + (4 pi theta dt / dV) Mtilde x
 //       - theta dt D_E x, in one pass over the 3^DIM neighbours of each node.
 // curl_CN curl_NC is a constant 3^DIM-point stencil (a sum of tensor products
@@ -520,60 +471,22 @@ struct CurlCurl {
   double k[27][9];
 };
 
-// A x at every node (BP false), then, on a walled x axis, again at the node
-// planes of the walls and of the inflow plane (BP true: a second launch over
-// those two planes, which overwrites what the first wrote there).  Keeping
-// the mirror-cell curl-curl out of the first launch, and that launch free of
-// an early exit, keeps it at 65 registers per thread (it had taken 386).
-template <typename T, int DIM, bool BP>
+// A x at every node; on a walled x axis k_apply_A_planes then rewrites the
+// rows of the two boundary node planes, where this kernel's periodic stencil
+// does not apply.  Keeping the mirror-cell curl-curl out of this kernel, and
+// this kernel free of an early exit, keeps it at 65 registers per thread.
+template <typename T, int DIM>
 __global__ __launch_bounds__(256) void k_apply_A(DGrid G, const double* __restrict__ x, const T* __restrict__ Mt,
                                                  const double* __restrict__ kE, CurlCurl K, double k2, double mcoef,
                                                  double tdt, double* __restrict__ y) {
   const int64_t t = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   const int64_t N = G.N;
+  if (t >= N) return;
   int gx, gy, gz;
-  int64_t g;
-  if (BP) {
-    const int64_t plane = (int64_t)G.n[1] * G.n[2];
-    if (t >= 2 * plane) return;
-    const int64_t r = t < plane ? t : t - plane;
-    gx = t < plane ? 0 : G.nxp;
-    gy = (int)(r % G.n[1]);
-    gz = (int)(r / G.n[1]);
-    g = flat3(G, gx, gy, gz);
-  } else {
-    if (t >= N) return;
-    g = visit_order(G, (unsigned)t, gx, gy, gz);
-  }
+  const int64_t g = visit_order(G, (unsigned)t, gx, gy, gz);
   double acc[3] = {x[g], x[N + g], x[2 * N + g]};
   const double x0[3] = {acc[0], acc[1], acc[2]};
-  if (BP) {
-    // held components are identity rows: all three on the inflow plane, the
-    // tangential ones on a wall, whose normal (x) row is computed here with
-    // the mirror cells (the plane's nodes lie n_x apart in memory, so every
-    // load of this launch touches its own cache line: load only that row)
-#pragma unroll
-    for (int m = 1; m < 3; ++m) y[m * N + g] = x0[m];
-    if (held(G, gx, 0)) {
-      y[g] = x0[0];
-      return;
-    }
-    double cc[3];
-    curlcurl_wall<DIM>(G, x, gx, gy, gz, cc);
-    double a0 = x0[0] + k2 * cc[0];
-    if (Mt) a0 += mcoef * half_row0<T, DIM>(G, Mt, x, g, gx, gy, gz);
-    if (kE) {
-#pragma unroll
-      for (int d = 0; d < DIM; ++d) {
-        const int64_t gp = flat3(G, gx + (d == 0), gy + (d == 1), gz + (d == 2));
-        const int64_t gm = flat3(G, gx - (d == 0), gy - (d == 1), gz - (d == 2));
-        const double kp = kE[(d * 3) * N + g], km = kE[(d * 3) * N + gm];
-        a0 -= tdt * G.idx[d] * (kp * (x[gp] - x0[0]) - km * (x0[0] - x[gm]));
-      }
-    }
-    y[g] = a0;
-    return;
-  } else {
+  {
     constexpr int RY = DIM >= 2 ? 1 : 0, RZ = DIM >= 3 ? 1 : 0;
 #pragma unroll
     for (int oz = -RZ; oz <= RZ; ++oz)
@@ -609,6 +522,87 @@ __global__ __launch_bounds__(256) void k_apply_A(DGrid G, const double* __restri
   }
 #pragma unroll
   for (int m = 0; m < 3; ++m) y[m * N + g] = acc[m];
+}
+
+// Rows of A x at the node planes x = 0 and x = nxp of a walled grid, written
+// after k_apply_A.  Held components are identity rows (all three on an inflow
+// plane, the tangential ones on a wall).  The normal row of a wall node takes
+// curl_CN over the cells around the node, those beyond the wall being mirror
+// images of curl_NC x (a pseudo-vector: x component odd; the ghost cell of an
+// inflow plane carries zero), plus row 0 of the half-stencil mass term and
+// the diffusion term.  The plane's nodes lie n[0] apart in memory, so each
+// load touches its own cache line; 8 lanes share a node to keep many loads in
+// flight: lane p takes cell p of the curl-curl, mass-matrix blocks p and
+// p + 8 and, for p < DIM, the diffusion along axis p, and the 8 parts are
+// summed in a fixed order.  One group of 8 lanes per node of the two planes.
+template <typename T, int DIM>
+__global__ __launch_bounds__(256) void k_apply_A_planes(DGrid G, const double* __restrict__ x,
+                                                        const T* __restrict__ Mt, const double* __restrict__ kE,
+                                                        double k2, double mcoef, double tdt, double* __restrict__ y) {
+  constexpr int NC = Gd<DIM>::NC;
+  using HS = HalfStencil<DIM>;
+  const int64_t N = G.N;
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int p = (int)(threadIdx.x & 7);
+  const int64_t node = t >> 3, plane = (int64_t)G.n[1] * G.n[2];
+  const bool live = node < 2 * plane;  // every lane takes part in the sums below
+  const int64_t r = !live ? 0 : (node < plane ? node : node - plane);
+  const int gx = live && node >= plane ? G.nxp : 0;
+  const int gy = (int)(r % G.n[1]), gz = (int)(r / G.n[1]);
+  const int64_t g = flat3(G, gx, gy, gz);
+  const double x0 = x[g];
+  double s = 0.0;
+  if (live && !held(G, gx, 0)) {
+    if (p < NC) {
+      // cell p below/above the node along each axis; D[1][2] - D[2][1] of
+      // curl_CN takes its curl with the sign of its side
+      const int ci = gx - ax_bit(p, 0), cj = gy - (DIM >= 2 ? ax_bit(p, 1) : 0),
+                ck = gz - (DIM >= 3 ? ax_bit(p, 2) : 0);
+      double sg;
+      const int cm = cell_mirror(G, ci, sg, true);
+      if (cm < G.nxp) {
+        double C[3];
+        curl_nc_cell<DIM>(G, x, cm, cj, ck, C);  // C[0] (odd) is not used by the normal row
+        const double inv = 2.0 / NC;
+        double cc = 0.0;
+        if (DIM >= 2) cc += (ax_bit(p, 1) ? -1.0 : 1.0) * C[2] * inv * G.idx[1];
+        if (DIM >= 3) cc -= (ax_bit(p, 2) ? -1.0 : 1.0) * C[1] * inv * G.idx[2];
+        s += k2 * cc;
+      }
+    }
+    if (Mt) {
+      double m0 = 0.0;
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        const int h = p + 8 * k;
+        if (h >= HS::NH) break;
+        const int o0 = HS::o[h][0], o1 = HS::o[h][1], o2 = HS::o[h][2];
+        const int64_t gp = flat3(G, gx + o0, gy + o1, gz + o2);
+#pragma unroll
+        for (int j = 0; j < 3; ++j) m0 += (double)Mt[(int64_t)(h * 9 + j) * N + g] * x[j * N + gp];
+        if (h == 0) continue;
+        const int64_t gm = flat3(G, gx - o0, gy - o1, gz - o2);
+#pragma unroll
+        for (int j = 0; j < 3; ++j) m0 += (double)Mt[(int64_t)(h * 9 + j) * N + gm] * x[j * N + gm];
+      }
+      s += mcoef * m0;
+    }
+    if (kE && p < DIM) {
+      const int d = p;
+      const int64_t gp = flat3(G, gx + (d == 0), gy + (d == 1), gz + (d == 2));
+      const int64_t gm = flat3(G, gx - (d == 0), gy - (d == 1), gz - (d == 2));
+      const double kp = kE[(d * 3) * N + g], km = kE[(d * 3) * N + gm];
+      s -= tdt * G.idx[d] * (kp * (x[gp] - x0) - km * (x0 - x[gm]));
+    }
+  }
+  s += __shfl_xor(s, 1);
+  s += __shfl_xor(s, 2);
+  s += __shfl_xor(s, 4);
+  if (live && p == 0) {
+    y[g] = x0 + s;  // s = 0 on a held row
+    y[N + g] = x[N + g];
+    y[2 * N + g] = x[2 * N + g];
+  }
 }
 
 // B^{n+1} = B^n - c dt curl_NC E^{n+theta} + dt D_B B^n  (C holds curl_NC E^{n+theta})
@@ -938,11 +932,11 @@ static void apply_t(ge_ctx* c, const double* x, double* y) {
   const T* Mt = c->have_deposit ? (const T*)c->Mt : nullptr;
   const double* kE = c->P.lf_E ? c->kE : nullptr;
   const CurlCurl K = curl_curl_stencil(c->G);
-  hipLaunchKernelGGL((k_apply_A<T, DIM, false>), grid1(c->G.N), dim3(256), 0, c->stream, c->G, x, Mt, kE, K,
-                     ctd * ctd, mcoef, c->P.theta * c->P.dt, y);
+  hipLaunchKernelGGL((k_apply_A<T, DIM>), grid1(c->G.N), dim3(256), 0, c->stream, c->G, x, Mt, kE, K, ctd * ctd,
+                     mcoef, c->P.theta * c->P.dt, y);
   if (walled(c->G))
-    hipLaunchKernelGGL((k_apply_A<T, DIM, true>), grid1(2 * (int64_t)c->G.n[1] * c->G.n[2]), dim3(256), 0, c->stream,
-                       c->G, x, Mt, kE, K, ctd * ctd, mcoef, c->P.theta * c->P.dt, y);
+    hipLaunchKernelGGL((k_apply_A_planes<T, DIM>), grid1(16 * (int64_t)c->G.n[1] * c->G.n[2]), dim3(256), 0,
+                       c->stream, c->G, x, Mt, kE, ctd * ctd, mcoef, c->P.theta * c->P.dt, y);
 }
 int ge_launch_apply_A(ge_ctx* c, const double* x, double* y) {
   switch (c->G.dim * 2 + (c->P.precision == GE_FP32 ? 1 : 0)) {
