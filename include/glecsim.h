@@ -203,7 +203,9 @@ int ge_deposit(ge_ctx* ctx);
  * FP64, starting from E^n, until ||b - A x|| <= tol ||b||.  precond:
  * GE_PC_NONE, GE_PC_JACOBI (node 3x3 block diagonal, right-preconditioned) or
  * GE_PC_CNN (flexible GMRES with the learned network of ge_cnn_*, 3D only;
- * falls back to plain GMRES from the current iterate if the network returns
+ * on a walled grid the preconditioned vector keeps the input's values on the
+ * held boundary components, whose operator rows are the identity (see
+ * ge_cnn_apply); falls back to plain GMRES from the current iterate if the network returns
  * NaN/Inf or a restart cycle reduces the residual by less than a factor 2).  If harvesting is
  * on (ge_cnn_harvest), a converged GE_PC_NONE/JACOBI solve also stores
  * training pairs: (b - A E^n, E^{n+theta} - E^n) and/or (A v_j, v_j) for the
@@ -376,7 +378,9 @@ int ge_diagnostics_noalloc(ge_ctx* ctx, ge_diag* out);
  *                                                 [1] deposit kernel
  *   [2] node assembly kernel                      [3] rest of the grid pass
  *   [4] field update kernels                      [5] solve (host wall time)
- *   [6] 0                                         [7] number of steps averaged
+ *   [6] the part of [0] before the pushes: corner-field packing and the
+ *       segment scans (the re-binning's own kernels; the pushes record the
+ *       direction runs as they write)            [7] number of steps averaged
  * The accumulators are reset by the call. */
 int ge_timings(ge_ctx* ctx, double* out8);
 
@@ -412,7 +416,10 @@ int ge_cnn_size(void);
 /* Copy the master weights to (set = 0) or from (set = 1) host_w[ge_cnn_size()]. */
 int ge_cnn_weights(ge_ctx* ctx, int set, float* host_w);
 /* z = N(r) on the whole periodic grid, r normalised by its RMS and the
- * output scaled back (device double [3][N]).  Synchronises. */
+ * output scaled back (device double [3][N]).  On a walled grid the network
+ * sees a domain periodic along x over the node planes that are not wholly
+ * held (an inflow plane is left out), and z = r on the held components.
+ * Synchronises. */
 int ge_cnn_apply(ge_ctx* ctx, const double* r, double* z);
 /* Pair harvesting from converged solves: 0 = off, else an OR of
  * GE_HARVEST_SOLUTION (the pair (b - A E^n, E^{n+theta} - E^n)) and

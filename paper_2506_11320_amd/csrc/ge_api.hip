@@ -102,6 +102,7 @@ void accumulate_timings(ge_ctx* c, double solve_s) {
   float ms;
   for (int k = 0; k < 5; ++k)
     if (hipEventElapsedTime(&ms, c->ev[2 * k], c->ev[2 * k + 1]) == hipSuccess) c->tsum[k] += ms * 1e-3;
+  if (hipEventElapsedTime(&ms, c->ev[0], c->ev[10]) == hipSuccess) c->tsum[6] += ms * 1e-3;
   (void)hipGetLastError();
   c->tsum[5] += solve_s;
   c->tcnt += 1;
@@ -326,7 +327,7 @@ int ge_create(const ge_grid* grid, const ge_params* params, void* hip_stream, ge
   (void)hipMemsetAsync(c->rho, 0, sizeof(double) * GE_MAX_SPECIES * N, s);
   (void)hipMemsetAsync(c->psi, 0, sizeof(double) * N, s);
   (void)hipMemsetAsync(c->flags, 0, sizeof(int) * GE_FL_COUNT, s);
-  for (int k = 0; k < 10; ++k) (void)hipEventCreate(&c->ev[k]);
+  for (int k = 0; k < 11; ++k) (void)hipEventCreate(&c->ev[k]);
   for (int k = 0; k < 8; ++k) c->tsum[k] = 0;
   c->tcnt = 0;
   if (hipGetLastError() != hipSuccess) {
@@ -362,7 +363,7 @@ void ge_destroy(ge_ctx* c) {
     dfree(c->sp[s].inj_cell);
   }
   ge_far_free(c);
-  for (int k = 0; k < 10; ++k)
+  for (int k = 0; k < 11; ++k)
     if (c->ev[k]) (void)hipEventDestroy(c->ev[k]);
   ge_cnn_free(c);
   dfree(c->Zb);
@@ -546,6 +547,7 @@ int ge_push(ge_ctx* c) {
   if ((rc = ge_launch_pack_node8(c, 0))) return rc;
   for (int s = 0; s < c->nsp; ++s)
     if ((rc = ge_launch_scan_counts(c, s))) return rc;
+  (void)hipEventRecord(c->ev[10], c->stream);
   for (int s = 0; s < c->nsp; ++s)
     if ((rc = ge_launch_push(c, s))) return rc;
   (void)hipEventRecord(c->ev[1], c->stream);

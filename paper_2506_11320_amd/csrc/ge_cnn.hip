@@ -121,6 +121,25 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs A) {
   }
 }
 
+// x extent of the network's periodic domain: the stored node planes, less an
+// inflow plane (all of whose components are held, so the preconditioned
+// vector there is the input itself)
+inline int cnn_nx(const DGrid& G) { return walled(G) && G.bch == GE_BC_INFLOW ? G.nxp : G.n[0]; }
+
+// z = v on the held components of a walled grid's boundary node planes
+// (x = 0 and x = nxp): their operator rows are the identity, so the exact
+// preconditioner keeps the input there.  One thread per node of the two
+// planes (t < 2 n[1] n[2]).
+__global__ void k_hold_rows(DGrid G, const double* __restrict__ v, double* __restrict__ z) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t np = (int64_t)G.n[1] * G.n[2];
+  if (t >= 2 * np) return;
+  const int gx = t < np ? 0 : G.nxp;
+  const int64_t g = gx + (int64_t)G.n[0] * (t < np ? t : t - np);
+  for (int q = 0; q < 3; ++q)
+    if (held(G, gx, q)) z[q * G.N + g] = v[q * G.N + g];
+}
+
 // Whole-grid (periodic) layer, the one that runs inside every FGMRES
 // iteration.  A workgroup of 8 waves owns an output tile of 16 x 8 x 4 nodes;
 // its input halo (18 x 10 x 6 nodes) and the layer's weights sit in LDS, so
@@ -130,6 +149,9 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs A) {
 // accumulator lane holds 4 consecutive channels of one node and stores them
 // as one 8-byte write.  Rows of 64 bytes (32 channels) are XOR-swizzled in
 // 16-byte chunks so that the 16 lanes of an LDS phase hit distinct banks.
+// With 32 input channels (one tap per K step) a wave's 4 output rows are
+// consecutive in y, so for each (tx, tz) its 6 input rows are read once and
+// serve the 3 taps along y (6 activation reads for 12 products instead of 12).
 // Blocks are persistent; each prefetches its next tile's halo into registers
 // while it computes the current one, and the block -> tile order keeps
 // neighbouring tiles (shared halos) on one XCD.
@@ -145,7 +167,8 @@ struct TileArgs {
   const __bf16* w;   // [27][COUT][CIN]
   __bf16* out;       // [N][COUT] (unless OUT_F64)
   double* z;         // [3][N] (OUT_F64)
-  int nx, ny, nz, ntx, nty, ntiles;
+  int nx, ny, nz, ntx, nty, ntiles;  // nx: the network's periodic x extent (<= sx)
+  int sx;                            // x row length of the grid storage
   int64_t N;
 };
 
@@ -184,7 +207,7 @@ __global__ __launch_bounds__(TNT) void k_conv_tile(TileArgs A) {
       if (c < THN * CH) {
         const int h = c / CH, part = c % CH;
         const int hx = h % THX, hy = (h / THX) % THY, hz = h / (THX * THY);
-        const int64_t g = pmod(x0 + hx, A.nx) + (int64_t)A.nx * (pmod(y0 + hy, A.ny) + (int64_t)A.ny * pmod(z0 + hz, A.nz));
+        const int64_t g = pmod(x0 + hx, A.nx) + (int64_t)A.sx * (pmod(y0 + hy, A.ny) + (int64_t)A.ny * pmod(z0 + hz, A.nz));
         if constexpr (IN_F64) {
           pd[i][0] = A.v[g];
           pd[i][1] = A.v[A.N + g];
@@ -226,6 +249,31 @@ __global__ __launch_bounds__(TNT) void k_conv_tile(TileArgs A) {
     for (int m = 0; m < 4; ++m)
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) acc[m][nb] = f4{0, 0, 0, 0};
+    if constexpr (CIN == 32) {
+      // one tap per K step: for each (tx, tz) the wave's 4 output rows
+      // (consecutive y at one z) read 6 input rows, each used by up to 3 taps
+      const int r0 = 4 * wv, yb = r0 % TLY, zb = r0 / TLY;
+#pragma unroll 1
+      for (int tz = 0; tz < 3; ++tz)
+#pragma unroll
+        for (int tx = 0; tx < 3; ++tx) {
+          bf8 bv[6];
+#pragma unroll
+          for (int j = 0; j < 6; ++j) bv[j] = sh[swz<CH>(((zb + tz) * THY + yb + j) * THX + row + tx, kq)];
+#pragma unroll
+          for (int ty = 0; ty < 3; ++ty) {
+            const int t = tx + 3 * ty + 9 * tz;
+            bf8 a[NB];
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) a[nb] = sw[swz<CH>(t * COUT + 16 * nb + row, kq)];
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+#pragma unroll
+              for (int nb = 0; nb < NB; ++nb)
+                acc[m][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[nb], bv[m + ty], acc[m][nb], 0, 0, 0);
+          }
+        }
+    } else
 #pragma unroll 3
     for (int q = 0; q < NK; ++q) {
       const int traw = q * TPK + (8 * kq) / CIN;
@@ -252,7 +300,7 @@ __global__ __launch_bounds__(TNT) void k_conv_tile(TileArgs A) {
       const int r = 4 * wv + m;
       const int gy = ty * TLY + r % TLY, gz = tz * TLZ + r / TLY;
       if (gx >= A.nx || gy >= A.ny || gz >= A.nz) continue;
-      const int64_t g = gx + (int64_t)A.nx * (gy + (int64_t)A.ny * gz);
+      const int64_t g = gx + (int64_t)A.sx * (gy + (int64_t)A.ny * gz);
       if constexpr (OUT_F64) {
         if (kq == 0) {
           const double inv = 1.0 / A.s;
@@ -362,7 +410,8 @@ struct CropArgs {
   const float* pr;  // pair store residuals [P][3][N]
   const float* pe;  // pair store corrections
   int64_t N;
-  int nx, ny, nz;   // grid
+  int nx, ny, nz;   // the network's periodic domain (nx <= sx)
+  int sx;           // x row length of the grid storage
   int n;            // output crop edge
   const int* meta;  // per crop: ox, oy, oz, p0, p1
   const float* wts; // per crop: w0, w1
@@ -381,7 +430,7 @@ __global__ void k_make_crops(CropArgs A) {
   const int y = (int)(r % m), z = (int)(r / m);
   const int* mt = A.meta + 5 * b;
   const int gx = wrapi((mt[0] + x) % A.nx, A.nx), gy = wrapi((mt[1] + y) % A.ny, A.ny), gz = wrapi((mt[2] + z) % A.nz, A.nz);
-  const int64_t g = gx + (int64_t)A.nx * (gy + (int64_t)A.ny * gz);
+  const int64_t g = gx + (int64_t)A.sx * (gy + (int64_t)A.ny * gz);
   const float w0 = A.wts[2 * b], w1 = A.wts[2 * b + 1];
   const float* r0 = A.pr + (int64_t)mt[3] * 3 * A.N;
   const float* r1 = A.pr + (int64_t)mt[4] * 3 * A.N;
@@ -638,6 +687,9 @@ static void conv_tile(ge_ctx* c, TileArgs A) {
 }
 
 // z = N(s v) / s on the whole periodic grid (v, z: device double [3][N]).
+// On a walled grid the network's domain is periodic over the node planes
+// that are not wholly held (an inflow plane is left out), and z = v on the
+// held components, whose operator rows are the identity.
 int ge_cnn_apply_grid(ge_ctx* c, const double* v, double* z, double scale) {
   ge_cnn_state* s = cnn(c);
   if (!s || !s->ready) return ge_fail(c, GE_ERR_STATE, "CNN weights not initialised");
@@ -652,13 +704,17 @@ int ge_cnn_apply_grid(ge_ctx* c, const double* v, double* z, double scale) {
   }
   TileArgs A;
   std::memset(&A, 0, sizeof(A));
-  A.nx = c->G.n[0]; A.ny = c->G.n[1]; A.nz = c->G.n[2]; A.N = N; A.s = scale;
+  A.nx = cnn_nx(c->G); A.sx = c->G.n[0]; A.ny = c->G.n[1]; A.nz = c->G.n[2]; A.N = N; A.s = scale;
   A.v = v; A.w = s->wf[0]; A.out = s->act1;
   conv_tile<8, 32, true, false>(c, A);
   A.v = nullptr; A.in = s->act1; A.w = s->wf[1]; A.out = s->act2;
   conv_tile<32, 32, false, false>(c, A);
   A.in = s->act2; A.w = s->wf[2]; A.out = nullptr; A.z = z;
   conv_tile<32, 16, false, true>(c, A);
+  if (walled(c->G)) {
+    const int64_t np2 = 2 * (int64_t)c->G.n[1] * c->G.n[2];
+    hipLaunchKernelGGL(k_hold_rows, dim3((unsigned)((np2 + 255) / 256)), dim3(256), 0, c->stream, c->G, v, z);
+  }
   GE_HIP(c, hipGetLastError());
   return GE_OK;
 }
@@ -895,7 +951,7 @@ int ge_cnn_train(ge_ctx* c, const ge_train_cfg* cfg, ge_train_report* rep) {
   for (int it = 0; it < cfg->iters; ++it) {
     for (int b = 0; b < B; ++b) {
       auto u = [&]() { return (hash32(cfg->seed * 0x85EBCA6BU + (ctr++) * 0x9E3779B9U) + 0.5) / 4294967296.0; };
-      meta[5 * b + 0] = (int)(u() * c->G.n[0]);
+      meta[5 * b + 0] = (int)(u() * cnn_nx(c->G));
       meta[5 * b + 1] = (int)(u() * c->G.n[1]);
       meta[5 * b + 2] = (int)(u() * c->G.n[2]);
       meta[5 * b + 3] = (int)(u() * np) % np;
@@ -908,7 +964,7 @@ int ge_cnn_train(ge_ctx* c, const ge_train_cfg* cfg, ge_train_report* rep) {
     GE_HIP(c, hipMemcpyAsync(s->t_wts, wts.data(), sizeof(float) * 2 * B, hipMemcpyHostToDevice, c->stream));
     CropArgs CA;
     CA.pr = s->pr; CA.pe = s->pe; CA.N = c->G.N;
-    CA.nx = c->G.n[0]; CA.ny = c->G.n[1]; CA.nz = c->G.n[2];
+    CA.nx = cnn_nx(c->G); CA.sx = c->G.n[0]; CA.ny = c->G.n[1]; CA.nz = c->G.n[2];
     CA.n = n; CA.meta = s->t_meta; CA.wts = s->t_wts; CA.in = s->t_in; CA.tgt = s->t_tgt; CA.B = B;
     const int64_t vin = (int64_t)(n + 6) * (n + 6) * (n + 6) * B;
     hipLaunchKernelGGL(k_make_crops, g1(vin), dim3(256), 0, c->stream, CA);

@@ -245,7 +245,7 @@ struct ge_ctx {
   FarScratch fx;
   void* cnn;           // learned preconditioner state (ge_cnn.hip), lazily created
   double* Zb;          // flexible-GMRES basis of preconditioned vectors (lazily allocated)
-  hipEvent_t ev[10];   // pairs: push, deposit, assemble, grid rest, update
+  hipEvent_t ev[11];   // pairs: push, deposit, assemble, grid rest, update; [10] end of the push's scans
   double tsum[8];      // accumulated per-phase seconds (see ge_timings)
   int tcnt;
 };

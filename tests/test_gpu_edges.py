@@ -133,3 +133,22 @@ def test_explicit_step_with_empty_cells_and_species(name, dim, n, ppc, base, fp3
     assert H.relerr(sim.gather("J_eff").cpu().numpy(), r["J"]) < tol
     assert sim.particles(1)["cell"].numel() == 0
     sim.close()
+
+
+def test_phase_timings_of_a_step():
+    """ge_timings: every timed phase of a step is positive, the re-binning's
+    own kernels (slot 6) are part of the push phase (slot 0), and the call
+    resets the accumulators."""
+    print("[gpu] phase timings", flush=True)
+    wl = _wl(3, (6, 5, 4), 20, "c5", True)
+    parts = H.species_arrays(wl, True)
+    E, B = H.perturbed_fields(wl)
+    sim = H.make_sim(wl, parts, E, B)
+    for _ in range(2):
+        sim.step(tol=1e-8, maxit=500, restart=30)
+    t = sim.timings()
+    assert t[7] == 2
+    assert all(v > 0 for v in t[:7]), t
+    assert t[6] < t[0], t
+    assert sim.timings() == [0.0] * 8
+    sim.close()
