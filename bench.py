@@ -123,6 +123,41 @@ def _oracle_sample(args):
     return npart, time.perf_counter() - t0
 
 
+def oracle_full_solve(wname):
+    """The FP64 oracle on the whole grid of a workload, on one core: the
+    deposit and grid pass of the initial state (lab and comoving deposits,
+    bulk velocity and its filter, E_M, J_eff, the LF coefficients and the
+    right-hand side), then the field solve by plain GMRES(30) from E^n to
+    1e-8, timed separately.  Takes minutes on the 3D workloads."""
+    import oracle as O
+    import synth
+    wl = synth.workloads()[wname]
+    G = O.grid(wl.dim, wl.n, wl.dx, bc=wl.bc)
+    E, B = synth.fields(wl)
+    sp = []
+    for s in range(wl.nsp):
+        p = synth.particles(wl, s, f32=wl.fp32)
+        sp.append(O.Species(wl.q[s], wl.m[s], O.global_positions(G, p["cell"], p["off"].astype(np.float64)),
+                            p["v"].astype(np.float64).T, p["w"].astype(np.float64)))
+        del p
+    npart = sum(x.w.size for x in sp)
+    log(f"oracle full solve {wname}: {npart} particles, {O.nnodes(G)} nodes")
+    P = O.params(wl.theta, wl.dt)
+    t0 = time.perf_counter()
+    dep = O.deposit(G, sp, wl.dt, B, wl.comoving, wl.n_smooth_u)
+    a_node = O.diffusion_speed(G, dep["u"], wl.a_mode)
+    kE = O.kappa_E(G, E, a_node, wl.beta_lim) if wl.lf_E else None
+    b = O.rhs(G, P, E, B, dep["J_eff"])
+    t1 = time.perf_counter()
+    log(f"oracle deposit and grid pass {t1 - t0:.1f} s")
+    _, its, rel = O.gmres(G, P, dep["Mt"], kE, b, E, tol=1e-8, maxit=5000, restart=30)
+    t2 = time.perf_counter()
+    return {"oracle_full_solve": {"workload": wname, "nodes": O.nnodes(G), "particles": npart,
+                                  "deposit_and_grid_pass_s": round(t1 - t0, 2), "gmres_s": round(t2 - t1, 2),
+                                  "gmres_iterations": its, "relres": rel, "tol": 1e-8, "cores": 1,
+                                  "cpu_model": cpu_model(), "kind": "oracle, single-threaded C, gcc -O2"}}
+
+
 def cpu_baseline(wname, box, procs):
     """The FP64 C oracle, as it stands, timed on bounded samples of the same
     workload: one process (one core), then `procs` processes at once on
@@ -314,13 +349,19 @@ def main():
                          "per step to PATH: phase times, GMRES iterations and residual, FP64 energies, momenta, "
                          "Gauss residual, moves")
     ap.add_argument("--metrics-steps", type=int, default=10)
+    ap.add_argument("--oracle-full-solve", action="store_true",
+                    help="only time the FP64 oracle's deposit and plain GMRES solve on the whole grid of --workload "
+                         "(one core, no GPU) and exit")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain device copy of 4 GiB (reference for the HBM byte counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only: this build has no multi-GPU path (got --gpus {args.gpus}); "
-              "the sharding design is described in DESIGN.md", file=sys.stderr)
+        print(f"bench.py runs on one GPU only: there is no multi-GPU path (got --gpus {args.gpus})", file=sys.stderr)
         sys.exit(2)
+
+    if args.oracle_full_solve:
+        print(json.dumps(oracle_full_solve(args.workload)), flush=True)
+        return
 
     import torch
     import synth
