@@ -75,17 +75,29 @@ def algorithmic_bytes(wl, nsp, npart):
             "per_particle": per_p, "per_node_deposit": node_dep}
 
 
-def measured_traffic(kernel_file, record):
-    """HBM bytes per launch of the dominant kernel from the committed counter
-    record (profiles/), or None when the kernel source changed since the
-    counters were taken (the record holds the source's SHA-256)."""
+TRAFFIC_SOURCES = ("paper_2506_11320_amd/csrc/ge_particles.hip", "paper_2506_11320_amd/csrc/ge_internal.h")
+
+
+def sources_sha256(files=TRAFFIC_SOURCES):
+    """SHA-256 over the kernel's source files (the kernel file and the header
+    that fixes its data layouts), in the given order."""
     import hashlib
+    h = hashlib.sha256()
+    for f in files:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()
+
+
+def measured_traffic(record):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    record (profiles/), or None when its sources changed since the counters
+    were taken (the record holds their SHA-256)."""
     try:
         rec = json.load(open(os.path.join(ROOT, record)))
-        src = open(os.path.join(ROOT, kernel_file), "rb").read()
-    except (OSError, ValueError):
+        sha = sources_sha256(tuple(rec.get("sources", ())))
+    except (OSError, ValueError, TypeError):
         return None
-    if rec.get("source_sha256") != hashlib.sha256(src).hexdigest():
+    if not rec.get("sources") or rec.get("sources_sha256") != sha:
         return None
     return float(rec["traffic_bytes"])
 
@@ -431,7 +443,7 @@ def main():
     roof = {"bound": "hbm", "kernel": f"k_deposit<{tname}>",
             "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic("paper_2506_11320_amd/csrc/ge_particles.hip", "profiles/c5_deposit_traffic.json")
+            "traffic": measured_traffic("profiles/c5_deposit_traffic.json")
             if (args.workload == "c5" and wl.fp32) else None,
             "algorithmic_bytes_per_launch": ab["deposit"], "launch_ms": round(tm[1] * 1e3, 4),
             "algorithmic_bytes_per_unit": {"particle": ab["per_particle"], "node": ab["per_node_deposit"]}}

@@ -300,7 +300,7 @@ int ge_create(const ge_grid* grid, const ge_params* params, void* hip_stream, ge
   if (!rc) rc = dalloc(c, &c->node8, es * 8 * N);
   if (!rc) rc = dalloc(c, &c->Mt, es * c->nh * 9 * N);
   if (!rc) rc = dalloc(c, &c->M0, es * c->nh * 9 * N);
-  if (!rc) rc = dalloc(c, &c->cellQ, es * (size_t)c->Q * ((N + 3) / 4 * 4));
+  if (!rc) rc = dalloc(c, &c->cellQ, es * (size_t)c->Q * ((N + GE_CQG - 1) / GE_CQG * GE_CQG));
   if (!rc) rc = dalloc(c, &c->seg_next, sizeof(int32_t) * GE_MAX_SPECIES * N);
   c->scan_nblocks = (N + 1023) / 1024;
   if (!rc) rc = dalloc(c, &c->scan_blocks, sizeof(int32_t) * (c->scan_nblocks + 1));

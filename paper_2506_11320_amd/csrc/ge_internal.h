@@ -120,13 +120,15 @@ __device__ inline int64_t nbr3(const DGrid& G, int64_t g, int ox, int oy, int oz
 }
 
 // Per-cell partial sums: value k of cell c at cq_index(c, k, Q), laid out as
-// [cell/4][Q/4][4 cells][4 values] (Q a multiple of 4).  The 4 cells of a
-// group share cache lines (their deposit waves run side by side), and 4
-// consecutive values of one cell form one 16-byte vector, which the node
+// [cell/8][Q/4][8 cells][4 values] (Q a multiple of 4).  The 8 cells of a
+// group fill whole 128-byte lines (their deposit waves run side by side, and
+// a node-assembly wave reads 64 consecutive cells' vectors as 8 full lines),
+// and 4 consecutive values of one cell form one 16-byte vector, which the node
 // assembly reads with a single load.
-__host__ __device__ inline int cq_off(int k) { return (k >> 2) * 16 + (k & 3); }
+constexpr int GE_CQG = 8;  // cells per group
+__host__ __device__ inline int cq_off(int k) { return (k >> 2) * (4 * GE_CQG) + (k & 3); }
 __host__ __device__ inline int64_t cq_index(int64_t c, int k, int Q) {
-  return ((c >> 2) * (Q >> 2) * 4 + (c & 3)) * 4 + cq_off(k);
+  return ((c / GE_CQG) * (Q >> 2) * GE_CQG + (c % GE_CQG)) * 4 + cq_off(k);
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs; remap so that each
