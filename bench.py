@@ -341,10 +341,10 @@ def main():
     ap.add_argument("--compare-precond", action="store_true", help="also time a Jacobi-preconditioned solve")
     ap.add_argument("--no-nn", action="store_true", help="skip the learned-preconditioner comparison")
     ap.add_argument("--nn-harvest", type=int, default=8, help="plain solves whose (residual, correction) pairs train")
-    ap.add_argument("--nn-iters", type=int, default=300, help="training steps")
+    ap.add_argument("--nn-iters", type=int, default=800, help="training steps")
     ap.add_argument("--nn-crop", type=int, default=16)
     ap.add_argument("--nn-batch", type=int, default=16)
-    ap.add_argument("--nn-lr", type=float, default=1e-3)
+    ap.add_argument("--nn-lr", type=float, default=2e-3)
     ap.add_argument("--nn-eval", type=int, default=4, help="steps solved both ways after training")
     ap.add_argument("--nn-pairs", type=int, default=96, help="pair store capacity")
     ap.add_argument("--nn-data", default="both", choices=["solution", "krylov", "both"],

@@ -42,8 +42,10 @@ __global__ __launch_bounds__(KB) void k_multidot(const double* __restrict__ V, i
   if (threadIdx.x < NV) part[threadIdx.x * KRED + blockIdx.x] = sh[threadIdx.x][0];
 }
 
-// out[i] = sum_b part[i * KRED + b] in a fixed tree order (one block per i)
-__global__ __launch_bounds__(KB) void k_reduce(const double* __restrict__ part, double* __restrict__ out) {
+// out[i] = sum_b part[i * KRED + b] in a fixed tree order (one block per i),
+// and add[i] += out[i] when add is given
+__global__ __launch_bounds__(KB) void k_reduce(const double* __restrict__ part, double* __restrict__ out,
+                                               double* __restrict__ add = nullptr) {
   __shared__ double sh[KB];
   const int i = blockIdx.x;
   double a = 0;
@@ -54,7 +56,10 @@ __global__ __launch_bounds__(KB) void k_reduce(const double* __restrict__ part, 
     if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[i] = sh[0];
+  if (threadIdx.x == 0) {
+    out[i] = sh[0];
+    if (add) add[i] += sh[0];
+  }
 }
 
 // w[k] += sign * sum_{i<nv} h[i] V_i[k]
@@ -188,8 +193,9 @@ static int multidot(ge_ctx* c, const double* V, int64_t ld, int nv, const double
 }
 
 // Passes 1b and 2 of CGS2 for nv <= 16 vectors (h1 from the first multi-dot):
-// w -= V h1, h2 = V^T w, w -= V h2, |w|^2, with V read twice instead of three times.
-static int cgs2_fused(ge_ctx* c, double* w, const double* V, int64_t ld, int nv, const double* h1, double* h2,
+// w -= V h1, h2 = V^T w, h1 += h2, w -= V h2, |w|^2, with V read twice
+// instead of three times.
+static int cgs2_fused(ge_ctx* c, double* w, const double* V, int64_t ld, int nv, double* h1, double* h2,
                       double* nrm2, int64_t n) {
   double* part = c->partials;
   switch (nv) {
@@ -198,7 +204,7 @@ static int cgs2_fused(ge_ctx* c, double* w, const double* V, int64_t ld, int nv,
 #undef AD
     default: return ge_fail(c, GE_ERR_ARG, "fused Gram-Schmidt takes at most 16 vectors");
   }
-  hipLaunchKernelGGL(k_reduce, dim3(nv), dim3(KB), 0, c->stream, part, h2);
+  hipLaunchKernelGGL(k_reduce, dim3(nv), dim3(KB), 0, c->stream, part, h2, h1);
   switch (nv) {
 #define AN(K) case K: hipLaunchKernelGGL(k_axpy_norm<K>, dim3(KRED), dim3(KB), 0, c->stream, w, V, ld, h2, n, part); break;
     AN(1) AN(2) AN(3) AN(4) AN(5) AN(6) AN(7) AN(8) AN(9) AN(10) AN(11) AN(12) AN(13) AN(14) AN(15) AN(16)
@@ -293,7 +299,6 @@ int ge_gmres(ge_ctx* c, double tol, int maxit, int m, int precond, ge_solve_repo
       if ((rc = multidot(c, V, n, j + 1, w, n, hd))) return rc;
       if (j + 1 <= 16) {
         if ((rc = cgs2_fused(c, w, V, n, j + 1, hd, hd + HSTRIDE, hd + 128, n))) return rc;
-        hipLaunchKernelGGL(k_sum2, dim3(1), dim3(HSTRIDE), 0, c->stream, hd, hd + HSTRIDE, j + 1);
       } else {
         hipLaunchKernelGGL(k_multiaxpy, vgrid(n), dim3(KB), 0, c->stream, w, V, n, j + 1, hd, -1.0, n);
         if ((rc = multidot(c, V, n, j + 1, w, n, hd + HSTRIDE))) return rc;
