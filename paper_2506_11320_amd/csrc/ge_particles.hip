@@ -1276,9 +1276,12 @@ __device__ inline int count_below(const int32_t* a, int n, int x) {
   return lo;
 }
 
-// One wavefront per destination cell: merge its direction runs and its far
-// movers by buffer position into one contiguous segment of the other buffer;
-// the cell's run table then holds the single run "no move".
+// Two destination cells per wavefront, one per 32-lane half (a cell holds a
+// few tens of particles; a whole wavefront per cell would leave most lanes
+// idle): merge the cell's direction runs and its far movers by buffer position
+// into one contiguous segment of the other buffer; the cell's run table then
+// holds the single run "no move".  The runs are collected as in runs_setup,
+// within each half.
 template <typename T, int DIM>
 __global__ __launch_bounds__(64) void k_far_merge(DGrid G, const T* __restrict__ rec, const int32_t* __restrict__ runs,
                                                   const int32_t* __restrict__ sorted,
@@ -1287,39 +1290,61 @@ __global__ __launch_bounds__(64) void k_far_merge(DGrid G, const T* __restrict__
                                                   const int32_t* __restrict__ newstart, T* __restrict__ rec_o,
                                                   int32_t* __restrict__ runs_o) {
   constexpr int ND = Dm<DIM>::ND;
-  __shared__ int s_start[32], s_pre[32];
-  const int lane = threadIdx.x;
-  const int64_t c = blockIdx.x;
-  if (c >= G.N) return;
-  int nseg;
-  const int total = runs_setup<DIM>(G, c, runs, s_start, s_pre, lane, nseg);
-  const int nf = cnt_in[c];
-  const int32_t* fl = sorted + start_in[c];  // ascending buffer positions
-  const int64_t o = newstart[c];
-  for (int t = lane; t < total; t += 64) {
+  static_assert(ND <= 32, "the runs of a cell fit in half a wavefront");
+  __shared__ int s_start[2][32], s_pre[2][32];
+  const int lane = threadIdx.x, half = lane >> 5, hl = lane & 31;
+  const int64_t c = 2 * (int64_t)blockIdx.x + half;
+  const bool live = c < G.N;  // both halves take part in the wave-wide steps
+  const int64_t cc = live ? c : 0;
+  int cx, cy, cz;
+  unflat3(G, cc, cx, cy, cz);
+  int cnt = 0, st = 0;
+  if (live && hl < ND) {
+    const i2 rv = reinterpret_cast<const i2*>(runs)[cc * ND + run_dir<DIM>(G, cx, cy, cz, hl)];
+    st = rv.x;
+    cnt = rv.y;
+  }
+  const int incl = dpp_scan<false, true>(cnt);  // within each half
+  const int tot0 = rl_i(incl, 31), tot1 = rl_i(incl, 63);
+  const int total = half ? tot1 : tot0;
+  const uint64_t m = __ballot(cnt > 0);
+  const uint32_t mh = (uint32_t)(m >> (32 * half));
+  if (cnt > 0) {
+    const int pos = __popc(mh & ((1u << hl) - 1u));
+    s_start[half][pos] = st;
+    s_pre[half][pos] = incl - cnt;
+  }
+  const int nseg = __popc(mh);
+  wave_sync();
+  const int* sst = s_start[half];
+  const int* spr = s_pre[half];
+  const int nf = live ? cnt_in[cc] : 0;
+  const int32_t* fl = sorted + (live ? start_in[cc] : 0);  // ascending buffer positions
+  const int64_t o = live ? newstart[cc] : 0;
+  for (int t = hl; t < total; t += 32) {
     int k = 0;
     for (int i = 1; i < nseg; ++i)
-      if (s_pre[i] <= t) k = i;
-    const int src = s_start[k] + (t - s_pre[k]);
-    const int nb = nf > 0 ? count_below(fl, nf, s_start[k]) : 0;
+      if (spr[i] <= t) k = i;
+    const int src = sst[k] + (t - spr[k]);
+    const int nb = nf > 0 ? count_below(fl, nf, sst[k]) : 0;
     T f[3], v[3], w;
     read_rec<T, DIM>(rec, src, f, v, w);
     write_rec<T>(rec_o, o + t + nb, f, v, w);
   }
-  for (int j = lane; j < nf; j += 64) {
+  for (int j = hl; j < nf; j += 32) {
     const int p = fl[j];
     int nn = 0;
     for (int k = 0; k < nseg; ++k) {
-      const int ck = (k + 1 < nseg ? s_pre[k + 1] : total) - s_pre[k];
-      if (s_start[k] < p) nn += ck;
+      const int ck = (k + 1 < nseg ? spr[k + 1] : total) - spr[k];
+      if (sst[k] < p) nn += ck;
     }
     T f[3], v[3], w;
     read_rec<T, DIM>(rec, p, f, v, w);
     write_rec<T>(rec_o, o + j + nn, f, v, w);
   }
-  if (lane < ND) {
-    const bool centre = lane == (ND - 1) / 2;
-    reinterpret_cast<i2*>(runs_o)[c * ND + lane] = centre ? i2{(int)o, total + nf} : i2{0, 0};
+  if (live && hl < ND) {
+    const bool centre = hl == (ND - 1) / 2;
+    reinterpret_cast<i2*>(runs_o)[cc * ND + hl] = centre ? i2{(int)o, total + nf} : i2{0, 0};
   }
 }
 
@@ -1434,7 +1459,7 @@ static void far_kernels_t(ge_ctx* c, SpeciesBuf& S, int64_t F, int64_t nfar) {
   hipLaunchKernelGGL((k_far_newcount<DIM>), dim3((N + 255) / 256), dim3(256), 0, c->stream, c->G, S.runs[cur],
                      X.cnt_in, X.newstart);
   scan_into(c, X.newstart, X.newstart);
-  hipLaunchKernelGGL((k_far_merge<T, DIM>), dim3((unsigned)N), dim3(64), 0, c->stream, c->G, (const T*)S.rec[cur],
+  hipLaunchKernelGGL((k_far_merge<T, DIM>), dim3((unsigned)((N + 1) / 2)), dim3(64), 0, c->stream, c->G, (const T*)S.rec[cur],
                      S.runs[cur], X.sorted, X.cnt_in, X.start_in, X.newstart, (T*)S.rec[1 - cur], S.runs[1 - cur]);
 }
 
