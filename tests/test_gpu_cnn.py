@@ -63,6 +63,42 @@ def test_forward_matches_oracle(n):
     sim.close()
 
 
+def test_forward_on_a_walled_grid():
+    """On a grid with a wall at x = 0 and an inflow plane at x = L the network
+    runs on the domain periodic along x over the node planes 0 .. nxp - 1 (the
+    inflow plane, all of whose components are held, is left out), and the
+    output equals the input on the held components: the tangential ones on the
+    wall plane and all three on the inflow plane."""
+    from paper_2506_11320_amd import Simulation
+    print("[gpu] cnn forward on a walled grid", flush=True)
+    n = (12, 10, 9)  # physical cells along x; the grid stores 13 node planes
+    sim = Simulation(3, n, (0.5, 0.5, 0.5), theta=0.5, dt=0.5, bc=(1, 2))  # wall, inflow
+    nxs = n[0] + 1
+    N = nxs * n[1] * n[2]
+    sim.cnn_init(7)
+    rng = np.random.default_rng(13)
+    w = _rand_w(rng)
+    sim.cnn_set_weights(w)
+    r = rng.standard_normal((3, N)) * 3e-3
+    z = sim.cnn_apply(torch.from_numpy(r).to(sim.device)).cpu().numpy()
+    rg = r.reshape(3, n[2], n[1], nxs)
+    zg = z.reshape(3, n[2], n[1], nxs)
+    assert np.array_equal(zg[1:, :, :, 0], rg[1:, :, :, 0])
+    assert np.array_equal(zg[:, :, :, n[0]], rg[:, :, :, n[0]])
+    # the rest: the network on the reduced periodic domain, with the GPU's
+    # normalisation (the RMS of the whole input)
+    inner = np.ascontiguousarray(rg[..., :n[0]]).reshape(3, -1)
+    rms = np.sqrt(np.mean(r * r))
+    ref = C.forward_grid(w.astype(np.float64), inner, n, 1.0 / rms, quant=True).reshape(3, n[2], n[1], n[0])
+    got = zg[..., :n[0]].copy()
+    got[1:, :, :, 0] = 0.0
+    ref[1:, :, :, 0] = 0.0
+    e = H.relerr(got, ref)
+    print(f"  rel err vs BF16-rounded FP64 reference {e:.2e}", flush=True)
+    assert e <= 1e-3
+    sim.close()
+
+
 def _dyadic_w(rng):
     """Sparse weights in {0, +-1/2, +-1/4}: every partial sum of the network
     on +-1 inputs is a short dyadic number, exact in FP32."""
