@@ -135,12 +135,13 @@ def _oracle_sample(args):
     return npart, time.perf_counter() - t0
 
 
-def oracle_full_solve(wname):
-    """The FP64 oracle on the whole grid of a workload, on one core: the
-    deposit and grid pass of the initial state (lab and comoving deposits,
-    bulk velocity and its filter, E_M, J_eff, the LF coefficients and the
-    right-hand side), then the field solve by plain GMRES(30) from E^n to
-    1e-8, timed separately.  Takes minutes on the 3D workloads."""
+def _oracle_full_grid(wname):
+    """The cpu_baseline leg on the whole grid of a workload: the FP64 oracle,
+    on one core, runs the deposit and grid pass of the initial state (lab and
+    comoving deposits, bulk velocity and its filter, E_M, J_eff, the LF
+    coefficients and the right-hand side), then the field solve by plain
+    GMRES(30) from E^n to 1e-8, timed separately.  Takes minutes on the 3D
+    workloads."""
     import oracle as O
     import synth
     wl = synth.workloads()[wname]
@@ -164,16 +165,19 @@ def oracle_full_solve(wname):
     log(f"oracle deposit and grid pass {t1 - t0:.1f} s")
     _, its, rel = O.gmres(G, P, dep["Mt"], kE, b, E, tol=1e-8, maxit=5000, restart=30)
     t2 = time.perf_counter()
-    return {"oracle_full_solve": {"workload": wname, "nodes": O.nnodes(G), "particles": npart,
+    return {"cpu_baseline_full_grid": {"workload": wname, "nodes": O.nnodes(G), "particles": npart,
                                   "deposit_and_grid_pass_s": round(t1 - t0, 2), "gmres_s": round(t2 - t1, 2),
                                   "gmres_iterations": its, "relres": rel, "tol": 1e-8, "cores": 1,
                                   "cpu_model": cpu_model(), "kind": "oracle, single-threaded C, gcc -O2"}}
 
 
-def cpu_baseline(wname, box, procs):
+def cpu_baseline(wname, box, procs, full_grid=False):
     """The FP64 C oracle, as it stands, timed on bounded samples of the same
     workload: one process (one core), then `procs` processes at once on
-    independent sub-boxes (all cores, aggregate rate)."""
+    independent sub-boxes (all cores, aggregate rate).  full_grid: instead,
+    its deposit and GMRES solve on the workload's whole grid, one core."""
+    if full_grid:
+        return _oracle_full_grid(wname)
     import multiprocessing as mp
     os.environ.setdefault("OMP_NUM_THREADS", "1")
     n1, t1 = _oracle_sample((wname, box, 0))
@@ -361,9 +365,9 @@ def main():
                          "per step to PATH: phase times, GMRES iterations and residual, FP64 energies, momenta, "
                          "Gauss residual, moves")
     ap.add_argument("--metrics-steps", type=int, default=10)
-    ap.add_argument("--oracle-full-solve", action="store_true",
-                    help="only time the FP64 oracle's deposit and plain GMRES solve on the whole grid of --workload "
-                         "(one core, no GPU) and exit")
+    ap.add_argument("--cpu-baseline-full-grid", action="store_true",
+                    help="only run the CPU-baseline leg on the whole grid of --workload: the FP64 oracle's deposit "
+                         "and plain GMRES solve, one core, no GPU; print its record and exit")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain device copy of 4 GiB (reference for the HBM byte counters) and exit")
     args = ap.parse_args()
@@ -371,8 +375,8 @@ def main():
         print(f"bench.py runs on one GPU only: there is no multi-GPU path (got --gpus {args.gpus})", file=sys.stderr)
         sys.exit(2)
 
-    if args.oracle_full_solve:
-        print(json.dumps(oracle_full_solve(args.workload)), flush=True)
+    if args.cpu_baseline_full_grid:
+        print(json.dumps(cpu_baseline(args.workload, 0, 1, full_grid=True)), flush=True)
         return
 
     import torch
