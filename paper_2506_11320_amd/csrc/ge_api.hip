@@ -305,13 +305,13 @@ int ge_create(const ge_grid* grid, const ge_params* params, void* hip_stream, ge
   c->scan_nblocks = (N + 1023) / 1024;
   if (!rc) rc = dalloc(c, &c->scan_blocks, sizeof(int32_t) * (c->scan_nblocks + 1));
   if (!rc) rc = dalloc(c, &c->V, sizeof(double) * 3 * N * (c->kr_m + 1));
-  if (!rc) rc = dalloc(c, &c->hdev, sizeof(double) * 256);
-  if (!rc && hipHostMalloc((void**)&c->hhost, sizeof(double) * 256, hipHostMallocDefault) != hipSuccess) {
+  if (!rc) rc = dalloc(c, &c->hdev, sizeof(double) * 1024);
+  if (!rc && hipHostMalloc((void**)&c->hhost, sizeof(double) * 1024, hipHostMallocDefault) != hipSuccess) {
     c->hhost = nullptr;
     (void)hipGetLastError();
     rc = ge_fail(c, GE_ERR_OOM, "pinned host buffer allocation failed");
   }
-  if (!rc) rc = dalloc(c, &c->partials, sizeof(double) * 16 * 512);  // 16 dots x 512 blocks
+  if (!rc) rc = dalloc(c, &c->partials, sizeof(double) * 32 * 512);  // up to 32 dots x 512 blocks
   if (!rc) rc = dalloc(c, &c->flags, sizeof(int) * GE_FL_COUNT);
   if (!rc) rc = ge_noalloc_setup(c);
   if (rc) {
@@ -367,6 +367,7 @@ void ge_destroy(ge_ctx* c) {
     if (c->ev[k]) (void)hipEventDestroy(c->ev[k]);
   ge_cnn_free(c);
   dfree(c->Zb);
+  dfree(c->Ub);
   delete c;
 }
 

@@ -235,6 +235,7 @@ struct ge_ctx {
   int n_cu;     // compute units of the device (persistent launches)
   int kr_last;  // Arnoldi vectors built in the last GMRES cycle
   double *V, *Zp, *kw, *kr, *kx, *hdev, *partials, *scal;
+  double* Ub;     // GMRES candidate basis (delayed CGS2), allocated by the first solve
   double* hhost;  // pinned host copy of hdev (per-iteration read-backs of the solve)
   int64_t nred_blocks;
   int* flags;            // GE_FL_COUNT ints (see GE_FL_*)

@@ -1,10 +1,13 @@
 // Restarted GMRES in FP64 for the implicit E system.  The Arnoldi basis is
-// orthogonalised by classical Gram-Schmidt applied twice (CGS2): each pass is
-// one fused multi-dot (block partial sums, reduced in a fixed order, so every
-// run gives the same bits) and one fused multi-axpy; for up to 16 basis
-// vectors the first pass's update and the second pass's dots share one read
-// of the basis, and the second update carries the norm.  The Hessenberg column
-// travels to the host once per iteration for the Givens update.
+// orthogonalised by classical Gram-Schmidt applied twice (CGS2).  For restart
+// lengths up to 32 the second pass of each vector is delayed into the next
+// step's first pass (two reads of the basis per step, no separate
+// normalisation; see the delayed-CGS2 section below); longer restarts run the
+// plain CGS2 step, where each pass is one fused multi-dot and one fused
+// multi-axpy and, for up to 16 basis vectors, the first pass's update and the
+// second pass's dots share one read of the basis.  Dot products are block
+// partial sums reduced in a fixed order, so every run gives the same bits.
+// The Hessenberg column travels to the host once per iteration.
 #include <chrono>
 #include <cmath>
 #include <vector>
@@ -168,6 +171,122 @@ __global__ void k_sum2(double* __restrict__ a, const double* __restrict__ b, int
   if (i < nv) a[i] += b[i];
 }
 
+// ---------------------------------------------------------------- delayed CGS2
+// Arnoldi with the second Gram-Schmidt pass of each vector delayed into the
+// next step's first pass (one read of the basis per pass instead of two).
+// Step j holds the final orthonormal basis V_0 .. V_{j-1} and the candidate
+// U_j = nrm_j u_j (u_j: the new direction after one projection, nrm_j its
+// norm); z_j = u_j (or its preconditioned image) and Y = nrm_j A z_j.
+//   pass A: s = V^T u_j, t = V^T A z_j, alpha = u_j . u_j, tau = u_j . A z_j
+//   v_j = (u_j - V s) / rho, rho^2 = alpha - s . s   (the delayed second pass)
+//   h_{<j,j} = t, h_jj = (tau - s . t) / rho          (first pass of A z_j)
+//   pass B: V_j = v_j, U_{j+1} = A z_j - V t - h_jj v_j, and its squared norm
+// The previous column is completed with s and rho (the relation A z_{j-1} =
+// V h + h_{j,j-1} u_j rewritten in v_j).
+
+// Pass A: rows i < NVC of part hold V_i . u, rows NVC + i hold V_i . y, and
+// with TAIL the last two rows u . u and u . y (block partials, KRED blocks).
+template <int NVC, bool TAIL>
+__global__ __launch_bounds__(KB) void k_dc_dots(const double* __restrict__ V, int64_t ld, const double* __restrict__ u,
+                                                const double* __restrict__ y, int64_t n, double* __restrict__ part) {
+  constexpr int R = 2 * NVC + (TAIL ? 2 : 0);
+  __shared__ double sh[R][KB];
+  double a[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) a[r] = 0;
+  for (int64_t k = blockIdx.x * (int64_t)KB + threadIdx.x; k < n; k += (int64_t)gridDim.x * KB) {
+    const double uk = u[k], yk = y[k];
+#pragma unroll
+    for (int i = 0; i < NVC; ++i) {
+      const double v = V[i * ld + k];
+      a[i] += v * uk;
+      a[NVC + i] += v * yk;
+    }
+    if (TAIL) {
+      a[2 * NVC] += uk * uk;
+      a[2 * NVC + 1] += uk * yk;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) sh[r][threadIdx.x] = a[r];
+  __syncthreads();
+  for (int st = KB / 2; st > 0; st >>= 1) {
+    if (threadIdx.x < st)
+#pragma unroll
+      for (int r = 0; r < R; ++r) sh[r][threadIdx.x] += sh[r][threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x < R) part[threadIdx.x * KRED + blockIdx.x] = sh[threadIdx.x][0];
+}
+
+// Coefficients of step j in a fixed order (one thread).  D: V^T U_j (j),
+// V^T Y (j), U_j . U_j, U_j . Y; *nrm2 = |U_j|^2.  C: s_i / rho (j), t_i (j),
+// then 1 / (nrm rho), 1 / nrm, h_jj, rho, nrm.
+__global__ void k_dc_coef(int j, const double* __restrict__ D, const double* __restrict__ nrm2, double* __restrict__ C) {
+  if (threadIdx.x != 0) return;
+  const double nrm = sqrt(*nrm2), inv = 1.0 / nrm;
+  double ss = 0, st = 0;
+  for (int i = 0; i < j; ++i) {
+    const double si = D[i] * inv, ti = D[j + i] * inv;
+    ss += si * si;
+    st += si * ti;
+  }
+  const double al = D[2 * j] * inv * inv, ta = D[2 * j + 1] * inv * inv;
+  const double r2 = al - ss;
+  const double rho = sqrt(r2 > 0 ? r2 : 0.0);  // 0: breakdown, reported through the non-finite coefficients
+  for (int i = 0; i < j; ++i) {
+    C[i] = D[i] * inv / rho;
+    C[j + i] = D[j + i] * inv;
+  }
+  C[2 * j] = inv / rho;
+  C[2 * j + 1] = inv;
+  C[2 * j + 2] = (ta - st) / rho;
+  C[2 * j + 3] = rho;
+  C[2 * j + 4] = nrm;
+}
+
+// Pass B: v = cu U_j - sum_i cs_i V_i (into vout), w = cy Y - sum_i ct_i V_i
+// - chv v (into wout), part[b] = block b's share of w . w.
+template <int NV>
+__global__ __launch_bounds__(KB) void k_dc_update(const double* __restrict__ V, int64_t ld, const double* __restrict__ u,
+                                                  const double* __restrict__ y, const double* __restrict__ C, int64_t n,
+                                                  double* __restrict__ vout, double* __restrict__ wout,
+                                                  double* __restrict__ part) {
+  __shared__ double cs[NV > 0 ? NV : 1], ct[NV > 0 ? NV : 1], sc[3];
+  __shared__ double sh[KB];
+  if (threadIdx.x < NV) {
+    cs[threadIdx.x] = C[threadIdx.x];
+    ct[threadIdx.x] = C[NV + threadIdx.x];
+  }
+  if (threadIdx.x < 3) sc[threadIdx.x] = C[2 * NV + threadIdx.x];
+  __syncthreads();
+  const double cu = sc[0], cy = sc[1], chv = sc[2];
+  double acc = 0;
+  for (int64_t k = blockIdx.x * (int64_t)KB + threadIdx.x; k < n; k += (int64_t)gridDim.x * KB) {
+    double v[NV > 0 ? NV : 1];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) v[i] = V[i * ld + k];
+    double sv = 0, sw = 0;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      sv += cs[i] * v[i];
+      sw += ct[i] * v[i];
+    }
+    const double vk = cu * u[k] - sv;
+    const double wk = cy * y[k] - sw - chv * vk;
+    vout[k] = vk;
+    wout[k] = wk;
+    acc += wk * wk;
+  }
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int st = KB / 2; st > 0; st >>= 1) {
+    if (threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
 inline dim3 vgrid(int64_t n) {
   int64_t b = (n + KB - 1) / KB;
   return dim3((unsigned)(b < 8192 ? b : 8192));
@@ -215,9 +334,229 @@ static int cgs2_fused(ge_ctx* c, double* w, const double* V, int64_t ld, int nv,
   return GE_OK;
 }
 
+// Layout of the small device buffer hdev (mirrored by the pinned hhost) for
+// the delayed-CGS2 cycle, after the part the CGS2 cycle uses.
+constexpr int DC_MAX = 32;  // restart lengths up to this run the delayed-CGS2 cycle
+constexpr int DOFF = 256, COFF = 384, NOFF = 520;
+
+// Pass A of step j into D: D[0, j) = V^T u, D[j, 2j) = V^T y, D[2j] = u . u,
+// D[2j + 1] = u . y (the basis in chunks of 8 vectors; u and y with the last).
+static int dc_dots(ge_ctx* c, const double* V, int64_t ld, int j, const double* u, const double* y, int64_t n,
+                   double* D) {
+  double* part = c->partials;
+  if (j == 0) {
+    hipLaunchKernelGGL((k_dc_dots<0, true>), dim3(KRED), dim3(KB), 0, c->stream, V, ld, u, y, n, part);
+    hipLaunchKernelGGL(k_reduce, dim3(2), dim3(KB), 0, c->stream, part, D, nullptr);
+  }
+  for (int c0 = 0; c0 < j; c0 += 8) {
+    const int k = j - c0 < 8 ? j - c0 : 8;
+    const bool tail = c0 + k == j;
+    const double* Vc = V + (int64_t)c0 * ld;
+    switch (2 * k + (tail ? 1 : 0)) {
+#define DD(K)                                                                                                  \
+  case 2 * K:                                                                                                  \
+    hipLaunchKernelGGL((k_dc_dots<K, false>), dim3(KRED), dim3(KB), 0, c->stream, Vc, ld, u, y, n, part);      \
+    break;                                                                                                     \
+  case 2 * K + 1:                                                                                              \
+    hipLaunchKernelGGL((k_dc_dots<K, true>), dim3(KRED), dim3(KB), 0, c->stream, Vc, ld, u, y, n, part);       \
+    break;
+      DD(1) DD(2) DD(3) DD(4) DD(5) DD(6) DD(7) DD(8)
+#undef DD
+    }
+    hipLaunchKernelGGL(k_reduce, dim3(k), dim3(KB), 0, c->stream, part, D + c0, nullptr);
+    hipLaunchKernelGGL(k_reduce, dim3(k), dim3(KB), 0, c->stream, part + (int64_t)k * KRED, D + j + c0, nullptr);
+    if (tail) hipLaunchKernelGGL(k_reduce, dim3(2), dim3(KB), 0, c->stream, part + (int64_t)2 * k * KRED, D + 2 * j, nullptr);
+  }
+  GE_HIP(c, hipGetLastError());
+  return GE_OK;
+}
+
+// Pass B of step j (coefficients C on the device): vout = v_j, wout =
+// U_{j+1}, *nrm2 = |U_{j+1}|^2.
+static int dc_update(ge_ctx* c, const double* V, int64_t ld, int j, const double* u, const double* y,
+                     const double* C, int64_t n, double* vout, double* wout, double* nrm2) {
+  double* part = c->partials;
+  switch (j) {
+#define DU(K)                                                                                                      \
+  case K:                                                                                                          \
+    hipLaunchKernelGGL((k_dc_update<K>), dim3(KRED), dim3(KB), 0, c->stream, V, ld, u, y, C, n, vout, wout, part); \
+    break;
+    DU(0) DU(1) DU(2) DU(3) DU(4) DU(5) DU(6) DU(7) DU(8) DU(9) DU(10) DU(11) DU(12) DU(13) DU(14) DU(15)
+    DU(16) DU(17) DU(18) DU(19) DU(20) DU(21) DU(22) DU(23) DU(24) DU(25) DU(26) DU(27) DU(28) DU(29) DU(30)
+    DU(31)
+#undef DU
+    default: return ge_fail(c, GE_ERR_ARG, "delayed Gram-Schmidt takes at most 32 vectors");
+  }
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(KB), 0, c->stream, part, nrm2, nullptr);
+  GE_HIP(c, hipGetLastError());
+  return GE_OK;
+}
+
+// min |beta e1 - H y| over the first k columns of the unrotated Hessenberg
+// H ((m + 1) x m, row-major) by Givens rotations in column order: returns the
+// residual norm and, when ys is given, the solution y (k values).
+static double hess_lsq(const std::vector<double>& H, int m, int k, double beta, double* ys) {
+  std::vector<double> R((size_t)(k + 1) * (k > 0 ? k : 1)), cs(k > 0 ? k : 1), sn(k > 0 ? k : 1), g(k + 1, 0.0);
+  for (int i = 0; i <= k; ++i)
+    for (int j = 0; j < k; ++j) R[(size_t)i * k + j] = H[(size_t)i * m + j];
+  g[0] = beta;
+  for (int j = 0; j < k; ++j) {
+    for (int i = 0; i < j; ++i) {
+      const double a0 = cs[i] * R[(size_t)i * k + j] + sn[i] * R[(size_t)(i + 1) * k + j];
+      const double a1 = -sn[i] * R[(size_t)i * k + j] + cs[i] * R[(size_t)(i + 1) * k + j];
+      R[(size_t)i * k + j] = a0;
+      R[(size_t)(i + 1) * k + j] = a1;
+    }
+    const double a = R[(size_t)j * k + j], b = R[(size_t)(j + 1) * k + j];
+    const double den = std::sqrt(a * a + b * b);
+    cs[j] = den > 0 ? a / den : 1.0;
+    sn[j] = den > 0 ? b / den : 0.0;
+    R[(size_t)j * k + j] = den;
+    R[(size_t)(j + 1) * k + j] = 0.0;
+    g[j + 1] = -sn[j] * g[j];
+    g[j] = cs[j] * g[j];
+  }
+  if (ys)
+    for (int i = k - 1; i >= 0; --i) {
+      double t = g[i];
+      for (int l = i + 1; l < k; ++l) t -= R[(size_t)i * k + l] * ys[l];
+      ys[i] = t / R[(size_t)i * k + i];
+    }
+  return std::fabs(g[k]);
+}
+
 static int precond_apply(ge_ctx* c, int precond, const double* x, double* y, int64_t n) {
   if (precond == GE_PC_JACOBI) return ge_launch_jacobi_apply(c, x, y);
   GE_HIP(c, hipMemcpyAsync(y, x, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
+  return GE_OK;
+}
+
+// Restart cycles of (flexible) GMRES with the delayed-CGS2 Arnoldi process.
+// The update directions are the candidates U_j themselves (no
+// preconditioner), their preconditioned images (network: Zb_j = nrm_j
+// M(u_j)), or D^-1 applied to their combination (Jacobi); the last column of
+// a cycle keeps its one-pass coefficients, and every cycle starts from the
+// true residual, which decides convergence.
+static int gmres_dcgs(ge_ctx* c, double tol, int maxit, int m, double bref, double cnn_scale, int& precond, int& it,
+                      int& restarts, int& conv, double& rel, int& fallback) {
+  const int64_t n = 3 * c->G.N;
+  int rc;
+  if (!c->Ub) {
+    if (hipMalloc((void**)&c->Ub, sizeof(double) * n * (DC_MAX + 1)) != hipSuccess) {
+      c->Ub = nullptr;
+      (void)hipGetLastError();
+      return ge_fail(c, GE_ERR_OOM, "GMRES candidate basis allocation failed");
+    }
+  }
+  double* x = c->Eth;
+  double* V = c->V;
+  double* U = c->Ub;
+  double* Y = c->kw;
+  double* z = c->Zp;
+  double* hd = c->hdev;
+  double* hh = c->hhost;
+  double* D = hd + DOFF;
+  double* C = hd + COFF;
+  double* nrm2 = hd + NOFF;
+  std::vector<double> H((size_t)(m + 1) * m), nrm(m + 1), yv(m);
+  while (true) {
+    // r = b - A x into U_0, |r|^2
+    if ((rc = ge_launch_apply_A(c, x, U))) return rc;
+    hipLaunchKernelGGL(k_residual, vgrid(n), dim3(KB), 0, c->stream, U, c->rhs, n);
+    if ((rc = multidot(c, U, n, 1, U, n, nrm2))) return rc;
+    GE_HIP(c, hipMemcpyAsync(hh + NOFF, nrm2, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    GE_HIP(c, hipStreamSynchronize(c->stream));
+    const double beta = std::sqrt(hh[NOFF]);
+    if (!std::isfinite(beta)) return ge_fail(c, GE_ERR_NONFINITE, "non-finite residual in GMRES");
+    const double rel_prev = rel;
+    rel = beta / bref;
+    if (rel <= tol) { conv = 1; break; }
+    if (it >= maxit) break;
+    if (precond == GE_PC_CNN && restarts > 0 && rel > 0.5 * rel_prev) {
+      // a whole flexible cycle gained less than a factor 2: the network does
+      // not help on this system; finish with plain GMRES from here
+      precond = GE_PC_NONE;
+      fallback = 1;
+    }
+    std::fill(H.begin(), H.end(), 0.0);
+    nrm[0] = beta;
+    int k = 0;
+    bool abandon = false;
+    for (int j = 0; j < m && it < maxit; ++j) {
+      double* Uj = U + (int64_t)j * n;
+      const double* av_in = Uj;
+      if (precond == GE_PC_CNN) {
+        double* zj = c->Zb + (int64_t)j * n;
+        if ((rc = ge_cnn_apply_grid(c, Uj, zj, cnn_scale / nrm[j]))) return rc;
+        av_in = zj;
+      } else if (precond != GE_PC_NONE) {
+        if ((rc = precond_apply(c, precond, Uj, z, n))) return rc;
+        av_in = z;
+      }
+      if ((rc = ge_launch_apply_A(c, av_in, Y))) return rc;
+      if ((rc = dc_dots(c, V, n, j, Uj, Y, n, D))) return rc;
+      hipLaunchKernelGGL(k_dc_coef, dim3(1), dim3(64), 0, c->stream, j, D, nrm2, C);
+      if ((rc = dc_update(c, V, n, j, Uj, Y, C, n, V + (int64_t)j * n, U + (int64_t)(j + 1) * n, nrm2))) return rc;
+      GE_HIP(c, hipMemcpyAsync(hh + COFF, C, sizeof(double) * (NOFF - COFF + 1), hipMemcpyDeviceToHost, c->stream));
+      GE_HIP(c, hipStreamSynchronize(c->stream));
+      ++it;
+      const double* cf = hh + COFF;
+      const double hjj = cf[2 * j + 2], rho = cf[2 * j + 3], nn = std::sqrt(hh[NOFF]);
+      bool finite = std::isfinite(hjj) && std::isfinite(rho) && std::isfinite(nn);
+      for (int i = 0; i < 2 * j; ++i) finite = finite && std::isfinite(cf[i]);
+      if (!finite && precond == GE_PC_CNN) {
+        // the learned preconditioner produced NaN/Inf: drop this cycle and
+        // continue with plain GMRES from the current iterate
+        precond = GE_PC_NONE;
+        fallback = 1;
+        abandon = true;
+        break;
+      }
+      if (!finite) return ge_fail(c, GE_ERR_NONFINITE, "non-finite Arnoldi vector");
+      if (rho < 0.5) break;  // the candidate lies (nearly) in the basis: close the cycle at column j - 1
+      // column j - 1 in the final basis: u_j = V s + rho v_j
+      if (j > 0) {
+        const double hp = H[(size_t)j * m + j - 1];
+        for (int i = 0; i < j; ++i) H[(size_t)i * m + j - 1] += hp * cf[i] * rho;
+        H[(size_t)j * m + j - 1] = hp * rho;
+      }
+      for (int i = 0; i < j; ++i) H[(size_t)i * m + j] = cf[j + i];
+      H[(size_t)j * m + j] = hjj;
+      H[(size_t)(j + 1) * m + j] = nn;
+      nrm[j + 1] = nn;
+      k = j + 1;
+      if (hess_lsq(H, m, k, beta, nullptr) <= tol * bref || nn == 0.0) break;
+    }
+    if (abandon) continue;
+    if (k == 0) return ge_fail(c, GE_ERR_NONFINITE, "GMRES breakdown at the first Arnoldi step");
+    c->kr_last = k;
+    hess_lsq(H, m, k, beta, yv.data());
+    bool yfinite = true;
+    for (int i = 0; i < k; ++i) yfinite = yfinite && std::isfinite(yv[i]);
+    if (!yfinite) {
+      // singular least-squares system: only a preconditioner that maps some
+      // u_j to zero (or a null direction of A) gets here
+      if (precond != GE_PC_CNN) return ge_fail(c, GE_ERR_NONFINITE, "singular GMRES least-squares system");
+      precond = GE_PC_NONE;
+      fallback = 1;
+      continue;
+    }
+    double* yc = hh + 192;  // update coefficients y_j / nrm_j (the directions are nrm_j times unit)
+    for (int i = 0; i < k; ++i) yc[i] = yv[i] / nrm[i];
+    GE_HIP(c, hipMemcpyAsync(hd + 192, yc, sizeof(double) * k, hipMemcpyHostToDevice, c->stream));
+    if (precond == GE_PC_NONE) {
+      hipLaunchKernelGGL(k_multiaxpy, vgrid(n), dim3(KB), 0, c->stream, x, U, n, k, hd + 192, 1.0, n);
+    } else if (precond == GE_PC_CNN) {
+      hipLaunchKernelGGL(k_multiaxpy, vgrid(n), dim3(KB), 0, c->stream, x, c->Zb, n, k, hd + 192, 1.0, n);
+    } else {
+      GE_HIP(c, hipMemsetAsync(Y, 0, sizeof(double) * n, c->stream));
+      hipLaunchKernelGGL(k_multiaxpy, vgrid(n), dim3(KB), 0, c->stream, Y, U, n, k, hd + 192, 1.0, n);
+      if ((rc = precond_apply(c, precond, Y, z, n))) return rc;
+      hipLaunchKernelGGL(k_add, vgrid(n), dim3(KB), 0, c->stream, x, z, n);
+    }
+    GE_HIP(c, hipGetLastError());
+    ++restarts;
+  }
   return GE_OK;
 }
 
@@ -255,10 +594,13 @@ int ge_gmres(ge_ctx* c, double tol, int maxit, int m, int precond, ge_solve_repo
   double bnorm = std::sqrt(hh[128]);
   if (!(bnorm >= 0) || std::isinf(bnorm)) return ge_fail(c, GE_ERR_NONFINITE, "non-finite right-hand side");
   const double bref = bnorm > 0 ? bnorm : 1.0;
-  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), s(m + 1);
-  double* y = hh + 192;  // host side of hd[192, 192 + m), m <= 64
   int it = 0, restarts = 0, conv = 0;
   double rel = 0;
+  if (m <= DC_MAX) {
+    if ((rc = gmres_dcgs(c, tol, maxit, m, bref, cnn_scale, precond, it, restarts, conv, rel, fallback))) return rc;
+  } else {
+  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), s(m + 1);
+  double* y = hh + 192;  // host side of hd[192, 192 + m), m <= 64
   while (true) {
     // r = b - A x, beta = ||r||
     if ((rc = ge_launch_apply_A(c, x, V))) return rc;
@@ -373,6 +715,7 @@ int ge_gmres(ge_ctx* c, double tol, int maxit, int m, int precond, ge_solve_repo
     }
     GE_HIP(c, hipGetLastError());
     ++restarts;
+  }
   }
   if (rep) {
     rep->iterations = it;
