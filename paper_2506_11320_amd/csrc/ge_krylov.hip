@@ -252,15 +252,18 @@ __global__ __launch_bounds__(KB) void k_dc_update(const double* __restrict__ V, 
                                                   const double* __restrict__ y, const double* __restrict__ C, int64_t n,
                                                   double* __restrict__ vout, double* __restrict__ wout,
                                                   double* __restrict__ part) {
-  __shared__ double cs[NV > 0 ? NV : 1], ct[NV > 0 ? NV : 1], sc[3];
   __shared__ double sh[KB];
-  if (threadIdx.x < NV) {
-    cs[threadIdx.x] = C[threadIdx.x];
-    ct[threadIdx.x] = C[NV + threadIdx.x];
+  // the coefficients are the same for every thread: wave-uniform scalar
+  // loads, so that all NV basis loads of an element are issued together
+  typedef const __attribute__((address_space(4))) double* cdp;
+  const cdp cc = reinterpret_cast<cdp>(reinterpret_cast<uintptr_t>(C));
+  double cs[NV > 0 ? NV : 1], ct[NV > 0 ? NV : 1];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    cs[i] = cc[i];
+    ct[i] = cc[NV + i];
   }
-  if (threadIdx.x < 3) sc[threadIdx.x] = C[2 * NV + threadIdx.x];
-  __syncthreads();
-  const double cu = sc[0], cy = sc[1], chv = sc[2];
+  const double cu = cc[2 * NV], cy = cc[2 * NV + 1], chv = cc[2 * NV + 2];
   double acc = 0;
   for (int64_t k = blockIdx.x * (int64_t)KB + threadIdx.x; k < n; k += (int64_t)gridDim.x * KB) {
     double v[NV > 0 ? NV : 1];
