@@ -376,6 +376,7 @@ __global__ __launch_bounds__(64) void k_push(DGrid G, PushArgs<T> A) {
   __shared__ int s_start[32], s_pre[32];
   __shared__ int s_mark[128];
   __shared__ T s_fc[48];
+  __shared__ uint64_t s_dm[64];  // lane masks per direction, two slots
   const int lane = threadIdx.x;
   // one wavefront (one workgroup) per cell; the cell is uniform over the
   // wave: keep its index (and coordinates) scalar
@@ -430,17 +431,28 @@ __global__ __launch_bounds__(64) void k_push(DGrid G, PushArgs<T> A) {
     int d0 = 31, d1 = 31;
     if (a0) d0 = push_one<T, DIM>(f0, v0, fc, A.beta, A.dtx, A.lo, A.hi, stuck, mv, G, hx);
     if (a1) d1 = push_one<T, DIM>(f1, v1, fc, A.beta, A.dtx, A.lo, A.hi, stuck, mv, G, hx);
-    const DirStats q0 = dir_stats(a0, d0, lane);
-    // the second slot is empty in every lane of a cell of at most 64
-    // particles (a wave-uniform test): its statistics are zero then
-    const DirStats q1 = total > 64 ? dir_stats(a1, d1, lane) : DirStats{0, 0};
-    cnt = q0.count_k + q1.count_k;
+    // lanes sharing a direction: each lane ORs its bit into the 64-bit mask of
+    // its direction, one mask per direction and slot (s_dm[slot][dir]).  OR
+    // does not depend on the order in which the lanes' updates land, so the
+    // masks are exactly the sets of lanes; direction 31 (no particle) is
+    // never set and reads as empty.
+    s_dm[lane] = 0;
+    wave_sync();
+    const uint64_t bit = 1ull << lane;
+    if (a0) __hip_atomic_fetch_or(&s_dm[d0], bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+    if (a1) __hip_atomic_fetch_or(&s_dm[32 + d1], bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+    wave_sync();
+    const uint64_t same0 = s_dm[d0 & 31], same1 = s_dm[32 + (d1 & 31)];
+    // lane k <= GE_DIR_GONE: the count of direction k in each slot
+    const int c0k = lane <= GE_DIR_GONE ? __popcll(s_dm[lane & 31]) : 0;
+    const int c1k = lane <= GE_DIR_GONE ? __popcll(s_dm[32 + (lane & 31)]) : 0;
+    cnt = c0k + c1k;
     dir_off = excl_scan(cnt);
     const int b0 = __shfl(dir_off, d0 & 31, 64);
-    const int b1 = __shfl(dir_off + q0.count_k, d1 & 31, 64);
+    const int b1 = __shfl(dir_off + c0k, d1 & 31, 64);
     const uint64_t lt = lanemask_lt(lane);
-    if (a0) store_particle(A, base + b0 + __popcll(q0.same & lt), f0, v0, w0);
-    if (a1) store_particle(A, base + b1 + __popcll(q1.same & lt), f1, v1, w1);
+    if (a0) store_particle(A, base + b0 + __popcll(same0 & lt), f0, v0, w0);
+    if (a1) store_particle(A, base + b1 + __popcll(same1 & lt), f1, v1, w1);
   } else {
     int running = 0;
 #pragma clang loop unroll(disable)
