@@ -857,7 +857,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
     v4 aX[NRB], aM0[NRB];
 #pragma unroll
     for (int rb = 0; rb < NRB; ++rb) aX[rb] = aM0[rb] = v4{0, 0, 0, 0};
-    for (int s = 0; s < A.nsp; ++s) {
+    // one species: p0, p1 hold its particles 0..127 when 'fast' (species 0
+    // and 1, passed as compile-time register operands at each call)
+    auto species = [&](const int s, const PState<T>& p0, const PState<T>& p1, const bool fast) {
       const DepSpecies<T>& S = A.sp[s];
       const int total = L.total[s];
       // the MFMA sums each chunk of up to 64 particles from zero; the chunk
@@ -998,12 +1000,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
         }
         ++nchunk;
       };
-      // particles 0..127 of species 0 and 1 come from the prefetched registers
-      // (selected with compile-time indices: a dynamic index would send the
-      // arrays to scratch memory); the rest are loaded here
-      const int nfast = s < 2 ? min(total, 128) : 0;
-      if (nfast > 0) chunk(s == 0 ? P[0][0] : P[1][0], 0);
-      if (nfast > 64) chunk(s == 0 ? P[0][1] : P[1][1], 64);
+      // particles 0..127 of species 0 and 1 come from the prefetched registers;
+      // the rest are loaded here
+      const int nfast = fast ? min(total, 128) : 0;
+      if (nfast > 0) chunk(p0, 0);
+      if (nfast > 64) chunk(p1, 64);
       for (int t0 = nfast; t0 < total; t0 += 64) {
         PState<T> q;
         const int t = t0 + lane;
@@ -1023,7 +1024,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
           const int r = 16 * rb + M::row(lane, i);
           if (col == 15 && r < NR) lin[r * LW + 7 + s] = qs * val;
         }
-    }
+    };
+    // species 0 and 1 with their prefetched particles as fixed registers (a
+    // run-time choice between the two would copy them into common registers,
+    // and a dynamic index would send the arrays to scratch memory)
+    species(0, P[0][0], P[0][1], true);
+    if (A.nsp > 1) species(1, P[1][0], P[1][1], true);
+    for (int s = 2; s < A.nsp; ++s) species(s, P[0][0], P[0][0], false);
     // linear sums to LDS for the corner sums (rows < NR, columns 9..15)
 #pragma unroll
     for (int rb = 0; rb < NRB; ++rb)
