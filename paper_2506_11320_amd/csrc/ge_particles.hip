@@ -798,6 +798,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
   typedef typename M::v4 v4;
   using C = DepCfg<T, DIM>;
   constexpr int NC = Dm<DIM>::NC, NRB = C::NRB, NR = C::NR, AW = C::AW, ST = C::ST;
+  static_assert(64 * ST >= 18 * NR + NC * (7 + GE_MAX_SPECIES) + 3, "the staging rows hold a cell's values");
   __shared__ DepLds<T, DIM> L;
   const int lane = threadIdx.x;
   const int64_t c = __builtin_amdgcn_readfirstlane((int)xcd_block(blockIdx.x, gridDim.x));
@@ -1014,11 +1015,16 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
       // scale this species' sums into the cell accumulators (each (row, col)
       // belongs to one lane)
       const T qs = S.q, ms = S.m, bq = S.beta * S.q, sx = col < 9 ? bq : (col < 12 ? qs : ms);
+      // the compensation terms are exactly zero unless a third chunk was added
+      if (nchunk > 2) {
+#pragma unroll
+        for (int rb = 0; rb < NRB; ++rb) acc[rb] += cmp[rb];
+      }
 #pragma unroll
       for (int rb = 0; rb < NRB; ++rb)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          const T val = acc[rb][i] + cmp[rb][i];
+          const T val = acc[rb][i];
           aX[rb][i] += sx * val;
           aM0[rb][i] += qs * val;
           const int r = 16 * rb + M::row(lane, i);
@@ -1031,31 +1037,28 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
     species(0, P[0][0], P[0][1], true);
     if (A.nsp > 1) species(1, P[1][0], P[1][1], true);
     for (int s = 2; s < A.nsp; ++s) species(s, P[0][0], P[0][0], false);
-    // linear sums to LDS for the corner sums (rows < NR, columns 9..15)
+    // The cell's values k < QW are gathered in LDS (the staging rows are free
+    // now) and written as 4-value vectors: values 4j..4j+3 of the cell are
+    // contiguous at Qc + cq_off(4j).  First the quadratic rows of Mtilde and
+    // M0, and the linear sums (rows < NR, columns 9..15) for the corner sums.
+    T* V = L.stage;
 #pragma unroll
     for (int rb = 0; rb < NRB; ++rb)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int r = 16 * rb + M::row(lane, i);
-        if (r < NR && col >= 9) lin[r * LW + col - 9] = aX[rb][i];
-      }
-    wave_sync();
-    // write the cell: quadratic rows of Mtilde and M0, then corner sums of the
-    // linear quantities, W_a = prod_d (X_{a_d} + X_{a_d + 1})
-    T* Qc = A.cellQ + cq_index(c, 0, A.Qn);  // value k of this cell at Qc[cq_off(k)]
-    if (col < 9) {
-#pragma unroll
-      for (int rb = 0; rb < NRB; ++rb)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int r = 16 * rb + M::row(lane, i);
-          if (r < NR) {
-            Qc[cq_off(r * 9 + col)] = aX[rb][i];
-            Qc[cq_off(9 * NR + r * 9 + col)] = aM0[rb][i];
+        if (r < NR) {
+          if (col < 9) {
+            V[r * 9 + col] = aX[rb][i];
+            V[9 * NR + r * 9 + col] = aM0[rb][i];
+          } else {
+            lin[r * LW + col - 9] = aX[rb][i];
           }
         }
-    }
-    const int NK = 7 + A.nsp;
+      }
+    wave_sync();
+    // corner sums of the linear quantities, W_a = prod_d (X_{a_d} + X_{a_d + 1})
+    const int NK = 7 + A.nsp, QW = 18 * NR + NK * NC, QV = (QW + 3) >> 2;
     for (int t = lane; t < NC * NK; t += 64) {
       const int a = t % NC, k = t / NC;
       T sum = 0;
@@ -1066,8 +1069,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
         if (DIM >= 3) r += 9 * (((a >> 2) & 1) + ((b >> 2) & 1));
         sum += lin[r * LW + k];
       }
-      Qc[cq_off(18 * NR + k * NC + a)] = sum;
+      V[18 * NR + k * NC + a] = sum;
     }
+    if (lane < 4 * QV - QW) V[QW + lane] = 0;  // the rest of the last vector
+    wave_sync();
+    typedef T t4 __attribute__((ext_vector_type(4)));
+    T* Qc = A.cellQ + cq_index(c, 0, A.Qn);
+    for (int j = lane; j < QV; j += 64)
+      *reinterpret_cast<t4*>(Qc + cq_off(4 * j)) = reinterpret_cast<const t4*>(V)[j];
   }
 }
 
