@@ -655,16 +655,19 @@ template <typename T, int DIM>
 struct DepCfg {
   static constexpr int NR = Dm<DIM>::ND;
   static constexpr int NRB = Dm<DIM>::NRB;
-  // staged row of a particle: the quadratic weight factors of x (3 values)
-  // and the products of those of the other axes (NB = 3^(DIM-1) values), whose
-  // products are the NR A values (row r = factor r % 3 times product r / 3,
-  // formed when the MFMA operands are read); then the 16 B columns, padded to
-  // a multiple of 4 with ST / 4 odd (3D and 2D: 7, 1D: 5), so that the 16
-  // lanes of a 16-byte write phase hit 16 different bank groups.
+  // staged values of a particle: the quadratic weight factors of x (3
+  // values) and the products of those of the other axes (NB = 3^(DIM-1)
+  // values), whose products are the NR A values (row r = factor r % 3 times
+  // product r / 3, formed when the MFMA operands are read); then the 16 B
+  // columns.  Stored value-major, value k of particle p at k SP + p: the 16
+  // MFMA steps of one operand read lie within 64 elements of one base address,
+  // in reach of the paired LDS reads' offsets (no address arithmetic per
+  // step), and the stride SP = 66 puts the lanes of each half-wave read on
+  // distinct banks (or on one address).
   static constexpr int NB = DIM == 3 ? 9 : (DIM == 2 ? 3 : 1);
   static constexpr int AW = 3 + NB;
-  static constexpr int ST0 = (AW + 16 + 3) / 4 * 4;
-  static constexpr int ST = (ST0 / 4) % 2 ? ST0 : ST0 + 4;
+  static constexpr int NV = AW + 16;
+  static constexpr int SP = 66;
   // linear sums only (quadratic ones stay in registers): [NR][LW], the 7
   // species-summed columns then the charge of each species (odd stride)
   static constexpr int LW = 7 + GE_MAX_SPECIES;
@@ -707,19 +710,21 @@ __device__ inline RunRegs load_runs(const DGrid& G, int64_t c, const DepArgs<T>&
   return R;
 }
 
-// Per-wave LDS of the deposit: compacted run tables of the cell, the
-// run-start markers, corner values, MFMA staging, accumulators.
+// Per-wave LDS of the deposit: MFMA staging (first, at offset 0, so that a
+// lane's read addresses are its own offsets and the steps' particle offsets
+// fit the LDS reads' immediates), accumulators, compacted run tables of the
+// cell, the run-start markers, corner values.
 template <typename T, int DIM>
 struct DepLds {
+  union {  // the run-start markers are dead before the staging starts
+    int mark[2][128];
+    __attribute__((aligned(16))) T stage[DepCfg<T, DIM>::NV * DepCfg<T, DIM>::SP];
+  };
+  T acc[DepCfg<T, DIM>::NACC];
   int runs[GE_MAX_SPECIES][2][32];  // [species][start, pre][run]
   int nseg[GE_MAX_SPECIES];
   int total[GE_MAX_SPECIES];
   T fc[24];
-  union {  // the run-start markers are dead before the staging starts
-    int mark[2][128];
-    __attribute__((aligned(16))) T stage[64 * DepCfg<T, DIM>::ST];
-  };
-  T acc[DepCfg<T, DIM>::NACC];
 };
 
 // Compact the run tables R (of one cell) and find the source index of the
@@ -797,8 +802,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
   using M = Mfma<T>;
   typedef typename M::v4 v4;
   using C = DepCfg<T, DIM>;
-  constexpr int NC = Dm<DIM>::NC, NRB = C::NRB, NR = C::NR, AW = C::AW, ST = C::ST;
-  static_assert(64 * ST >= 18 * NR + NC * (7 + GE_MAX_SPECIES) + 3, "the staging rows hold a cell's values");
+  constexpr int NC = Dm<DIM>::NC, NRB = C::NRB, NR = C::NR, AW = C::AW, NV = C::NV, SP = C::SP;
+  static_assert(NV * SP >= 18 * NR + NC * (7 + GE_MAX_SPECIES) + 3, "the staging memory holds a cell's values");
   __shared__ DepLds<T, DIM> L;
   const int lane = threadIdx.x;
   const int64_t c = __builtin_amdgcn_readfirstlane((int)xcd_block(blockIdx.x, gridDim.x));
@@ -806,14 +811,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
   constexpr int LW = C::LW;
   T* lin = L.acc;  // [NR][LW]: q alpha v (3), m v (3), m w, then q_s w of each species
   const int col = lane & 15;
-  // MFMA operand reads of a step: row 4 stp + lane/16; A row col (and 16 +
-  // col) as the product of its two staged factors, B column col.  A rows past
-  // NR read other (finite) values of the row: their products land in
+  // MFMA operand reads of a step: particle 4 stp + lane/16; A row col (and
+  // 16 + col) as the product of its two staged factors, B column col.  A rows
+  // past NR read other (finite) staged values: their products land in
   // accumulator rows that are never used.
-  const int rrow = (lane >> 4) * ST, r1 = 16 + col;
-  const int rofsXa0 = rrow + col % 3, rofsXb0 = rrow + 3 + col / 3;
-  const int rofsXa1 = rrow + r1 % 3, rofsXb1 = rrow + 3 + r1 / 3;
-  const int rofsB = rrow + AW + col;
+  const int prt = lane >> 4, r1 = 16 + col;
+  const int rofsXa0 = (col % 3) * SP + prt, rofsXb0 = (3 + col / 3) * SP + prt;
+  const int rofsXa1 = (r1 % 3) * SP + prt, rofsXb1 = (3 + r1 / 3) * SP + prt;
+  const int rofsB = (AW + col) * SP + prt;
 
   // B at the corners: FP32 in scalar registers (wave-uniform loads); FP64 (twice
   // the registers) one corner per lane (lanes past the corners reload corner 0)
@@ -877,7 +882,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
         // the corner-0 position with zero velocity, so every staged value is
         // finite and the MFMA adds exact zeros for them
         const bool ok = t0 + lane < total;
-        T vals[ST];  // the A factors, then the 16 B columns
+        T vals[NV];  // the A factors, then the 16 B columns
         {
           T f[3], v[3];
 #pragma unroll
@@ -927,27 +932,29 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
           for (int k = 0; k < 3; ++k) vals[k] = X[0][k];
 #pragma unroll
           for (int k = 0; k < C::NB; ++k) vals[3 + k] = X[1][k % 3] * X[2][k / 3];
-#pragma unroll
-          for (int k = AW + 16; k < ST; ++k) vals[k] = 0;
         }
         {
-          typedef T t4 __attribute__((ext_vector_type(4)));
-          t4* row = reinterpret_cast<t4*>(L.stage + lane * ST);
+          // this lane's particle, value-major; single stores (volatile keeps
+          // them from being paired), whose 16-bit offsets reach every value
+          // from one address, where paired stores would need a new base
+          // address every two values
+          typedef volatile __attribute__((address_space(3))) T* lds_ptr;
+          const lds_ptr own = (lds_ptr)(L.stage + lane);
 #pragma unroll
-          for (int j = 0; j < ST / 4; ++j) row[j] = t4{vals[4 * j], vals[4 * j + 1], vals[4 * j + 2], vals[4 * j + 3]};
+          for (int k = 0; k < NV; ++k) own[k * SP] = vals[k];
         }
         wave_sync();
-        // groups of 4 MFMA steps (16 particles; rows past the count are
+        // groups of 4 MFMA steps (16 particles; particles past the count are
         // zero); the group count is wave-uniform, and the operands of group
-        // g + 1 are read from LDS while the MFMAs of group g run.  Row offsets
-        // are immediates of the LDS reads, the lane's column offsets are
+        // g + 1 are read from LDS while the MFMAs of group g run.  Particle
+        // offsets are immediates of the LDS reads, the lane's value offsets are
         // precomputed (rofs*).
         const int ngrp = __builtin_amdgcn_readfirstlane((min(64, total - t0) + 15) >> 4);
         T ca[2][4], cb[4];
         auto rd = [&](int g, T (&a)[2][4], T (&b)[4]) {
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
-            const T* rows = L.stage + (16 * g + 4 * i) * ST;
+            const T* rows = L.stage + (16 * g + 4 * i);
             b[i] = rows[rofsB];
             a[0][i] = rows[rofsXa0] * rows[rofsXb0];
             a[1][i] = NRB == 2 ? rows[rofsXa1] * rows[rofsXb1] : (T)0;
