@@ -296,6 +296,7 @@ int ge_create(const ge_grid* grid, const ge_params* params, void* hip_stream, ge
   if (!rc) rc = dalloc(c, &c->psi, sizeof(double) * N);
   if (!rc) rc = dalloc(c, &c->kE, sizeof(double) * 9 * N);
   if (!rc) rc = dalloc(c, &c->kB, sizeof(double) * 9 * N);
+  if (!rc && c->P.precision == GE_FP32) rc = dalloc(c, &c->kEf, sizeof(float) * 9 * N);
   if (!rc) rc = dalloc(c, &c->jac, sizeof(double) * 9 * N);
   if (!rc) rc = dalloc(c, &c->node8, es * 8 * N);
   if (!rc) rc = dalloc(c, &c->Mt, es * c->nh * 9 * N);
@@ -324,6 +325,7 @@ int ge_create(const ge_grid* grid, const ge_params* params, void* hip_stream, ge
   (void)hipMemsetAsync(c->B, 0, sizeof(double) * 3 * N, s);
   (void)hipMemsetAsync(c->kE, 0, sizeof(double) * 9 * N, s);
   (void)hipMemsetAsync(c->kB, 0, sizeof(double) * 9 * N, s);
+  if (c->kEf) (void)hipMemsetAsync(c->kEf, 0, sizeof(float) * 9 * N, s);
   (void)hipMemsetAsync(c->rho, 0, sizeof(double) * GE_MAX_SPECIES * N, s);
   (void)hipMemsetAsync(c->psi, 0, sizeof(double) * N, s);
   (void)hipMemsetAsync(c->flags, 0, sizeof(int) * GE_FL_COUNT, s);
@@ -348,6 +350,7 @@ void ge_destroy(ge_ctx* c) {
   for (auto p : f) dfree(*p);
   if (c->hhost) (void)hipHostFree(c->hhost);
   dfree(c->node8);
+  dfree(c->kEf);
   dfree(c->Mt);
   dfree(c->M0);
   dfree(c->cellQ);

@@ -269,15 +269,20 @@ __device__ inline double mc_limiter(double num, double den, double beta) {
 }
 
 // E: flux between node g and g + e_d (stored at g); ratio lagged to E^n.
+// kEf (FP32 path, else null): the same values rounded to float, which the
+// interior field operator reads (half the bytes per matvec).
 template <int DIM>
 __global__ void k_kappa_E(DGrid G, const double* __restrict__ E, const double* __restrict__ anode, double beta,
-                          double* __restrict__ kE) {
+                          double* __restrict__ kE, float* __restrict__ kEf) {
   int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (g >= G.N) return;
   const int64_t N = G.N;
   for (int d = 0; d < 3; ++d) {
     if (d >= DIM) {
-      for (int m = 0; m < 3; ++m) kE[(d * 3 + m) * N + g] = 0.0;
+      for (int m = 0; m < 3; ++m) {
+        kE[(d * 3 + m) * N + g] = 0.0;
+        if (kEf) kEf[(d * 3 + m) * N + g] = 0.0f;
+      }
       continue;
     }
     int o[3] = {0, 0, 0};
@@ -294,7 +299,9 @@ __global__ void k_kappa_E(DGrid G, const double* __restrict__ E, const double* _
     for (int m = 0; m < 3; ++m) {
       double phi = mc_limiter(E[m * N + g] - E[m * N + gm], E[m * N + gp] - E[m * N + g], beta);
       if (bx == 0) phi = 0.0;
-      kE[(d * 3 + m) * N + g] = 0.5 * (1.0 - phi) * a;
+      const double k = 0.5 * (1.0 - phi) * a;
+      kE[(d * 3 + m) * N + g] = k;
+      if (kEf) kEf[(d * 3 + m) * N + g] = (float)k;
     }
   }
 }
@@ -477,7 +484,7 @@ struct CurlCurl {
 // this kernel free of an early exit, keeps it at 65 registers per thread.
 template <typename T, int DIM>
 __global__ __launch_bounds__(256) void k_apply_A(DGrid G, const double* __restrict__ x, const T* __restrict__ Mt,
-                                                 const double* __restrict__ kE, CurlCurl K, double k2, double mcoef,
+                                                 const T* __restrict__ kE, CurlCurl K, double k2, double mcoef,
                                                  double tdt, double* __restrict__ y) {
   const int64_t t = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   const int64_t N = G.N;
@@ -515,7 +522,7 @@ __global__ __launch_bounds__(256) void k_apply_A(DGrid G, const double* __restri
       const int64_t gm = flat3(G, gx - (d == 0), gy - (d == 1), gz - (d == 2));
 #pragma unroll
       for (int m = 0; m < 3; ++m) {
-        const double kp = kE[(d * 3 + m) * N + g], km = kE[(d * 3 + m) * N + gm];
+        const double kp = (double)kE[(d * 3 + m) * N + g], km = (double)kE[(d * 3 + m) * N + gm];
         acc[m] -= tdt * G.idx[d] * (kp * (x[m * N + gp] - x0[m]) - km * (x0[m] - x[m * N + gm]));
       }
     }
@@ -861,7 +868,7 @@ int ge_launch_smooth_current(ge_ctx* c) {
 // LF coefficients of the E operator from the field E (E^n in the grid pass,
 // the first E^{n+theta} for the Picard step of the limiter)
 int ge_launch_kappa_E(ge_ctx* c, const double* E) {
-  DISPATCH_DIM(c, k_kappa_E, grid1(c->G.N), dim3(256), 0, c->stream, c->G, E, c->anode, c->P.beta_lim, c->kE);
+  DISPATCH_DIM(c, k_kappa_E, grid1(c->G.N), dim3(256), 0, c->stream, c->G, E, c->anode, c->P.beta_lim, c->kE, c->kEf);
   GE_HIP(c, hipGetLastError());
   return GE_OK;
 }
@@ -883,7 +890,8 @@ int ge_launch_grid_pass(ge_ctx* c) {
     GE_HIP(c, hipMemcpyAsync(c->Jeff, c->Jlab, sizeof(double) * 3 * N, hipMemcpyDeviceToDevice, c->stream));
     smooth_current(c);
   }
-  if (c->P.lf_E) DISPATCH_DIM(c, k_kappa_E, grid1(N), dim3(256), 0, c->stream, G, c->E, c->anode, c->P.beta_lim, c->kE);
+  if (c->P.lf_E)
+    DISPATCH_DIM(c, k_kappa_E, grid1(N), dim3(256), 0, c->stream, G, c->E, c->anode, c->P.beta_lim, c->kE, c->kEf);
   if (c->P.lf_B) DISPATCH_DIM(c, k_kappa_B, grid1(N), dim3(256), 0, c->stream, G, c->B, c->anode, c->P.beta_lim, c->kB);
   const double ctd = c->P.c * c->P.theta * c->P.dt, ftd = 4.0 * M_PI * c->P.theta * c->P.dt;
   DISPATCH_DIM(c, k_rhs, grid1(N), dim3(256), 0, c->stream, G, c->E, c->B, c->Jeff, ctd, ftd, c->rhs);
@@ -931,8 +939,10 @@ static void apply_t(ge_ctx* c, const double* x, double* y) {
   const double mcoef = 4.0 * M_PI * c->P.theta * c->P.dt / c->G.dV;
   const T* Mt = c->have_deposit ? (const T*)c->Mt : nullptr;
   const double* kE = c->P.lf_E ? c->kE : nullptr;
+  // the interior operator reads the coefficients in the matrices' type
+  const T* kEt = c->P.lf_E ? (sizeof(T) == 4 ? (const T*)(const void*)c->kEf : (const T*)(const void*)c->kE) : nullptr;
   const CurlCurl K = curl_curl_stencil(c->G);
-  hipLaunchKernelGGL((k_apply_A<T, DIM>), grid1(c->G.N), dim3(256), 0, c->stream, c->G, x, Mt, kE, K, ctd * ctd,
+  hipLaunchKernelGGL((k_apply_A<T, DIM>), grid1(c->G.N), dim3(256), 0, c->stream, c->G, x, Mt, kEt, K, ctd * ctd,
                      mcoef, c->P.theta * c->P.dt, y);
   if (walled(c->G))
     hipLaunchKernelGGL((k_apply_A_planes<T, DIM>), grid1(16 * (int64_t)c->G.n[1] * c->G.n[2]), dim3(256), 0,

@@ -222,7 +222,10 @@ struct ge_ctx {
   double *E, *B, *Eth, *Bn, *Jlab, *Jeff, *rho, *mm, *mass, *u, *utmp, *EM, *anode, *kE, *kB, *rhs, *Bnew, *ccell;
   double* psi;  // divergence-cleaning scalar at cells [N]
   // FP32 copies for particle gathers
-  void* node8;  // T[N][8] in the particle precision: E^{n+theta} (3), 0, node-averaged B^n (3), 0
+  void* node8;
+  // FP32 path: the E diffusion coefficients rounded to float, read by the
+  // interior field operator (kE stays the FP64 value of record)
+  float* kEf;  // T[N][8] in the particle precision: E^{n+theta} (3), 0, node-averaged B^n (3), 0
   // mass matrices (T) and per-cell partial sums (T)
   void *Mt, *M0, *cellQ;
   // Jacobi blocks (double [9][N], inverted 3x3 per node)
