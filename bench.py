@@ -281,13 +281,16 @@ def nn_compare(wl, args, Simulation, torch, synth):
         sim.cnn_harvest(0)
         tr = sim.cnn_train(crop=args.nn_crop, batch=args.nn_batch, iters=args.nn_iters, lr=args.nn_lr, seed=7)
         log(f"trained: {tr}")
-        # one application of the network alone (event-timed), for its MFMA rate
+        # one application of the network alone (event-timed), for its MFMA rate:
+        # the scaled form that the flexible GMRES runs (no RMS reduction, no host
+        # round trip), on a vector of RMS 1
         r0 = torch.randn((3, sim.N), dtype=torch.float64, device=sim.device)
-        sim.cnn_apply(r0)
+        z0 = torch.empty_like(r0)
+        sim.cnn_apply_scaled(r0, 1.0, z0)
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         ev0.record(sim.stream)
         for _ in range(5):
-            sim.cnn_apply(r0)
+            sim.cnn_apply_scaled(r0, 1.0, z0)
         ev1.record(sim.stream)
         ev1.synchronize()
         app_s = ev0.elapsed_time(ev1) / 5 * 1e-3

@@ -421,6 +421,14 @@ int ge_cnn_weights(ge_ctx* ctx, int set, float* host_w);
  * held (an inflow plane is left out), and z = r on the held components.
  * Synchronises. */
 int ge_cnn_apply(ge_ctx* ctx, const double* r, double* z);
+/* z = N(scale r) / scale: ge_cnn_apply with the input scale given by the
+ * caller instead of 1 / RMS(r) (the form the flexible GMRES of ge_solve uses,
+ * where the Krylov vectors' norms are known), so no reduction and no host
+ * round trip.  scale must be finite and positive (else GE_ERR_ARG); since
+ * the network is positively homogeneous, scale only sets where the BF16
+ * activations sit (scale r of RMS near 1 is what the network was trained on).
+ * Same walled-grid behaviour as ge_cnn_apply.  Asynchronous. */
+int ge_cnn_apply_scaled(ge_ctx* ctx, const double* r, double* z, double scale);
 /* Pair harvesting from converged solves: 0 = off, else an OR of
  * GE_HARVEST_SOLUTION (the pair (b - A E^n, E^{n+theta} - E^n)) and
  * GE_HARVEST_KRYLOV (the exact pairs (A v_j, v_j) of the last cycle's Arnoldi

@@ -876,6 +876,12 @@ int ge_cnn_weights(ge_ctx* c, int set, float* host_w) {
   return GE_OK;
 }
 
+int ge_cnn_apply_scaled(ge_ctx* c, const double* r, double* z, double scale) {
+  if (!c || !r || !z) return GE_ERR_ARG;
+  if (!(scale > 0.0 && scale < INFINITY)) return ge_fail(c, GE_ERR_ARG, "ge_cnn_apply_scaled: scale must be finite and positive");
+  return ge_cnn_apply_grid(c, r, z, scale);
+}
+
 int ge_cnn_apply(ge_ctx* c, const double* r, double* z) {
   if (!c || !r || !z) return GE_ERR_ARG;
   // normalise by the RMS of r (the network is positively homogeneous)

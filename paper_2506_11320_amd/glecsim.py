@@ -33,7 +33,8 @@ EXPORTS = [
     "ge_get_particles", "ge_apply_operator", "ge_diagnostics", "ge_timings", "ge_explicit_current", "ge_explicit_step",
     "ge_moves", "ge_diagnostics_noalloc", "ge_step_count", "ge_species_count", "ge_checkpoint", "ge_restore",
     "ge_inject",
-    "ge_cnn_init", "ge_cnn_size", "ge_cnn_weights", "ge_cnn_apply", "ge_cnn_harvest", "ge_cnn_add_pair",
+    "ge_cnn_init", "ge_cnn_size", "ge_cnn_weights", "ge_cnn_apply", "ge_cnn_apply_scaled", "ge_cnn_harvest",
+    "ge_cnn_add_pair",
     "ge_cnn_npairs", "ge_cnn_train", "ge_cnn_loss_grad",
 ]
 
@@ -137,6 +138,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.ge_cnn_size.argtypes = []
     L.ge_cnn_weights.argtypes = [vp, ctypes.c_int, vp]
     L.ge_cnn_apply.argtypes = [vp, vp, vp]
+    L.ge_cnn_apply_scaled.argtypes = [vp, vp, vp, ctypes.c_double]
     L.ge_cnn_harvest.argtypes = [vp, ctypes.c_int]
     L.ge_cnn_add_pair.argtypes = [vp, vp, vp]
     L.ge_cnn_npairs.argtypes = [vp]
@@ -380,6 +382,15 @@ class Simulation:
         _require(tuple(r.shape) == (3, self.N), "r: [3, N]")
         z = torch.empty_like(r)
         self._check(self.L.ge_cnn_apply(self.h, _ptr(r), _ptr(z)))
+        return z
+
+    def cnn_apply_scaled(self, r: torch.Tensor, scale: float, z: torch.Tensor = None) -> torch.Tensor:
+        r = r.to(device=self.device, dtype=torch.float64).contiguous()
+        _require(tuple(r.shape) == (3, self.N), "r: [3, N]")
+        if z is None:
+            z = torch.empty_like(r)
+        _require(tuple(z.shape) == (3, self.N) and z.dtype == torch.float64 and z.is_contiguous(), "z: [3, N] float64")
+        self._check(self.L.ge_cnn_apply_scaled(self.h, _ptr(r), _ptr(z), float(scale)))
         return z
 
     def cnn_harvest(self, flags: int = GE_HARVEST_SOLUTION):

@@ -63,6 +63,36 @@ def test_forward_matches_oracle(n):
     sim.close()
 
 
+def test_scaled_application():
+    """ge_cnn_apply_scaled(r, s) = N(s r) / s: against the BF16-rounded FP64
+    reference on the input scaled by 1/RMS (what ge_cnn_apply does), exactly
+    twice as large for (2 r, s / 2) (the network's input is then bit-identical
+    and its output divided by an exactly halved scale), and a non-positive or
+    non-finite scale is refused."""
+    print("[gpu] cnn scaled application (12, 10, 9)", flush=True)
+    from paper_2506_11320_amd import GlecsimError
+    n = (12, 10, 9)
+    N = n[0] * n[1] * n[2]
+    sim = _ctx(n)
+    sim.cnn_init(7)
+    rng = np.random.default_rng(12)
+    w = _rand_w(rng)
+    sim.cnn_set_weights(w)
+    r = rng.standard_normal((3, N)) * 3e-3
+    s = 1.0 / np.sqrt(np.mean(r * r))
+    rt = torch.from_numpy(r).to(sim.device)
+    z1 = sim.cnn_apply_scaled(rt, s).cpu().numpy()
+    ref = C.forward_apply(w.astype(np.float64), r, n, quant=True)
+    assert H.relerr(z1, ref) <= 1e-3
+    assert H.relerr(z1, sim.cnn_apply(rt).cpu().numpy()) <= 1e-3
+    z2 = sim.cnn_apply_scaled(2.0 * rt, s / 2.0).cpu().numpy()
+    assert np.array_equal(z2, 2.0 * z1)
+    for bad in (0.0, -1.0, float("nan"), float("inf")):
+        with pytest.raises(GlecsimError):
+            sim.cnn_apply_scaled(rt, bad)
+    sim.close()
+
+
 def test_forward_on_a_walled_grid():
     """On a grid with a wall at x = 0 and an inflow plane at x = L the network
     runs on the domain periodic along x over the node planes 0 .. nxp - 1 (the
