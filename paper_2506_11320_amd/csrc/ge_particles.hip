@@ -484,11 +484,17 @@ __global__ __launch_bounds__(64) void k_push(DGrid G, PushArgs<T> A) {
     if (lane <= GE_DIR_GONE && running != cnt) bad = 1;
   }
   if (lane < ND) {
-    // run (c, lane) is recorded at its destination cell
-    int cx, cy, cz;
-    unflat3(G, c, cx, cy, cz);
-    const int64_t dst = flat3(G, cx + lane % 3 - 1, DIM >= 2 ? cy + (lane / 3) % 3 - 1 : cy, DIM >= 3 ? cz + lane / 9 - 1 : cz);
-    reinterpret_cast<i2*>(A.runs_o)[dst * ND + lane] = i2{(int)(base + dir_off), cnt};
+    // run (c, lane) is recorded at its destination cell; away from the faces
+    // of the grid (a wave-uniform test) no coordinate wraps and the
+    // destination is c plus the direction's offset
+    const int ox = lane % 3 - 1, oy = DIM >= 2 ? (lane / 3) % 3 - 1 : 0, oz = DIM >= 3 ? lane / 9 - 1 : 0;
+    const bool inner = hx > 0 && hx < G.n[0] - 1 && (DIM < 2 || (hy > 0 && hy < G.n[1] - 1)) &&
+                       (DIM < 3 || (hz > 0 && hz < G.n[2] - 1));
+    const i2 run = i2{(int)(base + dir_off), cnt};
+    if (inner)
+      reinterpret_cast<i2*>(A.runs_o)[(int64_t)((int)c + ox + G.n[0] * (oy + G.n[1] * oz)) * ND + lane] = run;
+    else
+      reinterpret_cast<i2*>(A.runs_o)[flat3(G, hx + ox, hy + oy, hz + oz) * ND + lane] = run;
   }
   // the far movers close the home segment; their run is kept at the home
   // cell, with the cell's largest move (reduced over the cells afterwards:
