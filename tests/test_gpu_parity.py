@@ -45,7 +45,24 @@ def _tol(fp32):
 @pytest.mark.parametrize("name,dim,n,ppc,base,fp32", CASES)
 def test_deposit_and_grid_pass(name, dim, n, ppc, base, fp32):
     print(f"[gpu] deposit parity {name}", flush=True)
-    wl = _wl(dim, n, ppc, base, fp32)
+    _check_deposit_and_grid_pass(_wl(dim, n, ppc, base, fp32), dim, fp32)
+
+
+@pytest.mark.parametrize("fp32", [False, True])
+def test_deposit_with_four_species(fp32):
+    """Four species (the most the library holds): species 0 and 1 take the
+    deposit's prefetched path, species 2 and 3 the general one (every particle
+    located through the cell's run table); 150 particles per cell and species
+    give three 64-particle chunks each (compensated chunk sums in FP32)."""
+    print(f"[gpu] deposit parity, four species, fp32={fp32}", flush=True)
+    wl = synth.small("four_species", dim=3, n=(6, 5, 4), ppc=150, fp32=fp32, base="c5")
+    wl = wl.replace(q=(-1.0, 1.0, 1.0, -1.0), m=(1.0, 100.0, 16.0, 1.0), vth=(wl.vth[0], wl.vth[1], 0.02, 0.08),
+                    dsheet=(wl.dsheet[0], wl.dsheet[1], 0.0, 0.0))
+    assert wl.nsp == 4
+    _check_deposit_and_grid_pass(wl, 3, fp32)
+
+
+def _check_deposit_and_grid_pass(wl, dim, fp32):
     parts = H.species_arrays(wl, fp32)
     E, B = H.perturbed_fields(wl)
     G, sp = H.oracle_species(wl, parts)
