@@ -203,7 +203,7 @@ __device__ inline void gather_lds(const T W[8], const T* fc, T out[3]) {
 // far, 2: non-finite).  mv: running maximum of the accepted moves in cells
 // along any axis.
 template <typename T, int DIM>
-__device__ inline int push_one(T f[3], T v[3], const T* fc, T beta, const T dtx[3], const T lo[3], const T hi[3],
+__device__ inline int push_one(T f[3], T v[3], const T* fc, T beta, const T dtx[3],
                                int& stuck, T& mv, const DGrid& G, int hx) {
   constexpr int NC = Dm<DIM>::NC;
   T W[8];
@@ -228,7 +228,9 @@ __device__ inline int push_one(T f[3], T v[3], const T* fc, T beta, const T dtx[
   for (int d = 0; d < DIM; ++d) {
     const T m = v[d] * dtx[d];
     sn[d] = f[d] + m;
-    T lo_d = lo[d], hi_d = hi[d];
+    // accepted new positions relative to the home cell: [-(n - 2), n - 1)
+    // (derived here rather than passed: fewer live scalar registers)
+    T lo_d = (T)(2 - G.n[d]), hi_d = (T)(G.n[d] - 1);
     if (d == 0 && walled(G)) {
       // walled x: specular reflection on a wall (about x = 0: hx + s -> -(hx + s);
       // about x = L: -> 2 nxp - (hx + s)), or leaving through an inflow plane;
@@ -290,7 +292,6 @@ struct PushArgs {
   int32_t* far_o;  // [N][4]: far movers of each home cell (start, count), largest move (float bits), 0
   T beta;
   T dtx[3];
-  T lo[3], hi[3];  // accepted new positions relative to the home cell: [-(n - 2), n - 1) per axis
   int64_t n;
   int* flags;      // error flags, then this species' statistics at flags + GE_FL_SPECIES + 4 s
   int* stats;
@@ -429,8 +430,8 @@ __global__ __launch_bounds__(64) void k_push(DGrid G, PushArgs<T> A) {
     // and does not hold the second store for the first one's completion
     __builtin_amdgcn_s_waitcnt(0xF70);
     int d0 = 31, d1 = 31;
-    if (a0) d0 = push_one<T, DIM>(f0, v0, fc, A.beta, A.dtx, A.lo, A.hi, stuck, mv, G, hx);
-    if (a1) d1 = push_one<T, DIM>(f1, v1, fc, A.beta, A.dtx, A.lo, A.hi, stuck, mv, G, hx);
+    if (a0) d0 = push_one<T, DIM>(f0, v0, fc, A.beta, A.dtx, stuck, mv, G, hx);
+    if (a1) d1 = push_one<T, DIM>(f1, v1, fc, A.beta, A.dtx, stuck, mv, G, hx);
     // lanes sharing a direction: each lane ORs its bit into the 64-bit mask of
     // its direction, one mask per direction and slot (s_dm[slot][dir]).  OR
     // does not depend on the order in which the lanes' updates land, so the
@@ -464,7 +465,7 @@ __global__ __launch_bounds__(64) void k_push(DGrid G, PushArgs<T> A) {
         int dir = 31;
         if (act) {
           load_particle<T, DIM>(A, run_index(t, sst, spr, nseg), f, v, w);
-          dir = push_one<T, DIM>(f, v, fc, A.beta, A.dtx, A.lo, A.hi, stuck, mv, G, hx);
+          dir = push_one<T, DIM>(f, v, fc, A.beta, A.dtx, stuck, mv, G, hx);
         }
         const DirStats q = dir_stats(act, dir, lane);
         if (pass == 0) {
@@ -1432,8 +1433,6 @@ static void launch_push_t(ge_ctx* c, int s) {
   A.beta = (T)S.beta;
   for (int d = 0; d < 3; ++d) {
     A.dtx[d] = (T)(c->P.dt * c->G.idx[d]);
-    A.lo[d] = (T)(2 - c->G.n[d]);
-    A.hi[d] = (T)(c->G.n[d] - 1);
   }
   A.n = S.n;
   A.flags = c->flags;
